@@ -1,0 +1,196 @@
+/*
+ * erem.h - C ABI of the MI355X exponential Rosenbrock-Euler (EREM) library.
+ *
+ * The library advances the semi-discrete energy equation dT/dt = G(T) of a
+ * two-point-flux (TPFA) finite-volume discretisation with upwind advection
+ * (Tambue, Berre, Nordbotten, Sec. 3.1) by the EREM step
+ *
+ *     T^{n+1} = T^n + h phi1(h J_n) G(T^n),   J_n = D_T G(T^n)   (Eq. EERM)
+ *
+ * with phi1(h J) v evaluated by Newton interpolation at real Leja points
+ * (Sec. 4.2, Eqs. lejaa, approle, newt) or by an Arnoldi projection
+ * (Sec. 4.1, Eq. approphi, Alg. alg:al2).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Cells of an nx x ny x nz Cartesian grid (nz = 1 in 2D) are stored flat,
+ *   index x + nx*(y + ny*z).  All field arrays are FP64 unless stated.
+ * - Pointers named d_* are DEVICE pointers (HIP global memory on the device
+ *   that was current at erem_create).  The caller owns them; the library
+ *   reads or writes them only during the call's stream-ordered work and keeps
+ *   no reference afterwards (inputs are copied into context storage).
+ * - Pointers named h_* or plain out/in are HOST pointers.
+ * - Every call enqueues its device work on the stream given to erem_create
+ *   (a hipStream_t passed as void*; NULL = the null stream).  Calls that fill
+ *   an erem_stats or return host data synchronise that stream before
+ *   returning.
+ * - Return value: EREM_OK (0) or a negative error code; on error a message is
+ *   available from erem_last_error(ctx) and, for erem_step, T is unmodified.
+ *   No C++ exception crosses the ABI.
+ * - Units are SI; temperatures in degrees C.
+ */
+#ifndef EREM_H
+#define EREM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    EREM_OK = 0,
+    EREM_EINVAL = -1,      /* invalid argument (sizes, NULL, state order) */
+    EREM_ENOMEM = -2,      /* device or host allocation failed */
+    EREM_EDEVICE = -3,     /* a HIP runtime call failed */
+    EREM_ENOCONV = -4,     /* phi1 or pressure solve did not converge within limits */
+    EREM_ENONFINITE = -5   /* NaN or Inf met in a norm */
+};
+
+enum { EREM_METHOD_LEJA = 0, EREM_METHOD_KRYLOV = 1 };
+enum { EREM_PREC_FP64 = 0, EREM_PREC_MIXED = 1 };
+enum { EREM_LAW_CONSTANT = 0, EREM_LAW_WATER = 1 };
+
+typedef struct erem_ctx erem_ctx;
+
+/* Cartesian grid: dim is 2 or 3 (dim 2 requires nz == 1); cell sizes in m. */
+typedef struct {
+    int32_t dim;
+    int64_t nx, ny, nz;
+    double dx, dy, dz;
+} erem_grid;
+
+/* Options of one phi1 evaluation / EREM step.
+ * tol_a, tol_r: absolute / relative tolerance of the scaled error norm
+ *   sqrt(1/N sum (e_i / scal)^2), scal = tol_a + tol_r * ||T^n||_inf
+ *   (Sec. 4.2).  For erem_phi1_apply, ||T^n||_inf is replaced by h*||v||_inf.
+ * p_order: the stop test is 10^p_order * (mean of the last five estimates) < 1.
+ * m_max: maximum Leja degree per substep (<= 1024).
+ * max_substeps: maximum number of substeps the step may be split into.
+ * krylov_m: Arnoldi dimension of the Krylov method.
+ * rho_max: a-priori substep rule, substeps s = ceil(h (beta - alpha) / rho_max)
+ *   where [alpha, beta] is the Gershgorin interval of J (<= 0 disables).
+ * chunk: Leja terms enqueued before the host polls the device stop flag
+ *   (0 = automatic). */
+typedef struct {
+    int32_t method;
+    int32_t precision;
+    double tol_a, tol_r;
+    int32_t p_order, m_max, max_substeps, krylov_m, chunk;
+    double rho_max;
+} erem_opts;
+
+/* Statistics of the last call that fills them. */
+typedef struct {
+    int32_t m_total;       /* Leja terms (or Arnoldi steps) summed over substeps */
+    int32_t substeps;      /* substeps actually used */
+    int32_t iterations;    /* PCG iterations (erem_solve_pressure) */
+    int32_t restarts;      /* step restarts after non-convergence */
+    double alpha, beta;    /* Gershgorin interval of J */
+    double est_err;        /* last scaled error estimate (Leja) / residual (PCG) */
+} erem_stats;
+
+/* Fill *opts with the defaults: Leja, FP64, tol_a 0, tol_r 1e-12, p 2,
+ * m_max 256, max_substeps 64, krylov_m 10, chunk 0, rho_max 64. */
+void erem_default_opts(erem_opts* opts);
+
+/* Create a context for one grid on the current HIP device.  Allocates all
+ * device storage the path needs (about 20 FP64 words per cell).  stream is a
+ * hipStream_t (or NULL).  Errors: EINVAL for non-positive sizes, dim not in
+ * {2,3}, dim 2 with nz != 1; ENOMEM; EDEVICE. */
+int erem_create(const erem_grid* grid, void* stream, erem_ctx** out);
+int erem_destroy(erem_ctx* ctx);
+const char* erem_last_error(const erem_ctx* ctx);
+
+/* Rock: d_logk natural log of the permeability [m^2] and d_poro porosity,
+ * both N cells; lambda bulk thermal conductivity [W/m/K]; rhoc_s rock
+ * volumetric heat capacity [J/m^3/K].  The arrays are copied (Sec. 2). */
+int erem_set_rock(erem_ctx* ctx, const double* d_logk, const double* d_poro,
+                  double lambda, double rhoc_s);
+
+/* Fluid: law EREM_LAW_CONSTANT (rho = rho0, mu = mu0) or EREM_LAW_WATER
+ * (rho = 1000 (1 - 3e-4 (T - 20)), mu = 2.414e-5 * 10^(247.8/(T + 133)));
+ * c_f specific heat [J/kg/K].  The heat capacity of a cell is
+ * C = phi rho(T) c_f + (1 - phi) rhoc_s (Sec. 2, local equilibrium). */
+int erem_set_fluid(erem_ctx* ctx, int32_t law, double c_f, double mu0, double rho0);
+
+/* Boundary conditions: pressure Dirichlet p_left on the x = 0 face and
+ * p_right on the x = nx face (no flow elsewhere); temperature Dirichlet
+ * T_left on x = 0 (half-cell conduction when dirichlet_left != 0, and
+ * advective inflow), advective outflow on x = nx (inflow there enters at
+ * T_right), no heat flux elsewhere (Sec. 3.1 boundary fluxes and upwind
+ * rule). */
+int erem_set_bc(erem_ctx* ctx, double p_left, double p_right, double T_left, double T_right,
+                int32_t dirichlet_left);
+
+/* TPFA transmissibilities of the mass mobility rho(T) K / mu(T) with the
+ * harmonic mean |s| k_i k_j / (k_i d_j + k_j d_i) on interior faces and the
+ * Dirichlet half-cell |s| k_i / d_i on x faces (Sec. 3.1).  d_T gives the
+ * cell temperatures for the fluid laws (NULL: use T = 20 C). */
+int erem_assemble_transmissibilities(erem_ctx* ctx, const double* d_T);
+
+/* Steady pressure of the TPFA system sum_s tau_s (p_i - p_nb) = 0 by
+ * preconditioned conjugate gradients to relative residual rtol (at most
+ * max_iter iterations), then the face mass fluxes F = tau (p_i - p_j)
+ * (Darcy's law, Eq. darcy, g = 0).  d_p (N, may be NULL) is read as the
+ * initial guess when warm != 0 and receives the pressure.  stats (may be
+ * NULL) gets iterations and the final relative residual.  ENOCONV if rtol
+ * is not reached. */
+int erem_solve_pressure(erem_ctx* ctx, double rtol, int32_t max_iter, int32_t warm,
+                        double* d_p, erem_stats* stats);
+
+/* Set the face mass fluxes [kg/s] directly, replacing the pressure solve:
+ * d_fx (nz, ny, nx+1), d_fy (nz, ny+1, nx), d_fz (nz+1, ny, nx; NULL in 2D),
+ * positive along +x/+y/+z, boundary faces included. */
+int erem_set_face_fluxes(erem_ctx* ctx, const double* d_fx, const double* d_fy,
+                         const double* d_fz);
+
+/* Copy the face mass fluxes (same layouts as erem_set_face_fluxes) and the
+ * x/y/z face transmissibilities of the last assembly (same layouts; NULL
+ * pointers are skipped). */
+int erem_get_faces(erem_ctx* ctx, double* d_fx, double* d_fy, double* d_fz,
+                   double* d_tx, double* d_ty, double* d_tz);
+
+/* Form the Jacobian J = D_T G (Eq. linear) as a 5-point (2D) or 7-point (3D)
+ * stencil and F = G(T) at d_T, with the current face fluxes:
+ * G_i = R_i(T) / (V C_i(T)), R_i = sum of the TPFA conductive and upwind
+ * advective face terms (Sec. 3.1). */
+int erem_form_jacobian(erem_ctx* ctx, const double* d_T);
+
+/* Copy the stencil of J to d_coef (ndir x N, ndir = 5 in 2D, 7 in 3D,
+ * direction order centre, -x, +x, -y, +y, -z, +z; a coefficient toward a
+ * missing neighbour is 0) and F = G(T) to d_F (N).  Either may be NULL. */
+int erem_get_jacobian(erem_ctx* ctx, double* d_coef, double* d_F);
+
+/* d_out = phi1(h J) d_v for the J of the last erem_form_jacobian
+ * (Sec. 4.2 Newton-Leja or Sec. 4.1 Krylov, per opts->method).  d_v and
+ * d_out hold N values and must not alias. */
+int erem_phi1_apply(erem_ctx* ctx, double h, const double* d_v, double* d_out,
+                    const erem_opts* opts, erem_stats* stats);
+
+/* One EREM step in place: forms J and G at d_T with the current fluxes and
+ * sets d_T <- d_T + h phi1(h J) G(d_T) (Eq. EERM).  Substeps (Sec. 4.2,
+ * splitting when the degree is too large) integrate the linearised problem
+ * u' = J u + G(T^n) exactly up to the tolerance: u <- u + delta phi1(delta J)
+ * (G + J u). */
+int erem_step(erem_ctx* ctx, double h, double* d_T, const erem_opts* opts, erem_stats* stats);
+
+/* ---- host-side numerics (no device work; callable without a GPU) ---- */
+
+/* The first n real Leja points of [-2, 2] (Eq. lejaa): xi_0 = 2, then each
+ * new point maximises prod_k |xi - xi_k| over the interval; ties take the
+ * larger point.  n <= 1024. */
+int erem_leja_points(int32_t n, double* out);
+
+/* Newton divided differences d_k = g[xi_0..xi_k], k < n, of
+ * g(xi) = phi1(hc + hg xi) at the points xi (host array of n values),
+ * computed as the first column of phi1(hc I + hg L) with L lower bidiagonal
+ * (diagonal xi, subdiagonal 1) (Sec. 4.2), through the exponential of the
+ * augmented lower-bidiagonal matrix by Taylor scaling-and-squaring. */
+int erem_phi1_divided_differences(double hc, double hg, const double* xi, int32_t n,
+                                  double* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EREM_H */
