@@ -1,0 +1,207 @@
+#!/usr/bin/env python3
+"""Benchmark of the MI355X EREM path (one GPU).
+
+Default workload: the 512 x 512 sequential coupled problem (water laws,
+log-normal permeability sigma = 2 / correlation 16 cells, Peclet ~ 100,
+h = 1e6 s): each step recomputes the TPFA transmissibilities at T^n, solves
+the steady pressure (warm start, double-double refined PCG) and takes one
+EREM temperature step with the real-Leja phi1 (FP64).  Inputs are
+synthetic (seeded generators) and already resident in HBM when timing
+starts.
+
+Prints ONE JSON line: steps/s over the timed steps, the roofline of the
+dominant kernel (HIP-event timing of every launch inside the timed region),
+the Leja term kernel's own figures, and the CPU oracle timed on a bounded
+sample beside it (with the GPU/oracle agreement on that sample).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "EREM steps/s & Leja SpMV GB/s (% of HBM peak) at 1e-10 rel. err vs FP64 oracle"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic bytes per cell per launch (one pass per launch; stencil
+# structure implicit; halo re-reads counted once).
+LEJA_BYTES = {2: {"f64": 72, "f32": 36}, 3: {"f64": 88, "f32": 44}}
+PCG_A_BYTES = {2: 48, 3: 64}    # read z, p_old, face transmissibilities; write p_new, q
+PCG_B_BYTES = {2: 64, 3: 64}    # read x, p_new, r, q, diag; write x, r, z
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_workload(name):
+    from paper_1209_5553_amd import inputs
+    if name == "coupled512":
+        prob = inputs.coupled_problem(512)
+        desc = ("coupled 2D 512x512: TPFA steady pressure (water laws, sigma_logK=2, corr 16, "
+                "Pe~100) + EREM-Leja temperature step, h=1e6 s")
+        return prob, desc, True
+    if name == "linear32":
+        prob = inputs.linear_problem(32)
+        desc = "linear 2D 32x32 heat transport, fixed Darcy field, EREM-Leja, h=1e6 s"
+        return prob, desc, False
+    if name == "layered128":
+        prob = inputs.layered3d_problem(128)
+        desc = "linear 3D 128^3 7-point heat transport, layered K (3 decades), EREM-Leja, h=1e6 s"
+        return prob, desc, False
+    raise SystemExit(f"unknown workload {name}")
+
+
+def gpu_run(prob, coupled, steps, warmup, rtol_p):
+    import torch
+    from paper_1209_5553_amd.api import EremContext, make_opts
+
+    ctx = EremContext.from_problem(prob, device="cuda:0")
+    dev = ctx.device
+    T = torch.as_tensor(prob.T0, dtype=torch.float64, device=dev).clone()
+    p = torch.zeros(prob.n, dtype=torch.float64, device=dev)
+    opts = make_opts()
+    state = {"n": 0, "last": None, "pcg": 0}
+
+    if not coupled:
+        st = ctx.pressure_and_fluxes(rtol=rtol_p)
+
+    def one_step():
+        if coupled:
+            sp = ctx.pressure_and_fluxes(T, rtol=rtol_p, p=p, warm=state["n"] > 0)
+            state["pcg"] += sp["iterations"]
+        state["last"] = ctx.step(prob.h, T, opts)
+        state["n"] += 1
+
+    snapshots = {}
+    for w in range(warmup):
+        one_step()
+        if state["n"] <= 3:
+            snapshots[state["n"]] = T.clone()
+    log(f"warmup done ({warmup} steps), last stats {state['last']}")
+    torch.cuda.synchronize()
+    ctx.profile(True)
+    state["pcg"] = 0
+    m_total = 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        one_step()
+        m_total += state["last"]["m_total"]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    times = ctx.profile_read()
+    ctx.profile(False)
+    log(f"timed {steps} steps in {t1 - t0:.3f} s; kernel times {times}")
+    snaps = {k: v.cpu().numpy() for k, v in snapshots.items()}
+    return dict(elapsed=t1 - t0, times=times, m_per_step=m_total / steps,
+                pcg_per_step=state["pcg"] / steps, last=state["last"], snapshots=snaps,
+                T_final=T.cpu().numpy())
+
+
+def cpu_baseline(prob, coupled, nsteps, gpu_snaps):
+    """The oracle as it stands, on a bounded sample: the first `nsteps` steps
+    of the same workload (tier-B sparse action; SuperLU pressure)."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import erem as oerem
+    with threadpool_limits(limits=1):
+        T = np.asarray(prob.T0, dtype=np.float64).copy()
+        t0 = time.perf_counter()
+        if coupled:
+            for _ in range(nsteps):
+                T, _ = oerem.coupled_step(prob, T, tier="taylor")
+        else:
+            tier = "dense" if prob.n <= 4096 else "taylor"
+            layered = prob.nz > 1
+            T, _ = oerem.run_linear(prob, nsteps=nsteps, tier=tier, layered=layered)
+        t1 = time.perf_counter()
+    out = {"value": nsteps / (t1 - t0), "unit": "steps/s", "cores": 1, "kind": "oracle",
+           "sample": f"first {nsteps} steps of the same workload from T0 "
+                     f"({'SuperLU pressure + ' if coupled else ''}substepped Taylor action of the "
+                     f"augmented exponential, FP64, 1 thread)",
+           "seconds": t1 - t0}
+    if nsteps in gpu_snaps:
+        Tg = gpu_snaps[nsteps]
+        out["gpu_rel_err"] = float(np.abs(Tg - T).max() / np.abs(T).max())
+        out["gpu_increment_rel_err"] = float(np.abs((Tg - prob.T0) - (T - prob.T0)).max()
+                                             / np.abs(T - prob.T0).max())
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="coupled512", choices=["coupled512", "linear32", "layered128"])
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pressure-rtol", type=float, default=1e-16)
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this EREM build runs on exactly one GPU; multi-GPU runs "
+              "(--gpus > 1) are not part of it.", file=sys.stderr, flush=True)
+        sys.exit(2)
+    # the first min(3, cpu-steps) GPU steps are kept for the oracle comparison
+    args.cpu_steps = max(1, min(args.cpu_steps, 3))
+    if not args.no_cpu_baseline and args.warmup < args.cpu_steps:
+        args.warmup = args.cpu_steps
+
+    prob, desc, coupled = make_workload(args.workload)
+    log(f"workload {args.workload}: {desc}; N={prob.n}")
+    res = gpu_run(prob, coupled, args.steps, args.warmup, args.pressure_rtol)
+    dim = prob.dim
+    N = prob.n
+    t = res["times"]
+    kern = {
+        "leja_term": (t["leja_term_ms"], t["leja_term_launches"], LEJA_BYTES[dim]["f64"] * N),
+        "pcg_a": (t["pcg_a_ms"], t["pcg_a_launches"], PCG_A_BYTES[dim] * N),
+        "pcg_b": (t["pcg_b_ms"], t["pcg_b_launches"], PCG_B_BYTES[dim] * N),
+    }
+    dominant = max(kern, key=lambda k: kern[k][0])
+
+    def roof(name):
+        ms, n, bytes_per = kern[name]
+        if n == 0:
+            return None
+        avg_s = ms / n * 1e-3
+        ach = bytes_per / avg_s / 1e9
+        return {"kernel": name, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "avg_launch_us": round(avg_s * 1e6, 3), "launches": n,
+                "bytes_per_launch": bytes_per, "share_of_kernel_time": round(
+                    ms / max(sum(v[0] for v in kern.values()), 1e-30), 4)}
+
+    steps_s = args.steps / res["elapsed"]
+    line = {
+        "metric": METRIC, "value": round(steps_s, 3), "unit": "steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * res["elapsed"] / args.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded generators)",
+        "config": {"workload": desc, "grid": [prob.nx, prob.ny, prob.nz], "cells": N, "h_s": prob.h,
+                   "tol_r": 1e-12, "pressure_rtol": args.pressure_rtol if coupled else None},
+        "roofline": roof(dominant),
+        "leja": roof("leja_term"),
+        "leja_terms_per_step": res["m_per_step"],
+        "substeps": res["last"]["substeps"],
+        "pcg_iterations_per_step": res["pcg_per_step"],
+        "interval_hJ": [res["last"]["alpha"] * prob.h, res["last"]["beta"] * prob.h],
+    }
+    if not args.no_cpu_baseline:
+        log(f"cpu baseline: {args.cpu_steps} oracle step(s)")
+        line["cpu_baseline"] = cpu_baseline(prob, coupled, args.cpu_steps, res["snapshots"])
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

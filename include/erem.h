@@ -162,6 +162,12 @@ int erem_form_jacobian(erem_ctx* ctx, const double* d_T);
  * missing neighbour is 0) and F = G(T) to d_F (N).  Either may be NULL. */
 int erem_get_jacobian(erem_ctx* ctx, double* d_coef, double* d_F);
 
+/* Replace J and F by a caller-given stencil (same layout as
+ * erem_get_jacobian; coefficients toward missing neighbours must be 0) and
+ * F (N values), e.g. for a matrix that does not come from the TPFA model.
+ * The Gershgorin interval (Sec. 4.2) is recomputed from the rows. */
+int erem_set_jacobian(erem_ctx* ctx, const double* d_coef, const double* d_F);
+
 /* d_out = phi1(h J) d_v for the J of the last erem_form_jacobian
  * (Sec. 4.2 Newton-Leja or Sec. 4.1 Krylov, per opts->method).  d_v and
  * d_out hold N values and must not alias. */
@@ -174,6 +180,33 @@ int erem_phi1_apply(erem_ctx* ctx, double h, const double* d_v, double* d_out,
  * u' = J u + G(T^n) exactly up to the tolerance: u <- u + delta phi1(delta J)
  * (G + J u). */
 int erem_step(erem_ctx* ctx, double h, double* d_T, const erem_opts* opts, erem_stats* stats);
+
+/* As erem_step but with the J and F already held by the context (from
+ * erem_set_jacobian or erem_form_jacobian): d_T <- d_T + h phi1(h J) F. */
+int erem_step_frozen(erem_ctx* ctx, double h, double* d_T, const erem_opts* opts,
+                     erem_stats* stats);
+
+/* ---- measurement support ---- */
+
+/* Accumulated device time of the hot kernels while profiling is on,
+ * measured with a HIP event before and after each launch on the context's
+ * stream.  Only launches that did work are counted (a Leja term launch
+ * after the stop test passed, or a PCG iteration after convergence,
+ * returns at entry and is left out). */
+typedef struct {
+    double leja_term_ms;        /* Newton-Leja term kernels (Eq. newt) */
+    int64_t leja_term_launches;
+    double pcg_a_ms;            /* PCG: search direction + operator apply */
+    int64_t pcg_a_launches;
+    double pcg_b_ms;            /* PCG: iterate / residual / preconditioner update */
+    int64_t pcg_b_launches;
+} erem_kernel_times;
+
+/* Turn per-launch event timing on (enable != 0) or off and reset the
+ * counters.  Synchronises the stream.  Profiling adds one event record per
+ * launch (up to 8 substeps per evaluation are timed). */
+int erem_profile(erem_ctx* ctx, int32_t enable);
+int erem_profile_read(erem_ctx* ctx, erem_kernel_times* out);
 
 /* ---- host-side numerics (no device work; callable without a GPU) ---- */
 

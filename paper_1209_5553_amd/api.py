@@ -1,0 +1,216 @@
+"""Thin torch-facing binding of the EREM C ABI.
+
+Only argument marshalling happens here: tensors are checked (FP64,
+contiguous, on the context's device, right length) and their device pointers
+are handed to liberem.so together with the context's HIP stream.  Every step
+of the computation runs in the library's kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _native as nat
+
+
+class EremError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{nat.ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def make_opts(**kw) -> nat.Opts:
+    """erem_opts with the library defaults, overridden by keyword."""
+    o = nat.default_opts()
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def leja_points(n: int) -> np.ndarray:
+    out = np.zeros(n, dtype=np.float64)
+    rc = nat.load().erem_leja_points(n, out.ctypes.data_as(nat._PD))
+    if rc != 0:
+        raise EremError(rc, "erem_leja_points")
+    return out
+
+
+def phi1_divided_differences(hc: float, hg: float, xi) -> np.ndarray:
+    xi = np.ascontiguousarray(xi, dtype=np.float64)
+    out = np.zeros(xi.size, dtype=np.float64)
+    rc = nat.load().erem_phi1_divided_differences(hc, hg, xi.ctypes.data_as(nat._PD), xi.size,
+                                                  out.ctypes.data_as(nat._PD))
+    if rc != 0:
+        raise EremError(rc, "erem_phi1_divided_differences")
+    return out
+
+
+class EremContext:
+    """One grid's EREM state on one HIP device (see include/erem.h)."""
+
+    def __init__(self, nx: int, ny: int, nz: int = 1, dx: float = 1.0, dy: float = 1.0,
+                 dz: float = 1.0, device=None):
+        self.lib = nat.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("EremContext needs a HIP device")
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None
+                                   else torch.device(device).index or 0)
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.n = self.nx * self.ny * self.nz
+        self.dim = 3 if self.nz > 1 else 2
+        g = nat.Grid(self.dim, self.nx, self.ny, self.nz, dx, dy, dz)
+        with torch.cuda.device(self.device):
+            self.stream = torch.cuda.current_stream(self.device)
+            h = ctypes.c_void_p()
+            rc = self.lib.erem_create(ctypes.byref(g), ctypes.c_void_p(self.stream.cuda_stream),
+                                      ctypes.byref(h))
+        if rc != 0:
+            raise EremError(rc, "erem_create")
+        self.handle = h
+        self.ndir = 7 if self.dim == 3 else 5
+
+    # -- helpers -----------------------------------------------------------
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.erem_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int, what: str):
+        if rc != 0:
+            msg = self.lib.erem_last_error(self.handle)
+            raise EremError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def _ptr(self, t, n: int, name: str):
+        if t is None:
+            return None
+        if not isinstance(t, torch.Tensor):
+            raise TypeError(f"{name} must be a torch tensor")
+        if t.dtype != torch.float64 or not t.is_contiguous() or t.device != self.device:
+            raise ValueError(f"{name} must be a contiguous float64 tensor on {self.device}")
+        if t.numel() != n:
+            raise ValueError(f"{name} must hold {n} values, got {t.numel()}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def _new(self, n: int):
+        return torch.empty(n, dtype=torch.float64, device=self.device)
+
+    @property
+    def face_counts(self):
+        nx, ny, nz = self.nx, self.ny, self.nz
+        return nz * ny * (nx + 1), nz * (ny + 1) * nx, (nz + 1) * ny * nx
+
+    # -- ABI -----------------------------------------------------------------
+    def set_rock(self, logk, poro, lam: float, rhoc_s: float):
+        self._check(self.lib.erem_set_rock(self.handle, self._ptr(logk, self.n, "logk"),
+                                           self._ptr(poro, self.n, "poro"), lam, rhoc_s),
+                    "erem_set_rock")
+
+    def set_fluid(self, law: int, c_f: float, mu0: float, rho0: float):
+        self._check(self.lib.erem_set_fluid(self.handle, law, c_f, mu0, rho0), "erem_set_fluid")
+
+    def set_bc(self, p_left, p_right, T_left, T_right, dirichlet_left=True):
+        self._check(self.lib.erem_set_bc(self.handle, p_left, p_right, T_left, T_right,
+                                         1 if dirichlet_left else 0), "erem_set_bc")
+
+    def assemble_transmissibilities(self, T=None):
+        self._check(self.lib.erem_assemble_transmissibilities(self.handle, self._ptr(T, self.n, "T")),
+                    "erem_assemble_transmissibilities")
+
+    def solve_pressure(self, rtol=1e-14, max_iter=50000, p=None, warm=False):
+        st = nat.Stats()
+        self._check(self.lib.erem_solve_pressure(self.handle, rtol, max_iter, 1 if warm else 0,
+                                                 self._ptr(p, self.n, "p"), ctypes.byref(st)),
+                    "erem_solve_pressure")
+        return st.as_dict()
+
+    def set_face_fluxes(self, fx, fy, fz=None):
+        nfx, nfy, nfz = self.face_counts
+        self._check(self.lib.erem_set_face_fluxes(self.handle, self._ptr(fx, nfx, "fx"),
+                                                  self._ptr(fy, nfy, "fy"),
+                                                  self._ptr(fz, nfz, "fz")),
+                    "erem_set_face_fluxes")
+
+    def get_faces(self):
+        nfx, nfy, nfz = self.face_counts
+        out = {k: self._new(n) for k, n in
+               (("fx", nfx), ("fy", nfy), ("fz", nfz), ("tx", nfx), ("ty", nfy), ("tz", nfz))}
+        self._check(self.lib.erem_get_faces(self.handle, *(ctypes.c_void_p(out[k].data_ptr())
+                                                           for k in ("fx", "fy", "fz", "tx", "ty", "tz"))),
+                    "erem_get_faces")
+        return out
+
+    def form_jacobian(self, T):
+        self._check(self.lib.erem_form_jacobian(self.handle, self._ptr(T, self.n, "T")),
+                    "erem_form_jacobian")
+
+    def get_jacobian(self):
+        coef = self._new(self.ndir * self.n)
+        F = self._new(self.n)
+        self._check(self.lib.erem_get_jacobian(self.handle, ctypes.c_void_p(coef.data_ptr()),
+                                               ctypes.c_void_p(F.data_ptr())), "erem_get_jacobian")
+        return coef.view(self.ndir, self.n), F
+
+    def set_jacobian(self, coef, F):
+        self._check(self.lib.erem_set_jacobian(self.handle, self._ptr(coef, self.ndir * self.n, "coef"),
+                                               self._ptr(F, self.n, "F")), "erem_set_jacobian")
+
+    def step_frozen(self, h: float, T, opts: nat.Opts | None = None):
+        o = opts if opts is not None else make_opts()
+        st = nat.Stats()
+        self._check(self.lib.erem_step_frozen(self.handle, h, self._ptr(T, self.n, "T"), ctypes.byref(o),
+                                              ctypes.byref(st)), "erem_step_frozen")
+        return st.as_dict()
+
+    def phi1_apply(self, h: float, v, out=None, opts: nat.Opts | None = None):
+        out = self._new(self.n) if out is None else out
+        o = opts if opts is not None else make_opts()
+        st = nat.Stats()
+        self._check(self.lib.erem_phi1_apply(self.handle, h, self._ptr(v, self.n, "v"),
+                                             self._ptr(out, self.n, "out"), ctypes.byref(o),
+                                             ctypes.byref(st)), "erem_phi1_apply")
+        return out, st.as_dict()
+
+    def step(self, h: float, T, opts: nat.Opts | None = None):
+        o = opts if opts is not None else make_opts()
+        st = nat.Stats()
+        self._check(self.lib.erem_step(self.handle, h, self._ptr(T, self.n, "T"), ctypes.byref(o),
+                                       ctypes.byref(st)), "erem_step")
+        return st.as_dict()
+
+    def profile(self, enable: bool = True):
+        self._check(self.lib.erem_profile(self.handle, 1 if enable else 0), "erem_profile")
+
+    def profile_read(self):
+        kt = nat.KernelTimes()
+        self._check(self.lib.erem_profile_read(self.handle, ctypes.byref(kt)), "erem_profile_read")
+        return kt.as_dict()
+
+    # -- convenience -----------------------------------------------------------
+    @classmethod
+    def from_problem(cls, prob, device=None):
+        """Context loaded with a paper_1209_5553_amd.inputs.Problem (rock,
+        fluid, boundary conditions); fluxes are not computed yet."""
+        ctx = cls(prob.nx, prob.ny, prob.nz, prob.dx, prob.dy, prob.dz, device=device)
+        dev = ctx.device
+        ctx._logk = torch.as_tensor(prob.logk, dtype=torch.float64, device=dev).contiguous()
+        ctx._poro = torch.as_tensor(prob.poro, dtype=torch.float64, device=dev).contiguous()
+        ctx.set_rock(ctx._logk, ctx._poro, prob.lam, prob.rhoc_s)
+        ctx.set_fluid(prob.law, prob.c_f, prob.mu0, prob.rho0)
+        ctx.set_bc(prob.p_left, prob.p_right, prob.T_left, prob.T_right,
+                   getattr(prob, "dirichlet_left", True))
+        return ctx
+
+    def pressure_and_fluxes(self, T=None, rtol=1e-14, p=None, warm=False, max_iter=50000):
+        """Transmissibilities at T, steady pressure and face fluxes."""
+        self.assemble_transmissibilities(T)
+        return self.solve_pressure(rtol=rtol, max_iter=max_iter, p=p, warm=warm)

@@ -1,0 +1,133 @@
+// Shared declarations of the EREM device kernels and their host launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace erem {
+
+constexpr int kBX = 64;        // threads along x per block (one wavefront)
+constexpr int kBY = 4;         // rows per block -> 256 threads, 4 wavefronts
+constexpr int kThreads = kBX * kBY;
+constexpr int kSlots = 8;      // spread of the atomic partial sums
+constexpr int kMaxTerms = 1024;  // Leja degree cap per substep
+
+struct Dims {
+  int nx, ny, nz;      // cells
+  int dim;             // 2 or 3
+  int N;               // nx*ny*nz
+  double dx, dy, dz;
+};
+
+struct Phys {
+  int law;             // 0 constant, 1 water laws
+  int dirichlet_left;  // conduction half-cell on x = 0
+  double c_f, mu0, rho0, lam, rhoc_s;
+  double p_left, p_right, T_left, T_right;
+};
+
+// Per-evaluation Leja coefficients (device resident).
+struct LejaCoef {
+  double inv_g;                 // 1 / gamma
+  double thresh;                // 10^-p
+  double shift[kMaxTerms + 1];  // c/gamma + xi_{k-1} for term k
+  double dk[kMaxTerms + 1];     // divided differences d_k
+  double estf[kMaxTerms + 1];   // |delta d_k| / (sqrt(N) scal)
+};
+
+// Per-substep Leja stop state (device resident).
+struct LejaState {
+  int stopped;     // -1 running, else last term index included
+  int nonfinite;
+  int pad[2];
+  double sums[(kMaxTerms + 1) * kSlots];  // sum q_k^2, spread over kSlots
+};
+
+// Reduction targets of the assembly pass (ordered-integer encodings).
+struct AsmReduce {
+  unsigned long long lo;    // min_i (J_ii - R_i)
+  unsigned long long hi;    // max_i (J_ii + R_i)
+  unsigned long long tmax;  // max_i |T_i|
+  unsigned long long vmax;  // max_i |v_i| (phi1_apply)
+};
+
+// Conjugate-gradient scalars: ring of 4 iterations x kSlots partial sums.
+struct PcgState {
+  int done;        // 1 once converged
+  int it_done;     // iteration count at convergence
+  int nonfinite;
+  int pad;
+  double bb;       // ||b||^2 (reduced by the start kernel)
+  double tol2;     // rtol^2
+  double bb_sl[kSlots];
+  double rz[4 * kSlots];
+  double rr[4 * kSlots];
+  double pq[4 * kSlots];
+};
+
+inline dim3 cell_grid(const Dims& d) {
+  return dim3((d.nx + kBX - 1) / kBX, (d.ny + kBY - 1) / kBY, d.nz);
+}
+inline dim3 cell_block() { return dim3(kBX, kBY, 1); }
+
+// Host launchers (kernels.hip).  All enqueue on `s` and return hipGetLastError().
+hipError_t launch_transmissibility(const Dims& d, const Phys& ph, const double* logk,
+                                   const double* T, double* tx, double* ty, double* tz,
+                                   hipStream_t s);
+hipError_t launch_face_fluxes(const Dims& d, const Phys& ph, const double* p, const double* tx,
+                              const double* ty, const double* tz, double* fx, double* fy,
+                              double* fz, hipStream_t s);
+hipError_t launch_reset_reduce(AsmReduce* r, hipStream_t s);
+hipError_t launch_assemble(const Dims& d, const Phys& ph, const double* poro, const double* fx,
+                           const double* fy, const double* fz, const double* T, double* coef,
+                           double* F, AsmReduce* red, hipStream_t s);
+hipError_t launch_absmax(const Dims& d, const double* v, AsmReduce* red, hipStream_t s);
+hipError_t launch_gershgorin(const Dims& d, const double* coef, AsmReduce* red, hipStream_t s);
+hipError_t launch_stencil_axpy(const Dims& d, const double* coef, const double* v,
+                               const double* u, double* w, hipStream_t s);
+hipError_t launch_leja_reset(LejaState* st, int nslots, int nterms, hipStream_t s);
+hipError_t launch_leja_init(const Dims& d, const LejaCoef* cf, const double* v, double* q0,
+                            double* p, LejaState* st, hipStream_t s);
+hipError_t launch_leja_term(const Dims& d, const LejaCoef* cf, const double* coef,
+                            const double* qin, double* qout, double* p, LejaState* st, int k,
+                            hipStream_t s);
+hipError_t launch_substep_update(const Dims& d, double* u, const double* p, double delta,
+                                 int first, hipStream_t s);
+hipError_t launch_axpby(const Dims& d, double* y, double a, const double* x, double b,
+                        hipStream_t s);
+hipError_t launch_pcg_reset(PcgState* st, double tol2, hipStream_t s);
+hipError_t launch_pcg_start(const Dims& d, const Phys& ph, const double* tx, const double* ty,
+                            const double* tz, const double* x, double* r, double* z, double* p0,
+                            double* diag, PcgState* st, hipStream_t s);
+hipError_t launch_pcg_start_rhs(const Dims& d, const double* tx, const double* ty, const double* tz,
+                                const double* rhs, double* x, double* r, double* z, double* p0,
+                                double* diag, PcgState* st, hipStream_t s);
+hipError_t launch_dd_residual(const Dims& d, const Phys& ph, const double* tx, const double* ty,
+                              const double* tz, const double* phi, const double* plo, double* r,
+                              PcgState* st, hipStream_t s);
+hipError_t launch_dd_update(const Dims& d, double* phi, double* plo, const double* delta,
+                            hipStream_t s);
+hipError_t launch_face_fluxes_dd(const Dims& d, const Phys& ph, const double* phi,
+                                 const double* plo, const double* tx, const double* ty,
+                                 const double* tz, double* fx, double* fy, double* fz,
+                                 hipStream_t s);
+hipError_t launch_pcg_a(const Dims& d, const double* tx, const double* ty, const double* tz,
+                        const double* z, const double* pold, double* pnew, double* q,
+                        PcgState* st, int it, hipStream_t s);
+hipError_t launch_pcg_b(const Dims& d, double* x, double* r, double* z, const double* pnew,
+                        const double* q, const double* diag, PcgState* st, int it,
+                        hipStream_t s);
+
+// Ordered encoding of doubles for atomic min/max on 64-bit unsigned integers.
+__host__ __device__ inline unsigned long long ord_encode(double v) {
+  union { double d; unsigned long long u; } c;
+  c.d = v;
+  return (c.u >> 63) ? ~c.u : (c.u | 0x8000000000000000ull);
+}
+__host__ __device__ inline double ord_decode(unsigned long long k) {
+  union { double d; unsigned long long u; } c;
+  c.u = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
+  return c.d;
+}
+
+}  // namespace erem

@@ -1,0 +1,736 @@
+// C ABI of the EREM library: context, assembly, pressure, phi1 and the step.
+//
+// Host control follows the paper's algorithm (Sec. 4.2): Gershgorin interval
+// of J, Leja points on [-2, 2], divided differences of phi1 on the scaled
+// interval, Newton recurrence with the scaled-norm stop test, and splitting
+// of the step when the degree would be too large.  All per-cell work runs in
+// the kernels of kernels.hip; the host only moves scalars.
+#include "erem.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "device.h"
+#include "host_numerics.h"
+
+using namespace erem;
+
+struct DivDiffCache {
+  double hc = NAN, hg = NAN;
+  int n = 0;
+  std::vector<double> d;
+};
+
+struct erem_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  Dims d{};
+  Phys ph{};
+  bool rock_set = false, fluid_set = false, bc_set = false;
+  bool trans_set = false, flux_set = false, jac_set = false;
+
+  // fields (device)
+  double *logk = nullptr, *poro = nullptr;
+  double *tx = nullptr, *ty = nullptr, *tz = nullptr;
+  double *fx = nullptr, *fy = nullptr, *fz = nullptr;
+  double *coef = nullptr, *F = nullptr;
+  double *qa = nullptr, *qb = nullptr, *pacc = nullptr, *u = nullptr, *w = nullptr;
+  double *pres = nullptr, *pr = nullptr, *pz = nullptr, *pp0 = nullptr, *pp1 = nullptr;
+  double *pq = nullptr, *pdiag = nullptr, *pres_lo = nullptr, *pdelta = nullptr, *prhs = nullptr;
+  size_t nfx = 0, nfy = 0, nfz = 0;
+
+  // device control blocks
+  LejaCoef* cf = nullptr;
+  LejaState* states = nullptr;
+  int nstates = 0;
+  AsmReduce* red = nullptr;
+  PcgState* pcg = nullptr;
+
+  // pinned host mirrors
+  LejaCoef* h_cf = nullptr;
+  LejaState* h_states = nullptr;
+  AsmReduce* h_red = nullptr;
+  PcgState* h_pcg = nullptr;
+
+  std::vector<double> xi;  // Leja points
+  DivDiffCache dd;
+  int last_m = 0;          // degree used by the previous evaluation
+  // profiling (HIP events around each Leja term and PCG half-iteration)
+  bool prof = false;
+  std::vector<hipEvent_t> ev;
+  double t_leja = 0.0, t_pcg_a = 0.0, t_pcg_b = 0.0;
+  long long n_leja = 0, n_pcg_a = 0, n_pcg_b = 0;
+  double alpha = 0.0, beta = 0.0, tmax = 0.0;
+  std::string err;
+};
+
+namespace {
+
+int fail(erem_ctx* c, int code, const std::string& msg) {
+  if (c) c->err = msg;
+  return code;
+}
+
+#define HIP_TRY(ctx, expr)                                                        \
+  do {                                                                            \
+    hipError_t _e = (expr);                                                       \
+    if (_e != hipSuccess)                                                         \
+      return fail((ctx), EREM_EDEVICE, std::string(#expr ": ") + hipGetErrorString(_e)); \
+  } while (0)
+
+// Make sure the event pool holds at least n events (profiling only).
+int ensure_events(erem_ctx* c, size_t n) {
+  while (c->ev.size() < n) {
+    hipEvent_t e;
+    HIP_TRY(c, hipEventCreate(&e));
+    c->ev.push_back(e);
+  }
+  return EREM_OK;
+}
+
+double elapsed_ms(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.0f;
+  return hipEventElapsedTime(&ms, a, b) == hipSuccess ? static_cast<double>(ms) : 0.0;
+}
+
+constexpr int kProfSubsteps = 8;  // profiled substeps per evaluation
+
+int check_opts(erem_ctx* c, const erem_opts* o) {
+  if (!o) return fail(c, EREM_EINVAL, "opts is NULL");
+  if (o->method != EREM_METHOD_LEJA && o->method != EREM_METHOD_KRYLOV)
+    return fail(c, EREM_EINVAL, "unknown method");
+  if (o->precision != EREM_PREC_FP64 && o->precision != EREM_PREC_MIXED)
+    return fail(c, EREM_EINVAL, "unknown precision");
+  if (!(o->tol_a >= 0.0) || !(o->tol_r >= 0.0) || (o->tol_a == 0.0 && o->tol_r == 0.0))
+    return fail(c, EREM_EINVAL, "tolerances must be >= 0 and not both 0");
+  if (o->m_max < 5 || o->m_max > kMaxTerms) return fail(c, EREM_EINVAL, "m_max must be in [5, 1024]");
+  if (o->max_substeps < 1 || o->max_substeps > 4096) return fail(c, EREM_EINVAL, "max_substeps must be in [1, 4096]");
+  if (o->p_order < 0 || o->p_order > 12) return fail(c, EREM_EINVAL, "p_order must be in [0, 12]");
+  if (o->chunk < 0) return fail(c, EREM_EINVAL, "chunk must be >= 0");
+  return EREM_OK;
+}
+
+template <class T>
+int dev_alloc(erem_ctx* c, T** p, size_t count) {
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
+  if (e != hipSuccess) return fail(c, EREM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  return EREM_OK;
+}
+
+void free_all(erem_ctx* c) {
+  double** bufs[] = {&c->logk, &c->poro, &c->tx, &c->ty, &c->tz, &c->fx, &c->fy, &c->fz,
+                     &c->coef, &c->F, &c->qa, &c->qb, &c->pacc, &c->u, &c->w, &c->pres,
+                     &c->pr, &c->pz, &c->pp0, &c->pp1, &c->pq, &c->pdiag,
+                     &c->pres_lo, &c->pdelta, &c->prhs};
+  for (double** b : bufs)
+    if (*b) { (void)hipFree(*b); *b = nullptr; }
+  if (c->cf) (void)hipFree(c->cf);
+  if (c->states) (void)hipFree(c->states);
+  if (c->red) (void)hipFree(c->red);
+  if (c->pcg) (void)hipFree(c->pcg);
+  if (c->h_cf) (void)hipHostFree(c->h_cf);
+  if (c->h_states) (void)hipHostFree(c->h_states);
+  if (c->h_red) (void)hipHostFree(c->h_red);
+  if (c->h_pcg) (void)hipHostFree(c->h_pcg);
+  c->cf = nullptr; c->states = nullptr; c->red = nullptr; c->pcg = nullptr;
+  c->h_cf = nullptr; c->h_states = nullptr; c->h_red = nullptr; c->h_pcg = nullptr;
+}
+
+int ndir(const erem_ctx* c) { return c->d.dim == 3 ? 7 : 5; }
+
+// Divided differences for (hc, hg) with at least n coefficients (cached).
+const std::vector<double>& divided_differences(erem_ctx* c, double hc, double hg, int n) {
+  DivDiffCache& dd = c->dd;
+  if (!(dd.hc == hc && dd.hg == hg && dd.n >= n)) {
+    dd.d.assign(n, 0.0);
+    phi1_divided_differences(hc, hg, c->xi.data(), n, dd.d.data());
+    dd.hc = hc;
+    dd.hg = hg;
+    dd.n = n;
+  }
+  return dd.d;
+}
+
+// Read the assembly reductions (Gershgorin interval, max |T|, max |v|).
+int read_reduce(erem_ctx* c) {
+  HIP_TRY(c, hipMemcpyAsync(c->h_red, c->red, sizeof(AsmReduce), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->alpha = ord_decode(c->h_red->lo);
+  c->beta = ord_decode(c->h_red->hi);
+  c->tmax = ord_decode(c->h_red->tmax);
+  return EREM_OK;
+}
+
+// u <- h phi1(h J) v by s Leja substeps of delta = h/s, each an exact
+// integration of the linear ODE u' = J u + v over delta:
+//   u_{j+1} = u_j + delta phi1(delta J) (v + J u_j)   (Sec. 4.2 splitting).
+// Returns EREM_OK, EREM_ENOCONV (some substep did not stop within K terms)
+// or an error.  `m_used` receives the summed degree.
+int leja_hphi1(erem_ctx* c, double h, const double* v, double scal, int s, int K,
+               const erem_opts* o, int* m_used, double* est_last) {
+  const double a = c->alpha, b = c->beta;
+  const double cc = 0.5 * (a + b);
+  const double gg = 0.25 * (b - a);
+  const double delta = h / s;
+  const int n = K + 1;
+  const std::vector<double>& dv = divided_differences(c, delta * cc, delta * gg, n);
+  LejaCoef* hc = c->h_cf;
+  hc->inv_g = 1.0 / gg;
+  hc->thresh = std::pow(10.0, -o->p_order);
+  const double rootN = std::sqrt(static_cast<double>(c->d.N));
+  for (int k = 0; k < n; ++k) {
+    hc->dk[k] = dv[k];
+    hc->shift[k] = (k > 0) ? cc / gg + c->xi[k - 1] : 0.0;
+    hc->estf[k] = std::fabs(delta * dv[k]) / (rootN * scal);
+  }
+  const size_t cf_bytes = offsetof(LejaCoef, shift) + 3 * sizeof(double) * (kMaxTerms + 1);
+  HIP_TRY(c, hipMemcpyAsync(c->cf, hc, cf_bytes, hipMemcpyHostToDevice, c->stream));
+  if (launch_leja_reset(c->states, s, K, c->stream) != hipSuccess)
+    return fail(c, EREM_EDEVICE, "leja reset launch failed");
+  const Dims& d = c->d;
+  const int nprof = c->prof ? std::min(s, kProfSubsteps) : 0;
+  if (nprof) {
+    const int rc = ensure_events(c, static_cast<size_t>(nprof) * (K + 1));
+    if (rc) return rc;
+  }
+  for (int j = 0; j < s; ++j) {
+    LejaState* st = c->states + j;
+    const double* src = v;
+    if (j > 0) {
+      HIP_TRY(c, launch_stencil_axpy(d, c->coef, v, c->u, c->w, c->stream));
+      src = c->w;
+    }
+    HIP_TRY(c, launch_leja_init(d, c->cf, src, c->qa, c->pacc, st, c->stream));
+    hipEvent_t* evj = j < nprof ? &c->ev[static_cast<size_t>(j) * (K + 1)] : nullptr;
+    if (evj) HIP_TRY(c, hipEventRecord(evj[0], c->stream));
+    for (int k = 1; k <= K; ++k) {
+      const double* qin = (k & 1) ? c->qa : c->qb;
+      double* qout = (k & 1) ? c->qb : c->qa;
+      HIP_TRY(c, launch_leja_term(d, c->cf, c->coef, qin, qout, c->pacc, st, k, c->stream));
+      if (evj) HIP_TRY(c, hipEventRecord(evj[k], c->stream));
+    }
+    HIP_TRY(c, launch_substep_update(d, c->u, c->pacc, delta, j == 0 ? 1 : 0, c->stream));
+  }
+  // Read the stop state of every substep (sums of the last terms included).
+  const size_t hdr = offsetof(LejaState, sums);
+  for (int j = 0; j < s; ++j)
+    HIP_TRY(c, hipMemcpyAsync(reinterpret_cast<char*>(c->h_states + j),
+                              reinterpret_cast<const char*>(c->states + j),
+                              hdr + sizeof(double) * kSlots * (K + 1), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  int total = 0;
+  double last = 0.0;
+  for (int j = 0; j < s; ++j) {
+    const LejaState& st = c->h_states[j];
+    if (st.nonfinite) return fail(c, EREM_ENONFINITE, "non-finite Leja term norm");
+    int stop = st.stopped;
+    auto est = [&](int k) {
+      double S = 0.0;
+      for (int q = 0; q < kSlots; ++q) S += st.sums[k * kSlots + q];
+      return hc->estf[k] * std::sqrt(S);
+    };
+    if (stop < 0) {
+      // No launch saw the test pass; evaluate it after the last term K.
+      for (int k = 0; k <= K; ++k)
+        if (!std::isfinite(est(k))) return fail(c, EREM_ENONFINITE, "non-finite Leja term norm");
+      double mean = 0.0;
+      for (int k = K - 4; k <= K; ++k) mean += est(k);
+      mean *= 0.2;
+      if (!(mean < hc->thresh)) return EREM_ENOCONV;
+      stop = K;
+    }
+    total += stop;
+    last = est(stop);
+    if (j < nprof) {
+      // launches 1..stop computed a term; later ones returned at entry
+      const hipEvent_t* evj = &c->ev[static_cast<size_t>(j) * (K + 1)];
+      for (int k = 1; k <= stop; ++k) c->t_leja += elapsed_ms(evj[k - 1], evj[k]);
+      c->n_leja += stop;
+    }
+  }
+  *m_used = total;
+  *est_last = last;
+  return EREM_OK;
+}
+
+// Full phi1 evaluation with the substep / restart policy.  On success c->u
+// holds h phi1(h J) v.
+int hphi1_eval(erem_ctx* c, double h, const double* v, double scal, const erem_opts* o, erem_stats* stats) {
+  const double width = c->beta - c->alpha;
+  const double mag = std::max(std::fabs(c->alpha), std::fabs(c->beta));
+  if (!std::isfinite(width)) return fail(c, EREM_ENONFINITE, "non-finite Gershgorin interval");
+  if (stats) { stats->alpha = c->alpha; stats->beta = c->beta; stats->restarts = 0; }
+  if (width <= 1e-14 * mag || width == 0.0) {
+    // Degenerate interval: J = c I (all Gershgorin radii zero, equal
+    // diagonal), so h phi1(h J) v = h phi1(h c) v exactly.
+    const double z = h * 0.5 * (c->alpha + c->beta);
+    const double f = (z == 0.0) ? h : h * (std::expm1(z) / z);
+    HIP_TRY(c, launch_axpby(c->d, c->u, 0.0, v, f, c->stream));
+    if (stats) { stats->m_total = 0; stats->substeps = 1; stats->est_err = 0.0; }
+    return EREM_OK;
+  }
+  int s = 1;
+  if (o->rho_max > 0.0) s = std::max(1, static_cast<int>(std::ceil(h * width / o->rho_max)));
+  if (s > o->max_substeps) s = o->max_substeps;
+  if (s > c->nstates) s = c->nstates;
+  int K = o->chunk > 0 ? std::min(o->chunk, o->m_max)
+                       : (c->last_m > 0 ? std::min(o->m_max, c->last_m + 8) : o->m_max);
+  int restarts = 0;
+  for (;;) {
+    int m_used = 0;
+    double est = 0.0;
+    const int rc = leja_hphi1(c, h, v, scal, s, K, o, &m_used, &est);
+    if (rc == EREM_OK) {
+      c->last_m = (m_used + s - 1) / s;
+      if (stats) {
+        stats->m_total = m_used;
+        stats->substeps = s;
+        stats->est_err = est;
+        stats->restarts = restarts;
+      }
+      return EREM_OK;
+    }
+    if (rc != EREM_ENOCONV) return rc;
+    ++restarts;
+    if (K < o->m_max) {
+      K = o->m_max;
+    } else if (2 * s <= std::min(o->max_substeps, c->nstates)) {
+      s *= 2;
+    } else {
+      return fail(c, EREM_ENOCONV, "phi1 did not converge within m_max terms and max_substeps substeps");
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" {
+
+void erem_default_opts(erem_opts* o) {
+  if (!o) return;
+  o->method = EREM_METHOD_LEJA;
+  o->precision = EREM_PREC_FP64;
+  o->tol_a = 0.0;
+  o->tol_r = 1e-12;
+  o->p_order = 2;
+  o->m_max = 256;
+  o->max_substeps = 64;
+  o->krylov_m = 10;
+  o->chunk = 0;
+  o->rho_max = 64.0;
+}
+
+int erem_create(const erem_grid* g, void* stream, erem_ctx** out) {
+  if (!out) return EREM_EINVAL;
+  *out = nullptr;
+  if (!g) return EREM_EINVAL;
+  if (g->dim != 2 && g->dim != 3) return EREM_EINVAL;
+  if (g->nx < 1 || g->ny < 1 || g->nz < 1) return EREM_EINVAL;
+  if (g->dim == 2 && g->nz != 1) return EREM_EINVAL;
+  if (!(g->dx > 0) || !(g->dy > 0) || !(g->dz > 0)) return EREM_EINVAL;
+  // Cell and face indices are 32-bit: at most 2^30 cells, 65535 layers.
+  // Launch grids put ny/4 blocks on the second grid axis (at most 65535).
+  if (g->nx > (1 << 30) || g->ny > 4ll * 65535 || g->nz > 65535) return EREM_EINVAL;
+  if (g->nx * g->ny > (1ll << 30)) return EREM_EINVAL;
+  const long long N = g->nx * g->ny * g->nz;
+  if (N + g->ny * g->nz > (1ll << 30) || N + g->nx * g->nz > (1ll << 30) || N + g->nx * g->ny > (1ll << 30))
+    return EREM_EINVAL;
+  erem_ctx* c = new (std::nothrow) erem_ctx();
+  if (!c) return EREM_ENOMEM;
+  c->stream = static_cast<hipStream_t>(stream);
+  if (hipGetDevice(&c->device) != hipSuccess) { delete c; return EREM_EDEVICE; }
+  c->d.nx = static_cast<int>(g->nx);
+  c->d.ny = static_cast<int>(g->ny);
+  c->d.nz = static_cast<int>(g->nz);
+  c->d.dim = g->dim;
+  c->d.N = static_cast<int>(N);
+  c->d.dx = g->dx; c->d.dy = g->dy; c->d.dz = g->dz;
+  const size_t n = static_cast<size_t>(N);
+  c->nfx = static_cast<size_t>(g->nz) * g->ny * (g->nx + 1);
+  c->nfy = static_cast<size_t>(g->nz) * (g->ny + 1) * g->nx;
+  c->nfz = static_cast<size_t>(g->nz + 1) * g->ny * g->nx;
+  int rc = EREM_OK;
+  rc |= dev_alloc(c, &c->logk, n);
+  rc |= dev_alloc(c, &c->poro, n);
+  rc |= dev_alloc(c, &c->tx, c->nfx);
+  rc |= dev_alloc(c, &c->ty, c->nfy);
+  rc |= dev_alloc(c, &c->tz, c->nfz);
+  rc |= dev_alloc(c, &c->fx, c->nfx);
+  rc |= dev_alloc(c, &c->fy, c->nfy);
+  rc |= dev_alloc(c, &c->fz, c->nfz);
+  rc |= dev_alloc(c, &c->coef, n * ndir(c));
+  rc |= dev_alloc(c, &c->F, n);
+  rc |= dev_alloc(c, &c->qa, n);
+  rc |= dev_alloc(c, &c->qb, n);
+  rc |= dev_alloc(c, &c->pacc, n);
+  rc |= dev_alloc(c, &c->u, n);
+  rc |= dev_alloc(c, &c->w, n);
+  rc |= dev_alloc(c, &c->pres, n);
+  rc |= dev_alloc(c, &c->pr, n);
+  rc |= dev_alloc(c, &c->pz, n);
+  rc |= dev_alloc(c, &c->pp0, n);
+  rc |= dev_alloc(c, &c->pp1, n);
+  rc |= dev_alloc(c, &c->pq, n);
+  rc |= dev_alloc(c, &c->pdiag, n);
+  rc |= dev_alloc(c, &c->pres_lo, n);
+  rc |= dev_alloc(c, &c->pdelta, n);
+  rc |= dev_alloc(c, &c->prhs, n);
+  c->nstates = 64;
+  rc |= dev_alloc(c, &c->cf, 1);
+  rc |= dev_alloc(c, &c->states, c->nstates);
+  rc |= dev_alloc(c, &c->red, 1);
+  rc |= dev_alloc(c, &c->pcg, 1);
+  if (rc == EREM_OK) {
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->h_cf), sizeof(LejaCoef), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&c->h_states), sizeof(LejaState) * c->nstates, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&c->h_red), sizeof(AsmReduce), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&c->h_pcg), sizeof(PcgState), hipHostMallocDefault) != hipSuccess)
+      rc = EREM_ENOMEM;
+  }
+  if (rc != EREM_OK) {
+    free_all(c);
+    delete c;
+    return EREM_ENOMEM;
+  }
+  // Zero-initialise the state that is read before it is written.
+  (void)hipMemsetAsync(c->pres, 0, n * sizeof(double), c->stream);
+  (void)hipMemsetAsync(c->pres_lo, 0, n * sizeof(double), c->stream);
+  (void)hipMemsetAsync(c->fz, 0, c->nfz * sizeof(double), c->stream);
+  (void)hipMemsetAsync(c->tz, 0, c->nfz * sizeof(double), c->stream);
+  (void)hipMemsetAsync(c->u, 0, n * sizeof(double), c->stream);
+  if (!leja_points(kMaxTerms + 1, c->xi)) {
+    free_all(c);
+    delete c;
+    return EREM_EINVAL;
+  }
+  if (hipStreamSynchronize(c->stream) != hipSuccess) {
+    free_all(c);
+    delete c;
+    return EREM_EDEVICE;
+  }
+  // Defaults of the linear workloads; every setter overrides them.
+  c->ph.law = EREM_LAW_CONSTANT;
+  c->ph.dirichlet_left = 1;
+  c->ph.c_f = 4200.0; c->ph.mu0 = 1e-3; c->ph.rho0 = 1000.0;
+  c->ph.lam = 2.5; c->ph.rhoc_s = 2.4e6;
+  c->ph.p_left = 0.0; c->ph.p_right = 0.0; c->ph.T_left = 20.0; c->ph.T_right = 20.0;
+  *out = c;
+  return EREM_OK;
+}
+
+int erem_destroy(erem_ctx* c) {
+  if (!c) return EREM_EINVAL;
+  (void)hipStreamSynchronize(c->stream);
+  for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+  c->ev.clear();
+  free_all(c);
+  delete c;
+  return EREM_OK;
+}
+
+const char* erem_last_error(const erem_ctx* c) {
+  if (!c) return "NULL context";
+  return c->err.c_str();
+}
+
+int erem_set_rock(erem_ctx* c, const double* d_logk, const double* d_poro, double lambda, double rhoc_s) {
+  if (!c) return EREM_EINVAL;
+  if (!d_logk || !d_poro) return fail(c, EREM_EINVAL, "logk and poro are required");
+  if (!(lambda > 0) || !(rhoc_s >= 0)) return fail(c, EREM_EINVAL, "lambda must be > 0, rhoc_s >= 0");
+  const size_t bytes = sizeof(double) * c->d.N;
+  HIP_TRY(c, hipMemcpyAsync(c->logk, d_logk, bytes, hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->poro, d_poro, bytes, hipMemcpyDeviceToDevice, c->stream));
+  c->ph.lam = lambda;
+  c->ph.rhoc_s = rhoc_s;
+  c->rock_set = true;
+  return EREM_OK;
+}
+
+int erem_set_fluid(erem_ctx* c, int32_t law, double c_f, double mu0, double rho0) {
+  if (!c) return EREM_EINVAL;
+  if (law != EREM_LAW_CONSTANT && law != EREM_LAW_WATER) return fail(c, EREM_EINVAL, "unknown law");
+  if (!(c_f > 0) || !(mu0 > 0) || !(rho0 > 0)) return fail(c, EREM_EINVAL, "c_f, mu0, rho0 must be > 0");
+  c->ph.law = law;
+  c->ph.c_f = c_f;
+  c->ph.mu0 = mu0;
+  c->ph.rho0 = rho0;
+  c->fluid_set = true;
+  return EREM_OK;
+}
+
+int erem_set_bc(erem_ctx* c, double p_left, double p_right, double T_left, double T_right,
+                int32_t dirichlet_left) {
+  if (!c) return EREM_EINVAL;
+  if (!std::isfinite(p_left) || !std::isfinite(p_right) || !std::isfinite(T_left) || !std::isfinite(T_right))
+    return fail(c, EREM_EINVAL, "boundary values must be finite");
+  c->ph.p_left = p_left;
+  c->ph.p_right = p_right;
+  c->ph.T_left = T_left;
+  c->ph.T_right = T_right;
+  c->ph.dirichlet_left = dirichlet_left ? 1 : 0;
+  c->bc_set = true;
+  return EREM_OK;
+}
+
+int erem_assemble_transmissibilities(erem_ctx* c, const double* d_T) {
+  if (!c) return EREM_EINVAL;
+  if (!c->rock_set) return fail(c, EREM_EINVAL, "erem_set_rock must come first");
+  HIP_TRY(c, launch_transmissibility(c->d, c->ph, c->logk, d_T, c->tx, c->ty, c->tz, c->stream));
+  c->trans_set = true;
+  return EREM_OK;
+}
+
+int erem_solve_pressure(erem_ctx* c, double rtol, int32_t max_iter, int32_t warm, double* d_p, erem_stats* stats) {
+  if (!c) return EREM_EINVAL;
+  if (!c->trans_set) return fail(c, EREM_EINVAL, "erem_assemble_transmissibilities must come first");
+  if (!(rtol > 0) || max_iter < 1) return fail(c, EREM_EINVAL, "rtol must be > 0 and max_iter >= 1");
+  const Dims& d = c->d;
+  const size_t bytes = sizeof(double) * d.N;
+  if (warm && d_p) HIP_TRY(c, hipMemcpyAsync(c->pres, d_p, bytes, hipMemcpyDeviceToDevice, c->stream));
+  if (!warm) HIP_TRY(c, hipMemsetAsync(c->pres, 0, bytes, c->stream));
+  if (!warm || d_p) HIP_TRY(c, hipMemsetAsync(c->pres_lo, 0, bytes, c->stream));
+  // Iterative refinement: residual of the double-double pressure, PCG on the
+  // correction to a relative 1e-9, double-double update.
+  const double inner_tol = 1e-9;
+  int total = 0;
+  bool ok = false;
+  double relres = NAN;
+  for (int outer = 0; outer < 8; ++outer) {
+    HIP_TRY(c, launch_pcg_reset(c->pcg, 0.0, c->stream));
+    HIP_TRY(c, launch_dd_residual(d, c->ph, c->tx, c->ty, c->tz, c->pres, c->pres_lo, c->prhs, c->pcg, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->h_pcg, c->pcg, sizeof(PcgState), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    double rr = 0.0, bb = 0.0;
+    for (int q = 0; q < kSlots; ++q) { rr += c->h_pcg->rr[q]; bb += c->h_pcg->bb_sl[q]; }
+    if (!std::isfinite(rr)) return fail(c, EREM_ENONFINITE, "non-finite pressure residual");
+    relres = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
+    if (relres <= rtol || rr == 0.0) { ok = true; break; }
+    if (total >= max_iter) break;
+    // PCG on A delta = r from delta = 0
+    HIP_TRY(c, launch_pcg_reset(c->pcg, inner_tol * inner_tol, c->stream));
+    HIP_TRY(c, launch_pcg_start_rhs(d, c->tx, c->ty, c->tz, c->prhs, c->pdelta, c->pr, c->pz, c->pp0, c->pdiag,
+                                    c->pcg, c->stream));
+    const int chunk = 64;
+    int it = 0;
+    bool done = false;
+    if (c->prof) {
+      const int rc = ensure_events(c, 2 * chunk + 1);
+      if (rc) return rc;
+    }
+    while (total + it < max_iter) {
+      const int n = std::min(chunk, max_iter - total - it);
+      const int it0 = it;
+      if (c->prof) HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
+      for (int j = 0; j < n; ++j, ++it) {
+        double* pold = (it & 1) ? c->pp1 : c->pp0;
+        double* pnew = (it & 1) ? c->pp0 : c->pp1;
+        HIP_TRY(c, launch_pcg_a(d, c->tx, c->ty, c->tz, c->pz, pold, pnew, c->pq, c->pcg, it, c->stream));
+        if (c->prof) HIP_TRY(c, hipEventRecord(c->ev[2 * j + 1], c->stream));
+        HIP_TRY(c, launch_pcg_b(d, c->pdelta, c->pr, c->pz, pnew, c->pq, c->pdiag, c->pcg, it, c->stream));
+        if (c->prof) HIP_TRY(c, hipEventRecord(c->ev[2 * j + 2], c->stream));
+      }
+      HIP_TRY(c, hipMemcpyAsync(c->h_pcg, c->pcg, sizeof(PcgState), hipMemcpyDeviceToHost, c->stream));
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+      if (c->h_pcg->nonfinite) return fail(c, EREM_ENONFINITE, "non-finite PCG residual");
+      const bool fin = c->h_pcg->done != 0;
+      if (c->prof) {
+        // iterations it0 .. it_done-1 ran fully; the test launch it_done returned at entry
+        const int ran = fin ? c->h_pcg->it_done - it0 : n;
+        for (int j = 0; j < ran; ++j) {
+          c->t_pcg_a += elapsed_ms(c->ev[2 * j], c->ev[2 * j + 1]);
+          c->t_pcg_b += elapsed_ms(c->ev[2 * j + 1], c->ev[2 * j + 2]);
+        }
+        c->n_pcg_a += ran;
+        c->n_pcg_b += ran;
+      }
+      if (fin) { done = true; it = c->h_pcg->it_done; break; }
+    }
+    total += it;
+    HIP_TRY(c, launch_dd_update(d, c->pres, c->pres_lo, c->pdelta, c->stream));
+    if (!done) {
+      // the iteration cap was reached inside this correction; check the
+      // residual once more and stop
+      if (total >= max_iter) continue;
+    }
+  }
+  if (stats) { stats->iterations = total; stats->est_err = relres; }
+  if (!ok) return fail(c, EREM_ENOCONV, "pressure solve did not reach rtol within max_iter");
+  HIP_TRY(c, launch_face_fluxes_dd(d, c->ph, c->pres, c->pres_lo, c->tx, c->ty, c->tz, c->fx, c->fy, c->fz,
+                                   c->stream));
+  if (d_p) HIP_TRY(c, hipMemcpyAsync(d_p, c->pres, bytes, hipMemcpyDeviceToDevice, c->stream));
+  c->flux_set = true;
+  return EREM_OK;
+}
+
+int erem_set_face_fluxes(erem_ctx* c, const double* d_fx, const double* d_fy, const double* d_fz) {
+  if (!c) return EREM_EINVAL;
+  if (!d_fx || !d_fy || (c->d.dim == 3 && !d_fz)) return fail(c, EREM_EINVAL, "flux arrays missing");
+  HIP_TRY(c, hipMemcpyAsync(c->fx, d_fx, c->nfx * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->fy, d_fy, c->nfy * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if (d_fz) HIP_TRY(c, hipMemcpyAsync(c->fz, d_fz, c->nfz * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  else HIP_TRY(c, hipMemsetAsync(c->fz, 0, c->nfz * sizeof(double), c->stream));
+  c->flux_set = true;
+  return EREM_OK;
+}
+
+int erem_get_faces(erem_ctx* c, double* d_fx, double* d_fy, double* d_fz, double* d_tx, double* d_ty,
+                   double* d_tz) {
+  if (!c) return EREM_EINVAL;
+  struct { double* dst; const double* src; size_t n; } cp[] = {
+      {d_fx, c->fx, c->nfx}, {d_fy, c->fy, c->nfy}, {d_fz, c->fz, c->nfz},
+      {d_tx, c->tx, c->nfx}, {d_ty, c->ty, c->nfy}, {d_tz, c->tz, c->nfz}};
+  for (auto& e : cp)
+    if (e.dst) HIP_TRY(c, hipMemcpyAsync(e.dst, e.src, e.n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  return EREM_OK;
+}
+
+int erem_form_jacobian(erem_ctx* c, const double* d_T) {
+  if (!c) return EREM_EINVAL;
+  if (!d_T) return fail(c, EREM_EINVAL, "T is NULL");
+  if (!c->rock_set || !c->flux_set) return fail(c, EREM_EINVAL, "rock and face fluxes must be set first");
+  HIP_TRY(c, launch_reset_reduce(c->red, c->stream));
+  HIP_TRY(c, launch_assemble(c->d, c->ph, c->poro, c->fx, c->fy, c->fz, d_T, c->coef, c->F, c->red, c->stream));
+  c->jac_set = true;
+  return EREM_OK;
+}
+
+int erem_get_jacobian(erem_ctx* c, double* d_coef, double* d_F) {
+  if (!c) return EREM_EINVAL;
+  if (!c->jac_set) return fail(c, EREM_EINVAL, "erem_form_jacobian must come first");
+  const size_t n = c->d.N;
+  if (d_coef) HIP_TRY(c, hipMemcpyAsync(d_coef, c->coef, n * ndir(c) * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if (d_F) HIP_TRY(c, hipMemcpyAsync(d_F, c->F, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  return EREM_OK;
+}
+
+int erem_phi1_apply(erem_ctx* c, double h, const double* d_v, double* d_out, const erem_opts* o, erem_stats* stats) {
+  if (!c) return EREM_EINVAL;
+  int rc = check_opts(c, o);
+  if (rc) return rc;
+  if (!d_v || !d_out || d_v == d_out) return fail(c, EREM_EINVAL, "v and out must be distinct non-NULL");
+  if (!c->jac_set) return fail(c, EREM_EINVAL, "erem_form_jacobian must come first");
+  if (!(h > 0) || !std::isfinite(h)) return fail(c, EREM_EINVAL, "h must be > 0");
+  if (o->method != EREM_METHOD_LEJA || o->precision != EREM_PREC_FP64)
+    return fail(c, EREM_EINVAL, "only the FP64 Leja method is available");
+  // max |v| (the Gershgorin interval of the last assembly is kept)
+  HIP_TRY(c, launch_absmax(c->d, d_v, c->red, c->stream));
+  rc = read_reduce(c);
+  if (rc) return rc;
+  const double vmax = ord_decode(c->h_red->vmax);
+  const double scal = o->tol_a + o->tol_r * h * vmax;
+  if (vmax == 0.0) {
+    HIP_TRY(c, hipMemsetAsync(d_out, 0, sizeof(double) * c->d.N, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (stats) { std::memset(stats, 0, sizeof(*stats)); stats->alpha = c->alpha; stats->beta = c->beta; }
+    return EREM_OK;
+  }
+  rc = hphi1_eval(c, h, d_v, scal, o, stats);
+  if (rc) return rc;
+  HIP_TRY(c, launch_axpby(c->d, d_out, 0.0, c->u, 1.0 / h, c->stream));
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  return EREM_OK;
+}
+
+int erem_set_jacobian(erem_ctx* c, const double* d_coef, const double* d_F) {
+  if (!c) return EREM_EINVAL;
+  if (!d_coef || !d_F) return fail(c, EREM_EINVAL, "coef and F are required");
+  const size_t n = c->d.N;
+  HIP_TRY(c, hipMemcpyAsync(c->coef, d_coef, n * ndir(c) * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->F, d_F, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  HIP_TRY(c, launch_gershgorin(c->d, c->coef, c->red, c->stream));
+  c->jac_set = true;
+  return EREM_OK;
+}
+
+namespace {
+
+int step_checks(erem_ctx* c, double h, double* d_T, const erem_opts* o) {
+  int rc = check_opts(c, o);
+  if (rc) return rc;
+  if (!d_T) return fail(c, EREM_EINVAL, "T is NULL");
+  if (!(h > 0) || !std::isfinite(h)) return fail(c, EREM_EINVAL, "h must be > 0");
+  if (o->method != EREM_METHOD_LEJA || o->precision != EREM_PREC_FP64)
+    return fail(c, EREM_EINVAL, "only the FP64 Leja method is available");
+  return EREM_OK;
+}
+
+// T += h phi1(h J) F with the context's J, F and interval; tmax = ||T||_inf.
+int step_core(erem_ctx* c, double h, double* d_T, const erem_opts* o, erem_stats* stats, double tmax) {
+  if (!std::isfinite(tmax)) return fail(c, EREM_ENONFINITE, "non-finite temperature");
+  const double scal = o->tol_a + o->tol_r * tmax;
+  if (!(scal > 0)) return fail(c, EREM_EINVAL, "error scale is zero (tol_a = 0 and T = 0)");
+  int rc = hphi1_eval(c, h, c->F, scal, o, stats);
+  if (rc) return rc;
+  HIP_TRY(c, launch_axpby(c->d, d_T, 1.0, c->u, 1.0, c->stream));
+  return EREM_OK;
+}
+
+}  // namespace
+
+int erem_step(erem_ctx* c, double h, double* d_T, const erem_opts* o, erem_stats* stats) {
+  if (!c) return EREM_EINVAL;
+  int rc = step_checks(c, h, d_T, o);
+  if (rc) return rc;
+  rc = erem_form_jacobian(c, d_T);
+  if (rc) return rc;
+  rc = read_reduce(c);
+  if (rc) return rc;
+  return step_core(c, h, d_T, o, stats, c->tmax);
+}
+
+int erem_step_frozen(erem_ctx* c, double h, double* d_T, const erem_opts* o, erem_stats* stats) {
+  if (!c) return EREM_EINVAL;
+  int rc = step_checks(c, h, d_T, o);
+  if (rc) return rc;
+  if (!c->jac_set) return fail(c, EREM_EINVAL, "no Jacobian in the context");
+  HIP_TRY(c, launch_absmax(c->d, d_T, c->red, c->stream));
+  rc = read_reduce(c);
+  if (rc) return rc;
+  return step_core(c, h, d_T, o, stats, ord_decode(c->h_red->vmax));
+}
+
+int erem_profile(erem_ctx* c, int32_t enable) {
+  if (!c) return EREM_EINVAL;
+  HIP_TRY(c, hipStreamSynchronize(c->stream));
+  c->prof = enable != 0;
+  c->t_leja = c->t_pcg_a = c->t_pcg_b = 0.0;
+  c->n_leja = c->n_pcg_a = c->n_pcg_b = 0;
+  return EREM_OK;
+}
+
+int erem_profile_read(erem_ctx* c, erem_kernel_times* out) {
+  if (!c || !out) return EREM_EINVAL;
+  out->leja_term_ms = c->t_leja;
+  out->leja_term_launches = c->n_leja;
+  out->pcg_a_ms = c->t_pcg_a;
+  out->pcg_a_launches = c->n_pcg_a;
+  out->pcg_b_ms = c->t_pcg_b;
+  out->pcg_b_launches = c->n_pcg_b;
+  return EREM_OK;
+}
+
+int erem_leja_points(int32_t n, double* out) {
+  if (n < 0 || n > kMaxTerms + 1 || (n > 0 && !out)) return EREM_EINVAL;
+  std::vector<double> v;
+  if (!leja_points(n, v)) return EREM_EINVAL;
+  std::copy(v.begin(), v.end(), out);
+  return EREM_OK;
+}
+
+int erem_phi1_divided_differences(double hc, double hg, const double* xi, int32_t n, double* out) {
+  if (n < 0 || n > kMaxTerms + 1 || (n > 0 && (!xi || !out))) return EREM_EINVAL;
+  if (!std::isfinite(hc) || !std::isfinite(hg)) return EREM_EINVAL;
+  if (n == 0) return EREM_OK;
+  phi1_divided_differences(hc, hg, xi, n, out);
+  return EREM_OK;
+}
+
+}  // extern "C"

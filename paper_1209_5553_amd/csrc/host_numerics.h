@@ -1,0 +1,22 @@
+// Host-side small dense numerics of the EREM library (no device code).
+#pragma once
+
+#include <cstdint>
+#include <vector>
+
+namespace erem {
+
+// First n real Leja points of [-2, 2] (Sec. 4.2, Eq. lejaa).  Thread-safe,
+// memoised; n <= kMaxLeja.
+constexpr int kMaxLeja = 1025;
+bool leja_points(int n, std::vector<double>& out);
+
+// Divided differences of g(xi) = phi1(hc + hg xi) at xi[0..n-1] (Sec. 4.2):
+// first column of phi1(hc I + hg L), L lower bidiagonal (diag xi, subdiag 1),
+// read off exp([[0, 0], [e_1, hc I + hg L]]).
+void phi1_divided_differences(double hc, double hg, const double* xi, int n, double* out);
+
+// Dense exponential of an n x n row-major matrix by Taylor scaling-and-squaring.
+void dense_expm(int n, const double* A, double* E);
+
+}  // namespace erem

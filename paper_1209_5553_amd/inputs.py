@@ -177,6 +177,18 @@ def fd_cells(N: int, count: int = 50, seed: int = 1) -> np.ndarray:
     return np.random.default_rng(seed).choice(N, count, replace=False)
 
 
+def random_solenoidal_fluxes(rng: np.random.Generator, nx: int, ny: int, scale: float = 1e-2):
+    """Divergence-free 2D mass fluxes with no boundary flux, from a random
+    stream function psi on the (nx+1) x (ny+1) grid nodes that vanishes on
+    the boundary: F_x = psi(x, y+1) - psi(x, y), F_y = psi(x, y) - psi(x+1, y)."""
+    psi = np.zeros((ny + 1, nx + 1))
+    psi[1:-1, 1:-1] = rng.standard_normal((ny - 1, nx - 1)) * scale
+    fx = (psi[1:, :] - psi[:-1, :])[None, :, :]            # (1, ny, nx+1)
+    fy = (psi[:, :-1] - psi[:, 1:])[None, :, :]            # (1, ny+1, nx)
+    fz = np.zeros((2, ny, nx))
+    return fx, fy, fz
+
+
 def random_interior_fluxes(rng: np.random.Generator, nx: int, ny: int, nz: int,
                            scale: float = 1e-3):
     """Arbitrary mass fluxes [kg/s] on interior faces, zero on every boundary

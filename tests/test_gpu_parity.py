@@ -1,0 +1,334 @@
+"""GPU parity of the HIP path (through the C ABI) against the CPU oracle.
+
+Tolerance: 1e-10 relative (max norm) for temperatures after EREM steps and
+phi1 actions (the FP64 target); assembly quantities that involve no
+iteration (transmissibilities, stencil, G) agree to 1e-13.
+"""
+import numpy as np
+import pytest
+
+from oracle import erem as oerem
+from oracle import phi as ophi
+from oracle import physics as oph
+from paper_1209_5553_amd import inputs
+
+from gpu_util import rel_inf, sparse_to_stencil, stencil_to_sparse
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _ctx(prob):
+    from paper_1209_5553_amd.api import EremContext
+    return EremContext.from_problem(prob, device="cuda:0")
+
+
+def _dev(torch, a):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device="cuda:0").clone()
+
+
+def _say(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+
+
+def _oracle_fluxes_to_dev(torch, disc):
+    fx, fy, fz = disc.fluxes
+    return _dev(torch, fx.ravel()), _dev(torch, fy.ravel()), _dev(torch, fz.ravel())
+
+
+# --------------------------------------------------------------- a1 / a2
+
+def test_transmissibilities_and_fluxes(torch_mod):
+    torch = torch_mod
+    prob = inputs.linear_problem(32)
+    _say(f"transmissibilities {prob.name}")
+    ctx = _ctx(prob)
+    st = ctx.pressure_and_fluxes(rtol=1e-14)
+    faces = {k: v.cpu().numpy() for k, v in ctx.get_faces().items()}
+    disc = oerem.Discretisation(prob, prob.T0)
+    g = disc.g
+    tx = faces["tx"].reshape(g.nz, g.ny, g.nx + 1)
+    assert rel_inf(tx[:, :, 1:-1], disc.trans["tx"]) <= 1e-13
+    assert rel_inf(tx[:, :, 0], disc.trans["t_left"]) <= 1e-13
+    assert rel_inf(tx[:, :, -1], disc.trans["t_right"]) <= 1e-13
+    ty = faces["ty"].reshape(g.nz, g.ny + 1, g.nx)
+    assert rel_inf(ty[:, 1:-1, :], disc.trans["ty"]) <= 1e-13
+    assert np.all(ty[:, 0, :] == 0) and np.all(ty[:, -1, :] == 0)
+    for name, ref in zip(("fx", "fy"), disc.fluxes[:2]):
+        got = faces[name].reshape(ref.shape)
+        assert rel_inf(got, ref) <= TOL, (name, rel_inf(got, ref), st)
+    assert st["est_err"] <= 1e-14
+
+
+# -------------------------------------------------------------------- a3/a4
+
+@pytest.mark.parametrize("kind", ["linear32", "coupled24", "layered3d"])
+def test_jacobian_stencil_and_G(torch_mod, kind):
+    torch = torch_mod
+    if kind == "linear32":
+        prob = inputs.linear_problem(32)
+        T = prob.T0.copy()
+        T[::7] += 13.0
+    elif kind == "coupled24":
+        prob = inputs.coupled_problem(24, seed=3)
+        T = np.random.default_rng(1).uniform(20, 80, prob.n)
+    else:
+        prob = inputs.layered3d_problem(9, seed=2)
+        T = np.random.default_rng(2).uniform(20, 80, prob.n)
+    _say(f"jacobian {kind}")
+    disc = oerem.Discretisation(prob, T)
+    ctx = _ctx(prob)
+    ctx.set_face_fluxes(*_oracle_fluxes_to_dev(torch, disc))
+    ctx.form_jacobian(_dev(torch, T))
+    coef, F = ctx.get_jacobian()
+    coef = coef.cpu().numpy()
+    Jref = disc.model.J_sparse(T)
+    ref = sparse_to_stencil(Jref, prob.nx, prob.ny, prob.nz)
+    assert rel_inf(coef, ref) <= 1e-13
+    assert rel_inf(F.cpu().numpy(), disc.model.G(T)) <= 1e-13
+    a, b = oph.gershgorin_interval(Jref)
+    out, st = ctx.phi1_apply(1.0, _dev(torch, np.ones(prob.n)))
+    assert st["alpha"] == pytest.approx(a, rel=1e-13)
+    assert abs(st["beta"] - b) <= 1e-13 * abs(a)
+
+
+# ---------------------------------------------------------------------- a6
+
+def test_phi1_apply_matches_dense_oracle(torch_mod):
+    torch = torch_mod
+    prob = inputs.linear_problem(32)
+    _say("phi1 apply 32x32")
+    disc = oerem.Discretisation(prob, prob.T0)
+    ctx = _ctx(prob)
+    ctx.set_face_fluxes(*_oracle_fluxes_to_dev(torch, disc))
+    ctx.form_jacobian(_dev(torch, prob.T0))
+    rng = np.random.default_rng(0)
+    v = rng.standard_normal(prob.n)
+    J = disc.model.J(prob.T0)
+    for h in (1e4, 1e6, 3e6):
+        out, st = ctx.phi1_apply(h, _dev(torch, v))
+        ref = ophi.phi1_action_dense(J, v, h)
+        err = rel_inf(out.cpu().numpy(), ref)
+        _say(f"  h={h:g} m={st['m_total']} s={st['substeps']} err={err:.2e}")
+        assert err <= TOL
+
+
+def test_diagonal_closed_form(torch_mod):
+    """Diagonal J: phi1(hJ) v = (e^{h lam} - 1)/(h lam) v (closed form)."""
+    torch = torch_mod
+    nx, ny = 40, 9
+    N = nx * ny
+    from paper_1209_5553_amd.api import EremContext
+    ctx = EremContext(nx, ny)
+    lam = -np.geomspace(1e-9, 2e-4, N)
+    np.random.default_rng(4).shuffle(lam)
+    coef = np.zeros((5, N))
+    coef[0] = lam
+    v = np.random.default_rng(5).standard_normal(N)
+    ctx.set_jacobian(_dev(torch, coef.ravel()), _dev(torch, v))
+    for h in (1e5, 1e6):
+        out, st = ctx.phi1_apply(h, _dev(torch, v))
+        ref = ophi.phi1_scalar(h * lam) * v
+        err = rel_inf(out.cpu().numpy(), ref)
+        _say(f"diagonal h={h:g} m={st['m_total']} s={st['substeps']} err={err:.2e}")
+        assert err <= 1e-12
+
+
+def test_newton_interpolation_is_exact_at_the_nodes(torch_mod):
+    """J = diag(c + gamma xi_k), k < N: the Newton polynomial through the
+    Leja nodes (Eq. approle) reproduces phi1 at every eigenvalue, so the
+    result is exact to rounding whatever the stop rule."""
+    torch = torch_mod
+    from paper_1209_5553_amd.api import EremContext, leja_points, make_opts
+    nx, ny = 4, 4
+    N = nx * ny
+    xi = leja_points(N)
+    c, gam = -2.0e-5, 9.0e-6
+    lam = c + gam * xi
+    coef = np.zeros((5, N))
+    coef[0] = lam
+    ctx = EremContext(nx, ny)
+    v = np.linspace(1.0, 2.0, N)
+    ctx.set_jacobian(_dev(torch, coef.ravel()), _dev(torch, v))
+    h = 1e6
+    out, st = ctx.phi1_apply(h, _dev(torch, v), opts=make_opts(rho_max=0.0))
+    ref = ophi.phi1_scalar(h * lam) * v
+    _say(f"node exactness m={st['m_total']} s={st['substeps']}")
+    assert st["substeps"] == 1
+    assert rel_inf(out.cpu().numpy(), ref) <= 1e-13
+
+
+def test_phi1_of_zero_matrix_is_identity(torch_mod):
+    torch = torch_mod
+    from paper_1209_5553_amd.api import EremContext
+    ctx = EremContext(7, 5)
+    v = np.arange(35, dtype=np.float64) - 11.0
+    ctx.set_jacobian(_dev(torch, np.zeros(5 * 35)), _dev(torch, v))
+    out, st = ctx.phi1_apply(3.0e5, _dev(torch, v))
+    assert np.array_equal(out.cpu().numpy(), v)
+
+
+# ------------------------------------------------------------- EREM steps
+
+def _run_gpu_linear(torch, prob, nsteps, h=None, opts=None, fluxes=None):
+    ctx = _ctx(prob)
+    if fluxes is None:
+        ctx.pressure_and_fluxes(rtol=1e-14)
+    else:
+        ctx.set_face_fluxes(*fluxes)
+    T = _dev(torch, prob.T0)
+    stats = [ctx.step(prob.h if h is None else h, T, opts) for _ in range(nsteps)]
+    torch.cuda.synchronize()
+    return T.cpu().numpy(), stats
+
+
+def test_linear_32x32_ten_steps(torch_mod):
+    """The 32x32 FP64 workload: 10 EREM steps of 1e6 s against the dense oracle."""
+    torch = torch_mod
+    prob = inputs.linear_problem(32)
+    _say("32x32 x 10 steps")
+    T_gpu, stats = _run_gpu_linear(torch, prob, prob.nsteps)
+    T_ref, _ = oerem.run_linear(prob)
+    err = rel_inf(T_gpu, T_ref)
+    inc = rel_inf(T_gpu - prob.T0, T_ref - prob.T0)
+    _say(f"  err={err:.2e} inc={inc:.2e} m={[s['m_total'] for s in stats]}")
+    assert err <= TOL and inc <= TOL
+
+
+def test_first_step_increment_32x32(torch_mod):
+    """One step from the uniform start, where the front is sharp."""
+    torch = torch_mod
+    prob = inputs.linear_problem(32)
+    T_gpu, st = _run_gpu_linear(torch, prob, 1)
+    T_ref, _ = oerem.run_linear(prob, nsteps=1)
+    assert rel_inf(T_gpu - prob.T0, T_ref - prob.T0) <= TOL
+
+
+def test_linear_exactness_on_gpu(torch_mod):
+    """Ten GPU steps of h equal one GPU step of 10 h (EREM is exact for
+    linear problems, R(z) = e^z), and both equal the oracle."""
+    torch = torch_mod
+    prob = inputs.linear_problem(24, seed=6)
+    T10, _ = _run_gpu_linear(torch, prob, 10)
+    T1, _ = _run_gpu_linear(torch, prob, 1, h=10 * prob.h)
+    assert rel_inf(T10 - prob.T0, T1 - prob.T0) <= TOL
+    disc = oerem.Discretisation(prob, prob.T0)
+    Tref = oerem.erem_step(disc.model, prob.T0, 10 * prob.h)
+    assert rel_inf(T1, Tref) <= TOL
+
+
+def test_energy_conserved_with_closed_boundaries(torch_mod):
+    torch = torch_mod
+    rng = np.random.default_rng(31)
+    prob = inputs.linear_problem(20, seed=7)
+    prob.dirichlet_left = False
+    prob.T0 = rng.uniform(20.0, 80.0, prob.n)
+    # incompressible circulation (stream function), closed boundaries: the
+    # Gershgorin interval stays in the left half-plane as for real flows
+    fl = inputs.random_solenoidal_fluxes(rng, prob.nx, prob.ny, scale=1e-2)
+    T_gpu, stats = _run_gpu_linear(torch, prob, 3, fluxes=tuple(_dev(torch, f.ravel()) for f in fl))
+    w = oph.heat_capacity(prob.T0, prob.poro, prob.law, prob.rho0, prob.c_f, prob.rhoc_s)
+    drift = abs(w @ T_gpu - w @ prob.T0) / abs(w @ prob.T0)
+    _say(f"conservation drift {drift:.2e} stats {stats[-1]}")
+    assert drift <= 1e-13
+    assert np.abs(T_gpu - prob.T0).max() > 1e-3
+
+
+@pytest.mark.parametrize("shape", [(70, 5), (1, 33), (33, 1), (1, 1), (129, 3)])
+def test_ragged_and_degenerate_shapes(torch_mod, shape):
+    torch = torch_mod
+    nx, ny = shape
+    rng = np.random.default_rng(nx * 100 + ny)
+    logk = np.log(1e-12) + 0.7 * rng.standard_normal(nx * ny)
+    prob = inputs.Problem(name=f"shape{nx}x{ny}", nx=nx, ny=ny, nz=1, logk=logk,
+                          poro=np.full(nx * ny, 0.2), T0=np.full(nx * ny, 20.0), nsteps=2)
+    _say(f"shape {shape}")
+    T_gpu, _ = _run_gpu_linear(torch, prob, 2)
+    T_ref, _ = oerem.run_linear(prob, nsteps=2)
+    assert rel_inf(T_gpu - prob.T0, T_ref - prob.T0) <= TOL
+
+
+def test_small_layered_3d(torch_mod):
+    torch = torch_mod
+    prob = inputs.layered3d_problem(10, seed=1, nsteps=2)
+    _say("layered 3D 10^3")
+    T_gpu, _ = _run_gpu_linear(torch, prob, 2)
+    T_ref, _ = oerem.run_linear(prob, nsteps=2, layered=True)
+    assert rel_inf(T_gpu - prob.T0, T_ref - prob.T0) <= TOL
+
+
+def test_coupled_steps_match_oracle(torch_mod):
+    """Sequential pressure / temperature steps with the water laws (48x48)."""
+    torch = torch_mod
+    prob = inputs.coupled_problem(48, seed=2, nsteps=3)
+    _say("coupled 48x48 x 3")
+    ctx = _ctx(prob)
+    T = _dev(torch, prob.T0)
+    p = torch.zeros(prob.n, dtype=torch.float64, device="cuda:0")
+    for n in range(prob.nsteps):
+        ctx.pressure_and_fluxes(T, rtol=1e-14, p=p, warm=n > 0)
+        ctx.step(prob.h, T)
+    T_gpu = T.cpu().numpy()
+    T_ref = oerem.run_coupled(prob)
+    err = rel_inf(T_gpu - prob.T0, T_ref - prob.T0)
+    _say(f"  inc err {err:.2e}")
+    assert err <= TOL
+
+
+def test_coupled_512_one_step_full_size(torch_mod):
+    """The 512x512 coupled workload at full size: one step against the
+    sparse (tier B) oracle."""
+    torch = torch_mod
+    prob = inputs.coupled_problem(512)
+    _say("coupled 512x512 one step")
+    ctx = _ctx(prob)
+    T = _dev(torch, prob.T0)
+    st_p = ctx.pressure_and_fluxes(T, rtol=1e-14)
+    st = ctx.step(prob.h, T)
+    T_gpu = T.cpu().numpy()
+    T_ref, _ = oerem.coupled_step(prob, prob.T0, tier="taylor")
+    err = rel_inf(T_gpu, T_ref)
+    inc = rel_inf(T_gpu - prob.T0, T_ref - prob.T0)
+    _say(f"  pcg it={st_p['iterations']} m={st['m_total']} s={st['substeps']} err={err:.2e} inc={inc:.2e}")
+    assert err <= TOL and inc <= TOL
+
+
+# ------------------------------------------------------------ error paths
+
+def test_error_paths_leave_T_unchanged(torch_mod):
+    torch = torch_mod
+    from paper_1209_5553_amd.api import EremError, make_opts
+    prob = inputs.linear_problem(32)
+    ctx = _ctx(prob)
+    ctx.pressure_and_fluxes()
+    T = _dev(torch, prob.T0)
+    T0 = T.clone()
+    with pytest.raises(EremError) as e:
+        ctx.step(prob.h, T, make_opts(m_max=5, max_substeps=1, rho_max=0.0))
+    assert e.value.code == -4
+    assert torch.equal(T, T0)
+    with pytest.raises(EremError) as e:
+        ctx.step(0.0, T)
+    assert e.value.code == -1
+    Tn = T.clone()
+    Tn[5] = float("nan")
+    with pytest.raises(EremError) as e:
+        ctx.step(prob.h, Tn)
+    assert e.value.code == -5
+    assert torch.isnan(Tn[5]) and torch.equal(Tn[:5], T0[:5])
+
+
+def test_step_is_deterministic(torch_mod):
+    torch = torch_mod
+    prob = inputs.linear_problem(32)
+    a, _ = _run_gpu_linear(torch, prob, 2)
+    b, _ = _run_gpu_linear(torch, prob, 2)
+    assert np.array_equal(a, b)

@@ -196,6 +196,18 @@ def test_heat_operator_conserves_energy_with_closed_boundaries():
     assert off.min() >= 0.0                  # upwind: nonnegative couplings
 
 
+def test_solenoidal_flux_generator_is_divergence_free():
+    fx, fy, fz = inputs.random_solenoidal_fluxes(np.random.default_rng(3), 9, 7)
+    div = (fx[:, :, 1:] - fx[:, :, :-1]) + (fy[:, 1:, :] - fy[:, :-1, :])
+    assert np.abs(div).max() <= 1e-15
+    assert np.all(fx[:, :, 0] == 0) and np.all(fx[:, :, -1] == 0)
+    assert np.all(fy[:, 0, :] == 0) and np.all(fy[:, -1, :] == 0)
+    g = ph.Grid(9, 7)
+    A, b = ph.heat_operator((fx, fy, fz), g, 2.5, 4200.0, 80.0, 20.0, dirichlet_left=False)
+    rowsum = np.asarray(A.sum(axis=1)).ravel()
+    assert np.abs(rowsum).max() <= 1e-12 * abs(A).max()   # and so beta <= 0 up to rounding
+
+
 def test_jacobian_matches_central_differences():
     """J = D_T G (Eq. linear), including the temperature-dependent capacity."""
     prob = inputs.coupled_problem(8, seed=2)
