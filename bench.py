@@ -36,6 +36,11 @@ HBM_PEAK_GBS = 8000.0
 LEJA_BYTES = {2: {"f64": 72, "f32": 36}, 3: {"f64": 88, "f32": 44}}
 PCG_A_BYTES = {2: 48, 3: 64}    # read z, p_old, face transmissibilities; write p_new, q
 PCG_B_BYTES = {2: 64, 3: 64}    # read x, p_new, r, q, diag; write x, r, z
+# One multigrid V-cycle per finest cell: on the finest level the four passes
+# (two-sweep smoothing, residual + restriction, prolongation + sweep, sweep)
+# read b, diag, faces and the iterate and write one vector each (~180 B);
+# the coarser levels add a third of that (2 x 2 aggregation).
+MG_BYTES = {2: 240, 3: 240}
 
 
 def log(msg):
@@ -166,6 +171,7 @@ def main():
         "leja_term": (t["leja_term_ms"], t["leja_term_launches"], LEJA_BYTES[dim]["f64"] * N),
         "pcg_a": (t["pcg_a_ms"], t["pcg_a_launches"], PCG_A_BYTES[dim] * N),
         "pcg_b": (t["pcg_b_ms"], t["pcg_b_launches"], PCG_B_BYTES[dim] * N),
+        "mg_vcycle": (t["mg_ms"], t["mg_cycles"], MG_BYTES[dim] * N),
     }
     dominant = max(kern, key=lambda k: kern[k][0])
 

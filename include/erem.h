@@ -139,6 +139,14 @@ int erem_assemble_transmissibilities(erem_ctx* ctx, const double* d_T);
 int erem_solve_pressure(erem_ctx* ctx, double rtol, int32_t max_iter, int32_t warm,
                         double* d_p, erem_stats* stats);
 
+/* Preconditioner of the pressure conjugate gradients: EREM_PRECOND_JACOBI
+ * (diagonal) or EREM_PRECOND_MULTIGRID (default: a symmetric V-cycle of
+ * 2 x 2 (x 2) cell aggregation with damped-Jacobi smoothing, Galerkin
+ * coarse operators, over-relaxed coarse correction).  Both give the same
+ * pressure up to the requested tolerance. */
+enum { EREM_PRECOND_JACOBI = 0, EREM_PRECOND_MULTIGRID = 1 };
+int erem_set_pressure_preconditioner(erem_ctx* ctx, int32_t kind);
+
 /* Set the face mass fluxes [kg/s] directly, replacing the pressure solve:
  * d_fx (nz, ny, nx+1), d_fy (nz, ny+1, nx), d_fz (nz+1, ny, nx; NULL in 2D),
  * positive along +x/+y/+z, boundary faces included. */
@@ -200,6 +208,8 @@ typedef struct {
     int64_t pcg_a_launches;
     double pcg_b_ms;            /* PCG: iterate / residual / preconditioner update */
     int64_t pcg_b_launches;
+    double mg_ms;               /* multigrid preconditioner (all its kernels) */
+    int64_t mg_cycles;
 } erem_kernel_times;
 
 /* Turn per-launch event timing on (enable != 0) or off and reset the

@@ -46,7 +46,8 @@ class Stats(ctypes.Structure):
 class KernelTimes(ctypes.Structure):
     _fields_ = [("leja_term_ms", c_double), ("leja_term_launches", c_int64),
                 ("pcg_a_ms", c_double), ("pcg_a_launches", c_int64),
-                ("pcg_b_ms", c_double), ("pcg_b_launches", c_int64)]
+                ("pcg_b_ms", c_double), ("pcg_b_launches", c_int64),
+                ("mg_ms", c_double), ("mg_cycles", c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -67,6 +68,7 @@ SIGNATURES = {
     "erem_assemble_transmissibilities": (c_int32, [_P, _P]),
     "erem_solve_pressure": (c_int32, [_P, c_double, c_int32, c_int32, _P, POINTER(Stats)]),
     "erem_set_face_fluxes": (c_int32, [_P, _P, _P, _P]),
+    "erem_set_pressure_preconditioner": (c_int32, [_P, c_int32]),
     "erem_get_faces": (c_int32, [_P, _P, _P, _P, _P, _P, _P]),
     "erem_form_jacobian": (c_int32, [_P, _P]),
     "erem_get_jacobian": (c_int32, [_P, _P, _P]),

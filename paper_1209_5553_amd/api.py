@@ -133,6 +133,11 @@ class EremContext:
                     "erem_solve_pressure")
         return st.as_dict()
 
+    def set_pressure_preconditioner(self, kind: str):
+        code = {"jacobi": 0, "multigrid": 1}[kind]
+        self._check(self.lib.erem_set_pressure_preconditioner(self.handle, code),
+                    "erem_set_pressure_preconditioner")
+
     def set_face_fluxes(self, fx, fy, fz=None):
         nfx, nfy, nfz = self.face_counts
         self._check(self.lib.erem_set_face_fluxes(self.handle, self._ptr(fx, nfx, "fx"),

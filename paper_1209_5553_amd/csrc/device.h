@@ -101,7 +101,7 @@ hipError_t launch_pcg_start(const Dims& d, const Phys& ph, const double* tx, con
                             double* diag, PcgState* st, hipStream_t s);
 hipError_t launch_pcg_start_rhs(const Dims& d, const double* tx, const double* ty, const double* tz,
                                 const double* rhs, double* x, double* r, double* z, double* p0,
-                                double* diag, PcgState* st, hipStream_t s);
+                                double* diag, PcgState* st, int jacobi, hipStream_t s);
 hipError_t launch_dd_residual(const Dims& d, const Phys& ph, const double* tx, const double* ty,
                               const double* tz, const double* phi, const double* plo, double* r,
                               PcgState* st, hipStream_t s);
@@ -116,7 +116,7 @@ hipError_t launch_pcg_a(const Dims& d, const double* tx, const double* ty, const
                         PcgState* st, int it, hipStream_t s);
 hipError_t launch_pcg_b(const Dims& d, double* x, double* r, double* z, const double* pnew,
                         const double* q, const double* diag, PcgState* st, int it,
-                        hipStream_t s);
+                        int jacobi, hipStream_t s);
 
 // Ordered encoding of doubles for atomic min/max on 64-bit unsigned integers.
 __host__ __device__ inline unsigned long long ord_encode(double v) {

@@ -19,6 +19,7 @@
 
 #include "device.h"
 #include "host_numerics.h"
+#include "mg.h"
 
 using namespace erem;
 
@@ -65,8 +66,12 @@ struct erem_ctx {
   // profiling (HIP events around each Leja term and PCG half-iteration)
   bool prof = false;
   std::vector<hipEvent_t> ev;
-  double t_leja = 0.0, t_pcg_a = 0.0, t_pcg_b = 0.0;
-  long long n_leja = 0, n_pcg_a = 0, n_pcg_b = 0;
+  double t_leja = 0.0, t_pcg_a = 0.0, t_pcg_b = 0.0, t_mg = 0.0;
+  long long n_leja = 0, n_pcg_a = 0, n_pcg_b = 0, n_mg = 0;
+  // multigrid preconditioner of the pressure operator
+  MgHierarchy mg;
+  bool use_mg = true;
+  std::vector<double*> mg_bufs;
   double alpha = 0.0, beta = 0.0, tmax = 0.0;
   std::string err;
 };
@@ -145,6 +150,102 @@ void free_all(erem_ctx* c) {
 }
 
 int ndir(const erem_ctx* c) { return c->d.dim == 3 ? 7 : 5; }
+
+void free_mg(erem_ctx* c) {
+  for (double* b : c->mg_bufs) (void)hipFree(b);
+  c->mg_bufs.clear();
+}
+
+// LDS words of the coarse solve over levels lc..nlev-1 (faces, diagonal and
+// three work vectors per level, plus the accumulated solution and the rhs).
+size_t mg_lds_words(const MgHierarchy& h, int lc) {
+  size_t w = 0;
+  for (int l = lc; l < h.nlev; ++l) {
+    const MgLevelDev& L = h.lev[l];
+    const size_t n = static_cast<size_t>(L.nx) * L.ny * L.nz;
+    w += static_cast<size_t>(L.nx + 1) * L.ny * L.nz + static_cast<size_t>(L.nx) * (L.ny + 1) * L.nz;
+    if (L.nz > 1) w += static_cast<size_t>(L.nx) * L.ny * (L.nz + 1);
+    w += 4 * n;
+  }
+  return w;
+}
+
+// Aggregation hierarchy down to one cell; level 0 aliases the context's
+// face arrays and diagonal.
+int build_mg(erem_ctx* c) {
+  MgHierarchy& h = c->mg;
+  int nx = c->d.nx, ny = c->d.ny, nz = c->d.nz;
+  int l = 0;
+  for (;;) {
+    if (l >= kMgMaxLevels) return fail(c, EREM_EINVAL, "grid too large for the multigrid hierarchy");
+    MgLevelDev& L = h.lev[l];
+    L.nx = nx; L.ny = ny; L.nz = nz;
+    const size_t n = static_cast<size_t>(nx) * ny * nz;
+    auto get = [&](double** p, size_t cnt) {
+      if (dev_alloc(c, p, cnt) != EREM_OK) return false;
+      c->mg_bufs.push_back(*p);
+      return true;
+    };
+    if (l == 0) {
+      L.tx = c->tx; L.ty = c->ty; L.tz = c->tz; L.diag = c->pdiag; L.b = nullptr;
+      if (!get(&L.x, n) || !get(&L.y, n)) return EREM_ENOMEM;
+    } else {
+      const size_t nfx = static_cast<size_t>(nz) * ny * (nx + 1);
+      const size_t nfy = static_cast<size_t>(nz) * (ny + 1) * nx;
+      const size_t nfz = static_cast<size_t>(nz + 1) * ny * nx;
+      if (!get(&L.tx, nfx) || !get(&L.ty, nfy) || !get(&L.tz, nfz) || !get(&L.diag, n) ||
+          !get(&L.b, n) || !get(&L.x, n) || !get(&L.y, n))
+        return EREM_ENOMEM;
+      (void)hipMemsetAsync(L.tz, 0, nfz * sizeof(double), c->stream);
+    }
+    ++l;
+    if (n == 1) break;
+    nx = (nx + 1) / 2;
+    ny = (ny + 1) / 2;
+    nz = nz > 1 ? (nz + 1) / 2 : 1;
+  }
+  h.nlev = l;
+  int max_lds = 0;
+  if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess)
+    max_lds = 65536;
+  // First level that fits one workgroup (cells and LDS, with 1 KiB kept for
+  // the kernel's static LDS); if the runtime refuses the dynamic LDS size,
+  // retry within 64 KiB.
+  int lc = h.nlev - 1;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    const size_t limit = static_cast<size_t>(attempt == 0 ? max_lds : std::min(max_lds, 65536)) - 1024;
+    lc = h.nlev - 1;
+    for (int k = 0; k < h.nlev; ++k) {
+      const MgLevelDev& L = h.lev[k];
+      const size_t n = static_cast<size_t>(L.nx) * L.ny * L.nz;
+      const size_t bytes = (mg_lds_words(h, k) + 2 * n) * sizeof(double);
+      if (n <= static_cast<size_t>(kMgLdsCells) && bytes <= limit) {
+        lc = k;
+        break;
+      }
+    }
+    const MgLevelDev& Lc = h.lev[lc];
+    const size_t bytes = (mg_lds_words(h, lc) + 2 * static_cast<size_t>(Lc.nx) * Lc.ny * Lc.nz) * sizeof(double);
+    if (mg_set_lds_limit(static_cast<int>(bytes)) == hipSuccess) break;
+    (void)hipGetLastError();
+    if (attempt == 1) return fail(c, EREM_EDEVICE, "cannot reserve LDS for the coarse multigrid solve");
+  }
+  h.lc = lc;
+  h.omega_c = 1.6;
+  MgCoarseArgs& a = h.coarse;
+  a.nlev = h.nlev - lc;
+  const MgLevelDev& L0 = h.lev[lc];
+  a.n0 = L0.nx * L0.ny * L0.nz;
+  a.lds_words = static_cast<int>(mg_lds_words(h, lc));
+  a.ninner = 3;
+  a.nu = 2;
+  a.nu_bottom = 1;
+  a.omega_c = h.omega_c;
+  for (int k = 0; k < a.nlev; ++k) a.lev[k] = h.lev[lc + k];
+  h.lds_bytes = (static_cast<size_t>(a.lds_words) + 2 * a.n0) * sizeof(double);
+  h.coarse_threads = std::min(1024, ((a.n0 + 63) / 64) * 64);
+  return EREM_OK;
+}
 
 // Divided differences for (hc, hg) with at least n coefficients (cached).
 const std::vector<double>& divided_differences(erem_ctx* c, double hc, double hg, int n) {
@@ -411,7 +512,17 @@ int erem_create(const erem_grid* g, void* stream, erem_ctx** out) {
     delete c;
     return EREM_EINVAL;
   }
+  {
+    const int mrc = build_mg(c);
+    if (mrc != EREM_OK) {
+      free_mg(c);
+      free_all(c);
+      delete c;
+      return mrc;
+    }
+  }
   if (hipStreamSynchronize(c->stream) != hipSuccess) {
+    free_mg(c);
     free_all(c);
     delete c;
     return EREM_EDEVICE;
@@ -431,6 +542,7 @@ int erem_destroy(erem_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   c->ev.clear();
+  free_mg(c);
   free_all(c);
   delete c;
   return EREM_OK;
@@ -503,6 +615,7 @@ int erem_solve_pressure(erem_ctx* c, double rtol, int32_t max_iter, int32_t warm
   int total = 0;
   bool ok = false;
   double relres = NAN;
+  if (c->use_mg) HIP_TRY(c, mg_setup(c->mg, c->stream));
   for (int outer = 0; outer < 8; ++outer) {
     HIP_TRY(c, launch_pcg_reset(c->pcg, 0.0, c->stream));
     HIP_TRY(c, launch_dd_residual(d, c->ph, c->tx, c->ty, c->tz, c->pres, c->pres_lo, c->prhs, c->pcg, c->stream));
@@ -516,13 +629,16 @@ int erem_solve_pressure(erem_ctx* c, double rtol, int32_t max_iter, int32_t warm
     if (total >= max_iter) break;
     // PCG on A delta = r from delta = 0
     HIP_TRY(c, launch_pcg_reset(c->pcg, inner_tol * inner_tol, c->stream));
+    const int jac = c->use_mg ? 0 : 1;
     HIP_TRY(c, launch_pcg_start_rhs(d, c->tx, c->ty, c->tz, c->prhs, c->pdelta, c->pr, c->pz, c->pp0, c->pdiag,
-                                    c->pcg, c->stream));
-    const int chunk = 64;
+                                    c->pcg, jac, c->stream));
+    if (c->use_mg) HIP_TRY(c, mg_apply(c->mg, c->pr, c->pz, c->pcg, 0, c->stream));
+    // Multigrid iterations are few: poll the device after a handful of them.
+    const int chunk = c->use_mg ? 8 : 64;
     int it = 0;
     bool done = false;
     if (c->prof) {
-      const int rc = ensure_events(c, 2 * chunk + 1);
+      const int rc = ensure_events(c, 3 * chunk + 1);
       if (rc) return rc;
     }
     while (total + it < max_iter) {
@@ -533,9 +649,11 @@ int erem_solve_pressure(erem_ctx* c, double rtol, int32_t max_iter, int32_t warm
         double* pold = (it & 1) ? c->pp1 : c->pp0;
         double* pnew = (it & 1) ? c->pp0 : c->pp1;
         HIP_TRY(c, launch_pcg_a(d, c->tx, c->ty, c->tz, c->pz, pold, pnew, c->pq, c->pcg, it, c->stream));
-        if (c->prof) HIP_TRY(c, hipEventRecord(c->ev[2 * j + 1], c->stream));
-        HIP_TRY(c, launch_pcg_b(d, c->pdelta, c->pr, c->pz, pnew, c->pq, c->pdiag, c->pcg, it, c->stream));
-        if (c->prof) HIP_TRY(c, hipEventRecord(c->ev[2 * j + 2], c->stream));
+        if (c->prof) HIP_TRY(c, hipEventRecord(c->ev[3 * j + 1], c->stream));
+        HIP_TRY(c, launch_pcg_b(d, c->pdelta, c->pr, c->pz, pnew, c->pq, c->pdiag, c->pcg, it, jac, c->stream));
+        if (c->prof) HIP_TRY(c, hipEventRecord(c->ev[3 * j + 2], c->stream));
+        if (c->use_mg) HIP_TRY(c, mg_apply(c->mg, c->pr, c->pz, c->pcg, (it + 1) & 3, c->stream));
+        if (c->prof) HIP_TRY(c, hipEventRecord(c->ev[3 * j + 3], c->stream));
       }
       HIP_TRY(c, hipMemcpyAsync(c->h_pcg, c->pcg, sizeof(PcgState), hipMemcpyDeviceToHost, c->stream));
       HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -545,11 +663,13 @@ int erem_solve_pressure(erem_ctx* c, double rtol, int32_t max_iter, int32_t warm
         // iterations it0 .. it_done-1 ran fully; the test launch it_done returned at entry
         const int ran = fin ? c->h_pcg->it_done - it0 : n;
         for (int j = 0; j < ran; ++j) {
-          c->t_pcg_a += elapsed_ms(c->ev[2 * j], c->ev[2 * j + 1]);
-          c->t_pcg_b += elapsed_ms(c->ev[2 * j + 1], c->ev[2 * j + 2]);
+          c->t_pcg_a += elapsed_ms(c->ev[3 * j], c->ev[3 * j + 1]);
+          c->t_pcg_b += elapsed_ms(c->ev[3 * j + 1], c->ev[3 * j + 2]);
+          if (c->use_mg) c->t_mg += elapsed_ms(c->ev[3 * j + 2], c->ev[3 * j + 3]);
         }
         c->n_pcg_a += ran;
         c->n_pcg_b += ran;
+        if (c->use_mg) c->n_mg += ran;
       }
       if (fin) { done = true; it = c->h_pcg->it_done; break; }
     }
@@ -701,8 +821,8 @@ int erem_profile(erem_ctx* c, int32_t enable) {
   if (!c) return EREM_EINVAL;
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->prof = enable != 0;
-  c->t_leja = c->t_pcg_a = c->t_pcg_b = 0.0;
-  c->n_leja = c->n_pcg_a = c->n_pcg_b = 0;
+  c->t_leja = c->t_pcg_a = c->t_pcg_b = c->t_mg = 0.0;
+  c->n_leja = c->n_pcg_a = c->n_pcg_b = c->n_mg = 0;
   return EREM_OK;
 }
 
@@ -714,6 +834,16 @@ int erem_profile_read(erem_ctx* c, erem_kernel_times* out) {
   out->pcg_a_launches = c->n_pcg_a;
   out->pcg_b_ms = c->t_pcg_b;
   out->pcg_b_launches = c->n_pcg_b;
+  out->mg_ms = c->t_mg;
+  out->mg_cycles = c->n_mg;
+  return EREM_OK;
+}
+
+int erem_set_pressure_preconditioner(erem_ctx* c, int32_t kind) {
+  if (!c) return EREM_EINVAL;
+  if (kind != EREM_PRECOND_JACOBI && kind != EREM_PRECOND_MULTIGRID)
+    return fail(c, EREM_EINVAL, "unknown preconditioner");
+  c->use_mg = kind == EREM_PRECOND_MULTIGRID;
   return EREM_OK;
 }
 

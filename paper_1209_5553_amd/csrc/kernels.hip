@@ -568,7 +568,8 @@ __global__ __launch_bounds__(kThreads) void k_pcg_start_rhs(Dims d, const double
                                                   const double* __restrict__ ty, const double* __restrict__ tz,
                                                   const double* __restrict__ rhs, double* __restrict__ xv,
                                                   double* __restrict__ r, double* __restrict__ zv,
-                                                  double* __restrict__ p0, double* __restrict__ diag, PcgState* st) {
+                                                  double* __restrict__ p0, double* __restrict__ diag, PcgState* st,
+                                                  int jacobi) {
   const int x = blockIdx.x * kBX + threadIdx.x;
   const int y = blockIdx.y * kBY + threadIdx.y;
   const int z = blockIdx.z;
@@ -581,7 +582,7 @@ __global__ __launch_bounds__(kThreads) void k_pcg_start_rhs(Dims d, const double
     const double zi = ri / dg;
     xv[i] = 0.0;
     r[i] = ri;
-    zv[i] = zi;
+    if (jacobi) zv[i] = zi;
     p0[i] = 0.0;
     diag[i] = dg;
     s[0] = ri * zi;
@@ -590,7 +591,7 @@ __global__ __launch_bounds__(kThreads) void k_pcg_start_rhs(Dims d, const double
   block_sum<2>(s);
   if (tid_lin() == 0) {
     const int sl = bid_lin() & (kSlots - 1);
-    atomicAdd(&st->rz[sl], s[0]);
+    if (jacobi) atomicAdd(&st->rz[sl], s[0]);  // otherwise the preconditioner adds r.z
     atomicAdd(&st->rr[sl], s[1]);
     atomicAdd(&st->bb_sl[sl], s[1]);
   }
@@ -781,7 +782,7 @@ __global__ __launch_bounds__(kThreads) void k_pcg_a(Dims d, const double* __rest
 __global__ __launch_bounds__(kThreads) void k_pcg_b(Dims d, double* __restrict__ xv, double* __restrict__ r,
                                           double* __restrict__ zv, const double* __restrict__ pnew,
                                           const double* __restrict__ q, const double* __restrict__ diag,
-                                          PcgState* st, int it) {
+                                          PcgState* st, int it, int jacobi) {
   __shared__ double alpha_sh;
   __shared__ int stop_sh;
   const int t = tid_lin();
@@ -805,16 +806,18 @@ __global__ __launch_bounds__(kThreads) void k_pcg_b(Dims d, double* __restrict__
     const int i = x + d.nx * (y + d.ny * z);
     xv[i] += alpha * pnew[i];
     const double ri = r[i] - alpha * q[i];
-    const double zi = ri / diag[i];
     r[i] = ri;
-    zv[i] = zi;
-    s[0] = ri * zi;
+    if (jacobi) {
+      const double zi = ri / diag[i];
+      zv[i] = zi;
+      s[0] = ri * zi;
+    }
     s[1] = ri * ri;
   }
   block_sum<2>(s);
   if (t == 0) {
     const int sl = ((it + 1) & 3) * kSlots + (bid_lin() & (kSlots - 1));
-    atomicAdd(&st->rz[sl], s[0]);
+    if (jacobi) atomicAdd(&st->rz[sl], s[0]);  // otherwise the preconditioner adds r.z
     atomicAdd(&st->rr[sl], s[1]);
   }
 }
@@ -912,8 +915,9 @@ hipError_t launch_pcg_start(const Dims& d, const Phys& ph, const double* tx, con
 
 hipError_t launch_pcg_start_rhs(const Dims& d, const double* tx, const double* ty, const double* tz,
                                 const double* rhs, double* x, double* r, double* z, double* p0, double* diag,
-                                PcgState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_start_rhs, cell_grid(d), cell_block(), 0, s, d, tx, ty, tz, rhs, x, r, z, p0, diag, st);
+                                PcgState* st, int jacobi, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_start_rhs, cell_grid(d), cell_block(), 0, s, d, tx, ty, tz, rhs, x, r, z, p0, diag, st,
+                     jacobi);
   return hipGetLastError();
 }
 
@@ -943,8 +947,8 @@ hipError_t launch_pcg_a(const Dims& d, const double* tx, const double* ty, const
 }
 
 hipError_t launch_pcg_b(const Dims& d, double* x, double* r, double* z, const double* pnew, const double* q,
-                        const double* diag, PcgState* st, int it, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_b, cell_grid(d), cell_block(), 0, s, d, x, r, z, pnew, q, diag, st, it);
+                        const double* diag, PcgState* st, int it, int jacobi, hipStream_t s) {
+  hipLaunchKernelGGL(k_pcg_b, cell_grid(d), cell_block(), 0, s, d, x, r, z, pnew, q, diag, st, it, jacobi);
   return hipGetLastError();
 }
 

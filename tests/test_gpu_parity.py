@@ -68,6 +68,43 @@ def test_transmissibilities_and_fluxes(torch_mod):
     assert st["est_err"] <= 1e-14
 
 
+@pytest.mark.parametrize("n", [64, 96, 33])
+def test_multigrid_and_jacobi_pressure_agree(torch_mod, n):
+    """Both preconditioners reach the same (double-double refined) pressure
+    and fluxes; the multigrid one in far fewer iterations."""
+    torch = torch_mod
+    prob = inputs.coupled_problem(n, seed=5)
+    T = _dev(torch, np.random.default_rng(2).uniform(20, 80, prob.n))
+    res = {}
+    for kind in ("jacobi", "multigrid"):
+        ctx = _ctx(prob)
+        ctx.set_pressure_preconditioner(kind)
+        p = torch.zeros(prob.n, dtype=torch.float64, device="cuda:0")
+        st = ctx.pressure_and_fluxes(T, rtol=1e-16, p=p)
+        res[kind] = (p.cpu().numpy(), ctx.get_faces()["fx"].cpu().numpy(), st["iterations"])
+        _say(f"pressure n={n} {kind}: {st}")
+    assert rel_inf(res["multigrid"][0], res["jacobi"][0]) <= 1e-13
+    assert rel_inf(res["multigrid"][1], res["jacobi"][1]) <= 1e-12
+    assert res["multigrid"][2] * 5 < res["jacobi"][2]
+    disc = oerem.Discretisation(prob, T.cpu().numpy())
+    assert rel_inf(res["multigrid"][1].reshape(disc.fluxes[0].shape), disc.fluxes[0]) <= TOL
+
+
+def test_multigrid_pressure_3d_layered_is_analytic(torch_mod):
+    torch = torch_mod
+    prob = inputs.layered3d_problem(24, seed=3)
+    ctx = _ctx(prob)
+    st = ctx.pressure_and_fluxes(rtol=1e-16)
+    g = oph.grid_of(prob)
+    mob = oph.mobility(prob.T0, prob.logk, prob.law, prob.rho0, prob.mu0)
+    fx, fy, fz = oph.layered_x_fluxes(mob, g, prob.p_left, prob.p_right)
+    faces = ctx.get_faces()
+    _say(f"3D multigrid pressure: {st}")
+    assert rel_inf(faces["fx"].cpu().numpy().reshape(fx.shape), fx) <= 1e-12
+    assert np.abs(faces["fy"].cpu().numpy()).max() <= 1e-12 * np.abs(fx).max()
+    assert np.abs(faces["fz"].cpu().numpy()).max() <= 1e-12 * np.abs(fx).max()
+
+
 # -------------------------------------------------------------------- a3/a4
 
 @pytest.mark.parametrize("kind", ["linear32", "coupled24", "layered3d"])
