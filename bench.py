@@ -65,7 +65,7 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def gpu_run(prob, coupled, steps, warmup, rtol_p):
+def gpu_run(prob, coupled, steps, warmup, rtol_p, mixed=False):
     import torch
     from paper_1209_5553_amd.api import EremContext, make_opts
 
@@ -73,7 +73,7 @@ def gpu_run(prob, coupled, steps, warmup, rtol_p):
     dev = ctx.device
     T = torch.as_tensor(prob.T0, dtype=torch.float64, device=dev).clone()
     p = torch.zeros(prob.n, dtype=torch.float64, device=dev)
-    opts = make_opts()
+    opts = make_opts(precision=1, tol_r=1e-7) if mixed else make_opts()
     state = {"n": 0, "last": None, "pcg": 0}
 
     if not coupled:
@@ -150,6 +150,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pressure-rtol", type=float, default=1e-16)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -163,12 +164,14 @@ def main():
 
     prob, desc, coupled = make_workload(args.workload)
     log(f"workload {args.workload}: {desc}; N={prob.n}")
-    res = gpu_run(prob, coupled, args.steps, args.warmup, args.pressure_rtol)
+    mixed = args.precision == "mixed"
+    res = gpu_run(prob, coupled, args.steps, args.warmup, args.pressure_rtol, mixed=mixed)
     dim = prob.dim
     N = prob.n
     t = res["times"]
     kern = {
-        "leja_term": (t["leja_term_ms"], t["leja_term_launches"], LEJA_BYTES[dim]["f64"] * N),
+        "leja_term": (t["leja_term_ms"], t["leja_term_launches"],
+                      LEJA_BYTES[dim]["f32" if mixed else "f64"] * N),
         "pcg_a": (t["pcg_a_ms"], t["pcg_a_launches"], PCG_A_BYTES[dim] * N),
         "pcg_b": (t["pcg_b_ms"], t["pcg_b_launches"], PCG_B_BYTES[dim] * N),
         "mg_vcycle": (t["mg_ms"], t["mg_cycles"], MG_BYTES[dim] * N),
@@ -192,10 +195,10 @@ def main():
         "metric": METRIC, "value": round(steps_s, 3), "unit": "steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(1e3 * res["elapsed"] / args.steps, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic (seeded generators)",
         "config": {"workload": desc, "grid": [prob.nx, prob.ny, prob.nz], "cells": N, "h_s": prob.h,
-                   "tol_r": 1e-12, "pressure_rtol": args.pressure_rtol if coupled else None},
+                   "tol_r": 1e-7 if mixed else 1e-12, "precision": args.precision, "pressure_rtol": args.pressure_rtol if coupled else None},
         "roofline": roof(dominant),
         "leja": roof("leja_term"),
         "leja_terms_per_step": res["m_per_step"],

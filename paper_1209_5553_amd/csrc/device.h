@@ -37,10 +37,11 @@ struct LejaCoef {
 
 // Per-substep Leja stop state (device resident).
 struct LejaState {
-  int stopped;     // -1 running, else last term index included
+  int stopped;     // -1 running, else the term at which the stop test passed
   int nonfinite;
-  int pad[2];
-  double sums[(kMaxTerms + 1) * kSlots];  // sum q_k^2, spread over kSlots
+  int checked;     // last term whose sum is final
+  int pad;
+  double sums[kMaxTerms + 1];  // sum q_k^2 (FP64)
 };
 
 // Reduction targets of the assembly pass (ordered-integer encodings).
@@ -85,14 +86,6 @@ hipError_t launch_absmax(const Dims& d, const double* v, AsmReduce* red, hipStre
 hipError_t launch_gershgorin(const Dims& d, const double* coef, AsmReduce* red, hipStream_t s);
 hipError_t launch_stencil_axpy(const Dims& d, const double* coef, const double* v,
                                const double* u, double* w, hipStream_t s);
-hipError_t launch_leja_reset(LejaState* st, int nslots, int nterms, hipStream_t s);
-hipError_t launch_leja_init(const Dims& d, const LejaCoef* cf, const double* v, double* q0,
-                            double* p, LejaState* st, hipStream_t s);
-hipError_t launch_leja_term(const Dims& d, const LejaCoef* cf, const double* coef,
-                            const double* qin, double* qout, double* p, LejaState* st, int k,
-                            hipStream_t s);
-hipError_t launch_substep_update(const Dims& d, double* u, const double* p, double delta,
-                                 int first, hipStream_t s);
 hipError_t launch_axpby(const Dims& d, double* y, double a, const double* x, double b,
                         hipStream_t s);
 hipError_t launch_pcg_reset(PcgState* st, double tol2, hipStream_t s);

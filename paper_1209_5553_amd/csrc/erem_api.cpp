@@ -19,6 +19,7 @@
 
 #include "device.h"
 #include "host_numerics.h"
+#include "leja.h"
 #include "mg.h"
 
 using namespace erem;
@@ -45,6 +46,10 @@ struct erem_ctx {
   double *qa = nullptr, *qb = nullptr, *pacc = nullptr, *u = nullptr, *w = nullptr;
   double *pres = nullptr, *pr = nullptr, *pz = nullptr, *pp0 = nullptr, *pp1 = nullptr;
   double *pq = nullptr, *pdiag = nullptr, *pres_lo = nullptr, *pdelta = nullptr, *prhs = nullptr;
+  double* part = nullptr;  // Leja block partial sums (ring of kLejaRing terms)
+  // FP32 copies for the mixed-precision Leja passes (allocated on first use)
+  float *coef32 = nullptr, *qa32 = nullptr, *qb32 = nullptr, *p32 = nullptr;
+  bool coef32_valid = false;
   size_t nfx = 0, nfy = 0, nfz = 0;
 
   // device control blocks
@@ -134,7 +139,7 @@ void free_all(erem_ctx* c) {
   double** bufs[] = {&c->logk, &c->poro, &c->tx, &c->ty, &c->tz, &c->fx, &c->fy, &c->fz,
                      &c->coef, &c->F, &c->qa, &c->qb, &c->pacc, &c->u, &c->w, &c->pres,
                      &c->pr, &c->pz, &c->pp0, &c->pp1, &c->pq, &c->pdiag,
-                     &c->pres_lo, &c->pdelta, &c->prhs};
+                     &c->pres_lo, &c->pdelta, &c->prhs, &c->part};
   for (double** b : bufs)
     if (*b) { (void)hipFree(*b); *b = nullptr; }
   if (c->cf) (void)hipFree(c->cf);
@@ -145,6 +150,9 @@ void free_all(erem_ctx* c) {
   if (c->h_states) (void)hipHostFree(c->h_states);
   if (c->h_red) (void)hipHostFree(c->h_red);
   if (c->h_pcg) (void)hipHostFree(c->h_pcg);
+  float** fbufs[] = {&c->coef32, &c->qa32, &c->qb32, &c->p32};
+  for (float** b : fbufs)
+    if (*b) { (void)hipFree(*b); *b = nullptr; }
   c->cf = nullptr; c->states = nullptr; c->red = nullptr; c->pcg = nullptr;
   c->h_cf = nullptr; c->h_states = nullptr; c->h_red = nullptr; c->h_pcg = nullptr;
 }
@@ -156,16 +164,35 @@ void free_mg(erem_ctx* c) {
   c->mg_bufs.clear();
 }
 
-// LDS words of the coarse solve over levels lc..nlev-1 (faces, diagonal and
-// three work vectors per level, plus the accumulated solution and the rhs).
-size_t mg_lds_words(const MgHierarchy& h, int lc) {
+// LDS layout of the coarse solve over levels lc..lb: per smoothed level the
+// faces (z faces only in 3D), the diagonal and three vectors; on the bottom
+// level two vectors; then the bottom inverse.  Fills the offsets when `a` is
+// given and returns the number of words.
+size_t mg_lds_layout(const MgHierarchy& h, int lc, MgCoarseArgs* a) {
   size_t w = 0;
-  for (int l = lc; l < h.nlev; ++l) {
+  for (int l = lc; l <= h.lb; ++l) {
     const MgLevelDev& L = h.lev[l];
     const size_t n = static_cast<size_t>(L.nx) * L.ny * L.nz;
-    w += static_cast<size_t>(L.nx + 1) * L.ny * L.nz + static_cast<size_t>(L.nx) * (L.ny + 1) * L.nz;
-    if (L.nz > 1) w += static_cast<size_t>(L.nx) * L.ny * (L.nz + 1);
-    w += 4 * n;
+    int* off = a ? a->off[l - lc] : nullptr;
+    if (l < h.lb) {
+      const size_t nfx = static_cast<size_t>(L.nx + 1) * L.ny * L.nz;
+      const size_t nfy = static_cast<size_t>(L.nx) * (L.ny + 1) * L.nz;
+      const size_t nfz = L.nz > 1 ? static_cast<size_t>(L.nx) * L.ny * (L.nz + 1) : 0;
+      const size_t sizes[7] = {nfx, nfy, nfz, n, n, n, n};
+      for (int k = 0; k < 7; ++k) {
+        if (off) off[k] = static_cast<int>(w);
+        w += sizes[k];
+      }
+    } else {
+      if (off) {
+        for (int k = 0; k < 7; ++k) off[k] = 0;
+        off[4] = static_cast<int>(w);
+        off[5] = static_cast<int>(w + n);
+      }
+      w += 2 * n;
+      if (a) a->inv_off = static_cast<int>(w);
+      w += n * n;
+    }
   }
   return w;
 }
@@ -199,33 +226,39 @@ int build_mg(erem_ctx* c) {
       (void)hipMemsetAsync(L.tz, 0, nfz * sizeof(double), c->stream);
     }
     ++l;
-    if (n == 1) break;
+    if (n <= static_cast<size_t>(kMgBottomCells)) break;
     nx = (nx + 1) / 2;
     ny = (ny + 1) / 2;
     nz = nz > 1 ? (nz + 1) / 2 : 1;
   }
   h.nlev = l;
+  h.lb = l - 1;
+  {
+    const MgLevelDev& B = h.lev[h.lb];
+    const size_t nb = static_cast<size_t>(B.nx) * B.ny * B.nz;
+    if (dev_alloc(c, &h.binv, nb * nb) != EREM_OK) return EREM_ENOMEM;
+    c->mg_bufs.push_back(h.binv);
+  }
   int max_lds = 0;
   if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, c->device) != hipSuccess)
     max_lds = 65536;
   // First level that fits one workgroup (cells and LDS, with 1 KiB kept for
   // the kernel's static LDS); if the runtime refuses the dynamic LDS size,
   // retry within 64 KiB.
-  int lc = h.nlev - 1;
+  int lc = h.lb;
   for (int attempt = 0; attempt < 2; ++attempt) {
     const size_t limit = static_cast<size_t>(attempt == 0 ? max_lds : std::min(max_lds, 65536)) - 1024;
-    lc = h.nlev - 1;
-    for (int k = 0; k < h.nlev; ++k) {
+    lc = h.lb;
+    for (int k = 0; k <= h.lb; ++k) {
       const MgLevelDev& L = h.lev[k];
       const size_t n = static_cast<size_t>(L.nx) * L.ny * L.nz;
-      const size_t bytes = (mg_lds_words(h, k) + 2 * n) * sizeof(double);
+      const size_t bytes = mg_lds_layout(h, k, nullptr) * sizeof(double);
       if (n <= static_cast<size_t>(kMgLdsCells) && bytes <= limit) {
         lc = k;
         break;
       }
     }
-    const MgLevelDev& Lc = h.lev[lc];
-    const size_t bytes = (mg_lds_words(h, lc) + 2 * static_cast<size_t>(Lc.nx) * Lc.ny * Lc.nz) * sizeof(double);
+    const size_t bytes = mg_lds_layout(h, lc, nullptr) * sizeof(double);
     if (mg_set_lds_limit(static_cast<int>(bytes)) == hipSuccess) break;
     (void)hipGetLastError();
     if (attempt == 1) return fail(c, EREM_EDEVICE, "cannot reserve LDS for the coarse multigrid solve");
@@ -233,16 +266,13 @@ int build_mg(erem_ctx* c) {
   h.lc = lc;
   h.omega_c = 1.6;
   MgCoarseArgs& a = h.coarse;
-  a.nlev = h.nlev - lc;
+  a.nlev = h.lb - lc + 1;
   const MgLevelDev& L0 = h.lev[lc];
   a.n0 = L0.nx * L0.ny * L0.nz;
-  a.lds_words = static_cast<int>(mg_lds_words(h, lc));
-  a.ninner = 3;
   a.nu = 2;
-  a.nu_bottom = 1;
   a.omega_c = h.omega_c;
+  h.lds_bytes = mg_lds_layout(h, lc, &a) * sizeof(double);
   for (int k = 0; k < a.nlev; ++k) a.lev[k] = h.lev[lc + k];
-  h.lds_bytes = (static_cast<size_t>(a.lds_words) + 2 * a.n0) * sizeof(double);
   h.coarse_threads = std::min(1024, ((a.n0 + 63) / 64) * 64);
   return EREM_OK;
 }
@@ -275,6 +305,63 @@ int read_reduce(erem_ctx* c) {
 //   u_{j+1} = u_j + delta phi1(delta J) (v + J u_j)   (Sec. 4.2 splitting).
 // Returns EREM_OK, EREM_ENOCONV (some substep did not stop within K terms)
 // or an error.  `m_used` receives the summed degree.
+template <class V>
+struct LejaBufs {
+  const V* coef;
+  V *qa, *qb, *p;
+};
+
+int ensure_mixed(erem_ctx* c) {
+  if (!c->coef32) {
+    const size_t n = c->d.N;
+    int rc = EREM_OK;
+    rc |= dev_alloc(c, &c->coef32, n * ndir(c));
+    rc |= dev_alloc(c, &c->qa32, n);
+    rc |= dev_alloc(c, &c->qb32, n);
+    rc |= dev_alloc(c, &c->p32, n);
+    if (rc) return EREM_ENOMEM;
+  }
+  if (!c->coef32_valid) {
+    HIP_TRY(c, launch_cast_f32(c->coef, c->coef32, static_cast<long long>(c->d.N) * ndir(c), c->stream));
+    c->coef32_valid = true;
+  }
+  return EREM_OK;
+}
+
+template <class V>
+int leja_run(erem_ctx* c, const LejaBufs<V>& B, const double* v, double delta, int s, int K, int nprof) {
+  const Dims& d = c->d;
+  for (int j = 0; j < s; ++j) {
+    LejaState* st = c->states + j;
+    const double* src = v;
+    if (j > 0) {
+      HIP_TRY(c, launch_stencil_axpy(d, c->coef, v, c->u, c->w, c->stream));
+      src = c->w;
+    }
+    HIP_TRY(c, launch_leja_init<V>(d, c->cf, src, B.qa, B.p, c->part, c->stream));
+    hipEvent_t* evj = j < nprof ? &c->ev[static_cast<size_t>(j) * 2 * K] : nullptr;
+    int prev = -1;  // last term already checked
+    for (int k = 1; k <= K; ++k) {
+      const V* qin = (k & 1) ? B.qa : B.qb;
+      V* qout = (k & 1) ? B.qb : B.qa;
+      if (evj) HIP_TRY(c, hipEventRecord(evj[2 * (k - 1)], c->stream));
+      HIP_TRY(c, launch_leja_term<V>(d, c->cf, B.coef, qin, qout, B.p, st, c->part, k, c->stream));
+      if (evj) HIP_TRY(c, hipEventRecord(evj[2 * (k - 1) + 1], c->stream));
+      if (k % kCheckEvery == 0 || k == K) {
+        HIP_TRY(c, launch_leja_check(d, c->cf, st, c->part, prev + 1, k, c->stream));
+        prev = k;
+      }
+    }
+    HIP_TRY(c, launch_substep_update<V>(d, c->u, B.p, delta, j == 0 ? 1 : 0, c->stream));
+  }
+  return EREM_OK;
+}
+
+// u <- h phi1(h J) v by s Leja substeps of delta = h/s, each an exact
+// integration of the linear ODE u' = J u + v over delta:
+//   u_{j+1} = u_j + delta phi1(delta J) (v + J u_j)   (Sec. 4.2 splitting).
+// Returns EREM_OK, EREM_ENOCONV (some substep did not stop within K terms)
+// or an error.  `m_used` receives the summed degree actually applied.
 int leja_hphi1(erem_ctx* c, double h, const double* v, double scal, int s, int K,
                const erem_opts* o, int* m_used, double* est_last) {
   const double a = c->alpha, b = c->beta;
@@ -294,67 +381,43 @@ int leja_hphi1(erem_ctx* c, double h, const double* v, double scal, int s, int K
   }
   const size_t cf_bytes = offsetof(LejaCoef, shift) + 3 * sizeof(double) * (kMaxTerms + 1);
   HIP_TRY(c, hipMemcpyAsync(c->cf, hc, cf_bytes, hipMemcpyHostToDevice, c->stream));
-  if (launch_leja_reset(c->states, s, K, c->stream) != hipSuccess)
-    return fail(c, EREM_EDEVICE, "leja reset launch failed");
-  const Dims& d = c->d;
+  HIP_TRY(c, launch_leja_reset(c->states, s, K, c->stream));
   const int nprof = c->prof ? std::min(s, kProfSubsteps) : 0;
   if (nprof) {
-    const int rc = ensure_events(c, static_cast<size_t>(nprof) * (K + 1));
+    const int rc = ensure_events(c, static_cast<size_t>(nprof) * 2 * K);
     if (rc) return rc;
   }
-  for (int j = 0; j < s; ++j) {
-    LejaState* st = c->states + j;
-    const double* src = v;
-    if (j > 0) {
-      HIP_TRY(c, launch_stencil_axpy(d, c->coef, v, c->u, c->w, c->stream));
-      src = c->w;
-    }
-    HIP_TRY(c, launch_leja_init(d, c->cf, src, c->qa, c->pacc, st, c->stream));
-    hipEvent_t* evj = j < nprof ? &c->ev[static_cast<size_t>(j) * (K + 1)] : nullptr;
-    if (evj) HIP_TRY(c, hipEventRecord(evj[0], c->stream));
-    for (int k = 1; k <= K; ++k) {
-      const double* qin = (k & 1) ? c->qa : c->qb;
-      double* qout = (k & 1) ? c->qb : c->qa;
-      HIP_TRY(c, launch_leja_term(d, c->cf, c->coef, qin, qout, c->pacc, st, k, c->stream));
-      if (evj) HIP_TRY(c, hipEventRecord(evj[k], c->stream));
-    }
-    HIP_TRY(c, launch_substep_update(d, c->u, c->pacc, delta, j == 0 ? 1 : 0, c->stream));
+  int rc;
+  if (o->precision == EREM_PREC_MIXED) {
+    rc = ensure_mixed(c);
+    if (rc) return rc;
+    rc = leja_run<float>(c, LejaBufs<float>{c->coef32, c->qa32, c->qb32, c->p32}, v, delta, s, K, nprof);
+  } else {
+    rc = leja_run<double>(c, LejaBufs<double>{c->coef, c->qa, c->qb, c->pacc}, v, delta, s, K, nprof);
   }
-  // Read the stop state of every substep (sums of the last terms included).
+  if (rc) return rc;
+  // Read the stop state of every substep.
   const size_t hdr = offsetof(LejaState, sums);
   for (int j = 0; j < s; ++j)
     HIP_TRY(c, hipMemcpyAsync(reinterpret_cast<char*>(c->h_states + j),
                               reinterpret_cast<const char*>(c->states + j),
-                              hdr + sizeof(double) * kSlots * (K + 1), hipMemcpyDeviceToHost, c->stream));
+                              hdr + sizeof(double) * (K + 1), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   int total = 0;
   double last = 0.0;
   for (int j = 0; j < s; ++j) {
     const LejaState& st = c->h_states[j];
     if (st.nonfinite) return fail(c, EREM_ENONFINITE, "non-finite Leja term norm");
-    int stop = st.stopped;
-    auto est = [&](int k) {
-      double S = 0.0;
-      for (int q = 0; q < kSlots; ++q) S += st.sums[k * kSlots + q];
-      return hc->estf[k] * std::sqrt(S);
-    };
-    if (stop < 0) {
-      // No launch saw the test pass; evaluate it after the last term K.
-      for (int k = 0; k <= K; ++k)
-        if (!std::isfinite(est(k))) return fail(c, EREM_ENONFINITE, "non-finite Leja term norm");
-      double mean = 0.0;
-      for (int k = K - 4; k <= K; ++k) mean += est(k);
-      mean *= 0.2;
-      if (!(mean < hc->thresh)) return EREM_ENOCONV;
-      stop = K;
-    }
-    total += stop;
-    last = est(stop);
+    if (st.stopped < 0) return EREM_ENOCONV;
+    // the stop test ran after every kCheckEvery terms: the terms up to the
+    // end of the group in which it passed were applied
+    const int applied = std::min(K, ((st.stopped + kCheckEvery - 1) / kCheckEvery) * kCheckEvery);
+    total += applied;
+    last = hc->estf[st.stopped] * std::sqrt(st.sums[st.stopped]);
     if (j < nprof) {
-      // launches 1..stop computed a term; later ones returned at entry
-      const hipEvent_t* evj = &c->ev[static_cast<size_t>(j) * (K + 1)];
-      for (int k = 1; k <= stop; ++k) c->t_leja += elapsed_ms(evj[k - 1], evj[k]);
-      c->n_leja += stop;
+      const hipEvent_t* evj = &c->ev[static_cast<size_t>(j) * 2 * K];
+      for (int k = 1; k <= applied; ++k) c->t_leja += elapsed_ms(evj[2 * (k - 1)], evj[2 * (k - 1) + 1]);
+      c->n_leja += applied;
     }
   }
   *m_used = total;
@@ -484,6 +547,7 @@ int erem_create(const erem_grid* g, void* stream, erem_ctx** out) {
   rc |= dev_alloc(c, &c->pres_lo, n);
   rc |= dev_alloc(c, &c->pdelta, n);
   rc |= dev_alloc(c, &c->prhs, n);
+  rc |= dev_alloc(c, &c->part, static_cast<size_t>(kLejaRing) * leja_num_blocks(c->d));
   c->nstates = 64;
   rc |= dev_alloc(c, &c->cf, 1);
   rc |= dev_alloc(c, &c->states, c->nstates);
@@ -719,6 +783,7 @@ int erem_form_jacobian(erem_ctx* c, const double* d_T) {
   HIP_TRY(c, launch_reset_reduce(c->red, c->stream));
   HIP_TRY(c, launch_assemble(c->d, c->ph, c->poro, c->fx, c->fy, c->fz, d_T, c->coef, c->F, c->red, c->stream));
   c->jac_set = true;
+  c->coef32_valid = false;
   return EREM_OK;
 }
 
@@ -738,8 +803,8 @@ int erem_phi1_apply(erem_ctx* c, double h, const double* d_v, double* d_out, con
   if (!d_v || !d_out || d_v == d_out) return fail(c, EREM_EINVAL, "v and out must be distinct non-NULL");
   if (!c->jac_set) return fail(c, EREM_EINVAL, "erem_form_jacobian must come first");
   if (!(h > 0) || !std::isfinite(h)) return fail(c, EREM_EINVAL, "h must be > 0");
-  if (o->method != EREM_METHOD_LEJA || o->precision != EREM_PREC_FP64)
-    return fail(c, EREM_EINVAL, "only the FP64 Leja method is available");
+  if (o->method != EREM_METHOD_LEJA)
+    return fail(c, EREM_EINVAL, "only the Leja method is available");
   // max |v| (the Gershgorin interval of the last assembly is kept)
   HIP_TRY(c, launch_absmax(c->d, d_v, c->red, c->stream));
   rc = read_reduce(c);
@@ -767,6 +832,7 @@ int erem_set_jacobian(erem_ctx* c, const double* d_coef, const double* d_F) {
   HIP_TRY(c, hipMemcpyAsync(c->F, d_F, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   HIP_TRY(c, launch_gershgorin(c->d, c->coef, c->red, c->stream));
   c->jac_set = true;
+  c->coef32_valid = false;
   return EREM_OK;
 }
 
@@ -777,8 +843,8 @@ int step_checks(erem_ctx* c, double h, double* d_T, const erem_opts* o) {
   if (rc) return rc;
   if (!d_T) return fail(c, EREM_EINVAL, "T is NULL");
   if (!(h > 0) || !std::isfinite(h)) return fail(c, EREM_EINVAL, "h must be > 0");
-  if (o->method != EREM_METHOD_LEJA || o->precision != EREM_PREC_FP64)
-    return fail(c, EREM_EINVAL, "only the FP64 Leja method is available");
+  if (o->method != EREM_METHOD_LEJA)
+    return fail(c, EREM_EINVAL, "only the Leja method is available");
   return EREM_OK;
 }
 

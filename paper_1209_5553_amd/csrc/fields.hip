@@ -1,4 +1,6 @@
-// HIP kernels of the EREM heat-transport path for gfx950 (MI355X).
+// HIP kernels of the EREM path for gfx950 (MI355X): TPFA transmissibilities,
+// face fluxes, Jacobian / G assembly, Gershgorin interval and the pressure
+// conjugate gradients.
 //
 // Every cell kernel runs one thread per cell on a (64 x 4) block: one
 // 64-lane wavefront per grid row segment, so loads along x are fully
@@ -353,119 +355,6 @@ __global__ __launch_bounds__(kThreads) void k_stencil_axpy(Dims d, const double*
   if (x >= d.nx || y >= d.ny) return;
   const int i = x + d.nx * (y + d.ny * z);
   w[i] = v[i] + stencil_apply(d, coef, u, x, y, z, i);
-}
-
-// ---------------------------------------------------------------------------
-// Newton-Leja recurrence (Sec. 4.2, Eq. newt):
-//   q_k = ((J - cI)/gamma - xi_{k-1} I) q_{k-1},  p += d_k q_k,
-// with sum q_k^2 for the scaled error norm ||delta d_k q_k|| (Sec. 4.2).
-// Stop test (Sec. 4.2): 10^p * mean of the last five estimates < 1,
-// evaluated by every block of the next term's kernel from the reduced sums;
-// once it holds the remaining launches return at entry.
-// ---------------------------------------------------------------------------
-__global__ void k_leja_reset(LejaState* st, int nslots, int nterms) {
-  const int words = (nterms + 1) * kSlots;
-  for (int s = blockIdx.x; s < nslots; s += gridDim.x) {
-    LejaState* t = st + s;
-    for (int j = threadIdx.x; j < words; j += blockDim.x) t->sums[j] = 0.0;
-    if (threadIdx.x == 0) {
-      t->stopped = -1;
-      t->nonfinite = 0;
-    }
-  }
-}
-
-__global__ __launch_bounds__(kThreads) void k_leja_init(Dims d, const LejaCoef* __restrict__ cf,
-                                              const double* __restrict__ v, double* __restrict__ q0,
-                                              double* __restrict__ p, LejaState* st) {
-  const int x = blockIdx.x * kBX + threadIdx.x;
-  const int y = blockIdx.y * kBY + threadIdx.y;
-  const int z = blockIdx.z;
-  double s[1] = {0.0};
-  if (x < d.nx && y < d.ny) {
-    const int i = x + d.nx * (y + d.ny * z);
-    const double vi = v[i];
-    q0[i] = vi;
-    p[i] = cf->dk[0] * vi;
-    s[0] = vi * vi;
-  }
-  block_sum<1>(s);
-  if (tid_lin() == 0) atomicAdd(&st->sums[bid_lin() & (kSlots - 1)], s[0]);
-}
-
-// Returns true when the stop test on terms <= k-1 already holds (or a norm
-// was not finite); block 0 records the stop index.
-__device__ inline bool leja_should_stop(const LejaCoef* __restrict__ cf, LejaState* st, int k) {
-  __shared__ int decision;
-  const int t = tid_lin();
-  if (t == 0) {
-    int stop = *(volatile int*)&st->stopped >= 0;
-    if (!stop) {
-      const double* sums = (const double*)st->sums;
-      const double Sk = slot_sum(sums + (k - 1) * kSlots);
-      if (!isfinite(Sk)) {
-        stop = 1;
-        if (bid_lin() == 0) {
-          st->nonfinite = 1;
-          st->stopped = k - 1;
-        }
-      } else if (k - 1 >= 4) {
-        double mean = 0.0;
-        for (int j = k - 5; j <= k - 1; ++j) mean += cf->estf[j] * sqrt(slot_sum(sums + j * kSlots));
-        mean *= 0.2;
-        if (mean < cf->thresh) {
-          stop = 1;
-          if (bid_lin() == 0) st->stopped = k - 1;
-        }
-      }
-    }
-    decision = stop;
-  }
-  __syncthreads();
-  return decision != 0;
-}
-
-template <int DIM>
-__global__ __launch_bounds__(kThreads) void k_leja_term(Dims d, const LejaCoef* __restrict__ cf,
-                                              const double* __restrict__ coef, const double* __restrict__ qin,
-                                              double* __restrict__ qout, double* __restrict__ p,
-                                              LejaState* st, int k) {
-  if (leja_should_stop(cf, st, k)) return;
-  const int x = blockIdx.x * kBX + threadIdx.x;
-  const int y = blockIdx.y * kBY + threadIdx.y;
-  const int z = blockIdx.z;
-  double s[1] = {0.0};
-  if (x < d.nx && y < d.ny) {
-    const int N = d.N;
-    const int i = x + d.nx * (y + d.ny * z);
-    const double qi = qin[i];
-    double jq = coef[i] * qi;
-    jq += coef[N + i] * qin[x > 0 ? i - 1 : i];
-    jq += coef[2 * N + i] * qin[x + 1 < d.nx ? i + 1 : i];
-    jq += coef[3 * N + i] * qin[y > 0 ? i - d.nx : i];
-    jq += coef[4 * N + i] * qin[y + 1 < d.ny ? i + d.nx : i];
-    if (DIM == 3) {
-      const int pl = d.nx * d.ny;
-      jq += coef[5 * N + i] * qin[z > 0 ? i - pl : i];
-      jq += coef[6 * N + i] * qin[z + 1 < d.nz ? i + pl : i];
-    }
-    const double r = jq * cf->inv_g - cf->shift[k] * qi;
-    p[i] += cf->dk[k] * r;
-    qout[i] = r;
-    s[0] = r * r;
-  }
-  block_sum<1>(s);
-  if (tid_lin() == 0) atomicAdd(&st->sums[k * kSlots + (bid_lin() & (kSlots - 1))], s[0]);
-}
-
-__global__ __launch_bounds__(kThreads) void k_substep_update(Dims d, double* __restrict__ u,
-                                                   const double* __restrict__ p, double delta, int first) {
-  const int x = blockIdx.x * kBX + threadIdx.x;
-  const int y = blockIdx.y * kBY + threadIdx.y;
-  const int z = blockIdx.z;
-  if (x >= d.nx || y >= d.ny) return;
-  const int i = x + d.nx * (y + d.ny * z);
-  u[i] = first ? delta * p[i] : u[i] + delta * p[i];
 }
 
 // y <- a*y + b*x
@@ -867,32 +756,6 @@ hipError_t launch_absmax(const Dims& d, const double* v, AsmReduce* red, hipStre
 hipError_t launch_stencil_axpy(const Dims& d, const double* coef, const double* v, const double* u,
                                double* w, hipStream_t s) {
   hipLaunchKernelGGL(k_stencil_axpy, cell_grid(d), cell_block(), 0, s, d, coef, v, u, w);
-  return hipGetLastError();
-}
-
-hipError_t launch_leja_reset(LejaState* st, int nslots, int nterms, hipStream_t s) {
-  hipLaunchKernelGGL(k_leja_reset, dim3(nslots < 64 ? nslots : 64), dim3(256), 0, s, st, nslots, nterms);
-  return hipGetLastError();
-}
-
-hipError_t launch_leja_init(const Dims& d, const LejaCoef* cf, const double* v, double* q0, double* p,
-                            LejaState* st, hipStream_t s) {
-  hipLaunchKernelGGL(k_leja_init, cell_grid(d), cell_block(), 0, s, d, cf, v, q0, p, st);
-  return hipGetLastError();
-}
-
-hipError_t launch_leja_term(const Dims& d, const LejaCoef* cf, const double* coef, const double* qin,
-                            double* qout, double* p, LejaState* st, int k, hipStream_t s) {
-  if (d.dim == 3)
-    hipLaunchKernelGGL(k_leja_term<3>, cell_grid(d), cell_block(), 0, s, d, cf, coef, qin, qout, p, st, k);
-  else
-    hipLaunchKernelGGL(k_leja_term<2>, cell_grid(d), cell_block(), 0, s, d, cf, coef, qin, qout, p, st, k);
-  return hipGetLastError();
-}
-
-hipError_t launch_substep_update(const Dims& d, double* u, const double* p, double delta, int first,
-                                 hipStream_t s) {
-  hipLaunchKernelGGL(k_substep_update, cell_grid(d), cell_block(), 0, s, d, u, p, delta, first);
   return hipGetLastError();
 }
 

@@ -1,0 +1,226 @@
+// Newton-Leja evaluation of phi1(delta J) v on the device (Sec. 4.2):
+//
+//   q_0 = v,  p_0 = d_0 q_0,
+//   q_k = ((J - c I)/gamma - xi_{k-1} I) q_{k-1},  p_k = p_{k-1} + d_k q_k   (Eq. newt)
+//
+// One fused pass per term reads the stencil of J and q_{k-1}, updates p and
+// writes q_k; each block also stores its partial sum of q_k^2 (in FP64 in
+// both precisions).  A one-workgroup check kernel, launched after every few
+// terms, reduces those partials in a fixed order (so results are
+// reproducible bit for bit), forms the scaled error estimates
+// ||delta d_k q_k|| = |delta d_k| ||q_k||_2 / (sqrt(N) scal) and applies the
+// stop test 10^p * mean(last five estimates) < 1 (Sec. 4.2).  Once it holds,
+// later term launches return at entry.
+//
+// Value type V is double (FP64 path) or float (mixed path: FP32 stencil,
+// vectors and accumulation; FP64 divided differences, norms and update).
+#include "device.h"
+#include "leja.h"
+
+#include <cmath>
+
+namespace erem {
+
+namespace {
+
+template <class V>
+__device__ inline V to_v(double x) { return static_cast<V>(x); }
+
+// Sum of one double over the 256-thread cell block; valid in thread 0.
+__device__ inline double block_sum256(double v) {
+  __shared__ double sh[kThreads / 64];
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int t = threadIdx.x + threadIdx.y * kBX;
+  if ((t & 63) == 0) sh[t >> 6] = v;
+  __syncthreads();
+  return t == 0 ? sh[0] + sh[1] + sh[2] + sh[3] : 0.0;
+}
+
+__device__ inline int block_id() { return blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z); }
+
+__global__ void k_leja_reset(LejaState* st, int nslots, int nterms) {
+  for (int s = blockIdx.x; s < nslots; s += gridDim.x) {
+    LejaState* t = st + s;
+    for (int j = threadIdx.x; j <= nterms; j += blockDim.x) t->sums[j] = 0.0;
+    if (threadIdx.x == 0) {
+      t->stopped = -1;
+      t->nonfinite = 0;
+      t->checked = -1;
+    }
+  }
+}
+
+template <class V>
+__global__ __launch_bounds__(kThreads) void k_leja_init(Dims d, const LejaCoef* __restrict__ cf,
+                                              const double* __restrict__ v, V* __restrict__ q0,
+                                              V* __restrict__ p, double* __restrict__ part, int nb) {
+  const int x = blockIdx.x * kBX + threadIdx.x;
+  const int y = blockIdx.y * kBY + threadIdx.y;
+  const int z = blockIdx.z;
+  double s = 0.0;
+  if (x < d.nx && y < d.ny) {
+    const int i = x + d.nx * (y + d.ny * z);
+    const V vi = to_v<V>(v[i]);
+    q0[i] = vi;
+    p[i] = to_v<V>(cf->dk[0]) * vi;
+    s = static_cast<double>(vi) * static_cast<double>(vi);
+  }
+  s = block_sum256(s);
+  if (threadIdx.x == 0 && threadIdx.y == 0) part[block_id()] = s;  // ring slot 0
+}
+
+template <int DIM, class V>
+__global__ __launch_bounds__(kThreads) void k_leja_term(Dims d, const LejaCoef* __restrict__ cf,
+                                              const V* __restrict__ coef, const V* __restrict__ qin,
+                                              V* __restrict__ qout, V* __restrict__ p,
+                                              const LejaState* __restrict__ st, double* __restrict__ part,
+                                              int nb, int k) {
+  if (*(volatile const int*)&st->stopped >= 0) return;  // stop test already passed
+  const int x = blockIdx.x * kBX + threadIdx.x;
+  const int y = blockIdx.y * kBY + threadIdx.y;
+  const int z = blockIdx.z;
+  double s = 0.0;
+  if (x < d.nx && y < d.ny) {
+    const int N = d.N;
+    const int i = x + d.nx * (y + d.ny * z);
+    const V qi = qin[i];
+    V jq = coef[i] * qi;
+    jq += coef[N + i] * qin[x > 0 ? i - 1 : i];
+    jq += coef[2 * N + i] * qin[x + 1 < d.nx ? i + 1 : i];
+    jq += coef[3 * N + i] * qin[y > 0 ? i - d.nx : i];
+    jq += coef[4 * N + i] * qin[y + 1 < d.ny ? i + d.nx : i];
+    if (DIM == 3) {
+      const int pl = d.nx * d.ny;
+      jq += coef[5 * N + i] * qin[z > 0 ? i - pl : i];
+      jq += coef[6 * N + i] * qin[z + 1 < d.nz ? i + pl : i];
+    }
+    const V r = jq * to_v<V>(cf->inv_g) - to_v<V>(cf->shift[k]) * qi;
+    p[i] += to_v<V>(cf->dk[k]) * r;
+    qout[i] = r;
+    s = static_cast<double>(r) * static_cast<double>(r);
+  }
+  s = block_sum256(s);
+  if (threadIdx.x == 0 && threadIdx.y == 0) part[(k % kLejaRing) * nb + block_id()] = s;
+}
+
+// Reduce the partials of terms k1..k2 (in order), record their sums and
+// apply the stop test.  One workgroup of kCheckThreads threads.
+__global__ __launch_bounds__(kCheckThreads) void k_leja_check(const LejaCoef* __restrict__ cf, LejaState* st,
+                                                    const double* __restrict__ part, int nb, int k1, int k2) {
+  if (st->stopped >= 0) return;
+  __shared__ double sh[kCheckThreads / 64];
+  __shared__ int stop_sh;
+  for (int k = k1; k <= k2; ++k) {
+    const double* pk = part + (k % kLejaRing) * nb;
+    double v = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kCheckThreads) v += pk[b];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double S = 0.0;
+      for (int w = 0; w < kCheckThreads / 64; ++w) S += sh[w];
+      st->sums[k] = S;
+      int stop = 0;
+      if (!isfinite(S)) {
+        st->nonfinite = 1;
+        stop = 1;
+      } else if (k >= 4) {
+        double mean = 0.0;
+        for (int j = k - 4; j <= k; ++j) mean += cf->estf[j] * sqrt(st->sums[j]);
+        mean *= 0.2;
+        stop = mean < cf->thresh;
+      }
+      if (stop) st->stopped = k;
+      st->checked = k;
+      stop_sh = stop;
+    }
+    __syncthreads();
+    if (stop_sh) return;
+  }
+}
+
+// u = (first ? 0 : u) + delta * p  (FP64 update of the substep increment)
+template <class V>
+__global__ __launch_bounds__(kThreads) void k_substep_update(Dims d, double* __restrict__ u, const V* __restrict__ p,
+                                                   double delta, int first) {
+  const int x = blockIdx.x * kBX + threadIdx.x;
+  const int y = blockIdx.y * kBY + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= d.nx || y >= d.ny) return;
+  const int i = x + d.nx * (y + d.ny * z);
+  const double pi = static_cast<double>(p[i]);
+  u[i] = first ? delta * pi : u[i] + delta * pi;
+}
+
+__global__ void k_cast_f32(const double* __restrict__ a, float* __restrict__ b, long long n) {
+  for (long long i = blockIdx.x * static_cast<long long>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<long long>(gridDim.x) * blockDim.x)
+    b[i] = static_cast<float>(a[i]);
+}
+
+}  // namespace
+
+int leja_num_blocks(const Dims& d) {
+  const dim3 g = cell_grid(d);
+  return static_cast<int>(g.x * g.y * g.z);
+}
+
+hipError_t launch_leja_reset(LejaState* st, int nslots, int nterms, hipStream_t s) {
+  hipLaunchKernelGGL(k_leja_reset, dim3(nslots < 64 ? nslots : 64), dim3(256), 0, s, st, nslots, nterms);
+  return hipGetLastError();
+}
+
+template <class V>
+hipError_t launch_leja_init(const Dims& d, const LejaCoef* cf, const double* v, V* q0, V* p, double* part,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_leja_init<V>, cell_grid(d), cell_block(), 0, s, d, cf, v, q0, p, part,
+                     leja_num_blocks(d));
+  return hipGetLastError();
+}
+
+template <class V>
+hipError_t launch_leja_term(const Dims& d, const LejaCoef* cf, const V* coef, const V* qin, V* qout, V* p,
+                            const LejaState* st, double* part, int k, hipStream_t s) {
+  const int nb = leja_num_blocks(d);
+  if (d.dim == 3)
+    hipLaunchKernelGGL((k_leja_term<3, V>), cell_grid(d), cell_block(), 0, s, d, cf, coef, qin, qout, p, st, part,
+                       nb, k);
+  else
+    hipLaunchKernelGGL((k_leja_term<2, V>), cell_grid(d), cell_block(), 0, s, d, cf, coef, qin, qout, p, st, part,
+                       nb, k);
+  return hipGetLastError();
+}
+
+hipError_t launch_leja_check(const Dims& d, const LejaCoef* cf, LejaState* st, const double* part, int k1, int k2,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_leja_check, dim3(1), dim3(kCheckThreads), 0, s, cf, st, part, leja_num_blocks(d), k1, k2);
+  return hipGetLastError();
+}
+
+template <class V>
+hipError_t launch_substep_update(const Dims& d, double* u, const V* p, double delta, int first, hipStream_t s) {
+  hipLaunchKernelGGL(k_substep_update<V>, cell_grid(d), cell_block(), 0, s, d, u, p, delta, first);
+  return hipGetLastError();
+}
+
+hipError_t launch_cast_f32(const double* a, float* b, long long n, hipStream_t s) {
+  long long blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_cast_f32, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, a, b, n);
+  return hipGetLastError();
+}
+
+template hipError_t launch_leja_init<double>(const Dims&, const LejaCoef*, const double*, double*, double*,
+                                             double*, hipStream_t);
+template hipError_t launch_leja_init<float>(const Dims&, const LejaCoef*, const double*, float*, float*, double*,
+                                            hipStream_t);
+template hipError_t launch_leja_term<double>(const Dims&, const LejaCoef*, const double*, const double*, double*,
+                                             double*, const LejaState*, double*, int, hipStream_t);
+template hipError_t launch_leja_term<float>(const Dims&, const LejaCoef*, const float*, const float*, float*, float*,
+                                            const LejaState*, double*, int, hipStream_t);
+template hipError_t launch_substep_update<double>(const Dims&, double*, const double*, double, int, hipStream_t);
+template hipError_t launch_substep_update<float>(const Dims&, double*, const float*, double, int, hipStream_t);
+
+}  // namespace erem

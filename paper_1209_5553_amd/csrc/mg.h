@@ -9,6 +9,7 @@ namespace erem {
 
 constexpr int kMgMaxLevels = 16;
 constexpr int kMgLdsCells = 1024;   // levels at or below this size run in one workgroup
+constexpr int kMgBottomCells = 64;  // bottom level, solved with a dense inverse
 
 // One level: faces in the fine-grid layout (x faces (nz, ny, nx+1), y faces
 // (nz, ny+1, nx), z faces (nz+1, ny, nx)), diagonal, and work vectors.
@@ -18,24 +19,25 @@ struct MgLevelDev {
   double *b, *x, *y;
 };
 
-// Arguments of the single-workgroup coarse solve over levels lc..nlev-1.
+// Arguments of the single-workgroup coarse solve over levels lc..lb.
 struct MgCoarseArgs {
-  int nlev;        // levels handled in LDS
-  int n0;          // cells of the first of them
-  int lds_words;   // LDS words taken by the level arrays
-  int ninner;      // V-cycles of the coarse solve
-  int nu;          // Jacobi sweeps before and after the coarse correction
-  int nu_bottom;   // sweeps on the coarsest level
-  double omega_c;  // coarse-correction relaxation
+  int nlev;                    // levels handled in LDS (the last is the bottom)
+  int n0;                      // cells of the first of them
+  int nu;                      // Jacobi sweeps before and after the coarse correction
+  int inv_off;                 // LDS offset of the bottom inverse
+  double omega_c;              // coarse-correction relaxation
+  int off[kMgMaxLevels][7];    // LDS offsets: tx, ty, tz, diag, B, E, T per level
   MgLevelDev lev[kMgMaxLevels];
 };
 
 struct MgHierarchy {
-  int nlev = 0;            // all levels, finest first
+  int nlev = 0;            // levels built (finest first), the last is the bottom
   int lc = 0;              // first level handled in LDS
+  int lb = 0;              // bottom level (= nlev - 1)
   int coarse_threads = 0;
   size_t lds_bytes = 0;
   double omega_c = 1.6;
+  double* binv = nullptr;  // dense inverse of the bottom operator (device)
   MgLevelDev lev[kMgMaxLevels];
   MgCoarseArgs coarse;
 };

@@ -7,9 +7,11 @@
 // so every level keeps the same face-array layout as the fine grid.
 // Smoother: damped Jacobi (omega 0.8), the same sweeps before and after the
 // coarse correction; the coarse correction is over-relaxed by omega_c; the
-// cycle is symmetric, so it is a valid conjugate-gradient preconditioner.
-// Fine levels run one kernel per operation; the levels with at most
-// kMgLdsCells cells run inside one workgroup with everything in LDS.
+// bottom level (at most kMgBottomCells cells) is solved exactly with a dense
+// inverse formed once per setup.  The cycle is symmetric, so it is a valid
+// conjugate-gradient preconditioner.  Fine levels run one kernel per
+// operation; the levels with at most kMgLdsCells cells run inside one
+// workgroup with everything in LDS.
 #include "device.h"
 #include "mg.h"
 
@@ -25,12 +27,11 @@ __device__ inline int fzi(int nx, int ny, int x, int y, int z) { return (z * ny 
 
 __device__ inline bool pcg_done(const PcgState* st) { return st && *(volatile const int*)&st->done; }
 
-// (A v)_i without the diagonal: sum over interior faces of t * v_nb.
-__device__ inline double offdiag_sum(const MgLevelDev& L, const double* __restrict__ tx,
+// sum over interior faces of t * v_nb  (so that (A v)_i = diag_i v_i - offdiag_sum)
+__device__ inline double offdiag_sum(int nx, int ny, int nz, const double* __restrict__ tx,
                                      const double* __restrict__ ty, const double* __restrict__ tz,
                                      const double* __restrict__ v, int x, int y, int z, int i) {
   double s = 0.0;
-  const int nx = L.nx, ny = L.ny, nz = L.nz;
   if (x > 0) s += tx[fxi(nx, ny, x, y, z)] * v[i - 1];
   if (x + 1 < nx) s += tx[fxi(nx, ny, x + 1, y, z)] * v[i + 1];
   if (y > 0) s += ty[fyi(nx, ny, x, y, z)] * v[i - nx];
@@ -51,9 +52,8 @@ __global__ __launch_bounds__(kThreads) void k_mg_coarsen(MgLevelDev F, MgLevelDe
   const int fnx = F.nx, fny = F.ny, fnz = F.nz;
   const int y0 = 2 * Y, y1 = min(2 * Y + 1, fny - 1);
   const int x0 = 2 * X, x1 = min(2 * X + 1, fnx - 1);
-  const int z0 = C.nz > 1 || fnz > 1 ? 2 * Z : 0;
+  const int z0 = fnz > 1 ? 2 * Z : 0;
   const int z1 = fnz > 1 ? min(2 * Z + 1, fnz - 1) : 0;
-  // sum of fine x faces at fine face index xf over the rows / layers of this aggregate
   auto sum_x = [&](int xf) {
     double s = 0.0;
     for (int z = z0; z <= z1; ++z)
@@ -77,7 +77,7 @@ __global__ __launch_bounds__(kThreads) void k_mg_coarsen(MgLevelDev F, MgLevelDe
   const double s = sum_y(2 * Y);
   const double n = sum_y(min(2 * Y + 2, fny));
   double b = 0.0, t = 0.0;
-  if (F.nz > 1) {
+  if (fnz > 1) {
     b = sum_z(2 * Z);
     t = sum_z(min(2 * Z + 2, fnz));
   }
@@ -89,6 +89,53 @@ __global__ __launch_bounds__(kThreads) void k_mg_coarsen(MgLevelDev F, MgLevelDe
   C.tz[fzi(cnx, cny, X, Y, Z + 1)] = t;
   if (Z == 0) C.tz[fzi(cnx, cny, X, Y, 0)] = b;
   C.diag[X + cnx * (Y + cny * Z)] = w + e + s + n + b + t;
+}
+
+// Dense inverse of the bottom-level operator (SPD, diagonally dominant, so
+// Gauss-Jordan without pivoting is stable), one workgroup, in place in LDS.
+__global__ __launch_bounds__(256) void k_mg_bottom_inverse(MgLevelDev L, double* __restrict__ inv) {
+  __shared__ double M[kMgBottomCells * kMgBottomCells];
+  __shared__ double prow[kMgBottomCells];
+  __shared__ double pcol[kMgBottomCells];
+  const int n = L.nx * L.ny * L.nz;
+  for (int j = threadIdx.x; j < n * n; j += blockDim.x) M[j] = 0.0;
+  __syncthreads();
+  for (int c = threadIdx.x; c < n; c += blockDim.x) {
+    const int x = c % L.nx, y = (c / L.nx) % L.ny, z = c / (L.nx * L.ny);
+    // diagonal = sum of the cell's face transmissibilities (Dirichlet faces
+    // included), formed here so that the finest level needs no other setup
+    double dg = L.tx[fxi(L.nx, L.ny, x, y, z)] + L.tx[fxi(L.nx, L.ny, x + 1, y, z)] +
+                L.ty[fyi(L.nx, L.ny, x, y, z)] + L.ty[fyi(L.nx, L.ny, x, y + 1, z)];
+    if (L.nz > 1) dg += L.tz[fzi(L.nx, L.ny, x, y, z)] + L.tz[fzi(L.nx, L.ny, x, y, z + 1)];
+    M[c * n + c] = dg;
+    if (x > 0) M[c * n + c - 1] = -L.tx[fxi(L.nx, L.ny, x, y, z)];
+    if (x + 1 < L.nx) M[c * n + c + 1] = -L.tx[fxi(L.nx, L.ny, x + 1, y, z)];
+    if (y > 0) M[c * n + c - L.nx] = -L.ty[fyi(L.nx, L.ny, x, y, z)];
+    if (y + 1 < L.ny) M[c * n + c + L.nx] = -L.ty[fyi(L.nx, L.ny, x, y + 1, z)];
+    if (z > 0) M[c * n + c - L.nx * L.ny] = -L.tz[fzi(L.nx, L.ny, x, y, z)];
+    if (z + 1 < L.nz) M[c * n + c + L.nx * L.ny] = -L.tz[fzi(L.nx, L.ny, x, y, z + 1)];
+  }
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    const double piv = 1.0 / M[k * n + k];
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+      prow[j] = (j == k) ? piv : M[k * n + j] * piv;  // new pivot row
+      pcol[j] = M[j * n + k];                          // old pivot column
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+      const int i = e / n, j = e - i * n;
+      if (i == k) {
+        M[e] = prow[j];
+      } else if (j == k) {
+        M[e] = -pcol[i] * piv;
+      } else {
+        M[e] -= pcol[i] * prow[j];
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) inv[e] = M[e];
 }
 
 // Two damped-Jacobi sweeps from zero: x1 = w b / D, x2 = x1 + w (b - A x1) / D.
@@ -111,7 +158,6 @@ __global__ __launch_bounds__(kThreads) void k_mg_smooth_down(MgLevelDev L, const
   if (z + 1 < nz) s += L.tz[fzi(nx, ny, x, y, z + 1)] * x1(i + nx * ny);
   const double D = L.diag[i];
   const double xi = kOmega * b[i] / D;
-  // b - A x1 = b - D x1 + sum t x1_nb
   xout[i] = xi + kOmega * (b[i] - D * xi + s) / D;
 }
 
@@ -131,7 +177,7 @@ __global__ __launch_bounds__(kThreads) void k_mg_restrict(MgLevelDev F, MgLevelD
     for (int y = 2 * Y; y <= y1; ++y)
       for (int x = 2 * X; x <= x1; ++x) {
         const int i = x + F.nx * (y + F.ny * z);
-        acc += b[i] - F.diag[i] * xv[i] + offdiag_sum(F, F.tx, F.ty, F.tz, xv, x, y, z, i);
+        acc += b[i] - F.diag[i] * xv[i] + offdiag_sum(F.nx, F.ny, F.nz, F.tx, F.ty, F.tz, xv, x, y, z, i);
       }
   bc[X + C.nx * (Y + C.ny * Z)] = acc;
 }
@@ -163,7 +209,7 @@ __global__ __launch_bounds__(kThreads) void k_mg_prolong_smooth(MgLevelDev F, Mg
   yout[i] = xi + kOmega * (b[i] - D * xi + s) / D;
 }
 
-// Last Jacobi sweep: out = y + w (b - A y) / D.  With rz != nullptr (the
+// Last Jacobi sweep: out = y + w (b - A y) / D.  With rz_slot >= 0 (the
 // finest level, b = r) also accumulates r . out into the CG ring slot.
 __global__ __launch_bounds__(kThreads) void k_mg_smooth_final(MgLevelDev L, const double* __restrict__ b,
                                                     const double* __restrict__ yv, double* __restrict__ out,
@@ -176,7 +222,8 @@ __global__ __launch_bounds__(kThreads) void k_mg_smooth_final(MgLevelDev L, cons
   if (x < L.nx && y < L.ny) {
     const int i = x + L.nx * (y + L.ny * z);
     const double D = L.diag[i];
-    const double v = yv[i] + kOmega * (b[i] - D * yv[i] + offdiag_sum(L, L.tx, L.ty, L.tz, yv, x, y, z, i)) / D;
+    const double v =
+        yv[i] + kOmega * (b[i] - D * yv[i] + offdiag_sum(L.nx, L.ny, L.nz, L.tx, L.ty, L.tz, yv, x, y, z, i)) / D;
     out[i] = v;
     part = b[i] * v;
   }
@@ -193,27 +240,38 @@ __global__ __launch_bounds__(kThreads) void k_mg_smooth_final(MgLevelDev L, cons
 }
 
 // ---------------------------------------------------------------------------
-// Coarse levels in one workgroup: `ninner` V-cycles of levels lc..end
-// (everything in LDS), from x = 0, on rhs b (global).  Writes x to out; with
-// rz_slot >= 0 also b . out into the CG ring.
+// Coarse levels in one workgroup, everything in LDS: one V-cycle over the
+// levels first..bottom-1 with the exact dense solve on the bottom level,
+// from x = 0, on rhs b (global).  Writes x to out; with rz_slot >= 0 also
+// b . out into the CG ring.  LDS per smoothed level: faces, diagonal and
+// three vectors; bottom: two vectors and the inverse; plus the rhs copy.
 // ---------------------------------------------------------------------------
 struct LdsLevel {
   double *tx, *ty, *tz, *diag, *B, *E, *T;
 };
 
-__device__ void lds_apply_smooth(const MgLevelDev& L, const LdsLevel& S, int sweeps, bool from_zero,
-                                 double omega) {
+__device__ inline void lds_level(const MgCoarseArgs& a, double* smem, int l, LdsLevel& S) {
+  S.tx = smem + a.off[l][0];
+  S.ty = smem + a.off[l][1];
+  S.tz = smem + a.off[l][2];
+  S.diag = smem + a.off[l][3];
+  S.B = smem + a.off[l][4];
+  S.E = smem + a.off[l][5];
+  S.T = smem + a.off[l][6];
+}
+
+__device__ void lds_smooth(const MgLevelDev& L, const LdsLevel& S, int sweeps, bool from_zero) {
   const int n = L.nx * L.ny * L.nz;
   for (int sw = 0; sw < sweeps; ++sw) {
     for (int c = threadIdx.x; c < n; c += blockDim.x) {
-      const int x = c % L.nx, y = (c / L.nx) % L.ny, z = c / (L.nx * L.ny);
       const double D = S.diag[c];
       double v;
       if (from_zero && sw == 0) {
-        v = omega * S.B[c] / D;
+        v = kOmega * S.B[c] / D;
       } else {
+        const int x = c % L.nx, y = (c / L.nx) % L.ny, z = c / (L.nx * L.ny);
         const double e = S.E[c];
-        v = e + omega * (S.B[c] - D * e + offdiag_sum(L, S.tx, S.ty, S.tz, S.E, x, y, z, c)) / D;
+        v = e + kOmega * (S.B[c] - D * e + offdiag_sum(L.nx, L.ny, L.nz, S.tx, S.ty, S.tz, S.E, x, y, z, c)) / D;
       }
       S.T[c] = v;
     }
@@ -224,94 +282,88 @@ __device__ void lds_apply_smooth(const MgLevelDev& L, const LdsLevel& S, int swe
 }
 
 __global__ __launch_bounds__(1024) void k_mg_coarse_lds(MgCoarseArgs a, const double* __restrict__ bglob,
-                                              double* __restrict__ out, PcgState* st, int rz_slot) {
+                                              const double* __restrict__ binv, double* __restrict__ out,
+                                              PcgState* st, int rz_slot) {
   if (pcg_done(st)) return;
   extern __shared__ double smem[];
-  LdsLevel S[kMgMaxLevels];
-  // carve LDS and load faces / diagonal of every coarse level
-  {
-    double* p = smem;
-    for (int l = 0; l < a.nlev; ++l) {
-      const MgLevelDev& L = a.lev[l];
-      const int n = L.nx * L.ny * L.nz;
-      const int nfx = (L.nx + 1) * L.ny * L.nz, nfy = L.nx * (L.ny + 1) * L.nz;
-      const int nfz = L.nz > 1 ? L.nx * L.ny * (L.nz + 1) : 0;  // 2D: z faces never read
-      S[l].tx = p; p += nfx;
-      S[l].ty = p; p += nfy;
-      S[l].tz = p; p += nfz;
-      S[l].diag = p; p += n;
-      S[l].B = p; p += n;
-      S[l].E = p; p += n;
-      S[l].T = p; p += n;
-      for (int j = threadIdx.x; j < nfx; j += blockDim.x) S[l].tx[j] = L.tx[j];
-      for (int j = threadIdx.x; j < nfy; j += blockDim.x) S[l].ty[j] = L.ty[j];
-      for (int j = threadIdx.x; j < nfz; j += blockDim.x) S[l].tz[j] = L.tz[j];
-      for (int j = threadIdx.x; j < n; j += blockDim.x) S[l].diag[j] = L.diag[j];
-    }
+  const int nl = a.nlev;          // levels in LDS, the last one is the bottom
+  // load faces / diagonals of the smoothed levels, the bottom inverse, the rhs
+  for (int l = 0; l + 1 < nl; ++l) {
+    const MgLevelDev& L = a.lev[l];
+    LdsLevel S;
+    lds_level(a, smem, l, S);
+    const int n = L.nx * L.ny * L.nz;
+    const int nfx = (L.nx + 1) * L.ny * L.nz, nfy = L.nx * (L.ny + 1) * L.nz;
+    const int nfz = L.nz > 1 ? L.nx * L.ny * (L.nz + 1) : 0;  // 2D: z faces never read
+    for (int j = threadIdx.x; j < nfx; j += blockDim.x) S.tx[j] = L.tx[j];
+    for (int j = threadIdx.x; j < nfy; j += blockDim.x) S.ty[j] = L.ty[j];
+    for (int j = threadIdx.x; j < nfz; j += blockDim.x) S.tz[j] = L.tz[j];
+    for (int j = threadIdx.x; j < n; j += blockDim.x) S.diag[j] = L.diag[j];
   }
-  double* X = smem + a.lds_words;            // accumulated solution on the first coarse level
-  double* R0 = X + a.n0;                      // original right-hand side
-  const MgLevelDev& L0 = a.lev[0];
+  const MgLevelDev& Lb = a.lev[nl - 1];
+  const int nb = Lb.nx * Lb.ny * Lb.nz;
+  double* Binv = smem + a.inv_off;
+  for (int j = threadIdx.x; j < nb * nb; j += blockDim.x) Binv[j] = binv[j];
+  LdsLevel S0;
+  lds_level(a, smem, 0, S0);
   const int n0 = a.n0;
-  for (int j = threadIdx.x; j < n0; j += blockDim.x) {
-    R0[j] = bglob[j];
-    X[j] = 0.0;
-  }
+  for (int j = threadIdx.x; j < n0; j += blockDim.x) S0.B[j] = bglob[j];
   __syncthreads();
-  for (int cyc = 0; cyc < a.ninner; ++cyc) {
-    // B_0 = R0 - A X
-    for (int c = threadIdx.x; c < n0; c += blockDim.x) {
-      const int x = c % L0.nx, y = (c / L0.nx) % L0.ny, z = c / (L0.nx * L0.ny);
-      S[0].B[c] = R0[c] - S[0].diag[c] * X[c] + offdiag_sum(L0, S[0].tx, S[0].ty, S[0].tz, X, x, y, z, c);
+  // down
+  for (int l = 0; l + 1 < nl; ++l) {
+    const MgLevelDev& F = a.lev[l];
+    const MgLevelDev& C = a.lev[l + 1];
+    LdsLevel S, SC;
+    lds_level(a, smem, l, S);
+    lds_level(a, smem, l + 1, SC);
+    lds_smooth(F, S, a.nu, true);
+    const int nc = C.nx * C.ny * C.nz;
+    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+      const int X0 = c % C.nx, Y0 = (c / C.nx) % C.ny, Z0 = c / (C.nx * C.ny);
+      const int x1 = min(2 * X0 + 1, F.nx - 1), y1 = min(2 * Y0 + 1, F.ny - 1);
+      const int z0 = F.nz > 1 ? 2 * Z0 : 0, z1 = F.nz > 1 ? min(2 * Z0 + 1, F.nz - 1) : 0;
+      double acc = 0.0;
+      for (int z = z0; z <= z1; ++z)
+        for (int y = 2 * Y0; y <= y1; ++y)
+          for (int x = 2 * X0; x <= x1; ++x) {
+            const int i = x + F.nx * (y + F.ny * z);
+            acc += S.B[i] - S.diag[i] * S.E[i] + offdiag_sum(F.nx, F.ny, F.nz, S.tx, S.ty, S.tz, S.E, x, y, z, i);
+          }
+      SC.B[c] = acc;
     }
     __syncthreads();
-    // down
-    for (int l = 0; l + 1 < a.nlev; ++l) {
-      const MgLevelDev& F = a.lev[l];
-      const MgLevelDev& C = a.lev[l + 1];
-      lds_apply_smooth(F, S[l], a.nu, true, kOmega);
-      const int nc = C.nx * C.ny * C.nz;
-      for (int c = threadIdx.x; c < nc; c += blockDim.x) {
-        const int X0 = c % C.nx, Y0 = (c / C.nx) % C.ny, Z0 = c / (C.nx * C.ny);
-        const int x1 = min(2 * X0 + 1, F.nx - 1), y1 = min(2 * Y0 + 1, F.ny - 1);
-        const int z0 = F.nz > 1 ? 2 * Z0 : 0, z1 = F.nz > 1 ? min(2 * Z0 + 1, F.nz - 1) : 0;
-        double acc = 0.0;
-        for (int z = z0; z <= z1; ++z)
-          for (int y = 2 * Y0; y <= y1; ++y)
-            for (int x = 2 * X0; x <= x1; ++x) {
-              const int i = x + F.nx * (y + F.ny * z);
-              acc += S[l].B[i] - S[l].diag[i] * S[l].E[i] +
-                     offdiag_sum(F, S[l].tx, S[l].ty, S[l].tz, S[l].E, x, y, z, i);
-            }
-        S[l + 1].B[c] = acc;
-      }
-      __syncthreads();
+  }
+  // bottom: E = inverse * B
+  {
+    LdsLevel S;
+    lds_level(a, smem, nl - 1, S);
+    for (int r = threadIdx.x; r < nb; r += blockDim.x) {
+      double acc = 0.0;
+      for (int j = 0; j < nb; ++j) acc += Binv[r * nb + j] * S.B[j];
+      S.E[r] = acc;
     }
-    // coarsest level: a single cell, solved exactly (undamped Jacobi)
-    {
-      const int l = a.nlev - 1;
-      lds_apply_smooth(a.lev[l], S[l], a.nu_bottom, true, 1.0);
-    }
-    // up
-    for (int l = a.nlev - 2; l >= 0; --l) {
-      const MgLevelDev& F = a.lev[l];
-      const MgLevelDev& C = a.lev[l + 1];
-      const int n = F.nx * F.ny * F.nz;
-      const int cz = F.nz > 1 ? 1 : 0;
-      for (int c = threadIdx.x; c < n; c += blockDim.x) {
-        const int x = c % F.nx, y = (c / F.nx) % F.ny, z = c / (F.nx * F.ny);
-        S[l].E[c] += a.omega_c * S[l + 1].E[(x >> 1) + C.nx * ((y >> 1) + C.ny * (z >> cz))];
-      }
-      __syncthreads();
-      lds_apply_smooth(F, S[l], a.nu, false, kOmega);
-    }
-    for (int c = threadIdx.x; c < n0; c += blockDim.x) X[c] += S[0].E[c];
     __syncthreads();
+  }
+  // up
+  for (int l = nl - 2; l >= 0; --l) {
+    const MgLevelDev& F = a.lev[l];
+    const MgLevelDev& C = a.lev[l + 1];
+    LdsLevel S, SC;
+    lds_level(a, smem, l, S);
+    lds_level(a, smem, l + 1, SC);
+    const int n = F.nx * F.ny * F.nz;
+    const int cz = F.nz > 1 ? 1 : 0;
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+      const int x = c % F.nx, y = (c / F.nx) % F.ny, z = c / (F.nx * F.ny);
+      S.E[c] += a.omega_c * SC.E[(x >> 1) + C.nx * ((y >> 1) + C.ny * (z >> cz))];
+    }
+    __syncthreads();
+    lds_smooth(F, S, a.nu, false);
   }
   double part = 0.0;
   for (int c = threadIdx.x; c < n0; c += blockDim.x) {
-    out[c] = X[c];
-    part += R0[c] * X[c];
+    out[c] = S0.E[c];
+    part += bglob[c] * S0.E[c];
   }
   if (rz_slot < 0) return;
   for (int off = 32; off > 0; off >>= 1) part += __shfl_down(part, off, 64);
@@ -328,23 +380,23 @@ __global__ __launch_bounds__(1024) void k_mg_coarse_lds(MgCoarseArgs a, const do
 }  // namespace
 
 hipError_t mg_setup(const MgHierarchy& h, hipStream_t s) {
-  for (int l = 1; l < h.nlev; ++l) {
+  for (int l = 1; l <= h.lb; ++l) {
     const MgLevelDev& F = h.lev[l - 1];
     const MgLevelDev& C = h.lev[l];
     const dim3 grid((C.nx + kBX - 1) / kBX, (C.ny + kBY - 1) / kBY, C.nz);
     hipLaunchKernelGGL(k_mg_coarsen, grid, cell_block(), 0, s, F, C);
   }
+  hipLaunchKernelGGL(k_mg_bottom_inverse, dim3(1), dim3(256), 0, s, h.lev[h.lb], h.binv);
   return hipGetLastError();
 }
 
-// z = M^{-1} r for the finest level (r = lev[0].b); with rz_slot >= 0 also
-// accumulates r . z into the CG ring.
+// z = M^{-1} r on the finest level; with rz_slot >= 0 also accumulates r . z
+// into the CG ring.
 hipError_t mg_apply(const MgHierarchy& h, const double* r, double* z, PcgState* st, int rz_slot, hipStream_t s) {
   const int lc = h.lc;
   auto grid_of = [](const MgLevelDev& L) {
     return dim3((L.nx + kBX - 1) / kBX, (L.ny + kBY - 1) / kBY, L.nz);
   };
-  // down the fine levels
   for (int l = 0; l < lc; ++l) {
     const MgLevelDev& F = h.lev[l];
     const MgLevelDev& C = h.lev[l + 1];
@@ -352,14 +404,12 @@ hipError_t mg_apply(const MgHierarchy& h, const double* r, double* z, PcgState* 
     hipLaunchKernelGGL(k_mg_smooth_down, grid_of(F), cell_block(), 0, s, F, b, F.x, st);
     hipLaunchKernelGGL(k_mg_restrict, grid_of(C), cell_block(), 0, s, F, C, b, F.x, C.b, st);
   }
-  // coarse levels in LDS
   {
     const double* b = lc == 0 ? r : h.lev[lc].b;
     double* out = lc == 0 ? z : h.lev[lc].x;
-    hipLaunchKernelGGL(k_mg_coarse_lds, dim3(1), dim3(h.coarse_threads), h.lds_bytes, s, h.coarse, b, out,
-                       st, lc == 0 ? rz_slot : -1);
+    hipLaunchKernelGGL(k_mg_coarse_lds, dim3(1), dim3(h.coarse_threads), h.lds_bytes, s, h.coarse, b, h.binv,
+                       out, st, lc == 0 ? rz_slot : -1);
   }
-  // up the fine levels
   for (int l = lc - 1; l >= 0; --l) {
     const MgLevelDev& F = h.lev[l];
     const MgLevelDev& C = h.lev[l + 1];

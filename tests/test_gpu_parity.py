@@ -338,6 +338,68 @@ def test_coupled_512_one_step_full_size(torch_mod):
     assert err <= TOL and inc <= TOL
 
 
+# ------------------------------------------------------- mixed precision
+
+MIXED_TOL = 1e-5
+
+
+def test_mixed_phi1_apply_matches_dense_oracle(torch_mod):
+    """FP32 stencil / vectors / accumulation, FP64 divided differences, norms
+    and update: within 1e-5 of the FP64 oracle."""
+    torch = torch_mod
+    from paper_1209_5553_amd.api import make_opts
+    prob = inputs.linear_problem(32)
+    disc = oerem.Discretisation(prob, prob.T0)
+    ctx = _ctx(prob)
+    ctx.set_face_fluxes(*_oracle_fluxes_to_dev(torch, disc))
+    ctx.form_jacobian(_dev(torch, prob.T0))
+    G = disc.model.G(prob.T0)
+    out, st = ctx.phi1_apply(prob.h, _dev(torch, G), opts=make_opts(precision=1, tol_r=1e-7))
+    ref = ophi.phi1_action_dense(disc.model.J(prob.T0), G, prob.h)
+    err = rel_inf(out.cpu().numpy(), ref)
+    _say(f"mixed phi1 m={st['m_total']} s={st['substeps']} err={err:.2e}")
+    assert err <= MIXED_TOL
+
+
+def test_mixed_steps_layered_3d_vs_oracle_and_fp64(torch_mod):
+    torch = torch_mod
+    from paper_1209_5553_amd.api import make_opts
+    prob = inputs.layered3d_problem(12, seed=4, nsteps=3)
+    T64, _ = _run_gpu_linear(torch, prob, 3)
+    T32, _ = _run_gpu_linear(torch, prob, 3, opts=make_opts(precision=1, tol_r=1e-7))
+    T_ref, _ = oerem.run_linear(prob, nsteps=3, layered=True)
+    e32 = rel_inf(T32, T_ref)
+    _say(f"mixed 3D err vs oracle {e32:.2e}, fp64 err {rel_inf(T64, T_ref):.2e}")
+    assert rel_inf(T64, T_ref) <= TOL
+    assert e32 <= MIXED_TOL
+    assert rel_inf(T32 - prob.T0, T_ref - prob.T0) <= MIXED_TOL
+
+
+def test_mixed_vs_fp64_full_size_layered_128(torch_mod):
+    """The 128^3 layered workload, 10 steps: mixed precision against the FP64
+    GPU path on the same inputs (the FP64 path is itself checked against the
+    oracle on smaller grids and by linear exactness)."""
+    torch = torch_mod
+    from paper_1209_5553_amd.api import make_opts
+    prob = inputs.layered3d_problem(128)
+    _say("layered 128^3 x 10, FP64 and mixed")
+    T64, s64 = _run_gpu_linear(torch, prob, prob.nsteps)
+    T32, s32 = _run_gpu_linear(torch, prob, prob.nsteps, opts=make_opts(precision=1, tol_r=1e-7))
+    err = rel_inf(T32, T64)
+    inc = rel_inf(T32 - prob.T0, T64 - prob.T0)
+    _say(f"  m64={s64[-1]['m_total']} m32={s32[-1]['m_total']} err={err:.2e} inc={inc:.2e}")
+    assert err <= MIXED_TOL and inc <= MIXED_TOL
+
+
+def test_linear_exactness_full_size_layered_128(torch_mod):
+    """Property at full size: ten steps of h equal one step of 10 h."""
+    torch = torch_mod
+    prob = inputs.layered3d_problem(128)
+    T10, _ = _run_gpu_linear(torch, prob, 10)
+    T1, _ = _run_gpu_linear(torch, prob, 1, h=10 * prob.h)
+    assert rel_inf(T10 - prob.T0, T1 - prob.T0) <= TOL
+
+
 # ------------------------------------------------------------ error paths
 
 def test_error_paths_leave_T_unchanged(torch_mod):
