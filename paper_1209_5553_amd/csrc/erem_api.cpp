@@ -19,6 +19,7 @@
 
 #include "device.h"
 #include "host_numerics.h"
+#include "krylov.h"
 #include "leja.h"
 #include "mg.h"
 
@@ -50,6 +51,10 @@ struct erem_ctx {
   // FP32 copies for the mixed-precision Leja passes (allocated on first use)
   float *coef32 = nullptr, *qa32 = nullptr, *qb32 = nullptr, *p32 = nullptr;
   bool coef32_valid = false;
+  // Krylov basis (m+1 vectors), work vector, Hessenberg matrix, norm, coefficients
+  double *kV = nullptr, *kw = nullptr, *kH = nullptr, *kbeta = nullptr, *kc = nullptr;
+  int kry_m = 0;
+  std::vector<double> hH;
   size_t nfx = 0, nfy = 0, nfz = 0;
 
   // device control blocks
@@ -152,6 +157,9 @@ void free_all(erem_ctx* c) {
   if (c->h_pcg) (void)hipHostFree(c->h_pcg);
   float** fbufs[] = {&c->coef32, &c->qa32, &c->qb32, &c->p32};
   for (float** b : fbufs)
+    if (*b) { (void)hipFree(*b); *b = nullptr; }
+  double** kbufs[] = {&c->kV, &c->kw, &c->kH, &c->kbeta, &c->kc};
+  for (double** b : kbufs)
     if (*b) { (void)hipFree(*b); *b = nullptr; }
   c->cf = nullptr; c->states = nullptr; c->red = nullptr; c->pcg = nullptr;
   c->h_cf = nullptr; c->h_states = nullptr; c->h_red = nullptr; c->h_pcg = nullptr;
@@ -425,6 +433,124 @@ int leja_hphi1(erem_ctx* c, double h, const double* v, double scal, int s, int K
   return EREM_OK;
 }
 
+// u <- h phi1(h J) v by the Krylov projection of Sec. 4.1 (Eq. approphi):
+// on each substep the Arnoldi basis V_{m+1}, H of w = v + J u is built on the
+// device (Alg. alg:al2), and on the host y = phi1(delta Hbar) e_1 with
+// Hbar = [[H_m, 0], [h_{m+1,m} e_m^T, 0]] is read off
+// exp([[delta Hbar, e_1], [0, 0]]).  The a-posteriori estimate is the size of
+// the last basis vector's contribution, delta beta |y_{m+1}| (scaled norm of
+// Sec. 4.2); while 10^p times it is not below 1 the substep is halved, reusing
+// the same basis.  Then u += delta beta V_{m+1} y.
+int krylov_hphi1(erem_ctx* c, double h, const double* v, double scal, const erem_opts* o, erem_stats* stats) {
+  const int m = o->krylov_m;
+  if (m < 1 || m > kMaxKrylov) return fail(c, EREM_EINVAL, "krylov_m must be in [1, 64]");
+  const size_t N = c->d.N;
+  if (c->kry_m < m) {
+    double** kbufs[] = {&c->kV, &c->kw, &c->kH, &c->kbeta, &c->kc};
+    for (double** b : kbufs)
+      if (*b) { (void)hipFree(*b); *b = nullptr; }
+    int rc = EREM_OK;
+    rc |= dev_alloc(c, &c->kV, N * (m + 1));
+    rc |= dev_alloc(c, &c->kw, N);
+    rc |= dev_alloc(c, &c->kH, static_cast<size_t>(m + 1) * m);
+    rc |= dev_alloc(c, &c->kbeta, 1);
+    rc |= dev_alloc(c, &c->kc, m + 1);
+    if (rc) return EREM_ENOMEM;
+    c->kry_m = m;
+  }
+  const Dims& d = c->d;
+  const double thresh = std::pow(10.0, -o->p_order);
+  const double rootN = std::sqrt(static_cast<double>(N));
+  const int max_halvings = 60;
+  c->hH.assign(static_cast<size_t>(m + 1) * m + 1, 0.0);
+  double t = 0.0, delta = h;
+  int nsub = 0, msum = 0;
+  double last_est = 0.0;
+  bool first = true;
+  while (t < h) {
+    if (nsub >= o->max_substeps)
+      return fail(c, EREM_ENOCONV, "Krylov phi1 needs more than max_substeps substeps");
+    // w = v + J u (u = 0 on the first substep) into V[0]
+    if (first) HIP_TRY(c, hipMemcpyAsync(c->kV, v, N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    else HIP_TRY(c, launch_stencil_axpy(d, c->coef, v, c->u, c->kV, c->stream));
+    HIP_TRY(c, arnoldi_mgs(d, c->coef, c->kV, c->kw, c->kH, c->kbeta, c->part, m, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->hH.data(), c->kH, sizeof(double) * (m + 1) * m, hipMemcpyDeviceToHost, c->stream));
+    double beta = 0.0;
+    HIP_TRY(c, hipMemcpyAsync(&beta, c->kbeta, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (!std::isfinite(beta)) return fail(c, EREM_ENONFINITE, "non-finite Krylov vector norm");
+    const std::vector<double>& H = c->hH;
+    if (beta == 0.0) {
+      // w = 0: u is a steady state of u' = J u + v, nothing changes any more
+      if (first) HIP_TRY(c, launch_axpby(d, c->u, 0.0, v, 0.0, c->stream));
+      break;
+    }
+    // Happy breakdown: the first column j whose subdiagonal h_{j+1,j} is
+    // negligible against the entries so far gives an exact invariant
+    // subspace; columns after it (built from a zero or noise vector) are
+    // never read.
+    double hnorm = 0.0;
+    int me = m;
+    bool exact = false;
+    for (int j = 0; j < m; ++j) {
+      for (int i = 0; i <= j; ++i) {
+        const double e = H[i * m + j];
+        if (!std::isfinite(e)) return fail(c, EREM_ENONFINITE, "non-finite Hessenberg entry");
+        hnorm = std::max(hnorm, std::fabs(e));
+      }
+      const double hj = H[(j + 1) * m + j];
+      if (!std::isfinite(hj)) return fail(c, EREM_ENONFINITE, "non-finite Hessenberg entry");
+      if (hj <= 1e-14 * hnorm) {
+        me = j + 1;
+        exact = true;
+        break;
+      }
+      hnorm = std::max(hnorm, hj);
+    }
+    const int n = exact ? me : me + 1;  // dimension of Hbar
+    std::vector<double> A((n + 1) * (n + 1)), E((n + 1) * (n + 1)), y(n);
+    double dl = std::min(delta, h - t);
+    bool ok = false;
+    double est = 0.0;
+    for (int tries = 0; tries < max_halvings; ++tries) {
+      std::fill(A.begin(), A.end(), 0.0);
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < std::min(me, n); ++j)
+          if (i <= j + 1 && i < m + 1 && j < m) A[i * (n + 1) + j] = dl * H[i * m + j];
+      A[0 * (n + 1) + n] = 1.0;  // augmented column e_1
+      dense_expm(n + 1, A.data(), E.data());
+      for (int i = 0; i < n; ++i) y[i] = E[i * (n + 1) + n];
+      est = exact ? 0.0 : dl * beta * std::fabs(y[n - 1]) / (rootN * scal);
+      if (!std::isfinite(est)) return fail(c, EREM_ENONFINITE, "non-finite Krylov estimate");
+      if (est < thresh) {  // 10^p * estimate < 1
+        ok = true;
+        break;
+      }
+      dl *= 0.5;
+    }
+    if (!ok) return fail(c, EREM_ENOCONV, "Krylov substep could not meet the tolerance");
+    std::vector<double> coeffs(n);
+    for (int i = 0; i < n; ++i) coeffs[i] = dl * beta * y[i];
+    HIP_TRY(c, hipMemcpyAsync(c->kc, coeffs.data(), sizeof(double) * n, hipMemcpyHostToDevice, c->stream));
+    HIP_TRY(c, krylov_combine(d, c->kV, n, c->kc, c->u, first ? 1 : 0, c->stream));
+    // the coefficient upload reuses a host vector: wait before it goes out of scope
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    t += dl;
+    delta = dl;
+    first = false;
+    ++nsub;
+    msum += me;
+    last_est = est;
+  }
+  if (stats) {
+    stats->m_total = msum;
+    stats->substeps = nsub;
+    stats->est_err = last_est;
+    stats->restarts = 0;
+  }
+  return EREM_OK;
+}
+
 // Full phi1 evaluation with the substep / restart policy.  On success c->u
 // holds h phi1(h J) v.
 int hphi1_eval(erem_ctx* c, double h, const double* v, double scal, const erem_opts* o, erem_stats* stats) {
@@ -441,6 +567,7 @@ int hphi1_eval(erem_ctx* c, double h, const double* v, double scal, const erem_o
     if (stats) { stats->m_total = 0; stats->substeps = 1; stats->est_err = 0.0; }
     return EREM_OK;
   }
+  if (o->method == EREM_METHOD_KRYLOV) return krylov_hphi1(c, h, v, scal, o, stats);
   int s = 1;
   if (o->rho_max > 0.0) s = std::max(1, static_cast<int>(std::ceil(h * width / o->rho_max)));
   if (s > o->max_substeps) s = o->max_substeps;
@@ -803,8 +930,8 @@ int erem_phi1_apply(erem_ctx* c, double h, const double* d_v, double* d_out, con
   if (!d_v || !d_out || d_v == d_out) return fail(c, EREM_EINVAL, "v and out must be distinct non-NULL");
   if (!c->jac_set) return fail(c, EREM_EINVAL, "erem_form_jacobian must come first");
   if (!(h > 0) || !std::isfinite(h)) return fail(c, EREM_EINVAL, "h must be > 0");
-  if (o->method != EREM_METHOD_LEJA)
-    return fail(c, EREM_EINVAL, "only the Leja method is available");
+  if (o->method == EREM_METHOD_KRYLOV && o->precision != EREM_PREC_FP64)
+    return fail(c, EREM_EINVAL, "the Krylov method runs in FP64 only");
   // max |v| (the Gershgorin interval of the last assembly is kept)
   HIP_TRY(c, launch_absmax(c->d, d_v, c->red, c->stream));
   rc = read_reduce(c);
@@ -843,8 +970,8 @@ int step_checks(erem_ctx* c, double h, double* d_T, const erem_opts* o) {
   if (rc) return rc;
   if (!d_T) return fail(c, EREM_EINVAL, "T is NULL");
   if (!(h > 0) || !std::isfinite(h)) return fail(c, EREM_EINVAL, "h must be > 0");
-  if (o->method != EREM_METHOD_LEJA)
-    return fail(c, EREM_EINVAL, "only the Leja method is available");
+  if (o->method == EREM_METHOD_KRYLOV && o->precision != EREM_PREC_FP64)
+    return fail(c, EREM_EINVAL, "the Krylov method runs in FP64 only");
   return EREM_OK;
 }
 

@@ -1,0 +1,18 @@
+// Device Arnoldi process for the Krylov evaluation of phi1 (krylov.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "device.h"
+
+namespace erem {
+
+constexpr int kMaxKrylov = 64;
+
+int kry_num_blocks(const Dims& d);
+hipError_t arnoldi_mgs(const Dims& d, const double* coef, double* V, double* w, double* H,
+                       double* beta, double* part, int m, hipStream_t s);
+hipError_t krylov_combine(const Dims& d, const double* V, int nvec, const double* c, double* u,
+                          int first, hipStream_t s);
+
+}  // namespace erem

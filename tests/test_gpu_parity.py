@@ -338,6 +338,71 @@ def test_coupled_512_one_step_full_size(torch_mod):
     assert err <= TOL and inc <= TOL
 
 
+# ---------------------------------------------------------------- Krylov
+
+def _krylov_opts(m=10, **kw):
+    from paper_1209_5553_amd.api import make_opts
+    return make_opts(method=1, krylov_m=m, max_substeps=4096, **kw)
+
+
+def test_krylov_phi1_apply_matches_dense_oracle(torch_mod):
+    """Arnoldi (Alg. alg:al2) + phi1 of the augmented Hessenberg matrix
+    (Eq. approphi), m = 10 as in the paper, against the oracle."""
+    torch = torch_mod
+    prob = inputs.linear_problem(32)
+    disc = oerem.Discretisation(prob, prob.T0)
+    ctx = _ctx(prob)
+    ctx.set_face_fluxes(*_oracle_fluxes_to_dev(torch, disc))
+    ctx.form_jacobian(_dev(torch, prob.T0))
+    J = disc.model.J(prob.T0)
+    v = np.random.default_rng(9).standard_normal(prob.n)
+    for m in (10, 30):
+        out, st = ctx.phi1_apply(prob.h, _dev(torch, v), opts=_krylov_opts(m))
+        err = rel_inf(out.cpu().numpy(), ophi.phi1_action_dense(J, v, prob.h))
+        _say(f"krylov m={m}: arnoldi steps={st['m_total']} substeps={st['substeps']} err={err:.2e}")
+        assert err <= TOL
+
+
+def test_krylov_full_dimension_is_exact(torch_mod):
+    """With m = N the Krylov space is the whole space (happy breakdown): one
+    substep reproduces phi1(hJ) v exactly (to rounding)."""
+    torch = torch_mod
+    prob = inputs.linear_problem(3, seed=2)
+    disc = oerem.Discretisation(prob, prob.T0)
+    ctx = _ctx(prob)
+    ctx.set_face_fluxes(*_oracle_fluxes_to_dev(torch, disc))
+    ctx.form_jacobian(_dev(torch, prob.T0))
+    v = np.linspace(1.0, 3.0, prob.n)
+    out, st = ctx.phi1_apply(prob.h, _dev(torch, v), opts=_krylov_opts(prob.n))
+    ref = ophi.phi1_action_dense(disc.model.J(prob.T0), v, prob.h)
+    _say(f"krylov m=N: {st}")
+    assert st["substeps"] == 1
+    assert rel_inf(out.cpu().numpy(), ref) <= 1e-12
+
+
+def test_krylov_erem_32x32_ten_steps(torch_mod):
+    torch = torch_mod
+    prob = inputs.linear_problem(32)
+    T_gpu, stats = _run_gpu_linear(torch, prob, prob.nsteps, opts=_krylov_opts(10))
+    T_ref, _ = oerem.run_linear(prob)
+    err = rel_inf(T_gpu - prob.T0, T_ref - prob.T0)
+    _say(f"krylov EREM 10 steps: inc err {err:.2e}, last {stats[-1]}")
+    assert err <= TOL
+
+
+def test_krylov_and_leja_agree_on_coupled_step(torch_mod):
+    torch = torch_mod
+    prob = inputs.coupled_problem(64, seed=4)
+    res = []
+    for opts in (None, _krylov_opts(10)):
+        ctx = _ctx(prob)
+        T = _dev(torch, prob.T0)
+        ctx.pressure_and_fluxes(T, rtol=1e-16)
+        ctx.step(prob.h, T, opts)
+        res.append(T.cpu().numpy())
+    assert rel_inf(res[1] - prob.T0, res[0] - prob.T0) <= TOL
+
+
 # ------------------------------------------------------- mixed precision
 
 MIXED_TOL = 1e-5
