@@ -194,6 +194,61 @@ int erem_step(erem_ctx* ctx, double h, double* d_T, const erem_opts* opts, erem_
 int erem_step_frozen(erem_ctx* ctx, double h, double* d_T, const erem_opts* opts,
                      erem_stats* stats);
 
+/* ---- batched form: many independent linear problems, one persistent launch ----
+ *
+ * Each problem is a 2D grid with fixed face fluxes and constant heat capacity
+ * (constant fluid law), so G_p(T) = J_p T + g_p with constant J_p and the EREM
+ * step (Eq. EERM) uses a fixed Gershgorin interval, substep count and set of
+ * divided differences per problem (Sec. 4.2).  erem_batch_run advances all
+ * problems by nsteps steps in ONE kernel launch: one workgroup owns one problem
+ * for all its steps, substeps and Newton terms and applies its own stop test,
+ * largest problems first; the launch can be captured once in a hipGraph and
+ * replayed.  Temperatures are packed: problem i owns cells
+ * [off_i, off_i + nx_i ny_i) of the caller's array (erem_batch_offsets). */
+typedef struct erem_batch erem_batch;
+
+typedef struct {
+    int64_t terms_total;   /* Newton-Leja terms summed over problems and steps */
+    int32_t terms_min, terms_max;  /* per problem, over the run */
+    int32_t failed;        /* problems that stopped on an error (see flags) */
+    int32_t tile_shape;    /* workgroup per problem: 0: 256 threads x 4 cells loaded ahead,
+                              1: 256 x 8, 2: 512 x 4, 3: 1024 x 2 */
+    int32_t graph;         /* 1 if the launch was replayed from a hipGraph */
+    int32_t grid;          /* workgroups of the launch (one per problem) */
+    double ms;             /* device time of the launch (HIP events) */
+    double leja_bytes;     /* algorithmic bytes of the Newton terms: sum over
+                              problems of terms x cells x (72 B FP64, 36 B FP32) */
+} erem_batch_stats;
+
+/* nprob 2D grids (dim 2, nz 1).  Errors: EINVAL, ENOMEM, EDEVICE. */
+int erem_batch_create(int32_t nprob, const erem_grid* grids, void* stream, erem_batch** out);
+int erem_batch_destroy(erem_batch* b);
+const char* erem_batch_last_error(const erem_batch* b);
+/* Host array of nprob + 1 cell offsets of the packed layout. */
+int erem_batch_offsets(const erem_batch* b, int64_t* out);
+/* Problem i: rock, constant fluid law, boundary conditions as for the
+ * single-problem context; computes the steady pressure, the face fluxes, the
+ * Jacobian stencil and g at d_T0 (device, N_i values). */
+int erem_batch_set_problem(erem_batch* b, int32_t i, const double* d_logk, const double* d_poro,
+                           double lambda, double rhoc_s, double c_f, double mu0, double rho0,
+                           double p_left, double p_right, double T_left, double T_right,
+                           const double* d_T0);
+/* Fix the step h and the options for every problem: Gershgorin interval,
+ * substeps s = ceil(h (beta - alpha) / rho_max), divided differences up to
+ * m_max; opts->precision selects FP64 or FP32 Newton passes. */
+int erem_batch_prepare(erem_batch* b, double h, const erem_opts* opts);
+/* Time every workgroup size on a copy of d_T (nsteps steps) and keep the fastest;
+ * *chosen receives its index.  d_T is not modified. */
+int erem_batch_autotune(erem_batch* b, const double* d_T, int32_t nsteps, int32_t* chosen);
+/* Select a workgroup shape by index (0 .. 3, see erem_batch_stats.tile_shape)
+ * instead of timing them.  EINVAL for another index. */
+int erem_batch_set_tile_shape(erem_batch* b, int32_t shape);
+/* Advance the packed temperatures d_T by nsteps EREM steps in one launch;
+ * use_graph != 0 captures the launch in a hipGraph on first use (per nsteps)
+ * and replays it.  ENOCONV / ENONFINITE if a problem failed (the others are
+ * still advanced). */
+int erem_batch_run(erem_batch* b, double* d_T, int32_t nsteps, int32_t use_graph, erem_batch_stats* st);
+
 /* ---- measurement support ---- */
 
 /* Accumulated device time of the hot kernels while profiling is on,

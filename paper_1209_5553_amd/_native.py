@@ -53,6 +53,15 @@ class KernelTimes(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class BatchStats(ctypes.Structure):
+    _fields_ = [("terms_total", c_int64), ("terms_min", c_int32), ("terms_max", c_int32),
+                ("failed", c_int32), ("tile_shape", c_int32), ("graph", c_int32),
+                ("grid", c_int32), ("ms", c_double), ("leja_bytes", c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 _P = c_void_p           # device pointer / opaque handle
 _PD = POINTER(c_double)  # host double array
 
@@ -76,6 +85,16 @@ SIGNATURES = {
     "erem_phi1_apply": (c_int32, [_P, c_double, _P, _P, POINTER(Opts), POINTER(Stats)]),
     "erem_step": (c_int32, [_P, c_double, _P, POINTER(Opts), POINTER(Stats)]),
     "erem_step_frozen": (c_int32, [_P, c_double, _P, POINTER(Opts), POINTER(Stats)]),
+    "erem_batch_create": (c_int32, [c_int32, POINTER(Grid), _P, POINTER(_P)]),
+    "erem_batch_destroy": (c_int32, [_P]),
+    "erem_batch_last_error": (c_char_p, [_P]),
+    "erem_batch_offsets": (c_int32, [_P, POINTER(c_int64)]),
+    "erem_batch_set_problem": (c_int32, [_P, c_int32, _P, _P, c_double, c_double, c_double, c_double,
+                                         c_double, c_double, c_double, c_double, c_double, _P]),
+    "erem_batch_prepare": (c_int32, [_P, c_double, POINTER(Opts)]),
+    "erem_batch_autotune": (c_int32, [_P, _P, c_int32, POINTER(c_int32)]),
+    "erem_batch_run": (c_int32, [_P, _P, c_int32, c_int32, POINTER(BatchStats)]),
+    "erem_batch_set_tile_shape": (c_int32, [_P, c_int32]),
     "erem_profile": (c_int32, [_P, c_int32]),
     "erem_profile_read": (c_int32, [_P, POINTER(KernelTimes)]),
     "erem_leja_points": (c_int32, [c_int32, _PD]),

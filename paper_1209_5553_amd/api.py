@@ -219,3 +219,101 @@ class EremContext:
         """Transmissibilities at T, steady pressure and face fluxes."""
         self.assemble_transmissibilities(T)
         return self.solve_pressure(rtol=rtol, max_iter=max_iter, p=p, warm=warm)
+
+
+class EremBatch:
+    """Many independent linear problems advanced in one persistent launch
+    (see the erem_batch_* functions of include/erem.h).
+
+    ``problems`` are paper_1209_5553_amd.inputs.Problem records with a
+    constant fluid law.  Temperatures are one packed FP64 tensor; use
+    :meth:`pack` / :meth:`unpack` to convert from / to per-problem arrays.
+    The batch owns a non-default HIP stream so that its launch can be
+    captured in a hipGraph.
+    """
+
+    def __init__(self, problems, device=None):
+        self.lib = nat.load()
+        if not torch.cuda.is_available():
+            raise RuntimeError("EremBatch needs a HIP device")
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None
+                                   else torch.device(device).index or 0)
+        self.problems = list(problems)
+        n = len(self.problems)
+        grids = (nat.Grid * n)(*[nat.Grid(2, p.nx, p.ny, 1, p.dx, p.dy, p.dz) for p in self.problems])
+        self.stream = torch.cuda.Stream(device=self.device)
+        h = ctypes.c_void_p()
+        rc = self.lib.erem_batch_create(n, grids, ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h))
+        if rc != 0:
+            raise EremError(rc, "erem_batch_create")
+        self.handle = h
+        off = (ctypes.c_int64 * (n + 1))()
+        self._check(self.lib.erem_batch_offsets(self.handle, off), "erem_batch_offsets")
+        self.offsets = [int(v) for v in off]
+        self.ntot = self.offsets[-1]
+        keep = []
+        for i, p in enumerate(self.problems):
+            if p.law != nat.LAW_CONSTANT:
+                raise ValueError("the batched form needs a constant fluid law (linear problems)")
+            logk = torch.as_tensor(p.logk, dtype=torch.float64, device=self.device).contiguous()
+            poro = torch.as_tensor(p.poro, dtype=torch.float64, device=self.device).contiguous()
+            T0 = torch.as_tensor(p.T0, dtype=torch.float64, device=self.device).contiguous()
+            keep.append((logk, poro, T0))
+            self.stream.wait_stream(torch.cuda.current_stream(self.device))
+            self._check(self.lib.erem_batch_set_problem(
+                self.handle, i, ctypes.c_void_p(logk.data_ptr()), ctypes.c_void_p(poro.data_ptr()),
+                p.lam, p.rhoc_s, p.c_f, p.mu0, p.rho0, p.p_left, p.p_right, p.T_left, p.T_right,
+                ctypes.c_void_p(T0.data_ptr())), f"erem_batch_set_problem({i})")
+        del keep
+
+    def _check(self, rc, what):
+        if rc != 0:
+            msg = self.lib.erem_batch_last_error(self.handle)
+            raise EremError(rc, f"{what}: {msg.decode() if msg else ''}")
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.erem_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):  # pragma: no cover
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def pack(self, arrays):
+        flat = np.concatenate([np.asarray(a, dtype=np.float64).ravel() for a in arrays])
+        assert flat.size == self.ntot
+        return torch.as_tensor(flat, dtype=torch.float64, device=self.device).clone()
+
+    def unpack(self, T):
+        host = T.detach().cpu().numpy()
+        return [host[self.offsets[i]:self.offsets[i + 1]] for i in range(len(self.problems))]
+
+    def _ptr(self, T):
+        if T.dtype != torch.float64 or not T.is_contiguous() or T.device != self.device or T.numel() != self.ntot:
+            raise ValueError(f"T must be a contiguous float64 tensor of {self.ntot} values on {self.device}")
+        return ctypes.c_void_p(T.data_ptr())
+
+    def prepare(self, h: float, opts: nat.Opts | None = None):
+        o = opts if opts is not None else make_opts(m_max=128)
+        self._check(self.lib.erem_batch_prepare(self.handle, h, ctypes.byref(o)), "erem_batch_prepare")
+
+    def autotune(self, T, nsteps: int = 1) -> int:
+        ch = ctypes.c_int32(-1)
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        self._check(self.lib.erem_batch_autotune(self.handle, self._ptr(T), nsteps, ctypes.byref(ch)),
+                    "erem_batch_autotune")
+        return ch.value
+
+    def set_tile_shape(self, shape: int):
+        self._check(self.lib.erem_batch_set_tile_shape(self.handle, int(shape)), "erem_batch_set_tile_shape")
+
+    def run(self, T, nsteps: int, use_graph: bool = True):
+        st = nat.BatchStats()
+        self.stream.wait_stream(torch.cuda.current_stream(self.device))
+        self._check(self.lib.erem_batch_run(self.handle, self._ptr(T), nsteps, 1 if use_graph else 0,
+                                            ctypes.byref(st)), "erem_batch_run")
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
+        return st.as_dict()
