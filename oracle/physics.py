@@ -317,10 +317,12 @@ class HeatModel:
         return self.J_sparse(T).toarray()
 
     def J_sparse(self, T):
-        VC = self.g.volume * self.capacity(T)
+        C = self.capacity(T)
+        VC = self.g.volume * C
         R = self.A @ T + self.b
         dC = heat_capacity_dT(T, self.poro, self.law, self.c_f)
-        return (sp.diags(1.0 / VC) @ self.A + sp.diags(-R * dC / (VC * VC))).tocsr()
+        # d/dT_i of R_i / (V C(T_i)) through C:  -R_i C'(T_i) / (V C_i^2)
+        return (sp.diags(1.0 / VC) @ self.A + sp.diags(-R * dC / (VC * C))).tocsr()
 
 
 def gershgorin_interval(J):

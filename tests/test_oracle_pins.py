@@ -208,9 +208,12 @@ def test_solenoidal_flux_generator_is_divergence_free():
     assert np.abs(rowsum).max() <= 1e-12 * abs(A).max()   # and so beta <= 0 up to rounding
 
 
-def test_jacobian_matches_central_differences():
-    """J = D_T G (Eq. linear), including the temperature-dependent capacity."""
-    prob = inputs.coupled_problem(8, seed=2)
+@pytest.mark.parametrize("cell", [(1.0, 1.0, 1.0), (2.0, 0.5, 3.0)])
+def test_jacobian_matches_central_differences(cell):
+    """J = D_T G (Eq. linear), including the temperature-dependent capacity,
+    on unit and on non-unit cells (cell volume != 1)."""
+    import dataclasses
+    prob = dataclasses.replace(inputs.coupled_problem(8, seed=2), dx=cell[0], dy=cell[1], dz=cell[2])
     T = np.random.default_rng(5).uniform(20.0, 80.0, prob.n)
     d = erem.Discretisation(prob, T)
     J = d.model.J(T)
