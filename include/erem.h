@@ -194,6 +194,48 @@ int erem_step(erem_ctx* ctx, double h, double* d_T, const erem_opts* opts, erem_
 int erem_step_frozen(erem_ctx* ctx, double h, double* d_T, const erem_opts* opts,
                      erem_stats* stats);
 
+/* ---- sequential coupled step and its adjoint (2D grids) ----
+ *
+ * The coupled step of Sec. 3.2.2 (pressure first, then temperature): TPFA
+ * transmissibilities of rho(T) K / mu(T) at T^n, steady pressure, face mass
+ * fluxes, J and G at T^n, then the EREM step T^{n+1} = T^n + h phi1(h J) G
+ * (Eq. EERM) by Newton-Leja substeps (Sec. 4.2).  The discrete choices of the
+ * step -- Gershgorin interval, substep count and the Newton-Leja degree of
+ * every substep -- form its tape.  Replaying a tape evaluates exactly the
+ * same polynomial in J without stop tests, so the step becomes a smooth map
+ * of (T^n, log K) near the recorded point; the adjoint differentiates that
+ * map. */
+#define EREM_TAPE_MAX_SUBSTEPS 256
+typedef struct {
+    int32_t substeps;                    /* s; 0 marks a step without Leja terms */
+    int32_t m[EREM_TAPE_MAX_SUBSTEPS];   /* Newton-Leja terms applied in substep j */
+    double alpha, beta;                  /* Gershgorin interval of J used by the step */
+} erem_tape;
+
+/* One coupled step in place on d_T (N values).  The pressure is solved from
+ * a zero initial guess to relative residual p_rtol (erem_solve_pressure).
+ * tape_in == NULL: the step chooses as erem_step does; otherwise it replays
+ * tape_in (method Leja, FP64).  tape_out (may be NULL) receives the choices
+ * used (Leja, FP64 only).  EINVAL for 3D grids, a Krylov or mixed-precision
+ * opts with a tape, or a tape whose substeps are outside [1, 256] or whose
+ * degrees are outside [1, m_max]. */
+int erem_coupled_step(erem_ctx* ctx, double h, double* d_T, double p_rtol, const erem_opts* opts,
+                      const erem_tape* tape_in, erem_tape* tape_out, erem_stats* stats);
+
+/* Adjoint of erem_coupled_step with the choices of `tape`: given T^n in d_T
+ * (unchanged) and Tbar = d phi / d T^{n+1} in d_Tbar, overwrite d_Tbar with
+ * d phi / d T^n and ADD d phi / d log K to d_logk_bar (N values each, device).
+ * The step is recomputed from T^n; the Leja iterates q_k of every substep are
+ * kept on the device when ckpt_stride is 1, or every ckpt_stride-th of them
+ * with the others recomputed segment by segment during the reverse sweep.
+ * The reverse Newton recurrence runs with the transposed stencil of J; the
+ * pressure adjoint is a second solve with the same symmetric matrix to
+ * relative residual p_rtol.  Errors as erem_coupled_step, plus EINVAL for
+ * ckpt_stride < 1 and ENOMEM if the iterate store does not fit. */
+int erem_coupled_step_adjoint(erem_ctx* ctx, double h, const double* d_T, double p_rtol,
+                              const erem_opts* opts, const erem_tape* tape, int32_t ckpt_stride,
+                              double* d_Tbar, double* d_logk_bar, erem_stats* stats);
+
 /* ---- batched form: many independent linear problems, one persistent launch ----
  *
  * Each problem is a 2D grid with fixed face fluxes and constant heat capacity

@@ -62,6 +62,18 @@ class BatchStats(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+TAPE_MAX_SUBSTEPS = 256
+
+
+class Tape(ctypes.Structure):
+    _fields_ = [("substeps", c_int32), ("m", c_int32 * TAPE_MAX_SUBSTEPS),
+                ("alpha", c_double), ("beta", c_double)]
+
+    def as_dict(self):
+        return {"substeps": self.substeps, "m": list(self.m[:self.substeps]),
+                "alpha": self.alpha, "beta": self.beta}
+
+
 _P = c_void_p           # device pointer / opaque handle
 _PD = POINTER(c_double)  # host double array
 
@@ -85,6 +97,10 @@ SIGNATURES = {
     "erem_phi1_apply": (c_int32, [_P, c_double, _P, _P, POINTER(Opts), POINTER(Stats)]),
     "erem_step": (c_int32, [_P, c_double, _P, POINTER(Opts), POINTER(Stats)]),
     "erem_step_frozen": (c_int32, [_P, c_double, _P, POINTER(Opts), POINTER(Stats)]),
+    "erem_coupled_step": (c_int32, [_P, c_double, _P, c_double, POINTER(Opts), POINTER(Tape),
+                                    POINTER(Tape), POINTER(Stats)]),
+    "erem_coupled_step_adjoint": (c_int32, [_P, c_double, _P, c_double, POINTER(Opts), POINTER(Tape),
+                                            c_int32, _P, _P, POINTER(Stats)]),
     "erem_batch_create": (c_int32, [c_int32, POINTER(Grid), _P, POINTER(_P)]),
     "erem_batch_destroy": (c_int32, [_P]),
     "erem_batch_last_error": (c_char_p, [_P]),

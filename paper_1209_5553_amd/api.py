@@ -192,6 +192,32 @@ class EremContext:
                                        ctypes.byref(st)), "erem_step")
         return st.as_dict()
 
+    def coupled_step(self, h: float, T, p_rtol: float = 1e-13, opts: nat.Opts | None = None,
+                     tape: nat.Tape | None = None, record: bool = True):
+        """One sequential coupled step in place on T (erem_coupled_step).
+        Returns (stats, tape): the tape of the choices used, replayed when
+        ``tape`` is given."""
+        o = opts if opts is not None else make_opts()
+        st = nat.Stats()
+        out = nat.Tape() if record else None
+        self._check(self.lib.erem_coupled_step(
+            self.handle, h, self._ptr(T, self.n, "T"), p_rtol, ctypes.byref(o),
+            ctypes.byref(tape) if tape is not None else None,
+            ctypes.byref(out) if out is not None else None, ctypes.byref(st)), "erem_coupled_step")
+        return st.as_dict(), out
+
+    def coupled_step_adjoint(self, h: float, T, tape: nat.Tape, Tbar, logk_bar, p_rtol: float = 1e-13,
+                             opts: nat.Opts | None = None, ckpt_stride: int = 1):
+        """Adjoint of one coupled step at T (erem_coupled_step_adjoint):
+        Tbar (in: d/dT^{n+1}, out: d/dT^n) in place, logk_bar accumulated."""
+        o = opts if opts is not None else make_opts()
+        st = nat.Stats()
+        self._check(self.lib.erem_coupled_step_adjoint(
+            self.handle, h, self._ptr(T, self.n, "T"), p_rtol, ctypes.byref(o), ctypes.byref(tape),
+            int(ckpt_stride), self._ptr(Tbar, self.n, "Tbar"), self._ptr(logk_bar, self.n, "logk_bar"),
+            ctypes.byref(st)), "erem_coupled_step_adjoint")
+        return st.as_dict()
+
     def profile(self, enable: bool = True):
         self._check(self.lib.erem_profile(self.handle, 1 if enable else 0), "erem_profile")
 
@@ -210,6 +236,7 @@ class EremContext:
         ctx._logk = torch.as_tensor(prob.logk, dtype=torch.float64, device=dev).contiguous()
         ctx._poro = torch.as_tensor(prob.poro, dtype=torch.float64, device=dev).contiguous()
         ctx.set_rock(ctx._logk, ctx._poro, prob.lam, prob.rhoc_s)
+        ctx.lam, ctx.rhoc_s = prob.lam, prob.rhoc_s
         ctx.set_fluid(prob.law, prob.c_f, prob.mu0, prob.rho0)
         ctx.set_bc(prob.p_left, prob.p_right, prob.T_left, prob.T_right,
                    getattr(prob, "dirichlet_left", True))

@@ -1,0 +1,119 @@
+// Internal view of the EREM context shared by the library's translation
+// units (erem_api.cpp, adjoint_api.cpp).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "device.h"
+#include "erem.h"
+#include "mg.h"
+
+struct DivDiffCache {
+  double hc = NAN, hg = NAN;
+  int n = 0;
+  std::vector<double> d;
+};
+
+struct erem_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  erem::Dims d{};
+  erem::Phys ph{};
+  bool rock_set = false, fluid_set = false, bc_set = false;
+  bool trans_set = false, flux_set = false, jac_set = false;
+
+  // fields (device)
+  double *logk = nullptr, *poro = nullptr;
+  double *tx = nullptr, *ty = nullptr, *tz = nullptr;
+  double *fx = nullptr, *fy = nullptr, *fz = nullptr;
+  double *coef = nullptr, *F = nullptr;
+  double *qa = nullptr, *qb = nullptr, *pacc = nullptr, *u = nullptr, *w = nullptr;
+  double *pres = nullptr, *pr = nullptr, *pz = nullptr, *pp0 = nullptr, *pp1 = nullptr;
+  double *pq = nullptr, *pdiag = nullptr, *pres_lo = nullptr, *pdelta = nullptr, *prhs = nullptr;
+  double* part = nullptr;  // Leja block partial sums (ring of kLejaRing terms)
+  // FP32 copies for the mixed-precision Leja passes (allocated on first use)
+  float *coef32 = nullptr, *qa32 = nullptr, *qb32 = nullptr, *p32 = nullptr;
+  bool coef32_valid = false;
+  // Krylov basis (m+1 vectors), work vector, Hessenberg matrix, norm, coefficients
+  double *kV = nullptr, *kw = nullptr, *kH = nullptr, *kbeta = nullptr, *kc = nullptr;
+  int kry_m = 0;
+  std::vector<double> hH;
+  size_t nfx = 0, nfy = 0, nfz = 0;
+
+  // device control blocks
+  erem::LejaCoef* cf = nullptr;
+  erem::LejaState* states = nullptr;
+  int nstates = 0;
+  erem::AsmReduce* red = nullptr;
+  erem::PcgState* pcg = nullptr;
+
+  // pinned host mirrors
+  erem::LejaCoef* h_cf = nullptr;
+  erem::LejaState* h_states = nullptr;
+  erem::AsmReduce* h_red = nullptr;
+  erem::PcgState* h_pcg = nullptr;
+
+  std::vector<double> xi;  // Leja points
+  DivDiffCache dd;
+  int last_m = 0;          // degree used by the previous evaluation
+  // profiling (HIP events around each Leja term and PCG half-iteration)
+  bool prof = false;
+  std::vector<hipEvent_t> ev;
+  double t_leja = 0.0, t_pcg_a = 0.0, t_pcg_b = 0.0, t_mg = 0.0;
+  long long n_leja = 0, n_pcg_a = 0, n_pcg_b = 0, n_mg = 0;
+  // multigrid preconditioner of the pressure operator
+  erem::MgHierarchy mg;
+  bool use_mg = true;
+  std::vector<double*> mg_bufs;
+  double alpha = 0.0, beta = 0.0, tmax = 0.0;
+  std::vector<int> applied;  // Leja terms applied per substep by the last evaluation
+  // adjoint storage (allocated on first use): stored Leja iterates, substep
+  // sums u_j, a recomputed segment of iterates, and the per-cell / per-face
+  // adjoint fields
+  double* adj_q = nullptr;
+  size_t adj_q_cap = 0;
+  double* adj_u = nullptr;
+  size_t adj_u_cap = 0;
+  double* adj_seg = nullptr;
+  size_t adj_seg_cap = 0;
+  double* adj_block = nullptr;
+  double *adj_sa = nullptr, *adj_sb = nullptr, *adj_jbar = nullptr, *adj_wbar = nullptr, *adj_ubar = nullptr;
+  double *adj_rbar = nullptr, *adj_dbar = nullptr, *adj_abar = nullptr, *adj_fxbar = nullptr;
+  double *adj_fybar = nullptr, *adj_pbar = nullptr, *adj_lam = nullptr, *adj_pscr = nullptr;
+  std::string err;
+};
+
+namespace erem_internal {
+
+int fail(erem_ctx* c, int code, const std::string& msg);
+
+#define HIP_TRY(ctx, expr)                                                        \
+  do {                                                                            \
+    hipError_t _e = (expr);                                                       \
+    if (_e != hipSuccess)                                                         \
+      return erem_internal::fail((ctx), EREM_EDEVICE, std::string(#expr ": ") + hipGetErrorString(_e)); \
+  } while (0)
+
+template <class T>
+int dev_alloc(erem_ctx* c, T** p, size_t count) {
+  if (count == 0) count = 1;
+  hipError_t e = hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
+  if (e != hipSuccess) return fail(c, EREM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
+  return EREM_OK;
+}
+
+int check_opts(erem_ctx* c, const erem_opts* o);
+int ndir(const erem_ctx* c);
+int read_reduce(erem_ctx* c);
+const std::vector<double>& divided_differences(erem_ctx* c, double hc, double hg, int n);
+// x <- A^{-1} b for the TPFA pressure matrix A (Dirichlet x faces folded into
+// the diagonal, no right-hand side from the boundary values): conjugate
+// gradients with the context's preconditioner, refined in FP64 until
+// ||b - A x|| <= rtol ||b||.  x and b are device arrays of N values.
+int spd_solve(erem_ctx* c, const double* b, double* x, double rtol, int max_iter, int* iters);
+
+}  // namespace erem_internal

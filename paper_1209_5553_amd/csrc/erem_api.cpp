@@ -17,6 +17,8 @@
 #include <string>
 #include <vector>
 
+#include "adjoint.h"
+#include "ctx.h"
 #include "device.h"
 #include "host_numerics.h"
 #include "krylov.h"
@@ -25,80 +27,12 @@
 
 using namespace erem;
 
-struct DivDiffCache {
-  double hc = NAN, hg = NAN;
-  int n = 0;
-  std::vector<double> d;
-};
-
-struct erem_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;
-  Dims d{};
-  Phys ph{};
-  bool rock_set = false, fluid_set = false, bc_set = false;
-  bool trans_set = false, flux_set = false, jac_set = false;
-
-  // fields (device)
-  double *logk = nullptr, *poro = nullptr;
-  double *tx = nullptr, *ty = nullptr, *tz = nullptr;
-  double *fx = nullptr, *fy = nullptr, *fz = nullptr;
-  double *coef = nullptr, *F = nullptr;
-  double *qa = nullptr, *qb = nullptr, *pacc = nullptr, *u = nullptr, *w = nullptr;
-  double *pres = nullptr, *pr = nullptr, *pz = nullptr, *pp0 = nullptr, *pp1 = nullptr;
-  double *pq = nullptr, *pdiag = nullptr, *pres_lo = nullptr, *pdelta = nullptr, *prhs = nullptr;
-  double* part = nullptr;  // Leja block partial sums (ring of kLejaRing terms)
-  // FP32 copies for the mixed-precision Leja passes (allocated on first use)
-  float *coef32 = nullptr, *qa32 = nullptr, *qb32 = nullptr, *p32 = nullptr;
-  bool coef32_valid = false;
-  // Krylov basis (m+1 vectors), work vector, Hessenberg matrix, norm, coefficients
-  double *kV = nullptr, *kw = nullptr, *kH = nullptr, *kbeta = nullptr, *kc = nullptr;
-  int kry_m = 0;
-  std::vector<double> hH;
-  size_t nfx = 0, nfy = 0, nfz = 0;
-
-  // device control blocks
-  LejaCoef* cf = nullptr;
-  LejaState* states = nullptr;
-  int nstates = 0;
-  AsmReduce* red = nullptr;
-  PcgState* pcg = nullptr;
-
-  // pinned host mirrors
-  LejaCoef* h_cf = nullptr;
-  LejaState* h_states = nullptr;
-  AsmReduce* h_red = nullptr;
-  PcgState* h_pcg = nullptr;
-
-  std::vector<double> xi;  // Leja points
-  DivDiffCache dd;
-  int last_m = 0;          // degree used by the previous evaluation
-  // profiling (HIP events around each Leja term and PCG half-iteration)
-  bool prof = false;
-  std::vector<hipEvent_t> ev;
-  double t_leja = 0.0, t_pcg_a = 0.0, t_pcg_b = 0.0, t_mg = 0.0;
-  long long n_leja = 0, n_pcg_a = 0, n_pcg_b = 0, n_mg = 0;
-  // multigrid preconditioner of the pressure operator
-  MgHierarchy mg;
-  bool use_mg = true;
-  std::vector<double*> mg_bufs;
-  double alpha = 0.0, beta = 0.0, tmax = 0.0;
-  std::string err;
-};
-
-namespace {
+namespace erem_internal {
 
 int fail(erem_ctx* c, int code, const std::string& msg) {
   if (c) c->err = msg;
   return code;
 }
-
-#define HIP_TRY(ctx, expr)                                                        \
-  do {                                                                            \
-    hipError_t _e = (expr);                                                       \
-    if (_e != hipSuccess)                                                         \
-      return fail((ctx), EREM_EDEVICE, std::string(#expr ": ") + hipGetErrorString(_e)); \
-  } while (0)
 
 // Make sure the event pool holds at least n events (profiling only).
 int ensure_events(erem_ctx* c, size_t n) {
@@ -132,13 +66,6 @@ int check_opts(erem_ctx* c, const erem_opts* o) {
   return EREM_OK;
 }
 
-template <class T>
-int dev_alloc(erem_ctx* c, T** p, size_t count) {
-  if (count == 0) count = 1;
-  hipError_t e = hipMalloc(reinterpret_cast<void**>(p), count * sizeof(T));
-  if (e != hipSuccess) return fail(c, EREM_ENOMEM, std::string("hipMalloc: ") + hipGetErrorString(e));
-  return EREM_OK;
-}
 
 void free_all(erem_ctx* c) {
   double** bufs[] = {&c->logk, &c->poro, &c->tx, &c->ty, &c->tz, &c->fx, &c->fy, &c->fz,
@@ -161,6 +88,10 @@ void free_all(erem_ctx* c) {
   double** kbufs[] = {&c->kV, &c->kw, &c->kH, &c->kbeta, &c->kc};
   for (double** b : kbufs)
     if (*b) { (void)hipFree(*b); *b = nullptr; }
+  double** abufs[] = {&c->adj_q, &c->adj_u, &c->adj_seg, &c->adj_block};
+  for (double** b : abufs)
+    if (*b) { (void)hipFree(*b); *b = nullptr; }
+  c->adj_q_cap = c->adj_u_cap = c->adj_seg_cap = 0;
   c->cf = nullptr; c->states = nullptr; c->red = nullptr; c->pcg = nullptr;
   c->h_cf = nullptr; c->h_states = nullptr; c->h_red = nullptr; c->h_pcg = nullptr;
 }
@@ -413,6 +344,7 @@ int leja_hphi1(erem_ctx* c, double h, const double* v, double scal, int s, int K
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   int total = 0;
   double last = 0.0;
+  c->applied.assign(s, 0);
   for (int j = 0; j < s; ++j) {
     const LejaState& st = c->h_states[j];
     if (st.nonfinite) return fail(c, EREM_ENONFINITE, "non-finite Leja term norm");
@@ -420,6 +352,7 @@ int leja_hphi1(erem_ctx* c, double h, const double* v, double scal, int s, int K
     // the stop test ran after every kCheckEvery terms: the terms up to the
     // end of the group in which it passed were applied
     const int applied = std::min(K, ((st.stopped + kCheckEvery - 1) / kCheckEvery) * kCheckEvery);
+    c->applied[j] = applied;
     total += applied;
     last = hc->estf[st.stopped] * std::sqrt(st.sums[st.stopped]);
     if (j < nprof) {
@@ -564,6 +497,7 @@ int hphi1_eval(erem_ctx* c, double h, const double* v, double scal, const erem_o
     const double z = h * 0.5 * (c->alpha + c->beta);
     const double f = (z == 0.0) ? h : h * (std::expm1(z) / z);
     HIP_TRY(c, launch_axpby(c->d, c->u, 0.0, v, f, c->stream));
+    c->applied.clear();
     if (stats) { stats->m_total = 0; stats->substeps = 1; stats->est_err = 0.0; }
     return EREM_OK;
   }
@@ -601,7 +535,94 @@ int hphi1_eval(erem_ctx* c, double h, const double* v, double scal, const erem_o
   }
 }
 
-}  // namespace
+// Conjugate gradients on A delta = prhs from delta = 0 (delta in c->pdelta)
+// to the relative residual inner_tol, with the context's preconditioner, at
+// most `budget` iterations.  *iters gets the iterations run, *done whether
+// the tolerance was reached.
+int pcg_inner(erem_ctx* c, int budget, int* iters, bool* done) {
+  const Dims& d = c->d;
+  const double inner_tol = 1e-9;
+  HIP_TRY(c, launch_pcg_reset(c->pcg, inner_tol * inner_tol, c->stream));
+  const int jac = c->use_mg ? 0 : 1;
+  HIP_TRY(c, launch_pcg_start_rhs(d, c->tx, c->ty, c->tz, c->prhs, c->pdelta, c->pr, c->pz, c->pp0, c->pdiag,
+                                  c->pcg, jac, c->stream));
+  if (c->use_mg) HIP_TRY(c, mg_apply(c->mg, c->pr, c->pz, c->pcg, 0, c->stream));
+  // Multigrid iterations are few: poll the device after a handful of them.
+  const int chunk = c->use_mg ? 8 : 64;
+  int it = 0;
+  *done = false;
+  if (c->prof) {
+    const int rc = ensure_events(c, 3 * chunk + 1);
+    if (rc) return rc;
+  }
+  while (it < budget) {
+    const int n = std::min(chunk, budget - it);
+    const int it0 = it;
+    if (c->prof) HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
+    for (int j = 0; j < n; ++j, ++it) {
+      double* pold = (it & 1) ? c->pp1 : c->pp0;
+      double* pnew = (it & 1) ? c->pp0 : c->pp1;
+      HIP_TRY(c, launch_pcg_a(d, c->tx, c->ty, c->tz, c->pz, pold, pnew, c->pq, c->pcg, it, c->stream));
+      if (c->prof) HIP_TRY(c, hipEventRecord(c->ev[3 * j + 1], c->stream));
+      HIP_TRY(c, launch_pcg_b(d, c->pdelta, c->pr, c->pz, pnew, c->pq, c->pdiag, c->pcg, it, jac, c->stream));
+      if (c->prof) HIP_TRY(c, hipEventRecord(c->ev[3 * j + 2], c->stream));
+      if (c->use_mg) HIP_TRY(c, mg_apply(c->mg, c->pr, c->pz, c->pcg, (it + 1) & 3, c->stream));
+      if (c->prof) HIP_TRY(c, hipEventRecord(c->ev[3 * j + 3], c->stream));
+    }
+    HIP_TRY(c, hipMemcpyAsync(c->h_pcg, c->pcg, sizeof(PcgState), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (c->h_pcg->nonfinite) return fail(c, EREM_ENONFINITE, "non-finite PCG residual");
+    const bool fin = c->h_pcg->done != 0;
+    if (c->prof) {
+      // iterations it0 .. it_done-1 ran fully; the test launch it_done returned at entry
+      const int ran = fin ? c->h_pcg->it_done - it0 : n;
+      for (int j = 0; j < ran; ++j) {
+        c->t_pcg_a += elapsed_ms(c->ev[3 * j], c->ev[3 * j + 1]);
+        c->t_pcg_b += elapsed_ms(c->ev[3 * j + 1], c->ev[3 * j + 2]);
+        if (c->use_mg) c->t_mg += elapsed_ms(c->ev[3 * j + 2], c->ev[3 * j + 3]);
+      }
+      c->n_pcg_a += ran;
+      c->n_pcg_b += ran;
+      if (c->use_mg) c->n_mg += ran;
+    }
+    if (fin) { *done = true; it = c->h_pcg->it_done; break; }
+  }
+  *iters = it;
+  return EREM_OK;
+}
+
+int spd_solve(erem_ctx* c, const double* b, double* x, double rtol, int max_iter, int* iters) {
+  const Dims& d = c->d;
+  if (d.dim != 2) return fail(c, EREM_EINVAL, "the general right-hand-side solve supports 2D grids");
+  HIP_TRY(c, hipMemsetAsync(x, 0, sizeof(double) * d.N, c->stream));
+  if (c->use_mg) HIP_TRY(c, mg_setup(c->mg, c->stream));
+  int total = 0;
+  bool ok = false;
+  for (int outer = 0; outer < 12; ++outer) {
+    HIP_TRY(c, launch_pcg_reset(c->pcg, 0.0, c->stream));
+    HIP_TRY(c, launch_spd_residual(d, c->tx, c->ty, x, b, c->prhs, c->pcg, c->stream));
+    HIP_TRY(c, hipMemcpyAsync(c->h_pcg, c->pcg, sizeof(PcgState), hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    double rr = 0.0, bb = 0.0;
+    for (int q = 0; q < kSlots; ++q) { rr += c->h_pcg->rr[q]; bb += c->h_pcg->bb_sl[q]; }
+    if (!std::isfinite(rr)) return fail(c, EREM_ENONFINITE, "non-finite residual in the adjoint pressure solve");
+    if (bb == 0.0 || rr <= rtol * rtol * bb) { ok = true; break; }
+    if (total >= max_iter) break;
+    int it = 0;
+    bool done = false;
+    const int rc = pcg_inner(c, max_iter - total, &it, &done);
+    if (rc) return rc;
+    total += it;
+    HIP_TRY(c, launch_axpby(d, x, 1.0, c->pdelta, 1.0, c->stream));
+  }
+  if (iters) *iters = total;
+  if (!ok) return fail(c, EREM_ENOCONV, "adjoint pressure solve did not reach rtol within max_iter");
+  return EREM_OK;
+}
+
+}  // namespace erem_internal
+
+using namespace erem_internal;
 
 extern "C" {
 
@@ -802,7 +823,6 @@ int erem_solve_pressure(erem_ctx* c, double rtol, int32_t max_iter, int32_t warm
   if (!warm || d_p) HIP_TRY(c, hipMemsetAsync(c->pres_lo, 0, bytes, c->stream));
   // Iterative refinement: residual of the double-double pressure, PCG on the
   // correction to a relative 1e-9, double-double update.
-  const double inner_tol = 1e-9;
   int total = 0;
   bool ok = false;
   double relres = NAN;
@@ -818,51 +838,11 @@ int erem_solve_pressure(erem_ctx* c, double rtol, int32_t max_iter, int32_t warm
     relres = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
     if (relres <= rtol || rr == 0.0) { ok = true; break; }
     if (total >= max_iter) break;
-    // PCG on A delta = r from delta = 0
-    HIP_TRY(c, launch_pcg_reset(c->pcg, inner_tol * inner_tol, c->stream));
-    const int jac = c->use_mg ? 0 : 1;
-    HIP_TRY(c, launch_pcg_start_rhs(d, c->tx, c->ty, c->tz, c->prhs, c->pdelta, c->pr, c->pz, c->pp0, c->pdiag,
-                                    c->pcg, jac, c->stream));
-    if (c->use_mg) HIP_TRY(c, mg_apply(c->mg, c->pr, c->pz, c->pcg, 0, c->stream));
-    // Multigrid iterations are few: poll the device after a handful of them.
-    const int chunk = c->use_mg ? 8 : 64;
     int it = 0;
     bool done = false;
-    if (c->prof) {
-      const int rc = ensure_events(c, 3 * chunk + 1);
+    {
+      const int rc = pcg_inner(c, max_iter - total, &it, &done);
       if (rc) return rc;
-    }
-    while (total + it < max_iter) {
-      const int n = std::min(chunk, max_iter - total - it);
-      const int it0 = it;
-      if (c->prof) HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
-      for (int j = 0; j < n; ++j, ++it) {
-        double* pold = (it & 1) ? c->pp1 : c->pp0;
-        double* pnew = (it & 1) ? c->pp0 : c->pp1;
-        HIP_TRY(c, launch_pcg_a(d, c->tx, c->ty, c->tz, c->pz, pold, pnew, c->pq, c->pcg, it, c->stream));
-        if (c->prof) HIP_TRY(c, hipEventRecord(c->ev[3 * j + 1], c->stream));
-        HIP_TRY(c, launch_pcg_b(d, c->pdelta, c->pr, c->pz, pnew, c->pq, c->pdiag, c->pcg, it, jac, c->stream));
-        if (c->prof) HIP_TRY(c, hipEventRecord(c->ev[3 * j + 2], c->stream));
-        if (c->use_mg) HIP_TRY(c, mg_apply(c->mg, c->pr, c->pz, c->pcg, (it + 1) & 3, c->stream));
-        if (c->prof) HIP_TRY(c, hipEventRecord(c->ev[3 * j + 3], c->stream));
-      }
-      HIP_TRY(c, hipMemcpyAsync(c->h_pcg, c->pcg, sizeof(PcgState), hipMemcpyDeviceToHost, c->stream));
-      HIP_TRY(c, hipStreamSynchronize(c->stream));
-      if (c->h_pcg->nonfinite) return fail(c, EREM_ENONFINITE, "non-finite PCG residual");
-      const bool fin = c->h_pcg->done != 0;
-      if (c->prof) {
-        // iterations it0 .. it_done-1 ran fully; the test launch it_done returned at entry
-        const int ran = fin ? c->h_pcg->it_done - it0 : n;
-        for (int j = 0; j < ran; ++j) {
-          c->t_pcg_a += elapsed_ms(c->ev[3 * j], c->ev[3 * j + 1]);
-          c->t_pcg_b += elapsed_ms(c->ev[3 * j + 1], c->ev[3 * j + 2]);
-          if (c->use_mg) c->t_mg += elapsed_ms(c->ev[3 * j + 2], c->ev[3 * j + 3]);
-        }
-        c->n_pcg_a += ran;
-        c->n_pcg_b += ran;
-        if (c->use_mg) c->n_mg += ran;
-      }
-      if (fin) { done = true; it = c->h_pcg->it_done; break; }
     }
     total += it;
     HIP_TRY(c, launch_dd_update(d, c->pres, c->pres_lo, c->pdelta, c->stream));

@@ -143,6 +143,44 @@ def coupled_problem(n: int = 512, seed: int = 0, nsteps: int = 100,
                    law=LAW_WATER, p_left=DP_COUPLED, nsteps=nsteps)
 
 
+def adjoint_problem(n: int = 256, seed: int = 0, nsteps: int = 20, structured_T0: bool = True,
+                    name: str | None = None) -> Problem:
+    """The adjoint workload: the coupled problem of side n (water laws,
+    sigma_logK = 2, corr 16), 20 steps.
+
+    With the uniform 20 C start the injected heat penetrates only a few
+    metres in 20 steps of 1e6 s (thermal front speed ~3.5e-10 m/s at the
+    workload's Peclet number, conduction length ~4 m), so the producer-block
+    temperature and all its sensitivities are exactly those of a uniform
+    state.  ``structured_T0`` gives the start a smooth temperature structure
+    instead: T0 = 20 + 60 * (1 + tanh z) / 2 with z a smoothed N(0, 1) field
+    (Gaussian, 8 cells, re-standardised; drawn after the permeability from
+    the same generator), so that the objective depends on T0 near the
+    producer and, through the pressure field and the advection of that
+    structure, on log K everywhere."""
+    rng = np.random.default_rng(seed)
+    logk = lognormal_field(rng, (n, n), 2.0, 16.0)
+    N = n * n
+    if structured_T0:
+        z = rng.standard_normal((n, n))
+        z = ndimage.gaussian_filter(z, sigma=8.0, mode="reflect", truncate=4.0)
+        z = (z - z.mean()) / z.std()
+        T0 = (T_INITIAL + 60.0 * 0.5 * (1.0 + np.tanh(z))).ravel().astype(np.float64)
+    else:
+        T0 = _uniform(N, T_INITIAL)
+    return Problem(name=name or f"adjoint2d_{n}", nx=n, ny=n, nz=1, logk=logk,
+                   poro=_uniform(N, POROSITY), T0=T0, law=LAW_WATER, p_left=DP_COUPLED,
+                   nsteps=nsteps)
+
+
+def producer_ring(nx: int, ny: int, block: int = 4, ring: int = 2):
+    """Flat indices of the producer block and ``ring`` cells around it
+    (inside the grid), for checks of d/dT0 where it is not negligible."""
+    ys = np.arange(max(0, ny // 2 - block // 2 - ring), min(ny, ny // 2 + block // 2 + ring))
+    xs = np.arange(max(0, nx - block - ring), nx)
+    return (xs[None, :] + nx * ys[:, None]).ravel()
+
+
 def layered3d_problem(n: int = 128, seed: int = 0, nsteps: int = 10,
                       name: str | None = None) -> Problem:
     """3D n^3 7-point heat transport, layered permeability (3 decades)."""
