@@ -141,12 +141,195 @@ def cpu_baseline(prob, coupled, nsteps, gpu_snaps):
     return out
 
 
+# Reverse Newton-Leja term (adjoint): read s_k, q_{k-1}, the stencil, ubar,
+# the five Jbar accumulators; write Jbar and s_{k-1}.
+ADJ_REV_BYTES = 8 + 8 + 40 + 8 + 80 + 8
+
+
+def bench_batch(args, mixed):
+    """256 realisations (seeds 0..255, sides from {64, 96, 128, 192, 256}),
+    50 EREM steps per launch, one hipGraph replay per timed step."""
+    import torch
+    from paper_1209_5553_amd import inputs
+    from paper_1209_5553_amd.api import EremBatch, make_opts
+
+    nprob, nst = 256, 50
+    probs = [inputs.batch_problem(s) for s in range(nprob)]
+    b = EremBatch(probs, device="cuda:0")
+    opts = make_opts(m_max=128, precision=1, tol_r=1e-7) if mixed else make_opts(m_max=128)
+    b.prepare(probs[0].h, opts)
+    T0 = b.pack([p.T0 for p in probs])
+    shape = b.autotune(T0, nsteps=2)
+    log(f"batch: {nprob} problems, {b.ntot} cells, autotuned shape {shape}")
+    T = T0.clone()
+    for _ in range(args.warmup):
+        T.copy_(T0)
+        b.run(T, nst, use_graph=True)
+    torch.cuda.synchronize()
+    ms, byts, terms = [], [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        T.copy_(T0)
+        st = b.run(T, nst, use_graph=True)
+        ms.append(st["ms"])
+        byts.append(st["leja_bytes"])
+        terms.append(st["terms_total"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    avg_s = float(np.mean(ms)) * 1e-3
+    ach = float(np.mean(byts)) / avg_s / 1e9
+    desc = (f"batched: {nprob} linear 2D realisations (seeds 0..{nprob - 1}, sides from {list(inputs.C3_SIDES)}), "
+            f"{nst} EREM-Leja steps each in one persistent launch replayed from a hipGraph")
+    line = {
+        "metric": METRIC, "value": round(nst * args.steps / elapsed, 3), "unit": "steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / (nst * args.steps), 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64" if mixed else "f64",
+        "data": "synthetic (seeded generators)",
+        "config": {"workload": desc, "cells": int(b.ntot), "problems": nprob, "steps_per_launch": nst,
+                   "step_unit": "one EREM step of all realisations", "tile_shape": shape,
+                   "tol_r": 1e-7 if mixed else 1e-12, "precision": args.precision},
+        "roofline": {"kernel": "k_batch_blocks", "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                     "avg_launch_us": round(avg_s * 1e6, 1), "launches": len(ms),
+                     "bytes_per_launch": float(np.mean(byts)),
+                     "bytes_rule": f"Newton terms only: sum over problems of terms x cells x "
+                                   f"{36 if mixed else 72} B"},
+        "leja_terms_per_launch": float(np.mean(terms)),
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = batch_cpu_baseline(probs, b, T0)
+    return line
+
+
+def batch_cpu_baseline(probs, b, T0):
+    """Oracle (tier-B action), one step of the first four realisations, scaled
+    to one step of the whole batch by cell count; agreement of the GPU's
+    one-step batch on those realisations."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle import erem as oerem
+    sample = probs[:4]
+    T1 = T0.clone()
+    b.run(T1, 1, use_graph=False)
+    got = b.unpack(T1)
+    errs = []
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        outs = [oerem.run_linear(p, nsteps=1, tier="taylor")[0] for p in sample]
+        t1 = time.perf_counter()
+    for i, (p, To) in enumerate(zip(sample, outs)):
+        errs.append(float(np.abs((got[i] - p.T0) - (To - p.T0)).max() / np.abs(To - p.T0).max()))
+    cells_sample = sum(p.n for p in sample)
+    cells_all = sum(p.n for p in probs)
+    per_batch_step = (t1 - t0) * cells_all / cells_sample
+    return {"value": 1.0 / per_batch_step, "unit": "steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"1 EREM step of realisations 0-3 ({cells_sample} cells, substepped Taylor action, "
+                      f"FP64, 1 thread), scaled by cell count to the {cells_all}-cell batch",
+            "seconds": t1 - t0, "gpu_increment_rel_err": max(errs)}
+
+
+def bench_adjoint(args):
+    """256 x 256 water-law coupled problem, 20 steps; one timed step = one
+    gradient of the producer-block mean temperature with respect to T0 and
+    log K (20 forward steps with tapes, 20 adjoint steps)."""
+    import torch
+    from paper_1209_5553_amd import inputs
+    from paper_1209_5553_amd.adjoint import coupled_run, run_with_tapes
+    from paper_1209_5553_amd.api import EremContext
+
+    nst = 20
+    prob = inputs.adjoint_problem(256, structured_T0=args.adjoint_start == "structured")
+    ctx = EremContext.from_problem(prob, device="cuda:0")
+    dev = ctx.device
+    prod = torch.as_tensor(inputs.producer_cells(prob.nx, prob.ny), device=dev)
+    T0 = torch.as_tensor(prob.T0, dtype=torch.float64, device=dev)
+    lk = torch.as_tensor(prob.logk, dtype=torch.float64, device=dev)
+
+    def grad_once():
+        a = T0.clone().requires_grad_(True)
+        k = lk.clone().requires_grad_(True)
+        TN = coupled_run(ctx, a, k, prob.h, nst)
+        TN[prod].mean().backward()
+        return a.grad, k.grad
+
+    for _ in range(args.warmup):
+        grad_once()
+    torch.cuda.synchronize()
+    # forward alone (same steps, tapes recorded)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run_with_tapes(ctx, T0, lk, prob.h, nst)
+    torch.cuda.synchronize()
+    fwd = time.perf_counter() - t0
+    ctx.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        grad_once()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    times = ctx.profile_read()
+    ctx.profile(False)
+    log(f"adjoint: forward {fwd:.3f} s, forward + adjoint {elapsed:.3f} s, kernel times {times}")
+    N = prob.n
+    kern = {
+        "adj_rev_term": (times["adj_rev_ms"], times["adj_rev_launches"], ADJ_REV_BYTES * N),
+        "leja_term": (times["leja_term_ms"], times["leja_term_launches"], LEJA_BYTES[2]["f64"] * N),
+        "pcg_a": (times["pcg_a_ms"], times["pcg_a_launches"], PCG_A_BYTES[2] * N),
+        "pcg_b": (times["pcg_b_ms"], times["pcg_b_launches"], PCG_B_BYTES[2] * N),
+        "mg_vcycle": (times["mg_ms"], times["mg_cycles"], MG_BYTES[2] * N),
+    }
+    desc = (f"adjoint: coupled 2D 256x256 water laws, {nst} EREM-Leja steps with tapes + {nst} adjoint steps "
+            f"(reverse Leja, transposed stencil, stored iterates), gradient of the producer-block mean T "
+            f"wrt T0 and log K ({args.adjoint_start} start)")
+    line = {
+        "metric": METRIC, "value": round(nst * args.steps / elapsed, 3), "unit": "steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / (nst * args.steps), 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded generators)",
+        "config": {"workload": desc, "grid": [prob.nx, prob.ny, 1], "cells": N, "h_s": prob.h,
+                   "step_unit": "one coupled step forward plus its adjoint", "tol_r": 1e-12},
+        "roofline": _roof(kern, max(kern, key=lambda k: kern[k][0])),
+        "adjoint_rev_term": _roof(kern, "adj_rev_term"),
+        "leja": _roof(kern, "leja_term"),
+        "forward_only_steps_per_s": round(nst * args.steps / fwd, 3),
+        "gradient_cost_in_forward_runs": round(elapsed / fwd, 3),
+    }
+    if not args.no_cpu_baseline:
+        from threadpoolctl import threadpool_limits
+
+        from oracle import erem as oerem
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            oerem.coupled_step(prob, np.asarray(prob.T0, dtype=np.float64), tier="taylor")
+            t1 = time.perf_counter()
+        line["cpu_baseline"] = {"value": 1.0 / (t1 - t0), "unit": "steps/s", "cores": 1, "kind": "oracle",
+                                "sample": "1 forward coupled step of the same workload (SuperLU pressure + "
+                                          "substepped Taylor action, FP64, 1 thread); the oracle's dense "
+                                          "adjoint is limited to grids of a few hundred cells",
+                                "seconds": t1 - t0}
+    return line
+
+
+def _roof(kern, name):
+    ms, n, bytes_per = kern[name]
+    if n == 0:
+        return None
+    avg_s = ms / n * 1e-3
+    ach = bytes_per / avg_s / 1e9
+    return {"kernel": name, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            "avg_launch_us": round(avg_s * 1e6, 3), "launches": n, "bytes_per_launch": bytes_per,
+            "share_of_kernel_time": round(ms / max(sum(v[0] for v in kern.values()), 1e-30), 4)}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="coupled512", choices=["coupled512", "linear32", "layered128"])
+    ap.add_argument("--workload", default="coupled512",
+                    choices=["coupled512", "linear32", "layered128", "batch256", "adjoint256"])
+    ap.add_argument("--adjoint-start", default="uniform", choices=["uniform", "structured"])
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pressure-rtol", type=float, default=1e-16)
@@ -162,9 +345,14 @@ def main():
     if not args.no_cpu_baseline and args.warmup < args.cpu_steps:
         args.warmup = args.cpu_steps
 
+    mixed = args.precision == "mixed"
+    if args.workload in ("batch256", "adjoint256"):
+        line = bench_batch(args, mixed) if args.workload == "batch256" else bench_adjoint(args)
+        print(json.dumps(line), flush=True)
+        return
+
     prob, desc, coupled = make_workload(args.workload)
     log(f"workload {args.workload}: {desc}; N={prob.n}")
-    mixed = args.precision == "mixed"
     res = gpu_run(prob, coupled, args.steps, args.warmup, args.pressure_rtol, mixed=mixed)
     dim = prob.dim
     N = prob.n
@@ -179,16 +367,7 @@ def main():
     dominant = max(kern, key=lambda k: kern[k][0])
 
     def roof(name):
-        ms, n, bytes_per = kern[name]
-        if n == 0:
-            return None
-        avg_s = ms / n * 1e-3
-        ach = bytes_per / avg_s / 1e9
-        return {"kernel": name, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
-                "avg_launch_us": round(avg_s * 1e6, 3), "launches": n,
-                "bytes_per_launch": bytes_per, "share_of_kernel_time": round(
-                    ms / max(sum(v[0] for v in kern.values()), 1e-30), 4)}
+        return _roof(kern, name)
 
     steps_s = args.steps / res["elapsed"]
     line = {

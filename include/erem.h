@@ -307,6 +307,8 @@ typedef struct {
     int64_t pcg_b_launches;
     double mg_ms;               /* multigrid preconditioner (all its kernels) */
     int64_t mg_cycles;
+    double adj_rev_ms;          /* reverse Newton-Leja term kernel (adjoint) */
+    int64_t adj_rev_launches;
 } erem_kernel_times;
 
 /* Turn per-launch event timing on (enable != 0) or off and reset the

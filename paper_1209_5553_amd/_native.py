@@ -47,7 +47,8 @@ class KernelTimes(ctypes.Structure):
     _fields_ = [("leja_term_ms", c_double), ("leja_term_launches", c_int64),
                 ("pcg_a_ms", c_double), ("pcg_a_launches", c_int64),
                 ("pcg_b_ms", c_double), ("pcg_b_launches", c_int64),
-                ("mg_ms", c_double), ("mg_cycles", c_int64)]
+                ("mg_ms", c_double), ("mg_cycles", c_int64),
+                ("adj_rev_ms", c_double), ("adj_rev_launches", c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}

@@ -65,6 +65,8 @@ struct erem_ctx {
   std::vector<hipEvent_t> ev;
   double t_leja = 0.0, t_pcg_a = 0.0, t_pcg_b = 0.0, t_mg = 0.0;
   long long n_leja = 0, n_pcg_a = 0, n_pcg_b = 0, n_mg = 0;
+  double t_adj = 0.0;
+  long long n_adj = 0;
   // multigrid preconditioner of the pressure operator
   erem::MgHierarchy mg;
   bool use_mg = true;
@@ -107,6 +109,8 @@ int dev_alloc(erem_ctx* c, T** p, size_t count) {
 }
 
 int check_opts(erem_ctx* c, const erem_opts* o);
+int ensure_events(erem_ctx* c, size_t n);  // event pool of at least n events (profiling)
+double elapsed_ms(hipEvent_t a, hipEvent_t b);
 int ndir(const erem_ctx* c);
 int read_reduce(erem_ctx* c);
 const std::vector<double>& divided_differences(erem_ctx* c, double hc, double hg, int n);

@@ -994,8 +994,8 @@ int erem_profile(erem_ctx* c, int32_t enable) {
   if (!c) return EREM_EINVAL;
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->prof = enable != 0;
-  c->t_leja = c->t_pcg_a = c->t_pcg_b = c->t_mg = 0.0;
-  c->n_leja = c->n_pcg_a = c->n_pcg_b = c->n_mg = 0;
+  c->t_leja = c->t_pcg_a = c->t_pcg_b = c->t_mg = c->t_adj = 0.0;
+  c->n_leja = c->n_pcg_a = c->n_pcg_b = c->n_mg = c->n_adj = 0;
   return EREM_OK;
 }
 
@@ -1009,6 +1009,8 @@ int erem_profile_read(erem_ctx* c, erem_kernel_times* out) {
   out->pcg_b_launches = c->n_pcg_b;
   out->mg_ms = c->t_mg;
   out->mg_cycles = c->n_mg;
+  out->adj_rev_ms = c->t_adj;
+  out->adj_rev_launches = c->n_adj;
   return EREM_OK;
 }
 
