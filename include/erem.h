@@ -230,7 +230,7 @@ int erem_coupled_step(erem_ctx* ctx, double h, double* d_T, double p_rtol, const
  * with the others recomputed segment by segment during the reverse sweep.
  * The reverse Newton recurrence runs with the transposed stencil of J; the
  * pressure adjoint is a second solve with the same symmetric matrix to
- * relative residual p_rtol.  Errors as erem_coupled_step, plus EINVAL for
+ * relative residual max(p_rtol, 1e-12).  Errors as erem_coupled_step, plus EINVAL for
  * ckpt_stride < 1 and ENOMEM if the iterate store does not fit. */
 int erem_coupled_step_adjoint(erem_ctx* ctx, double h, const double* d_T, double p_rtol,
                               const erem_opts* opts, const erem_tape* tape, int32_t ckpt_stride,

@@ -53,7 +53,7 @@ class CoupledRun(torch.autograd.Function):
         return Tbar, kbar, None, None, None, None, None, None, None
 
 
-def coupled_run(ectx: EremContext, T0, logk, h: float, nsteps: int, opts=None, p_rtol: float = 1e-13,
+def coupled_run(ectx: EremContext, T0, logk, h: float, nsteps: int, opts=None, p_rtol: float = 1e-16,
                 ckpt_stride: int = 1, tapes=None):
     """Differentiable T^N.  ``tapes`` (one per step) replays recorded
     choices, e.g. for finite differences with the discrete choices frozen."""
@@ -61,7 +61,7 @@ def coupled_run(ectx: EremContext, T0, logk, h: float, nsteps: int, opts=None, p
     return CoupledRun.apply(T0, logk, ectx, h, nsteps, o, p_rtol, ckpt_stride, tapes)
 
 
-def run_with_tapes(ectx: EremContext, T0, logk, h: float, nsteps: int, opts=None, p_rtol: float = 1e-13,
+def run_with_tapes(ectx: EremContext, T0, logk, h: float, nsteps: int, opts=None, p_rtol: float = 1e-16,
                    tapes=None):
     """Forward only: (T^N, tapes).  With ``tapes`` the steps replay them."""
     o = opts if opts is not None else make_opts()

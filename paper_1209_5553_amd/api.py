@@ -126,7 +126,7 @@ class EremContext:
         self._check(self.lib.erem_assemble_transmissibilities(self.handle, self._ptr(T, self.n, "T")),
                     "erem_assemble_transmissibilities")
 
-    def solve_pressure(self, rtol=1e-14, max_iter=50000, p=None, warm=False):
+    def solve_pressure(self, rtol=1e-16, max_iter=50000, p=None, warm=False):
         st = nat.Stats()
         self._check(self.lib.erem_solve_pressure(self.handle, rtol, max_iter, 1 if warm else 0,
                                                  self._ptr(p, self.n, "p"), ctypes.byref(st)),
@@ -192,7 +192,7 @@ class EremContext:
                                        ctypes.byref(st)), "erem_step")
         return st.as_dict()
 
-    def coupled_step(self, h: float, T, p_rtol: float = 1e-13, opts: nat.Opts | None = None,
+    def coupled_step(self, h: float, T, p_rtol: float = 1e-16, opts: nat.Opts | None = None,
                      tape: nat.Tape | None = None, record: bool = True):
         """One sequential coupled step in place on T (erem_coupled_step).
         Returns (stats, tape): the tape of the choices used, replayed when
@@ -206,7 +206,7 @@ class EremContext:
             ctypes.byref(out) if out is not None else None, ctypes.byref(st)), "erem_coupled_step")
         return st.as_dict(), out
 
-    def coupled_step_adjoint(self, h: float, T, tape: nat.Tape, Tbar, logk_bar, p_rtol: float = 1e-13,
+    def coupled_step_adjoint(self, h: float, T, tape: nat.Tape, Tbar, logk_bar, p_rtol: float = 1e-16,
                              opts: nat.Opts | None = None, ckpt_stride: int = 1):
         """Adjoint of one coupled step at T (erem_coupled_step_adjoint):
         Tbar (in: d/dT^{n+1}, out: d/dT^n) in place, logk_bar accumulated."""
@@ -242,7 +242,7 @@ class EremContext:
                    getattr(prob, "dirichlet_left", True))
         return ctx
 
-    def pressure_and_fluxes(self, T=None, rtol=1e-14, p=None, warm=False, max_iter=50000):
+    def pressure_and_fluxes(self, T=None, rtol=1e-16, p=None, warm=False, max_iter=50000):
         """Transmissibilities at T, steady pressure and face fluxes."""
         self.assemble_transmissibilities(T)
         return self.solve_pressure(rtol=rtol, max_iter=max_iter, p=p, warm=warm)

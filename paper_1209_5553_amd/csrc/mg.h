@@ -36,7 +36,7 @@ struct MgHierarchy {
   int lb = 0;              // bottom level (= nlev - 1)
   int coarse_threads = 0;
   size_t lds_bytes = 0;
-  double omega_c = 1.6;
+  double omega_c = 2.1;
   double* binv = nullptr;  // dense inverse of the bottom operator (device)
   MgLevelDev lev[kMgMaxLevels];
   MgCoarseArgs coarse;

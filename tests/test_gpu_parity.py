@@ -51,7 +51,7 @@ def test_transmissibilities_and_fluxes(torch_mod):
     prob = inputs.linear_problem(32)
     _say(f"transmissibilities {prob.name}")
     ctx = _ctx(prob)
-    st = ctx.pressure_and_fluxes(rtol=1e-14)
+    st = ctx.pressure_and_fluxes(rtol=1e-16)
     faces = {k: v.cpu().numpy() for k, v in ctx.get_faces().items()}
     disc = oerem.Discretisation(prob, prob.T0)
     g = disc.g
@@ -218,7 +218,7 @@ def test_phi1_of_zero_matrix_is_identity(torch_mod):
 def _run_gpu_linear(torch, prob, nsteps, h=None, opts=None, fluxes=None):
     ctx = _ctx(prob)
     if fluxes is None:
-        ctx.pressure_and_fluxes(rtol=1e-14)
+        ctx.pressure_and_fluxes(rtol=1e-16)
     else:
         ctx.set_face_fluxes(*fluxes)
     T = _dev(torch, prob.T0)
@@ -311,7 +311,7 @@ def test_coupled_steps_match_oracle(torch_mod):
     T = _dev(torch, prob.T0)
     p = torch.zeros(prob.n, dtype=torch.float64, device="cuda:0")
     for n in range(prob.nsteps):
-        ctx.pressure_and_fluxes(T, rtol=1e-14, p=p, warm=n > 0)
+        ctx.pressure_and_fluxes(T, rtol=1e-16, p=p, warm=n > 0)
         ctx.step(prob.h, T)
     T_gpu = T.cpu().numpy()
     T_ref = oerem.run_coupled(prob)
@@ -328,7 +328,7 @@ def test_coupled_512_one_step_full_size(torch_mod):
     _say("coupled 512x512 one step")
     ctx = _ctx(prob)
     T = _dev(torch, prob.T0)
-    st_p = ctx.pressure_and_fluxes(T, rtol=1e-14)
+    st_p = ctx.pressure_and_fluxes(T, rtol=1e-16)
     st = ctx.step(prob.h, T)
     T_gpu = T.cpu().numpy()
     T_ref, _ = oerem.coupled_step(prob, prob.T0, tier="taylor")
