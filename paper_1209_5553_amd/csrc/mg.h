@@ -16,7 +16,7 @@ constexpr int kMgBottomCells = 64;  // bottom level, solved with a dense inverse
 struct MgLevelDev {
   int nx, ny, nz;
   double *tx, *ty, *tz, *diag;
-  double *b, *x, *y;
+  double *b, *x, *y;  // rhs, down-leg iterate, up-leg result
 };
 
 // Arguments of the single-workgroup coarse solve over levels lc..lb.

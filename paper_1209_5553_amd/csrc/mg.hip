@@ -9,9 +9,11 @@
 // coarse correction; the coarse correction is over-relaxed by omega_c; the
 // bottom level (at most kMgBottomCells cells) is solved exactly with a dense
 // inverse formed once per setup.  The cycle is symmetric, so it is a valid
-// conjugate-gradient preconditioner.  Fine levels run one kernel per
-// operation; the levels with at most kMgLdsCells cells run inside one
-// workgroup with everything in LDS.
+// conjugate-gradient preconditioner.  Each fine level runs two kernels: the
+// down leg (two sweeps from zero + restricted residual) and the up leg
+// (coarse correction + two sweeps), each recomputing its neighbours'
+// intermediate sweep instead of waiting for a grid-wide pass; the levels with
+// at most kMgLdsCells cells run inside one workgroup with everything in LDS.
 #include "device.h"
 #include "mg.h"
 
@@ -93,7 +95,7 @@ __global__ __launch_bounds__(kThreads) void k_mg_coarsen(MgLevelDev F, MgLevelDe
 
 // Dense inverse of the bottom-level operator (SPD, diagonally dominant, so
 // Gauss-Jordan without pivoting is stable), one workgroup, in place in LDS.
-__global__ __launch_bounds__(256) void k_mg_bottom_inverse(MgLevelDev L, double* __restrict__ inv) {
+__global__ __launch_bounds__(1024) void k_mg_bottom_inverse(MgLevelDev L, double* __restrict__ inv) {
   __shared__ double M[kMgBottomCells * kMgBottomCells];
   __shared__ double prow[kMgBottomCells];
   __shared__ double pcol[kMgBottomCells];
@@ -138,92 +140,99 @@ __global__ __launch_bounds__(256) void k_mg_bottom_inverse(MgLevelDev L, double*
   for (int e = threadIdx.x; e < n * n; e += blockDim.x) inv[e] = M[e];
 }
 
-// Two damped-Jacobi sweeps from zero: x1 = w b / D, x2 = x1 + w (b - A x1) / D.
-__global__ __launch_bounds__(kThreads) void k_mg_smooth_down(MgLevelDev L, const double* __restrict__ b,
-                                                   double* __restrict__ xout, const PcgState* st) {
-  if (pcg_done(st)) return;
-  const int x = blockIdx.x * kBX + threadIdx.x;
-  const int y = blockIdx.y * kBY + threadIdx.y;
-  const int z = blockIdx.z;
-  if (x >= L.nx || y >= L.ny) return;
-  const int i = x + L.nx * (y + L.ny * z);
+// Cell index and the neighbour sum of one level; the neighbour order (-x, +x,
+// -y, +y, -z, +z) is the same everywhere, so fused and unfused forms of a
+// sweep round identically.
+__device__ inline int cidx(const MgLevelDev& L, int x, int y, int z) { return x + L.nx * (y + L.ny * z); }
+
+template <class F>
+__device__ inline double nb_sum(const MgLevelDev& L, int x, int y, int z, F&& v) {
   const int nx = L.nx, ny = L.ny, nz = L.nz;
-  auto x1 = [&](int j) { return kOmega * b[j] / L.diag[j]; };
   double s = 0.0;
-  if (x > 0) s += L.tx[fxi(nx, ny, x, y, z)] * x1(i - 1);
-  if (x + 1 < nx) s += L.tx[fxi(nx, ny, x + 1, y, z)] * x1(i + 1);
-  if (y > 0) s += L.ty[fyi(nx, ny, x, y, z)] * x1(i - nx);
-  if (y + 1 < ny) s += L.ty[fyi(nx, ny, x, y + 1, z)] * x1(i + nx);
-  if (z > 0) s += L.tz[fzi(nx, ny, x, y, z)] * x1(i - nx * ny);
-  if (z + 1 < nz) s += L.tz[fzi(nx, ny, x, y, z + 1)] * x1(i + nx * ny);
+  if (x > 0) s += L.tx[fxi(nx, ny, x, y, z)] * v(x - 1, y, z);
+  if (x + 1 < nx) s += L.tx[fxi(nx, ny, x + 1, y, z)] * v(x + 1, y, z);
+  if (y > 0) s += L.ty[fyi(nx, ny, x, y, z)] * v(x, y - 1, z);
+  if (y + 1 < ny) s += L.ty[fyi(nx, ny, x, y + 1, z)] * v(x, y + 1, z);
+  if (z > 0) s += L.tz[fzi(nx, ny, x, y, z)] * v(x, y, z - 1);
+  if (z + 1 < nz) s += L.tz[fzi(nx, ny, x, y, z + 1)] * v(x, y, z + 1);
+  return s;
+}
+
+// Two damped-Jacobi sweeps from zero at one cell: x1 = w b / D,
+// x2 = x1 + w (b - A x1) / D.
+__device__ inline double sweep2_from_zero(const MgLevelDev& L, const double* __restrict__ b, int x, int y, int z) {
+  auto x1 = [&](int xx, int yy, int zz) {
+    const int j = cidx(L, xx, yy, zz);
+    return kOmega * b[j] / L.diag[j];
+  };
+  const int i = cidx(L, x, y, z);
   const double D = L.diag[i];
   const double xi = kOmega * b[i] / D;
-  xout[i] = xi + kOmega * (b[i] - D * xi + s) / D;
+  return xi + kOmega * (b[i] - D * xi + nb_sum(L, x, y, z, x1)) / D;
 }
 
-// Residual b - A x of the fine cells of one aggregate, summed into the coarse rhs.
-__global__ __launch_bounds__(kThreads) void k_mg_restrict(MgLevelDev F, MgLevelDev C, const double* __restrict__ b,
-                                                const double* __restrict__ xv, double* __restrict__ bc,
-                                                const PcgState* st) {
+// Down leg of one level, fused: the two pre-smoothing sweeps (x written for
+// the up leg) and the restricted residual b - A x summed over each 2 x 2
+// (x 2) aggregate.  One thread per fine cell of a column pair in z; the
+// neighbours' sweeps are recomputed, so no grid-wide dependency remains.
+// x pairs are adjacent lanes, y pairs adjacent rows of the 64 x 4 block.
+__global__ __launch_bounds__(kThreads) void k_mg_down_restrict(MgLevelDev F, MgLevelDev C,
+                                                     const double* __restrict__ b, double* __restrict__ xout,
+                                                     double* __restrict__ bc, const PcgState* st) {
   if (pcg_done(st)) return;
-  const int X = blockIdx.x * kBX + threadIdx.x;
-  const int Y = blockIdx.y * kBY + threadIdx.y;
+  const int x = blockIdx.x * kBX + threadIdx.x;
+  const int y = blockIdx.y * kBY + threadIdx.y;
   const int Z = blockIdx.z;
-  if (X >= C.nx || Y >= C.ny) return;
-  const int x1 = min(2 * X + 1, F.nx - 1), y1 = min(2 * Y + 1, F.ny - 1);
   const int z0 = F.nz > 1 ? 2 * Z : 0, z1 = F.nz > 1 ? min(2 * Z + 1, F.nz - 1) : 0;
   double acc = 0.0;
-  for (int z = z0; z <= z1; ++z)
-    for (int y = 2 * Y; y <= y1; ++y)
-      for (int x = 2 * X; x <= x1; ++x) {
-        const int i = x + F.nx * (y + F.ny * z);
-        acc += b[i] - F.diag[i] * xv[i] + offdiag_sum(F.nx, F.ny, F.nz, F.tx, F.ty, F.tz, xv, x, y, z, i);
-      }
-  bc[X + C.nx * (Y + C.ny * Z)] = acc;
+  if (x < F.nx && y < F.ny) {
+    auto x2 = [&](int xx, int yy, int zz) { return sweep2_from_zero(F, b, xx, yy, zz); };
+    for (int z = z0; z <= z1; ++z) {
+      const int i = cidx(F, x, y, z);
+      const double xi = x2(x, y, z);
+      xout[i] = xi;
+      acc += b[i] - F.diag[i] * xi + nb_sum(F, x, y, z, x2);
+    }
+  }
+  acc += __shfl_xor(acc, 1, 64);
+  __shared__ double sh[kBY][kBX];
+  sh[threadIdx.y][threadIdx.x] = acc;
+  __syncthreads();
+  if ((threadIdx.x & 1) == 0 && (threadIdx.y & 1) == 0 && x < F.nx && y < F.ny) {
+    const int X = x >> 1, Y = y >> 1;
+    bc[X + C.nx * (Y + C.ny * Z)] = acc + sh[threadIdx.y + 1][threadIdx.x];
+  }
 }
 
-// y = xc + w (b - A xc) / D with xc = x + omega_c e[parent] (own and neighbour values).
-__global__ __launch_bounds__(kThreads) void k_mg_prolong_smooth(MgLevelDev F, MgLevelDev C, const double* __restrict__ b,
-                                                      const double* __restrict__ xv, const double* __restrict__ ec,
-                                                      double omega_c, double* __restrict__ yout, const PcgState* st) {
+// Up leg of one level, fused: coarse correction xc = x + omega_c e[parent],
+// one damped-Jacobi sweep y = xc + w (b - A xc) / D, and the last sweep
+// out = y + w (b - A y) / D, with the neighbours' y recomputed.  With
+// rz_slot >= 0 (the finest level, b = r) also accumulates r . out into the
+// CG ring slot.
+__global__ __launch_bounds__(kThreads) void k_mg_up_smooth(MgLevelDev F, MgLevelDev C, const double* __restrict__ b,
+                                                 const double* __restrict__ xv, const double* __restrict__ ec,
+                                                 double omega_c, double* __restrict__ out, PcgState* st,
+                                                 int rz_slot) {
   if (pcg_done(st)) return;
   const int x = blockIdx.x * kBX + threadIdx.x;
   const int y = blockIdx.y * kBY + threadIdx.y;
   const int z = blockIdx.z;
-  if (x >= F.nx || y >= F.ny) return;
-  const int nx = F.nx, ny = F.ny, nz = F.nz;
-  const int i = x + nx * (y + ny * z);
-  const int cz = nz > 1 ? 1 : 0;
-  auto xc = [&](int xx, int yy, int zz, int j) {
-    return xv[j] + omega_c * ec[(xx >> 1) + C.nx * ((yy >> 1) + C.ny * (zz >> cz))];
-  };
-  double s = 0.0;
-  if (x > 0) s += F.tx[fxi(nx, ny, x, y, z)] * xc(x - 1, y, z, i - 1);
-  if (x + 1 < nx) s += F.tx[fxi(nx, ny, x + 1, y, z)] * xc(x + 1, y, z, i + 1);
-  if (y > 0) s += F.ty[fyi(nx, ny, x, y, z)] * xc(x, y - 1, z, i - nx);
-  if (y + 1 < ny) s += F.ty[fyi(nx, ny, x, y + 1, z)] * xc(x, y + 1, z, i + nx);
-  if (z > 0) s += F.tz[fzi(nx, ny, x, y, z)] * xc(x, y, z - 1, i - nx * ny);
-  if (z + 1 < nz) s += F.tz[fzi(nx, ny, x, y, z + 1)] * xc(x, y, z + 1, i + nx * ny);
-  const double D = F.diag[i];
-  const double xi = xc(x, y, z, i);
-  yout[i] = xi + kOmega * (b[i] - D * xi + s) / D;
-}
-
-// Last Jacobi sweep: out = y + w (b - A y) / D.  With rz_slot >= 0 (the
-// finest level, b = r) also accumulates r . out into the CG ring slot.
-__global__ __launch_bounds__(kThreads) void k_mg_smooth_final(MgLevelDev L, const double* __restrict__ b,
-                                                    const double* __restrict__ yv, double* __restrict__ out,
-                                                    PcgState* st, int rz_slot) {
-  if (pcg_done(st)) return;
-  const int x = blockIdx.x * kBX + threadIdx.x;
-  const int y = blockIdx.y * kBY + threadIdx.y;
-  const int z = blockIdx.z;
+  const int cz = F.nz > 1 ? 1 : 0;
   double part = 0.0;
-  if (x < L.nx && y < L.ny) {
-    const int i = x + L.nx * (y + L.ny * z);
-    const double D = L.diag[i];
-    const double v =
-        yv[i] + kOmega * (b[i] - D * yv[i] + offdiag_sum(L.nx, L.ny, L.nz, L.tx, L.ty, L.tz, yv, x, y, z, i)) / D;
+  if (x < F.nx && y < F.ny) {
+    auto xc = [&](int xx, int yy, int zz) {
+      return xv[cidx(F, xx, yy, zz)] + omega_c * ec[(xx >> 1) + C.nx * ((yy >> 1) + C.ny * (zz >> cz))];
+    };
+    auto ys = [&](int xx, int yy, int zz) {
+      const int j = cidx(F, xx, yy, zz);
+      const double D = F.diag[j];
+      const double v = xc(xx, yy, zz);
+      return v + kOmega * (b[j] - D * v + nb_sum(F, xx, yy, zz, xc)) / D;
+    };
+    const int i = cidx(F, x, y, z);
+    const double D = F.diag[i];
+    const double yi = ys(x, y, z);
+    const double v = yi + kOmega * (b[i] - D * yi + nb_sum(F, x, y, z, ys)) / D;
     out[i] = v;
     part = b[i] * v;
   }
@@ -260,7 +269,9 @@ __device__ inline void lds_level(const MgCoarseArgs& a, double* smem, int l, Lds
   S.T = smem + a.off[l][6];
 }
 
-__device__ void lds_smooth(const MgLevelDev& L, const LdsLevel& S, int sweeps, bool from_zero) {
+// sweeps damped-Jacobi sweeps on one LDS level (E in, E out; T is scratch;
+// the roles swap after every sweep, so sweeps must be even).
+__device__ void lds_smooth(const MgLevelDev& L, LdsLevel S, int sweeps, bool from_zero) {
   const int n = L.nx * L.ny * L.nz;
   for (int sw = 0; sw < sweeps; ++sw) {
     for (int c = threadIdx.x; c < n; c += blockDim.x) {
@@ -276,8 +287,9 @@ __device__ void lds_smooth(const MgLevelDev& L, const LdsLevel& S, int sweeps, b
       S.T[c] = v;
     }
     __syncthreads();
-    for (int c = threadIdx.x; c < n; c += blockDim.x) S.E[c] = S.T[c];
-    __syncthreads();
+    double* t = S.E;
+    S.E = S.T;
+    S.T = t;
   }
 }
 
@@ -339,7 +351,9 @@ __global__ __launch_bounds__(1024) void k_mg_coarse_lds(MgCoarseArgs a, const do
     lds_level(a, smem, nl - 1, S);
     for (int r = threadIdx.x; r < nb; r += blockDim.x) {
       double acc = 0.0;
-      for (int j = 0; j < nb; ++j) acc += Binv[r * nb + j] * S.B[j];
+      // the inverse of the symmetric bottom operator is symmetric: read it
+      // by columns so that consecutive threads hit consecutive banks
+      for (int j = 0; j < nb; ++j) acc += Binv[j * nb + r] * S.B[j];
       S.E[r] = acc;
     }
     __syncthreads();
@@ -386,7 +400,7 @@ hipError_t mg_setup(const MgHierarchy& h, hipStream_t s) {
     const dim3 grid((C.nx + kBX - 1) / kBX, (C.ny + kBY - 1) / kBY, C.nz);
     hipLaunchKernelGGL(k_mg_coarsen, grid, cell_block(), 0, s, F, C);
   }
-  hipLaunchKernelGGL(k_mg_bottom_inverse, dim3(1), dim3(256), 0, s, h.lev[h.lb], h.binv);
+  hipLaunchKernelGGL(k_mg_bottom_inverse, dim3(1), dim3(1024), 0, s, h.lev[h.lb], h.binv);
   return hipGetLastError();
 }
 
@@ -401,8 +415,8 @@ hipError_t mg_apply(const MgHierarchy& h, const double* r, double* z, PcgState* 
     const MgLevelDev& F = h.lev[l];
     const MgLevelDev& C = h.lev[l + 1];
     const double* b = l == 0 ? r : F.b;
-    hipLaunchKernelGGL(k_mg_smooth_down, grid_of(F), cell_block(), 0, s, F, b, F.x, st);
-    hipLaunchKernelGGL(k_mg_restrict, grid_of(C), cell_block(), 0, s, F, C, b, F.x, C.b, st);
+    const dim3 g((F.nx + kBX - 1) / kBX, (F.ny + kBY - 1) / kBY, C.nz);
+    hipLaunchKernelGGL(k_mg_down_restrict, g, cell_block(), 0, s, F, C, b, F.x, C.b, st);
   }
   {
     const double* b = lc == 0 ? r : h.lev[lc].b;
@@ -410,13 +424,16 @@ hipError_t mg_apply(const MgHierarchy& h, const double* r, double* z, PcgState* 
     hipLaunchKernelGGL(k_mg_coarse_lds, dim3(1), dim3(h.coarse_threads), h.lds_bytes, s, h.coarse, b, h.binv,
                        out, st, lc == 0 ? rz_slot : -1);
   }
+  // The up leg reads its level's x at the neighbours, so it writes its result
+  // to y (z on the finest level); the LDS solve leaves its result in x.
   for (int l = lc - 1; l >= 0; --l) {
     const MgLevelDev& F = h.lev[l];
     const MgLevelDev& C = h.lev[l + 1];
     const double* b = l == 0 ? r : F.b;
-    double* out = l == 0 ? z : F.x;
-    hipLaunchKernelGGL(k_mg_prolong_smooth, grid_of(F), cell_block(), 0, s, F, C, b, F.x, C.x, h.omega_c, F.y, st);
-    hipLaunchKernelGGL(k_mg_smooth_final, grid_of(F), cell_block(), 0, s, F, b, F.y, out, st, l == 0 ? rz_slot : -1);
+    const double* ec = l + 1 == lc ? C.x : C.y;
+    double* out = l == 0 ? z : F.y;
+    hipLaunchKernelGGL(k_mg_up_smooth, grid_of(F), cell_block(), 0, s, F, C, b, F.x, ec, h.omega_c, out, st,
+                       l == 0 ? rz_slot : -1);
   }
   return hipGetLastError();
 }
