@@ -9,7 +9,7 @@ namespace erem {
 constexpr int kBX = 64;        // threads along x per block (one wavefront)
 constexpr int kBY = 4;         // rows per block -> 256 threads, 4 wavefronts
 constexpr int kThreads = kBX * kBY;
-constexpr int kSlots = 8;      // spread of the atomic partial sums
+constexpr int kSlots = 64;     // spread of the atomic partial sums (one wavefront sums them)
 constexpr int kMaxTerms = 1024;  // Leja degree cap per substep
 
 struct Dims {

@@ -41,11 +41,14 @@ __device__ inline void block_sum(double (&v)[NV]) {
   }
 }
 
-__device__ inline double slot_sum(const double* base) {
-  double s = 0.0;
-#pragma unroll
-  for (int j = 0; j < kSlots; ++j) s += base[j];
-  return s;
+// Sum of the kSlots partial sums at base, by one wavefront (kSlots == 64):
+// every lane loads one slot; a butterfly sums them and lane 0's result is
+// broadcast so that every lane takes the same decisions.
+static_assert(kSlots == 64, "one slot per lane");
+__device__ inline double wave_slot_sum(const double* base) {
+  double s = base[threadIdx.x & 63];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  return __shfl(s, 0, 64);  // lane 0's rounding for every lane
 }
 
 __device__ inline double rho_of(double T, const Phys& ph) {
@@ -613,29 +616,31 @@ __global__ __launch_bounds__(kThreads) void k_pcg_a(Dims d, const double* __rest
   __shared__ double beta_sh;
   __shared__ int stop_sh;
   const int t = tid_lin();
-  if (t == 0) {
+  if (t < 64) {  // the first wavefront decides
     int stop = *(volatile int*)&st->done;
     double beta = 0.0;
     if (!stop) {
-      const double rr = slot_sum(st->rr + (it & 3) * kSlots);
-      const double bb = slot_sum(st->bb_sl);
+      const double rr = wave_slot_sum(st->rr + (it & 3) * kSlots);
+      const double bb = wave_slot_sum(st->bb_sl);
+      const double rz1 = wave_slot_sum(st->rz + (it & 3) * kSlots);
+      const double rz0 = wave_slot_sum(st->rz + ((it - 1) & 3) * kSlots);
       if (!isfinite(rr)) {
         stop = 1;
-        if (bid_lin() == 0) { st->nonfinite = 1; st->done = 1; st->it_done = it; }
+        if (bid_lin() == 0 && t == 0) { st->nonfinite = 1; st->done = 1; st->it_done = it; }
       } else if (rr <= st->tol2 * bb) {
         stop = 1;
-        if (bid_lin() == 0) { st->done = 1; st->it_done = it; st->bb = bb; }
+        if (bid_lin() == 0 && t == 0) { st->done = 1; st->it_done = it; st->bb = bb; }
       } else if (it > 0) {
-        beta = slot_sum(st->rz + (it & 3) * kSlots) / slot_sum(st->rz + ((it - 1) & 3) * kSlots);
+        beta = rz1 / rz0;
       }
     }
-    stop_sh = stop;
-    beta_sh = beta;
+    if (t == 0) {
+      stop_sh = stop;
+      beta_sh = beta;
+    }
     if (!stop && bid_lin() == 0) {
-      for (int j = 0; j < kSlots; ++j) {
-        st->rz[((it + 1) & 3) * kSlots + j] = 0.0;
-        st->rr[((it + 1) & 3) * kSlots + j] = 0.0;
-      }
+      st->rz[((it + 1) & 3) * kSlots + t] = 0.0;
+      st->rr[((it + 1) & 3) * kSlots + t] = 0.0;
     }
   }
   __syncthreads();
@@ -675,13 +680,13 @@ __global__ __launch_bounds__(kThreads) void k_pcg_b(Dims d, double* __restrict__
   __shared__ double alpha_sh;
   __shared__ int stop_sh;
   const int t = tid_lin();
-  if (t == 0) {
+  if (t < 64) {  // the first wavefront decides
     const int stop = *(volatile int*)&st->done;
-    stop_sh = stop;
+    if (t == 0) stop_sh = stop;
     if (!stop) {
-      alpha_sh = slot_sum(st->rz + (it & 3) * kSlots) / slot_sum(st->pq + (it & 3) * kSlots);
-      if (bid_lin() == 0)
-        for (int j = 0; j < kSlots; ++j) st->pq[((it + 1) & 3) * kSlots + j] = 0.0;
+      const double alpha = wave_slot_sum(st->rz + (it & 3) * kSlots) / wave_slot_sum(st->pq + (it & 3) * kSlots);
+      if (t == 0) alpha_sh = alpha;
+      if (bid_lin() == 0) st->pq[((it + 1) & 3) * kSlots + t] = 0.0;
     }
   }
   __syncthreads();

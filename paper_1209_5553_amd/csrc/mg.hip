@@ -249,6 +249,139 @@ __global__ __launch_bounds__(kThreads) void k_mg_up_smooth(MgLevelDev F, MgLevel
 }
 
 // ---------------------------------------------------------------------------
+// 2D forms of the two legs with the intermediate sweep staged in LDS: a block
+// of 64 x 4 threads owns a tile of 64 x 8 cells (two rows per thread, so each
+// thread holds a whole y pair of aggregates), loads the first-sweep values on
+// the tile with a halo of two cells, computes the second sweep on the tile
+// with a halo of one into LDS, and finishes its own cells from there.  Same
+// arithmetic, in the same order, as the generic forms above.
+// ---------------------------------------------------------------------------
+constexpr int kTY = 8;           // tile rows (two per thread)
+constexpr int kW2 = kBX + 4;     // tile width with a halo of two
+constexpr int kH2 = kTY + 4;
+constexpr int kW1 = kBX + 2;     // with a halo of one
+constexpr int kH1 = kTY + 2;
+
+// sum over the four faces of (gx, gy) of t * v, v read from an LDS region
+// whose element (sy, sx) is the cell itself
+template <int W>
+__device__ inline double nb_sum_lds(const MgLevelDev& L, int gx, int gy, const double (*v)[W], int sy, int sx) {
+  const int nx = L.nx, ny = L.ny;
+  double s = 0.0;
+  if (gx > 0) s += L.tx[fxi(nx, ny, gx, gy, 0)] * v[sy][sx - 1];
+  if (gx + 1 < nx) s += L.tx[fxi(nx, ny, gx + 1, gy, 0)] * v[sy][sx + 1];
+  if (gy > 0) s += L.ty[fyi(nx, ny, gx, gy, 0)] * v[sy - 1][sx];
+  if (gy + 1 < ny) s += L.ty[fyi(nx, ny, gx, gy + 1, 0)] * v[sy + 1][sx];
+  return s;
+}
+
+__global__ __launch_bounds__(kThreads) void k_mg_down_restrict_2d(MgLevelDev F, MgLevelDev C,
+                                                        const double* __restrict__ b, double* __restrict__ xout,
+                                                        double* __restrict__ bc, const PcgState* st) {
+  if (pcg_done(st)) return;
+  __shared__ double sx1[kH2][kW2];
+  __shared__ double sx2[kH1][kW1];
+  const int nx = F.nx, ny = F.ny;
+  const int x0 = blockIdx.x * kBX, y0 = blockIdx.y * kTY;
+  const int tid = threadIdx.x + threadIdx.y * kBX;
+  for (int k = tid; k < kH2 * kW2; k += kThreads) {
+    const int ly = k / kW2, lx = k - ly * kW2;
+    const int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
+    double v = 0.0;
+    if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+      const int j = gx + nx * gy;
+      v = kOmega * b[j] / F.diag[j];
+    }
+    sx1[ly][lx] = v;
+  }
+  __syncthreads();
+  for (int k = tid; k < kH1 * kW1; k += kThreads) {
+    const int ly = k / kW1, lx = k - ly * kW1;
+    const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
+    double v = 0.0;
+    if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+      const int j = gx + nx * gy;
+      const double D = F.diag[j];
+      const double xi = sx1[ly + 1][lx + 1];
+      v = xi + kOmega * (b[j] - D * xi + nb_sum_lds<kW2>(F, gx, gy, sx1, ly + 1, lx + 1)) / D;
+      if (lx >= 1 && lx <= kBX && ly >= 1 && ly <= kTY) xout[j] = v;
+    }
+    sx2[ly][lx] = v;
+  }
+  __syncthreads();
+  const int gx = x0 + threadIdx.x;
+  double acc = 0.0;
+  for (int r = 0; r < 2; ++r) {
+    const int ly = 2 * threadIdx.y + r;
+    const int gy = y0 + ly;
+    if (gx < nx && gy < ny) {
+      const int i = gx + nx * gy;
+      const double xi = sx2[ly + 1][threadIdx.x + 1];
+      acc += b[i] - F.diag[i] * xi + nb_sum_lds<kW1>(F, gx, gy, sx2, ly + 1, threadIdx.x + 1);
+    }
+  }
+  acc += __shfl_xor(acc, 1, 64);
+  const int gy = y0 + 2 * threadIdx.y;
+  if ((threadIdx.x & 1) == 0 && gx < nx && gy < ny) bc[(gx >> 1) + C.nx * (gy >> 1)] = acc;
+}
+
+__global__ __launch_bounds__(kThreads) void k_mg_up_smooth_2d(MgLevelDev F, MgLevelDev C, const double* __restrict__ b,
+                                                    const double* __restrict__ xv, const double* __restrict__ ec,
+                                                    double omega_c, double* __restrict__ out, PcgState* st,
+                                                    int rz_slot) {
+  if (pcg_done(st)) return;
+  __shared__ double sxc[kH2][kW2];
+  __shared__ double sys[kH1][kW1];
+  const int nx = F.nx, ny = F.ny;
+  const int x0 = blockIdx.x * kBX, y0 = blockIdx.y * kTY;
+  const int tid = threadIdx.x + threadIdx.y * kBX;
+  for (int k = tid; k < kH2 * kW2; k += kThreads) {
+    const int ly = k / kW2, lx = k - ly * kW2;
+    const int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
+    double v = 0.0;
+    if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) v = xv[gx + nx * gy] + omega_c * ec[(gx >> 1) + C.nx * (gy >> 1)];
+    sxc[ly][lx] = v;
+  }
+  __syncthreads();
+  for (int k = tid; k < kH1 * kW1; k += kThreads) {
+    const int ly = k / kW1, lx = k - ly * kW1;
+    const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
+    double v = 0.0;
+    if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+      const int j = gx + nx * gy;
+      const double D = F.diag[j];
+      const double xi = sxc[ly + 1][lx + 1];
+      v = xi + kOmega * (b[j] - D * xi + nb_sum_lds<kW2>(F, gx, gy, sxc, ly + 1, lx + 1)) / D;
+    }
+    sys[ly][lx] = v;
+  }
+  __syncthreads();
+  const int gx = x0 + threadIdx.x;
+  double part = 0.0;
+  for (int r = 0; r < 2; ++r) {
+    const int ly = 2 * threadIdx.y + r;
+    const int gy = y0 + ly;
+    if (gx < nx && gy < ny) {
+      const int i = gx + nx * gy;
+      const double D = F.diag[i];
+      const double yi = sys[ly + 1][threadIdx.x + 1];
+      const double v = yi + kOmega * (b[i] - D * yi + nb_sum_lds<kW1>(F, gx, gy, sys, ly + 1, threadIdx.x + 1)) / D;
+      out[i] = v;
+      part += b[i] * v;
+    }
+  }
+  if (rz_slot < 0) return;
+  for (int off = 32; off > 0; off >>= 1) part += __shfl_down(part, off, 64);
+  __shared__ double sh[kThreads / 64];
+  if ((tid & 63) == 0) sh[tid >> 6] = part;
+  __syncthreads();
+  if (tid == 0) {
+    const int bid = blockIdx.x + gridDim.x * blockIdx.y;
+    atomicAdd(&st->rz[rz_slot * kSlots + (bid & (kSlots - 1))], sh[0] + sh[1] + sh[2] + sh[3]);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Coarse levels in one workgroup, everything in LDS: one V-cycle over the
 // levels first..bottom-1 with the exact dense solve on the bottom level,
 // from x = 0, on rhs b (global).  Writes x to out; with rz_slot >= 0 also
@@ -415,8 +548,13 @@ hipError_t mg_apply(const MgHierarchy& h, const double* r, double* z, PcgState* 
     const MgLevelDev& F = h.lev[l];
     const MgLevelDev& C = h.lev[l + 1];
     const double* b = l == 0 ? r : F.b;
-    const dim3 g((F.nx + kBX - 1) / kBX, (F.ny + kBY - 1) / kBY, C.nz);
-    hipLaunchKernelGGL(k_mg_down_restrict, g, cell_block(), 0, s, F, C, b, F.x, C.b, st);
+    if (F.nz == 1) {
+      const dim3 g((F.nx + kBX - 1) / kBX, (F.ny + kTY - 1) / kTY, 1);
+      hipLaunchKernelGGL(k_mg_down_restrict_2d, g, cell_block(), 0, s, F, C, b, F.x, C.b, st);
+    } else {
+      const dim3 g((F.nx + kBX - 1) / kBX, (F.ny + kBY - 1) / kBY, C.nz);
+      hipLaunchKernelGGL(k_mg_down_restrict, g, cell_block(), 0, s, F, C, b, F.x, C.b, st);
+    }
   }
   {
     const double* b = lc == 0 ? r : h.lev[lc].b;
@@ -432,8 +570,14 @@ hipError_t mg_apply(const MgHierarchy& h, const double* r, double* z, PcgState* 
     const double* b = l == 0 ? r : F.b;
     const double* ec = l + 1 == lc ? C.x : C.y;
     double* out = l == 0 ? z : F.y;
-    hipLaunchKernelGGL(k_mg_up_smooth, grid_of(F), cell_block(), 0, s, F, C, b, F.x, ec, h.omega_c, out, st,
-                       l == 0 ? rz_slot : -1);
+    if (F.nz == 1) {
+      const dim3 g((F.nx + kBX - 1) / kBX, (F.ny + kTY - 1) / kTY, 1);
+      hipLaunchKernelGGL(k_mg_up_smooth_2d, g, cell_block(), 0, s, F, C, b, F.x, ec, h.omega_c, out, st,
+                         l == 0 ? rz_slot : -1);
+    } else {
+      hipLaunchKernelGGL(k_mg_up_smooth, grid_of(F), cell_block(), 0, s, F, C, b, F.x, ec, h.omega_c, out, st,
+                         l == 0 ? rz_slot : -1);
+    }
   }
   return hipGetLastError();
 }
