@@ -311,9 +311,11 @@ typedef struct {
     int64_t adj_rev_launches;
 } erem_kernel_times;
 
-/* Turn per-launch event timing on (enable != 0) or off and reset the
- * counters.  Synchronises the stream.  Profiling adds one event record per
- * launch (up to 8 substeps per evaluation are timed). */
+/* Per-launch event timing: enable = 0 turns it off, enable = n > 0 times one
+ * launch in n (Newton terms whose index is a multiple of n, CG iterations
+ * whose index is a multiple of n: a sample that keeps the event overhead
+ * small), and resets the counters.  Synchronises the stream.  Up to 8
+ * substeps per evaluation are timed.  The averages are per timed launch. */
 int erem_profile(erem_ctx* ctx, int32_t enable);
 int erem_profile_read(erem_ctx* ctx, erem_kernel_times* out);
 

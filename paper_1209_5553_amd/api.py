@@ -218,8 +218,9 @@ class EremContext:
             ctypes.byref(st)), "erem_coupled_step_adjoint")
         return st.as_dict()
 
-    def profile(self, enable: bool = True):
-        self._check(self.lib.erem_profile(self.handle, 1 if enable else 0), "erem_profile")
+    def profile(self, enable: bool = True, stride: int = 1):
+        """Per-launch event timing on (one launch in ``stride``) or off."""
+        self._check(self.lib.erem_profile(self.handle, int(stride) if enable else 0), "erem_profile")
 
     def profile_read(self):
         kt = nat.KernelTimes()

@@ -282,16 +282,20 @@ int erem_coupled_step_adjoint(erem_ctx* c, double h, const double* d_T, double p
         }
         q = c->adj_seg + static_cast<size_t>(kk - a * S) * N;
       }
-      if (c->prof) HIP_TRY(c, hipEventRecord(c->ev[2 * (m - k)], c->stream));
+      const bool timed = c->prof && k % c->prof == 0;
+      if (timed) HIP_TRY(c, hipEventRecord(c->ev[2 * (m - k)], c->stream));
       HIP_TRY(c, launch_adj_rev_term(d, c->coef, sin, q, c->adj_ubar, delta * dk[kk], inv_g, shift[k], c->adj_jbar,
                                      sout, c->stream));
-      if (c->prof) HIP_TRY(c, hipEventRecord(c->ev[2 * (m - k) + 1], c->stream));
+      if (timed) HIP_TRY(c, hipEventRecord(c->ev[2 * (m - k) + 1], c->stream));
       std::swap(sin, sout);
     }
     if (c->prof) {
       HIP_TRY(c, hipStreamSynchronize(c->stream));
-      for (int k = 0; k < m; ++k) c->t_adj += elapsed_ms(c->ev[2 * k], c->ev[2 * k + 1]);
-      c->n_adj += m;
+      for (int k = m; k >= 1; --k) {
+        if (k % c->prof != 0) continue;
+        c->t_adj += elapsed_ms(c->ev[2 * (m - k)], c->ev[2 * (m - k) + 1]);
+        ++c->n_adj;
+      }
     }
     HIP_TRY(c, launch_adj_substep(d, c->coef, sin, j > 0 ? c->adj_u + j * N : nullptr, c->adj_wbar, c->adj_ubar,
                                   c->adj_jbar, c->stream));

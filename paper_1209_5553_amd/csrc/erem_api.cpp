@@ -117,14 +117,14 @@ size_t mg_lds_layout(const MgHierarchy& h, int lc, MgCoarseArgs* a) {
       const size_t nfx = static_cast<size_t>(L.nx + 1) * L.ny * L.nz;
       const size_t nfy = static_cast<size_t>(L.nx) * (L.ny + 1) * L.nz;
       const size_t nfz = L.nz > 1 ? static_cast<size_t>(L.nx) * L.ny * (L.nz + 1) : 0;
-      const size_t sizes[7] = {nfx, nfy, nfz, n, n, n, n};
-      for (int k = 0; k < 7; ++k) {
+      const size_t sizes[8] = {nfx, nfy, nfz, n, n, n, n, n};
+      for (int k = 0; k < 8; ++k) {
         if (off) off[k] = static_cast<int>(w);
         w += sizes[k];
       }
     } else {
       if (off) {
-        for (int k = 0; k < 7; ++k) off[k] = 0;
+        for (int k = 0; k < 8; ++k) off[k] = 0;
         off[4] = static_cast<int>(w);
         off[5] = static_cast<int>(w + n);
       }
@@ -287,9 +287,10 @@ int leja_run(erem_ctx* c, const LejaBufs<V>& B, const double* v, double delta, i
     for (int k = 1; k <= K; ++k) {
       const V* qin = (k & 1) ? B.qa : B.qb;
       V* qout = (k & 1) ? B.qb : B.qa;
-      if (evj) HIP_TRY(c, hipEventRecord(evj[2 * (k - 1)], c->stream));
+      const bool timed = evj && k % c->prof == 0;
+      if (timed) HIP_TRY(c, hipEventRecord(evj[2 * (k - 1)], c->stream));
       HIP_TRY(c, launch_leja_term<V>(d, c->cf, B.coef, qin, qout, B.p, st, c->part, k, c->stream));
-      if (evj) HIP_TRY(c, hipEventRecord(evj[2 * (k - 1) + 1], c->stream));
+      if (timed) HIP_TRY(c, hipEventRecord(evj[2 * (k - 1) + 1], c->stream));
       if (k % kCheckEvery == 0 || k == K) {
         HIP_TRY(c, launch_leja_check(d, c->cf, st, c->part, prev + 1, k, c->stream));
         prev = k;
@@ -361,8 +362,10 @@ int leja_hphi1(erem_ctx* c, double h, const double* v, double scal, int s, int K
     last = hc->estf[st.stopped] * std::sqrt(st.sums[st.stopped]);
     if (j < nprof) {
       const hipEvent_t* evj = &c->ev[static_cast<size_t>(j) * 2 * K];
-      for (int k = 1; k <= applied; ++k) c->t_leja += elapsed_ms(evj[2 * (k - 1)], evj[2 * (k - 1) + 1]);
-      c->n_leja += applied;
+      for (int k = c->prof; k <= applied; k += c->prof) {
+        c->t_leja += elapsed_ms(evj[2 * (k - 1)], evj[2 * (k - 1) + 1]);
+        ++c->n_leja;
+      }
     }
   }
   *m_used = total;
@@ -564,22 +567,23 @@ int pcg_inner(erem_ctx* c, double inner_tol, int budget, int* iters, bool* done)
   int it = 0;
   *done = false;
   if (c->prof) {
-    const int rc = ensure_events(c, 3 * chunk + 1);
+    const int rc = ensure_events(c, 4 * chunk);
     if (rc) return rc;
   }
   while (it < budget) {
     const int n = std::min(chunk, budget - it);
     const int it0 = it;
-    if (c->prof) HIP_TRY(c, hipEventRecord(c->ev[0], c->stream));
     for (int j = 0; j < n; ++j, ++it) {
       double* pold = (it & 1) ? c->pp1 : c->pp0;
       double* pnew = (it & 1) ? c->pp0 : c->pp1;
+      const bool timed = c->prof && it % c->prof == 0;  // sampled iterations
+      if (timed) HIP_TRY(c, hipEventRecord(c->ev[4 * j], c->stream));
       HIP_TRY(c, launch_pcg_a(d, c->tx, c->ty, c->tz, c->pz, pold, pnew, c->pq, c->pcg, it, c->stream));
-      if (c->prof) HIP_TRY(c, hipEventRecord(c->ev[3 * j + 1], c->stream));
+      if (timed) HIP_TRY(c, hipEventRecord(c->ev[4 * j + 1], c->stream));
       HIP_TRY(c, launch_pcg_b(d, c->pdelta, c->pr, c->pz, pnew, c->pq, c->pdiag, c->pcg, it, jac, c->stream));
-      if (c->prof) HIP_TRY(c, hipEventRecord(c->ev[3 * j + 2], c->stream));
+      if (timed) HIP_TRY(c, hipEventRecord(c->ev[4 * j + 2], c->stream));
       if (c->use_mg) HIP_TRY(c, mg_apply(c->mg, c->pr, c->pz, c->pcg, (it + 1) & 3, c->stream));
-      if (c->prof) HIP_TRY(c, hipEventRecord(c->ev[3 * j + 3], c->stream));
+      if (timed) HIP_TRY(c, hipEventRecord(c->ev[4 * j + 3], c->stream));
     }
     HIP_TRY(c, hipMemcpyAsync(c->h_pcg, c->pcg, sizeof(PcgState), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -589,13 +593,16 @@ int pcg_inner(erem_ctx* c, double inner_tol, int budget, int* iters, bool* done)
       // iterations it0 .. it_done-1 ran fully; the test launch it_done returned at entry
       const int ran = fin ? c->h_pcg->it_done - it0 : n;
       for (int j = 0; j < ran; ++j) {
-        c->t_pcg_a += elapsed_ms(c->ev[3 * j], c->ev[3 * j + 1]);
-        c->t_pcg_b += elapsed_ms(c->ev[3 * j + 1], c->ev[3 * j + 2]);
-        if (c->use_mg) c->t_mg += elapsed_ms(c->ev[3 * j + 2], c->ev[3 * j + 3]);
+        if ((it0 + j) % c->prof != 0) continue;
+        c->t_pcg_a += elapsed_ms(c->ev[4 * j], c->ev[4 * j + 1]);
+        c->t_pcg_b += elapsed_ms(c->ev[4 * j + 1], c->ev[4 * j + 2]);
+        ++c->n_pcg_a;
+        ++c->n_pcg_b;
+        if (c->use_mg) {
+          c->t_mg += elapsed_ms(c->ev[4 * j + 2], c->ev[4 * j + 3]);
+          ++c->n_mg;
+        }
       }
-      c->n_pcg_a += ran;
-      c->n_pcg_b += ran;
-      if (c->use_mg) c->n_mg += ran;
     }
     if (fin) { *done = true; it = c->h_pcg->it_done; break; }
   }
@@ -1007,7 +1014,7 @@ int erem_step_frozen(erem_ctx* c, double h, double* d_T, const erem_opts* o, ere
 int erem_profile(erem_ctx* c, int32_t enable) {
   if (!c) return EREM_EINVAL;
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  c->prof = enable != 0;
+  c->prof = enable > 0 ? enable : 0;
   c->t_leja = c->t_pcg_a = c->t_pcg_b = c->t_mg = c->t_adj = 0.0;
   c->n_leja = c->n_pcg_a = c->n_pcg_b = c->n_mg = c->n_adj = 0;
   return EREM_OK;

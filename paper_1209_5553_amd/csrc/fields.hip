@@ -616,6 +616,29 @@ __global__ __launch_bounds__(kThreads) void k_pcg_a(Dims d, const double* __rest
   __shared__ double beta_sh;
   __shared__ int stop_sh;
   const int t = tid_lin();
+  // operands first, so that their loads overlap the scalar decision below
+  const int x = blockIdx.x * kBX + threadIdx.x;
+  const int y = blockIdx.y * kBY + threadIdx.y;
+  const int z = blockIdx.z;
+  const bool in = x < d.nx && y < d.ny;
+  const int i = x + d.nx * (y + d.ny * z);
+  const int pl = d.nx * d.ny;
+  FaceT f{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double zc = 0.0, pc = 0.0;
+  double zn[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0}, pn[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  const bool has[6] = {x > 0, x + 1 < d.nx, y > 0, y + 1 < d.ny, z > 0, z + 1 < d.nz};
+  const int nbi[6] = {i - 1, i + 1, i - d.nx, i + d.nx, i - pl, i + pl};
+  if (in) {
+    f = load_faces(d, tx, ty, tz, x, y, z);
+    zc = zv[i];
+    pc = pold[i];
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+      if (has[k]) {
+        zn[k] = zv[nbi[k]];
+        pn[k] = pold[nbi[k]];
+      }
+  }
   if (t < 64) {  // the first wavefront decides
     int stop = *(volatile int*)&st->done;
     double beta = 0.0;
@@ -646,23 +669,15 @@ __global__ __launch_bounds__(kThreads) void k_pcg_a(Dims d, const double* __rest
   __syncthreads();
   if (stop_sh) return;
   const double beta = beta_sh;
-  const int x = blockIdx.x * kBX + threadIdx.x;
-  const int y = blockIdx.y * kBY + threadIdx.y;
-  const int z = blockIdx.z;
   double s[1] = {0.0};
-  if (x < d.nx && y < d.ny) {
-    const int i = x + d.nx * (y + d.ny * z);
-    const int pl = d.nx * d.ny;
-    const FaceT f = load_faces(d, tx, ty, tz, x, y, z);
+  if (in) {
+    const double fk[6] = {f.w, f.e, f.s, f.n, f.b, f.t};
     const double dg = f.w + f.e + f.s + f.n + f.b + f.t;
-    const double pi = zv[i] + beta * pold[i];
+    const double pi = zc + beta * pc;
     double Ap = dg * pi;
-    if (x > 0) Ap -= f.w * (zv[i - 1] + beta * pold[i - 1]);
-    if (x + 1 < d.nx) Ap -= f.e * (zv[i + 1] + beta * pold[i + 1]);
-    if (y > 0) Ap -= f.s * (zv[i - d.nx] + beta * pold[i - d.nx]);
-    if (y + 1 < d.ny) Ap -= f.n * (zv[i + d.nx] + beta * pold[i + d.nx]);
-    if (z > 0) Ap -= f.b * (zv[i - pl] + beta * pold[i - pl]);
-    if (z + 1 < d.nz) Ap -= f.t * (zv[i + pl] + beta * pold[i + pl]);
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+      if (has[k]) Ap -= fk[k] * (zn[k] + beta * pn[k]);
     pnew[i] = pi;
     q[i] = Ap;
     s[0] = pi * Ap;
@@ -680,6 +695,20 @@ __global__ __launch_bounds__(kThreads) void k_pcg_b(Dims d, double* __restrict__
   __shared__ double alpha_sh;
   __shared__ int stop_sh;
   const int t = tid_lin();
+  // operands first, so that their loads overlap the scalar decision below
+  const int x = blockIdx.x * kBX + threadIdx.x;
+  const int y = blockIdx.y * kBY + threadIdx.y;
+  const int z = blockIdx.z;
+  const bool in = x < d.nx && y < d.ny;
+  const int i = x + d.nx * (y + d.ny * z);
+  double xi = 0.0, pi = 0.0, ri = 0.0, qi = 0.0, di = 1.0;
+  if (in) {
+    xi = xv[i];
+    pi = pnew[i];
+    ri = r[i];
+    qi = q[i];
+    if (jacobi) di = diag[i];
+  }
   if (t < 64) {  // the first wavefront decides
     const int stop = *(volatile int*)&st->done;
     if (t == 0) stop_sh = stop;
@@ -692,21 +721,17 @@ __global__ __launch_bounds__(kThreads) void k_pcg_b(Dims d, double* __restrict__
   __syncthreads();
   if (stop_sh) return;
   const double alpha = alpha_sh;
-  const int x = blockIdx.x * kBX + threadIdx.x;
-  const int y = blockIdx.y * kBY + threadIdx.y;
-  const int z = blockIdx.z;
   double s[2] = {0.0, 0.0};
-  if (x < d.nx && y < d.ny) {
-    const int i = x + d.nx * (y + d.ny * z);
-    xv[i] += alpha * pnew[i];
-    const double ri = r[i] - alpha * q[i];
-    r[i] = ri;
+  if (in) {
+    xv[i] = xi + alpha * pi;
+    const double rn = ri - alpha * qi;
+    r[i] = rn;
     if (jacobi) {
-      const double zi = ri / diag[i];
+      const double zi = rn / di;
       zv[i] = zi;
-      s[0] = ri * zi;
+      s[0] = rn * zi;
     }
-    s[1] = ri * ri;
+    s[1] = rn * rn;
   }
   block_sum<2>(s);
   if (t == 0) {

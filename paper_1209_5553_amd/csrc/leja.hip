@@ -75,7 +75,9 @@ __global__ __launch_bounds__(kThreads) void k_leja_term(Dims d, const LejaCoef* 
                                               V* __restrict__ qout, V* __restrict__ p,
                                               const LejaState* __restrict__ st, double* __restrict__ part,
                                               int nb, int k) {
-  if (*(volatile const int*)&st->stopped >= 0) return;  // stop test already passed
+  // the stop flag is read while the operand loads are in flight; nothing is
+  // written before it is known
+  const bool stopped = *(volatile const int*)&st->stopped >= 0;
   const int x = blockIdx.x * kBX + threadIdx.x;
   const int y = blockIdx.y * kBY + threadIdx.y;
   const int z = blockIdx.z;
@@ -95,9 +97,13 @@ __global__ __launch_bounds__(kThreads) void k_leja_term(Dims d, const LejaCoef* 
       jq += coef[6 * N + i] * qin[z + 1 < d.nz ? i + pl : i];
     }
     const V r = jq * to_v<V>(cf->inv_g) - to_v<V>(cf->shift[k]) * qi;
-    p[i] += to_v<V>(cf->dk[k]) * r;
+    const V pi = p[i];
+    if (stopped) return;
+    p[i] = pi + to_v<V>(cf->dk[k]) * r;
     qout[i] = r;
     s = static_cast<double>(r) * static_cast<double>(r);
+  } else if (stopped) {
+    return;
   }
   s = block_sum256(s);
   if (threadIdx.x == 0 && threadIdx.y == 0) part[(k % kLejaRing) * nb + block_id()] = s;

@@ -23,10 +23,10 @@ struct MgLevelDev {
 struct MgCoarseArgs {
   int nlev;                    // levels handled in LDS (the last is the bottom)
   int n0;                      // cells of the first of them
-  int nu;                      // Jacobi sweeps before and after the coarse correction
+  int nu;                      // Jacobi sweeps before and after the coarse correction (the kernels do two)
   int inv_off;                 // LDS offset of the bottom inverse
   double omega_c;              // coarse-correction relaxation
-  int off[kMgMaxLevels][7];    // LDS offsets: tx, ty, tz, diag, B, E, T per level
+  int off[kMgMaxLevels][8];    // LDS offsets: tx, ty, tz, diag, B, E, T, 1/diag per level
   MgLevelDev lev[kMgMaxLevels];
 };
 

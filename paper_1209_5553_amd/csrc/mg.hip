@@ -249,12 +249,12 @@ __global__ __launch_bounds__(kThreads) void k_mg_up_smooth(MgLevelDev F, MgLevel
 }
 
 // ---------------------------------------------------------------------------
-// 2D forms of the two legs with the intermediate sweep staged in LDS: a block
-// of 64 x 4 threads owns a tile of 64 x 8 cells (two rows per thread, so each
-// thread holds a whole y pair of aggregates), loads the first-sweep values on
-// the tile with a halo of two cells, computes the second sweep on the tile
-// with a halo of one into LDS, and finishes its own cells from there.  Same
-// arithmetic, in the same order, as the generic forms above.
+// 2D forms of the two legs.  A block of 64 x 4 threads owns a tile of 64 x 8
+// cells (two rows per thread, so each thread holds a whole y pair of
+// aggregates).  Every global operand of the tile and its halo (two cells for
+// the first sweep, one for the second) is loaded into LDS in one phase, so the
+// chain of dependent memory latencies is a single one; the sweeps then run
+// from LDS.  Same arithmetic, in the same order, as the generic forms above.
 // ---------------------------------------------------------------------------
 constexpr int kTY = 8;           // tile rows (two per thread)
 constexpr int kW2 = kBX + 4;     // tile width with a halo of two
@@ -262,49 +262,71 @@ constexpr int kH2 = kTY + 4;
 constexpr int kW1 = kBX + 2;     // with a halo of one
 constexpr int kH1 = kTY + 2;
 
-// sum over the four faces of (gx, gy) of t * v, v read from an LDS region
-// whose element (sy, sx) is the cell itself
-template <int W>
-__device__ inline double nb_sum_lds(const MgLevelDev& L, int gx, int gy, const double (*v)[W], int sy, int sx) {
+// Faces of the halo-one region: x faces of its rows (face gx of cell gx is
+// its -x face) and y faces of its columns.
+struct TileFaces {
+  double tx[kH1][kW1 + 1];
+  double ty[kH1 + 1][kW1];
+};
+
+__device__ inline void load_tile_faces(const MgLevelDev& L, int x0, int y0, int tid, TileFaces& F) {
   const int nx = L.nx, ny = L.ny;
+  for (int k = tid; k < kH1 * (kW1 + 1); k += kThreads) {
+    const int ly = k / (kW1 + 1), lx = k - ly * (kW1 + 1);
+    const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
+    F.tx[ly][lx] = (gx >= 0 && gx <= nx && gy >= 0 && gy < ny) ? L.tx[fxi(nx, ny, gx, gy, 0)] : 0.0;
+  }
+  for (int k = tid; k < (kH1 + 1) * kW1; k += kThreads) {
+    const int ly = k / kW1, lx = k - ly * kW1;
+    const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
+    F.ty[ly][lx] = (gx >= 0 && gx < nx && gy >= 0 && gy <= ny) ? L.ty[fyi(nx, ny, gx, gy, 0)] : 0.0;
+  }
+}
+
+// Neighbour sum of the halo-one cell (l1x, l1y) at (gx, gy), values v in a
+// region whose element (sy, sx) is that cell.
+template <int W>
+__device__ inline double nb_sum_tile(const TileFaces& F, int nx, int ny, int gx, int gy, int l1x, int l1y,
+                                     const double (*v)[W], int sy, int sx) {
   double s = 0.0;
-  if (gx > 0) s += L.tx[fxi(nx, ny, gx, gy, 0)] * v[sy][sx - 1];
-  if (gx + 1 < nx) s += L.tx[fxi(nx, ny, gx + 1, gy, 0)] * v[sy][sx + 1];
-  if (gy > 0) s += L.ty[fyi(nx, ny, gx, gy, 0)] * v[sy - 1][sx];
-  if (gy + 1 < ny) s += L.ty[fyi(nx, ny, gx, gy + 1, 0)] * v[sy + 1][sx];
+  if (gx > 0) s += F.tx[l1y][l1x] * v[sy][sx - 1];
+  if (gx + 1 < nx) s += F.tx[l1y][l1x + 1] * v[sy][sx + 1];
+  if (gy > 0) s += F.ty[l1y][l1x] * v[sy - 1][sx];
+  if (gy + 1 < ny) s += F.ty[l1y + 1][l1x] * v[sy + 1][sx];
   return s;
 }
 
 __global__ __launch_bounds__(kThreads) void k_mg_down_restrict_2d(MgLevelDev F, MgLevelDev C,
                                                         const double* __restrict__ b, double* __restrict__ xout,
                                                         double* __restrict__ bc, const PcgState* st) {
-  if (pcg_done(st)) return;
-  __shared__ double sx1[kH2][kW2];
-  __shared__ double sx2[kH1][kW1];
+  const bool stop = pcg_done(st);
+  __shared__ double sb[kH2][kW2], sd[kH2][kW2], sx1[kH2][kW2], sx2[kH1][kW1];
+  __shared__ TileFaces tf;
   const int nx = F.nx, ny = F.ny;
   const int x0 = blockIdx.x * kBX, y0 = blockIdx.y * kTY;
   const int tid = threadIdx.x + threadIdx.y * kBX;
   for (int k = tid; k < kH2 * kW2; k += kThreads) {
     const int ly = k / kW2, lx = k - ly * kW2;
     const int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
-    double v = 0.0;
-    if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
-      const int j = gx + nx * gy;
-      v = kOmega * b[j] / F.diag[j];
-    }
-    sx1[ly][lx] = v;
+    const bool in = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+    const int j = gx + nx * gy;
+    const double bj = in ? b[j] : 0.0, dj = in ? F.diag[j] : 1.0;
+    sb[ly][lx] = bj;
+    sd[ly][lx] = dj;
+    sx1[ly][lx] = kOmega * bj / dj;  // first sweep from zero
   }
+  load_tile_faces(F, x0, y0, tid, tf);
+  if (stop) return;
   __syncthreads();
   for (int k = tid; k < kH1 * kW1; k += kThreads) {
     const int ly = k / kW1, lx = k - ly * kW1;
     const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
     double v = 0.0;
     if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
-      const int j = gx + nx * gy;
-      const double D = F.diag[j];
+      const double D = sd[ly + 1][lx + 1];
       const double xi = sx1[ly + 1][lx + 1];
-      v = xi + kOmega * (b[j] - D * xi + nb_sum_lds<kW2>(F, gx, gy, sx1, ly + 1, lx + 1)) / D;
-      if (lx >= 1 && lx <= kBX && ly >= 1 && ly <= kTY) xout[j] = v;
+      v = xi + kOmega * (sb[ly + 1][lx + 1] - D * xi + nb_sum_tile<kW2>(tf, nx, ny, gx, gy, lx, ly, sx1, ly + 1, lx + 1)) / D;
+      if (lx >= 1 && lx <= kBX && ly >= 1 && ly <= kTY) xout[gx + nx * gy] = v;
     }
     sx2[ly][lx] = v;
   }
@@ -315,9 +337,10 @@ __global__ __launch_bounds__(kThreads) void k_mg_down_restrict_2d(MgLevelDev F, 
     const int ly = 2 * threadIdx.y + r;
     const int gy = y0 + ly;
     if (gx < nx && gy < ny) {
-      const int i = gx + nx * gy;
-      const double xi = sx2[ly + 1][threadIdx.x + 1];
-      acc += b[i] - F.diag[i] * xi + nb_sum_lds<kW1>(F, gx, gy, sx2, ly + 1, threadIdx.x + 1);
+      const int l1x = threadIdx.x + 1, l1y = ly + 1;
+      const double xi = sx2[l1y][l1x];
+      acc += sb[l1y + 1][l1x + 1] - sd[l1y + 1][l1x + 1] * xi +
+             nb_sum_tile<kW1>(tf, nx, ny, gx, gy, l1x, l1y, sx2, l1y, l1x);
     }
   }
   acc += __shfl_xor(acc, 1, 64);
@@ -329,9 +352,9 @@ __global__ __launch_bounds__(kThreads) void k_mg_up_smooth_2d(MgLevelDev F, MgLe
                                                     const double* __restrict__ xv, const double* __restrict__ ec,
                                                     double omega_c, double* __restrict__ out, PcgState* st,
                                                     int rz_slot) {
-  if (pcg_done(st)) return;
-  __shared__ double sxc[kH2][kW2];
-  __shared__ double sys[kH1][kW1];
+  const bool stop = pcg_done(st);
+  __shared__ double sxc[kH2][kW2], sb[kH1][kW1], sd[kH1][kW1], sys[kH1][kW1];
+  __shared__ TileFaces tf;
   const int nx = F.nx, ny = F.ny;
   const int x0 = blockIdx.x * kBX, y0 = blockIdx.y * kTY;
   const int tid = threadIdx.x + threadIdx.y * kBX;
@@ -342,16 +365,25 @@ __global__ __launch_bounds__(kThreads) void k_mg_up_smooth_2d(MgLevelDev F, MgLe
     if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) v = xv[gx + nx * gy] + omega_c * ec[(gx >> 1) + C.nx * (gy >> 1)];
     sxc[ly][lx] = v;
   }
+  for (int k = tid; k < kH1 * kW1; k += kThreads) {
+    const int ly = k / kW1, lx = k - ly * kW1;
+    const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
+    const bool in = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+    const int j = gx + nx * gy;
+    sb[ly][lx] = in ? b[j] : 0.0;
+    sd[ly][lx] = in ? F.diag[j] : 1.0;
+  }
+  load_tile_faces(F, x0, y0, tid, tf);
+  if (stop) return;
   __syncthreads();
   for (int k = tid; k < kH1 * kW1; k += kThreads) {
     const int ly = k / kW1, lx = k - ly * kW1;
     const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
     double v = 0.0;
     if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
-      const int j = gx + nx * gy;
-      const double D = F.diag[j];
+      const double D = sd[ly][lx];
       const double xi = sxc[ly + 1][lx + 1];
-      v = xi + kOmega * (b[j] - D * xi + nb_sum_lds<kW2>(F, gx, gy, sxc, ly + 1, lx + 1)) / D;
+      v = xi + kOmega * (sb[ly][lx] - D * xi + nb_sum_tile<kW2>(tf, nx, ny, gx, gy, lx, ly, sxc, ly + 1, lx + 1)) / D;
     }
     sys[ly][lx] = v;
   }
@@ -362,12 +394,13 @@ __global__ __launch_bounds__(kThreads) void k_mg_up_smooth_2d(MgLevelDev F, MgLe
     const int ly = 2 * threadIdx.y + r;
     const int gy = y0 + ly;
     if (gx < nx && gy < ny) {
-      const int i = gx + nx * gy;
-      const double D = F.diag[i];
-      const double yi = sys[ly + 1][threadIdx.x + 1];
-      const double v = yi + kOmega * (b[i] - D * yi + nb_sum_lds<kW1>(F, gx, gy, sys, ly + 1, threadIdx.x + 1)) / D;
-      out[i] = v;
-      part += b[i] * v;
+      const int l1x = threadIdx.x + 1, l1y = ly + 1;
+      const double D = sd[l1y][l1x];
+      const double yi = sys[l1y][l1x];
+      const double bi = sb[l1y][l1x];
+      const double v = yi + kOmega * (bi - D * yi + nb_sum_tile<kW1>(tf, nx, ny, gx, gy, l1x, l1y, sys, l1y, l1x)) / D;
+      out[gx + nx * gy] = v;
+      part += bi * v;
     }
   }
   if (rz_slot < 0) return;
@@ -389,7 +422,7 @@ __global__ __launch_bounds__(kThreads) void k_mg_up_smooth_2d(MgLevelDev F, MgLe
 // three vectors; bottom: two vectors and the inverse; plus the rhs copy.
 // ---------------------------------------------------------------------------
 struct LdsLevel {
-  double *tx, *ty, *tz, *diag, *B, *E, *T;
+  double *tx, *ty, *tz, *diag, *B, *E, *T, *dinv;
 };
 
 __device__ inline void lds_level(const MgCoarseArgs& a, double* smem, int l, LdsLevel& S) {
@@ -400,36 +433,45 @@ __device__ inline void lds_level(const MgCoarseArgs& a, double* smem, int l, Lds
   S.B = smem + a.off[l][4];
   S.E = smem + a.off[l][5];
   S.T = smem + a.off[l][6];
+  S.dinv = smem + a.off[l][7];
 }
 
 // sweeps damped-Jacobi sweeps on one LDS level (E in, E out; T is scratch;
 // the roles swap after every sweep, so sweeps must be even).
-__device__ void lds_smooth(const MgLevelDev& L, LdsLevel S, int sweeps, bool from_zero) {
-  const int n = L.nx * L.ny * L.nz;
-  for (int sw = 0; sw < sweeps; ++sw) {
-    for (int c = threadIdx.x; c < n; c += blockDim.x) {
-      const double D = S.diag[c];
-      double v;
-      if (from_zero && sw == 0) {
-        v = kOmega * S.B[c] / D;
-      } else {
-        const int x = c % L.nx, y = (c / L.nx) % L.ny, z = c / (L.nx * L.ny);
-        const double e = S.E[c];
-        v = e + kOmega * (S.B[c] - D * e + offdiag_sum(L.nx, L.ny, L.nz, S.tx, S.ty, S.tz, S.E, x, y, z, c)) / D;
-      }
-      S.T[c] = v;
-    }
-    __syncthreads();
-    double* t = S.E;
-    S.E = S.T;
-    S.T = t;
+// (x, y, z) of cell c of a level
+__device__ inline void cell_xyz(const MgLevelDev& L, int c, int& x, int& y, int& z) {
+  if (L.nz == 1) {
+    y = c / L.nx;
+    x = c - y * L.nx;
+    z = 0;
+  } else {
+    const int pl = L.nx * L.ny;
+    z = c / pl;
+    const int r = c - z * pl;
+    y = r / L.nx;
+    x = r - y * L.nx;
   }
+}
+
+// Neighbour sum of cell c of an LDS level with values v(j, x, y, z) of the
+// neighbour j at (x, y, z)
+template <class V>
+__device__ inline double lds_nb_sum(const MgLevelDev& L, const LdsLevel& S, int x, int y, int z, int c, V&& v) {
+  const int nx = L.nx, ny = L.ny, nz = L.nz;
+  double s = 0.0;
+  if (x > 0) s += S.tx[fxi(nx, ny, x, y, z)] * v(c - 1, x - 1, y, z);
+  if (x + 1 < nx) s += S.tx[fxi(nx, ny, x + 1, y, z)] * v(c + 1, x + 1, y, z);
+  if (y > 0) s += S.ty[fyi(nx, ny, x, y, z)] * v(c - nx, x, y - 1, z);
+  if (y + 1 < ny) s += S.ty[fyi(nx, ny, x, y + 1, z)] * v(c + nx, x, y + 1, z);
+  if (z > 0) s += S.tz[fzi(nx, ny, x, y, z)] * v(c - nx * ny, x, y, z - 1);
+  if (z + 1 < nz) s += S.tz[fzi(nx, ny, x, y, z + 1)] * v(c + nx * ny, x, y, z + 1);
+  return s;
 }
 
 __global__ __launch_bounds__(1024) void k_mg_coarse_lds(MgCoarseArgs a, const double* __restrict__ bglob,
                                               const double* __restrict__ binv, double* __restrict__ out,
                                               PcgState* st, int rz_slot) {
-  if (pcg_done(st)) return;
+  const bool stop = pcg_done(st);  // checked once the level loads are in flight
   extern __shared__ double smem[];
   const int nl = a.nlev;          // levels in LDS, the last one is the bottom
   // load faces / diagonals of the smoothed levels, the bottom inverse, the rhs
@@ -443,7 +485,11 @@ __global__ __launch_bounds__(1024) void k_mg_coarse_lds(MgCoarseArgs a, const do
     for (int j = threadIdx.x; j < nfx; j += blockDim.x) S.tx[j] = L.tx[j];
     for (int j = threadIdx.x; j < nfy; j += blockDim.x) S.ty[j] = L.ty[j];
     for (int j = threadIdx.x; j < nfz; j += blockDim.x) S.tz[j] = L.tz[j];
-    for (int j = threadIdx.x; j < n; j += blockDim.x) S.diag[j] = L.diag[j];
+    for (int j = threadIdx.x; j < n; j += blockDim.x) {
+      const double dg = L.diag[j];
+      S.diag[j] = dg;
+      S.dinv[j] = 1.0 / dg;  // the sweeps multiply; one division per cell here
+    }
   }
   const MgLevelDev& Lb = a.lev[nl - 1];
   const int nb = Lb.nx * Lb.ny * Lb.nz;
@@ -453,6 +499,7 @@ __global__ __launch_bounds__(1024) void k_mg_coarse_lds(MgCoarseArgs a, const do
   lds_level(a, smem, 0, S0);
   const int n0 = a.n0;
   for (int j = threadIdx.x; j < n0; j += blockDim.x) S0.B[j] = bglob[j];
+  if (stop) return;
   __syncthreads();
   // down
   for (int l = 0; l + 1 < nl; ++l) {
@@ -461,10 +508,25 @@ __global__ __launch_bounds__(1024) void k_mg_coarse_lds(MgCoarseArgs a, const do
     LdsLevel S, SC;
     lds_level(a, smem, l, S);
     lds_level(a, smem, l + 1, SC);
-    lds_smooth(F, S, a.nu, true);
+    // two damped-Jacobi sweeps from zero in one pass: E = x2, the first
+    // sweep's x1 = w B / D recomputed at the neighbours
+    {
+      const int n = F.nx * F.ny * F.nz;
+      auto x1 = [&](int j, int, int, int) { return kOmega * S.B[j] * S.dinv[j]; };
+      for (int c = threadIdx.x; c < n; c += blockDim.x) {
+        int x, y, z;
+        cell_xyz(F, c, x, y, z);
+        const double di = S.dinv[c];
+        const double bi = S.B[c];
+        const double xi = kOmega * bi * di;
+        S.E[c] = xi + kOmega * ((bi + lds_nb_sum(F, S, x, y, z, c, x1)) * di - xi);
+      }
+      __syncthreads();
+    }
     const int nc = C.nx * C.ny * C.nz;
     for (int c = threadIdx.x; c < nc; c += blockDim.x) {
-      const int X0 = c % C.nx, Y0 = (c / C.nx) % C.ny, Z0 = c / (C.nx * C.ny);
+      int X0, Y0, Z0;
+      cell_xyz(C, c, X0, Y0, Z0);
       const int x1 = min(2 * X0 + 1, F.nx - 1), y1 = min(2 * Y0 + 1, F.ny - 1);
       const int z0 = F.nz > 1 ? 2 * Z0 : 0, z1 = F.nz > 1 ? min(2 * Z0 + 1, F.nz - 1) : 0;
       double acc = 0.0;
@@ -500,12 +562,28 @@ __global__ __launch_bounds__(1024) void k_mg_coarse_lds(MgCoarseArgs a, const do
     lds_level(a, smem, l + 1, SC);
     const int n = F.nx * F.ny * F.nz;
     const int cz = F.nz > 1 ? 1 : 0;
+    // coarse correction folded into the first sweep: T = y(E + w_c e[parent])
+    auto xc = [&](int j, int x, int y, int z) {
+      return S.E[j] + a.omega_c * SC.E[(x >> 1) + C.nx * ((y >> 1) + C.ny * (z >> cz))];
+    };
     for (int c = threadIdx.x; c < n; c += blockDim.x) {
-      const int x = c % F.nx, y = (c / F.nx) % F.ny, z = c / (F.nx * F.ny);
-      S.E[c] += a.omega_c * SC.E[(x >> 1) + C.nx * ((y >> 1) + C.ny * (z >> cz))];
+      int x, y, z;
+      cell_xyz(F, c, x, y, z);
+      const double di = S.dinv[c];
+      const double v = xc(c, x, y, z);
+      S.T[c] = v + kOmega * ((S.B[c] + lds_nb_sum(F, S, x, y, z, c, xc)) * di - v);
     }
     __syncthreads();
-    lds_smooth(F, S, a.nu, false);
+    // second sweep: E = T + w (B - A T) / D
+    auto tv = [&](int j, int, int, int) { return S.T[j]; };
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+      int x, y, z;
+      cell_xyz(F, c, x, y, z);
+      const double di = S.dinv[c];
+      const double v = S.T[c];
+      S.E[c] = v + kOmega * ((S.B[c] + lds_nb_sum(F, S, x, y, z, c, tv)) * di - v);
+    }
+    __syncthreads();
   }
   double part = 0.0;
   for (int c = threadIdx.x; c < n0; c += blockDim.x) {
