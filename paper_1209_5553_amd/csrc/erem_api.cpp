@@ -271,6 +271,14 @@ int ensure_mixed(erem_ctx* c) {
   return EREM_OK;
 }
 
+// Newton terms computed by the launch that starts at term k of at most K:
+// four (2D, a whole stop-test group), else two, else one.
+int leja_terms_per_launch(const Dims& d, int k, int K) {
+  if (d.dim != 2) return 1;
+  if (k + 3 <= K) return 4;
+  return k + 1 <= K ? 2 : 1;
+}
+
 template <class V>
 int leja_run(erem_ctx* c, const LejaBufs<V>& B, const double* v, double delta, int s, int K, int nprof) {
   const Dims& d = c->d;
@@ -284,16 +292,25 @@ int leja_run(erem_ctx* c, const LejaBufs<V>& B, const double* v, double delta, i
     HIP_TRY(c, launch_leja_init<V>(d, c->cf, src, B.qa, B.p, c->part, c->stream));
     hipEvent_t* evj = j < nprof ? &c->ev[static_cast<size_t>(j) * 2 * K] : nullptr;
     int prev = -1;  // last term already checked
-    for (int k = 1; k <= K; ++k) {
-      const V* qin = (k & 1) ? B.qa : B.qb;
-      V* qout = (k & 1) ? B.qb : B.qa;
-      const bool timed = evj && k % c->prof == 0;
+    V* cur = B.qa;  // latest q
+    V* oth = B.qb;
+    // 2D grids take the terms in groups of four (one stop-test group per
+    // launch, so the stop test still follows every kCheckEvery terms)
+    for (int k = 1, launch = 0; k <= K; ++launch) {
+      const int nt = leja_terms_per_launch(d, k, K);
+      const bool timed = evj && launch % c->prof == 0;
       if (timed) HIP_TRY(c, hipEventRecord(evj[2 * (k - 1)], c->stream));
-      HIP_TRY(c, launch_leja_term<V>(d, c->cf, B.coef, qin, qout, B.p, st, c->part, k, c->stream));
+      if (nt > 1)
+        HIP_TRY(c, launch_leja_terms<V>(d, c->cf, B.coef, cur, oth, B.p, st, c->part, k, nt, c->stream));
+      else
+        HIP_TRY(c, launch_leja_term<V>(d, c->cf, B.coef, cur, oth, B.p, st, c->part, k, c->stream));
       if (timed) HIP_TRY(c, hipEventRecord(evj[2 * (k - 1) + 1], c->stream));
-      if (k % kCheckEvery == 0 || k == K) {
-        HIP_TRY(c, launch_leja_check(d, c->cf, st, c->part, prev + 1, k, c->stream));
-        prev = k;
+      std::swap(cur, oth);
+      k += nt;
+      const int last = k - 1;
+      if (last % kCheckEvery == 0 || last == K) {
+        HIP_TRY(c, launch_leja_check(d, c->cf, st, c->part, prev + 1, last, c->stream));
+        prev = last;
       }
     }
     HIP_TRY(c, launch_substep_update<V>(d, c->u, B.p, delta, j == 0 ? 1 : 0, c->stream));
@@ -362,9 +379,13 @@ int leja_hphi1(erem_ctx* c, double h, const double* v, double scal, int s, int K
     last = hc->estf[st.stopped] * std::sqrt(st.sums[st.stopped]);
     if (j < nprof) {
       const hipEvent_t* evj = &c->ev[static_cast<size_t>(j) * 2 * K];
-      for (int k = c->prof; k <= applied; k += c->prof) {
-        c->t_leja += elapsed_ms(evj[2 * (k - 1)], evj[2 * (k - 1) + 1]);
-        ++c->n_leja;
+      for (int k = 1, launch = 0; k <= applied; ++launch) {
+        const int nt = leja_terms_per_launch(c->d, k, K);
+        if (launch % c->prof == 0) {
+          c->t_leja += elapsed_ms(evj[2 * (k - 1)], evj[2 * (k - 1) + 1]);
+          c->n_leja += nt;
+        }
+        k += nt;
       }
     }
   }

@@ -20,6 +20,11 @@ hipError_t launch_leja_init(const Dims& d, const LejaCoef* cf, const double* v, 
 template <class V>
 hipError_t launch_leja_term(const Dims& d, const LejaCoef* cf, const V* coef, const V* qin, V* qout,
                             V* p, const LejaState* st, double* part, int k, hipStream_t s);
+// Terms k .. k + nterms - 1 in one launch (2D grids only, nterms 2 or 4):
+// the last q to qout, p updated, every term's partial sums in its ring slot.
+template <class V>
+hipError_t launch_leja_terms(const Dims& d, const LejaCoef* cf, const V* coef, const V* qin, V* qout,
+                             V* p, const LejaState* st, double* part, int k, int nterms, hipStream_t s);
 hipError_t launch_leja_check(const Dims& d, const LejaCoef* cf, LejaState* st, const double* part,
                              int k1, int k2, hipStream_t s);
 template <class V>

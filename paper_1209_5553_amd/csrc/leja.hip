@@ -109,6 +109,103 @@ __global__ __launch_bounds__(kThreads) void k_leja_term(Dims d, const LejaCoef* 
   if (threadIdx.x == 0 && threadIdx.y == 0) part[(k % kLejaRing) * nb + block_id()] = s;
 }
 
+// NT Newton terms in one pass (2D), NT = 2 or 4: q_{k-1} is staged in LDS on
+// the block's 64 x 4 tile plus a halo of NT cells and the stencil on the tile
+// plus a halo of NT - 1; term k + t is then computed on the tile plus a halo
+// of NT - 1 - t, so the last one lands on the tile.  p gets d_k q_k, then
+// d_{k+1} q_{k+1}, ... (the order of single passes); the intermediate q's
+// never go to memory.  Per-block partial sums of every term's q^2 go to the
+// term's ring slot.
+template <int NT, class V>
+__global__ __launch_bounds__(kThreads) void k_leja_terms(Dims d, const LejaCoef* __restrict__ cf,
+                                               const V* __restrict__ coef, const V* __restrict__ qin,
+                                               V* __restrict__ qout, V* __restrict__ p,
+                                               const LejaState* __restrict__ st, double* __restrict__ part, int nb,
+                                               int k) {
+  constexpr int H = NT - 1;                         // halo of the stencil / intermediates
+  constexpr int WQ = kBX + 2 * NT, HQ = kBY + 2 * NT;
+  constexpr int WI = kBX + 2 * H, HI = kBY + 2 * H;
+  __shared__ V sq[HQ][WQ];           // q_{k-1}, halo NT
+  __shared__ V sc[5][HI][WI];        // stencil, halo NT - 1
+  __shared__ V sb[2][HI][WI];        // intermediates, halo NT - 1
+  const bool stopped = *(volatile const int*)&st->stopped >= 0;
+  const int nx = d.nx, ny = d.ny, N = d.N;
+  const int x0 = blockIdx.x * kBX, y0 = blockIdx.y * kBY;
+  const int tid = threadIdx.x + threadIdx.y * kBX;
+  for (int e = tid; e < HQ * WQ; e += kThreads) {
+    const int ly = e / WQ, lx = e - ly * WQ;
+    const int gx = x0 - NT + lx, gy = y0 - NT + ly;
+    sq[ly][lx] = (gx >= 0 && gx < nx && gy >= 0 && gy < ny) ? qin[gx + nx * gy] : V(0);
+  }
+  for (int e = tid; e < HI * WI; e += kThreads) {
+    const int ly = e / WI, lx = e - ly * WI;
+    const int gx = x0 - H + lx, gy = y0 - H + ly;
+    const bool in = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+    const int j = gx + nx * gy;
+#pragma unroll
+    for (int c = 0; c < 5; ++c) sc[c][ly][lx] = in ? coef[c * N + j] : V(0);
+  }
+  const int gx = x0 + threadIdx.x, gy = y0 + threadIdx.y;
+  const bool own = gx < nx && gy < ny;
+  const int i = gx + nx * gy;
+  V acc = own ? p[i] : V(0);
+  if (stopped) return;  // stop test already passed
+  __syncthreads();
+  const V ig = to_v<V>(cf->inv_g);
+  double a[NT];
+  V last = V(0);
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    const int h = H - t;  // halo of the region computed in this phase
+    const V sh = to_v<V>(cf->shift[k + t]);
+    const int w = kBX + 2 * h, hh = kBY + 2 * h;
+    V(*out)[WI] = sb[t & 1];
+    for (int e = tid; e < w * hh; e += kThreads) {
+      const int ry = e / w, rx = e - ry * w;
+      const int iy = ry + t, ix = rx + t;  // position in the halo-H buffers
+      V qc, qw, qe, qs, qn;
+      if (t == 0) {
+        qc = sq[iy + 1][ix + 1];
+        qw = sq[iy + 1][ix];
+        qe = sq[iy + 1][ix + 2];
+        qs = sq[iy][ix + 1];
+        qn = sq[iy + 2][ix + 1];
+      } else {
+        const V(*prev)[WI] = sb[(t - 1) & 1];
+        qc = prev[iy][ix];
+        qw = prev[iy][ix - 1];
+        qe = prev[iy][ix + 1];
+        qs = prev[iy - 1][ix];
+        qn = prev[iy + 1][ix];
+      }
+      V jq = sc[0][iy][ix] * qc;
+      jq += sc[1][iy][ix] * qw;
+      jq += sc[2][iy][ix] * qe;
+      jq += sc[3][iy][ix] * qs;
+      jq += sc[4][iy][ix] * qn;
+      out[iy][ix] = jq * ig - sh * qc;  // zero outside the grid (stencil and q are)
+    }
+    __syncthreads();
+    const V qo = out[threadIdx.y + H][threadIdx.x + H];
+    acc += to_v<V>(cf->dk[k + t]) * qo;
+    a[t] = own ? static_cast<double>(qo) * static_cast<double>(qo) : 0.0;
+    last = qo;
+  }
+  if (own) {
+    p[i] = acc;
+    qout[i] = last;
+  }
+  __shared__ double red[NT][kThreads / 64];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    double v = a[t];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((tid & 63) == 0) red[t][tid >> 6] = v;
+  }
+  __syncthreads();
+  if (tid < NT) part[((k + tid) % kLejaRing) * nb + block_id()] = red[tid][0] + red[tid][1] + red[tid][2] + red[tid][3];
+}
+
 // Reduce the partials of terms k1..k2 (in order), record their sums and
 // apply the stop test.  One workgroup of kCheckThreads threads.
 __global__ __launch_bounds__(kCheckThreads) void k_leja_check(const LejaCoef* __restrict__ cf, LejaState* st,
@@ -198,6 +295,21 @@ hipError_t launch_leja_term(const Dims& d, const LejaCoef* cf, const V* coef, co
   return hipGetLastError();
 }
 
+template <class V>
+hipError_t launch_leja_terms(const Dims& d, const LejaCoef* cf, const V* coef, const V* qin, V* qout, V* p,
+                             const LejaState* st, double* part, int k, int nterms, hipStream_t s) {
+  if (d.dim != 2) return hipErrorInvalidValue;
+  if (nterms == 4)
+    hipLaunchKernelGGL((k_leja_terms<4, V>), cell_grid(d), cell_block(), 0, s, d, cf, coef, qin, qout, p, st, part,
+                       leja_num_blocks(d), k);
+  else if (nterms == 2)
+    hipLaunchKernelGGL((k_leja_terms<2, V>), cell_grid(d), cell_block(), 0, s, d, cf, coef, qin, qout, p, st, part,
+                       leja_num_blocks(d), k);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
 hipError_t launch_leja_check(const Dims& d, const LejaCoef* cf, LejaState* st, const double* part, int k1, int k2,
                              hipStream_t s) {
   hipLaunchKernelGGL(k_leja_check, dim3(1), dim3(kCheckThreads), 0, s, cf, st, part, leja_num_blocks(d), k1, k2);
@@ -228,5 +340,10 @@ template hipError_t launch_leja_term<float>(const Dims&, const LejaCoef*, const 
                                             const LejaState*, double*, int, hipStream_t);
 template hipError_t launch_substep_update<double>(const Dims&, double*, const double*, double, int, hipStream_t);
 template hipError_t launch_substep_update<float>(const Dims&, double*, const float*, double, int, hipStream_t);
+
+template hipError_t launch_leja_terms<double>(const Dims&, const LejaCoef*, const double*, const double*, double*,
+                                              double*, const LejaState*, double*, int, int, hipStream_t);
+template hipError_t launch_leja_terms<float>(const Dims&, const LejaCoef*, const float*, const float*, float*, float*,
+                                             const LejaState*, double*, int, int, hipStream_t);
 
 }  // namespace erem
