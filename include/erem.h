@@ -254,7 +254,9 @@ typedef struct {
     int32_t terms_min, terms_max;  /* per problem, over the run */
     int32_t failed;        /* problems that stopped on an error (see flags) */
     int32_t tile_shape;    /* workgroup per problem: 0: 256 threads x 4 cells loaded ahead,
-                              1: 256 x 8, 2: 512 x 4, 3: 1024 x 2 */
+                              1: 256 x 8, 2: 512 x 4, 3: 1024 x 2, 4: 1024 threads taking
+                              the Newton terms four per pass over 64 x 16 tiles staged in
+                              LDS (runs the largest multiple of 4 not above m_max terms) */
     int32_t graph;         /* 1 if the launch was replayed from a hipGraph */
     int32_t grid;          /* workgroups of the launch (one per problem) */
     double ms;             /* device time of the launch (HIP events) */
@@ -282,7 +284,7 @@ int erem_batch_prepare(erem_batch* b, double h, const erem_opts* opts);
 /* Time every workgroup size on a copy of d_T (nsteps steps) and keep the fastest;
  * *chosen receives its index.  d_T is not modified. */
 int erem_batch_autotune(erem_batch* b, const double* d_T, int32_t nsteps, int32_t* chosen);
-/* Select a workgroup shape by index (0 .. 3, see erem_batch_stats.tile_shape)
+/* Select a workgroup shape by index (0 .. 4, see erem_batch_stats.tile_shape)
  * instead of timing them.  EINVAL for another index. */
 int erem_batch_set_tile_shape(erem_batch* b, int32_t shape);
 /* Advance the packed temperatures d_T by nsteps EREM steps in one launch;

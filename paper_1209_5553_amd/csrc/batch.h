@@ -7,8 +7,8 @@
 
 namespace erem {
 
-constexpr int kNumTileShapes = 4;
-extern const int kTileShapes[kNumTileShapes][2];  // {threads per problem, cells loaded ahead per thread}
+constexpr int kNumTileShapes = 5;
+extern const int kTileShapes[kNumTileShapes][2];  // {threads per problem, cells loaded ahead per thread (0: fused terms)}
 
 // Static description of one problem of the batch.
 struct BProb {
