@@ -501,94 +501,110 @@ __global__ __launch_bounds__(1024) void k_mg_coarse_lds(MgCoarseArgs a, const do
   for (int j = threadIdx.x; j < n0; j += blockDim.x) S0.B[j] = bglob[j];
   if (stop) return;
   __syncthreads();
-  // down
-  for (int l = 0; l + 1 < nl; ++l) {
-    const MgLevelDev& F = a.lev[l];
-    const MgLevelDev& C = a.lev[l + 1];
-    LdsLevel S, SC;
-    lds_level(a, smem, l, S);
-    lds_level(a, smem, l + 1, SC);
-    // two damped-Jacobi sweeps from zero in one pass: E = x2, the first
-    // sweep's x1 = w B / D recomputed at the neighbours
+  // a.ncyc V-cycles on the first LDS level: each later one starts from the
+  // residual B - A E the earlier ones left, and the corrections add up in out
+  for (int cyc = 0; cyc < a.ncyc; ++cyc) {
+    if (cyc > 0) {
+      const MgLevelDev& F = a.lev[0];
+      for (int c = threadIdx.x; c < n0; c += blockDim.x) {
+        int x, y, z;
+        cell_xyz(F, c, x, y, z);
+        const double e = S0.E[c];
+        S0.B[c] += offdiag_sum(F.nx, F.ny, F.nz, S0.tx, S0.ty, S0.tz, S0.E, x, y, z, c) - S0.diag[c] * e;
+        out[c] = (cyc > 1 ? out[c] : 0.0) + e;
+      }
+      __syncthreads();
+    }
+    // down
+    for (int l = 0; l + 1 < nl; ++l) {
+      const MgLevelDev& F = a.lev[l];
+      const MgLevelDev& C = a.lev[l + 1];
+      LdsLevel S, SC;
+      lds_level(a, smem, l, S);
+      lds_level(a, smem, l + 1, SC);
+      // two damped-Jacobi sweeps from zero in one pass: E = x2, the first
+      // sweep's x1 = w B / D recomputed at the neighbours
+      {
+        const int n = F.nx * F.ny * F.nz;
+        auto x1 = [&](int j, int, int, int) { return kOmega * S.B[j] * S.dinv[j]; };
+        for (int c = threadIdx.x; c < n; c += blockDim.x) {
+          int x, y, z;
+          cell_xyz(F, c, x, y, z);
+          const double di = S.dinv[c];
+          const double bi = S.B[c];
+          const double xi = kOmega * bi * di;
+          S.E[c] = xi + kOmega * ((bi + lds_nb_sum(F, S, x, y, z, c, x1)) * di - xi);
+        }
+        __syncthreads();
+      }
+      const int nc = C.nx * C.ny * C.nz;
+      for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+        int X0, Y0, Z0;
+        cell_xyz(C, c, X0, Y0, Z0);
+        const int x1 = min(2 * X0 + 1, F.nx - 1), y1 = min(2 * Y0 + 1, F.ny - 1);
+        const int z0 = F.nz > 1 ? 2 * Z0 : 0, z1 = F.nz > 1 ? min(2 * Z0 + 1, F.nz - 1) : 0;
+        double acc = 0.0;
+        for (int z = z0; z <= z1; ++z)
+          for (int y = 2 * Y0; y <= y1; ++y)
+            for (int x = 2 * X0; x <= x1; ++x) {
+              const int i = x + F.nx * (y + F.ny * z);
+              acc += S.B[i] - S.diag[i] * S.E[i] + offdiag_sum(F.nx, F.ny, F.nz, S.tx, S.ty, S.tz, S.E, x, y, z, i);
+            }
+        SC.B[c] = acc;
+      }
+      __syncthreads();
+    }
+    // bottom: E = inverse * B
     {
+      LdsLevel S;
+      lds_level(a, smem, nl - 1, S);
+      for (int r = threadIdx.x; r < nb; r += blockDim.x) {
+        double acc = 0.0;
+        // the inverse of the symmetric bottom operator is symmetric: read it
+        // by columns so that consecutive threads hit consecutive banks
+        for (int j = 0; j < nb; ++j) acc += Binv[j * nb + r] * S.B[j];
+        S.E[r] = acc;
+      }
+      __syncthreads();
+    }
+    // up
+    for (int l = nl - 2; l >= 0; --l) {
+      const MgLevelDev& F = a.lev[l];
+      const MgLevelDev& C = a.lev[l + 1];
+      LdsLevel S, SC;
+      lds_level(a, smem, l, S);
+      lds_level(a, smem, l + 1, SC);
       const int n = F.nx * F.ny * F.nz;
-      auto x1 = [&](int j, int, int, int) { return kOmega * S.B[j] * S.dinv[j]; };
+      const int cz = F.nz > 1 ? 1 : 0;
+      // coarse correction folded into the first sweep: T = y(E + w_c e[parent])
+      auto xc = [&](int j, int x, int y, int z) {
+        return S.E[j] + a.omega_c * SC.E[(x >> 1) + C.nx * ((y >> 1) + C.ny * (z >> cz))];
+      };
       for (int c = threadIdx.x; c < n; c += blockDim.x) {
         int x, y, z;
         cell_xyz(F, c, x, y, z);
         const double di = S.dinv[c];
-        const double bi = S.B[c];
-        const double xi = kOmega * bi * di;
-        S.E[c] = xi + kOmega * ((bi + lds_nb_sum(F, S, x, y, z, c, x1)) * di - xi);
+        const double v = xc(c, x, y, z);
+        S.T[c] = v + kOmega * ((S.B[c] + lds_nb_sum(F, S, x, y, z, c, xc)) * di - v);
+      }
+      __syncthreads();
+      // second sweep: E = T + w (B - A T) / D
+      auto tv = [&](int j, int, int, int) { return S.T[j]; };
+      for (int c = threadIdx.x; c < n; c += blockDim.x) {
+        int x, y, z;
+        cell_xyz(F, c, x, y, z);
+        const double di = S.dinv[c];
+        const double v = S.T[c];
+        S.E[c] = v + kOmega * ((S.B[c] + lds_nb_sum(F, S, x, y, z, c, tv)) * di - v);
       }
       __syncthreads();
     }
-    const int nc = C.nx * C.ny * C.nz;
-    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
-      int X0, Y0, Z0;
-      cell_xyz(C, c, X0, Y0, Z0);
-      const int x1 = min(2 * X0 + 1, F.nx - 1), y1 = min(2 * Y0 + 1, F.ny - 1);
-      const int z0 = F.nz > 1 ? 2 * Z0 : 0, z1 = F.nz > 1 ? min(2 * Z0 + 1, F.nz - 1) : 0;
-      double acc = 0.0;
-      for (int z = z0; z <= z1; ++z)
-        for (int y = 2 * Y0; y <= y1; ++y)
-          for (int x = 2 * X0; x <= x1; ++x) {
-            const int i = x + F.nx * (y + F.ny * z);
-            acc += S.B[i] - S.diag[i] * S.E[i] + offdiag_sum(F.nx, F.ny, F.nz, S.tx, S.ty, S.tz, S.E, x, y, z, i);
-          }
-      SC.B[c] = acc;
-    }
-    __syncthreads();
-  }
-  // bottom: E = inverse * B
-  {
-    LdsLevel S;
-    lds_level(a, smem, nl - 1, S);
-    for (int r = threadIdx.x; r < nb; r += blockDim.x) {
-      double acc = 0.0;
-      // the inverse of the symmetric bottom operator is symmetric: read it
-      // by columns so that consecutive threads hit consecutive banks
-      for (int j = 0; j < nb; ++j) acc += Binv[j * nb + r] * S.B[j];
-      S.E[r] = acc;
-    }
-    __syncthreads();
-  }
-  // up
-  for (int l = nl - 2; l >= 0; --l) {
-    const MgLevelDev& F = a.lev[l];
-    const MgLevelDev& C = a.lev[l + 1];
-    LdsLevel S, SC;
-    lds_level(a, smem, l, S);
-    lds_level(a, smem, l + 1, SC);
-    const int n = F.nx * F.ny * F.nz;
-    const int cz = F.nz > 1 ? 1 : 0;
-    // coarse correction folded into the first sweep: T = y(E + w_c e[parent])
-    auto xc = [&](int j, int x, int y, int z) {
-      return S.E[j] + a.omega_c * SC.E[(x >> 1) + C.nx * ((y >> 1) + C.ny * (z >> cz))];
-    };
-    for (int c = threadIdx.x; c < n; c += blockDim.x) {
-      int x, y, z;
-      cell_xyz(F, c, x, y, z);
-      const double di = S.dinv[c];
-      const double v = xc(c, x, y, z);
-      S.T[c] = v + kOmega * ((S.B[c] + lds_nb_sum(F, S, x, y, z, c, xc)) * di - v);
-    }
-    __syncthreads();
-    // second sweep: E = T + w (B - A T) / D
-    auto tv = [&](int j, int, int, int) { return S.T[j]; };
-    for (int c = threadIdx.x; c < n; c += blockDim.x) {
-      int x, y, z;
-      cell_xyz(F, c, x, y, z);
-      const double di = S.dinv[c];
-      const double v = S.T[c];
-      S.E[c] = v + kOmega * ((S.B[c] + lds_nb_sum(F, S, x, y, z, c, tv)) * di - v);
-    }
-    __syncthreads();
   }
   double part = 0.0;
   for (int c = threadIdx.x; c < n0; c += blockDim.x) {
-    out[c] = S0.E[c];
-    part += bglob[c] * S0.E[c];
+    const double v = (a.ncyc > 1 ? out[c] : 0.0) + S0.E[c];
+    out[c] = v;
+    part += bglob[c] * v;
   }
   if (rz_slot < 0) return;
   for (int off = 32; off > 0; off >>= 1) part += __shfl_down(part, off, 64);
