@@ -321,8 +321,8 @@ int erem_batch_set_problem(erem_batch* b, int32_t i, const double* d_logk, const
   BHIP(b, launch_gershgorin(d, b->tmp_coef, b->red, b->stream));
   BHIP(b, hipMemcpyAsync(b->h_red, b->red, sizeof(AsmReduce), hipMemcpyDeviceToHost, b->stream));
   BHIP(b, hipStreamSynchronize(b->stream));
-  b->alpha[i] = ord_decode(b->h_red->lo);
-  b->beta[i] = ord_decode(b->h_red->hi);
+  b->alpha[i] = slot_min(b->h_red->lo);
+  b->beta[i] = slot_max(b->h_red->hi);
   b->set[i] = 1;
   b->prepared = false;
   return EREM_OK;

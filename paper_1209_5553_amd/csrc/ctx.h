@@ -32,7 +32,7 @@ struct erem_ctx {
   double *fx = nullptr, *fy = nullptr, *fz = nullptr;
   double *coef = nullptr, *F = nullptr;
   double *qa = nullptr, *qb = nullptr, *pacc = nullptr, *u = nullptr, *w = nullptr;
-  double *pres = nullptr, *pr = nullptr, *pz = nullptr, *pp0 = nullptr, *pp1 = nullptr;
+  double *pres = nullptr, *pr = nullptr, *pr2 = nullptr, *pz = nullptr, *pp0 = nullptr, *pp1 = nullptr;
   double *pq = nullptr, *pdiag = nullptr, *pres_lo = nullptr, *pdelta = nullptr, *prhs = nullptr;
   double* part = nullptr;  // Leja block partial sums (ring of kLejaRing terms)
   // FP32 copies for the mixed-precision Leja passes (allocated on first use)

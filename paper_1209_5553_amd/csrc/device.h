@@ -44,12 +44,14 @@ struct LejaState {
   double sums[kMaxTerms + 1];  // sum q_k^2 (FP64)
 };
 
-// Reduction targets of the assembly pass (ordered-integer encodings).
+// Reduction targets of the assembly pass (ordered-integer encodings), one
+// partial per slot: the blocks spread their atomics over kSlots addresses
+// and the host folds the slots (slot_min / slot_max).
 struct AsmReduce {
-  unsigned long long lo;    // min_i (J_ii - R_i)
-  unsigned long long hi;    // max_i (J_ii + R_i)
-  unsigned long long tmax;  // max_i |T_i|
-  unsigned long long vmax;  // max_i |v_i| (phi1_apply)
+  unsigned long long lo[kSlots];    // min_i (J_ii - R_i)
+  unsigned long long hi[kSlots];    // max_i (J_ii + R_i)
+  unsigned long long tmax[kSlots];  // max_i |T_i|
+  unsigned long long vmax[kSlots];  // max_i |v_i| (phi1_apply)
 };
 
 // Conjugate-gradient scalars: ring of 4 iterations x kSlots partial sums.
@@ -111,6 +113,16 @@ hipError_t launch_pcg_b(const Dims& d, double* x, double* r, double* z, const do
                         const double* q, const double* diag, PcgState* st, int it,
                         int jacobi, hipStream_t s);
 
+// Sum of the kSlots partial sums at base, by one wavefront (kSlots == 64):
+// every lane loads one slot; a butterfly sums them and lane 0's result is
+// broadcast so that every lane takes the same decisions.
+static_assert(kSlots == 64, "one slot per lane");
+__device__ inline double wave_slot_sum(const double* base) {
+  double s = base[threadIdx.x & 63];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
+  return __shfl(s, 0, 64);  // lane 0's rounding for every lane
+}
+
 // Ordered encoding of doubles for atomic min/max on 64-bit unsigned integers.
 __host__ __device__ inline unsigned long long ord_encode(double v) {
   union { double d; unsigned long long u; } c;
@@ -121,6 +133,18 @@ __host__ __device__ inline double ord_decode(unsigned long long k) {
   union { double d; unsigned long long u; } c;
   c.u = (k >> 63) ? (k & 0x7fffffffffffffffull) : ~k;
   return c.d;
+}
+
+// The encodings order like the values: fold the slots of one target.
+inline double slot_min(const unsigned long long* v) {
+  unsigned long long m = v[0];
+  for (int k = 1; k < kSlots; ++k) m = v[k] < m ? v[k] : m;
+  return ord_decode(m);
+}
+inline double slot_max(const unsigned long long* v) {
+  unsigned long long m = v[0];
+  for (int k = 1; k < kSlots; ++k) m = v[k] > m ? v[k] : m;
+  return ord_decode(m);
 }
 
 }  // namespace erem

@@ -70,7 +70,7 @@ int check_opts(erem_ctx* c, const erem_opts* o) {
 void free_all(erem_ctx* c) {
   double** bufs[] = {&c->logk, &c->poro, &c->tx, &c->ty, &c->tz, &c->fx, &c->fy, &c->fz,
                      &c->coef, &c->F, &c->qa, &c->qb, &c->pacc, &c->u, &c->w, &c->pres,
-                     &c->pr, &c->pz, &c->pp0, &c->pp1, &c->pq, &c->pdiag,
+                     &c->pr, &c->pr2, &c->pz, &c->pp0, &c->pp1, &c->pq, &c->pdiag,
                      &c->pres_lo, &c->pdelta, &c->prhs, &c->part};
   for (double** b : bufs)
     if (*b) { (void)hipFree(*b); *b = nullptr; }
@@ -104,8 +104,9 @@ void free_mg(erem_ctx* c) {
 }
 
 // LDS layout of the coarse solve over levels lc..lb: per smoothed level the
-// faces (z faces only in 3D), the diagonal and three vectors; on the bottom
-// level two vectors; then the bottom inverse.  Fills the offsets when `a` is
+// faces (z faces only in 3D), the diagonal, three vectors and 1/diagonal; on
+// the bottom level two vectors and the partial products; then the bottom
+// inverse.  Fills the offsets when `a` is
 // given and returns the number of words.
 size_t mg_lds_layout(const MgHierarchy& h, int lc, MgCoarseArgs* a) {
   size_t w = 0;
@@ -123,12 +124,15 @@ size_t mg_lds_layout(const MgHierarchy& h, int lc, MgCoarseArgs* a) {
         w += sizes[k];
       }
     } else {
+      // bottom: B, E, the partial products of the dense solve (one row of
+      // nb per wavefront of the workgroup), then the inverse
       if (off) {
         for (int k = 0; k < 8; ++k) off[k] = 0;
         off[4] = static_cast<int>(w);
         off[5] = static_cast<int>(w + n);
+        off[6] = static_cast<int>(w + 2 * n);
       }
-      w += 2 * n;
+      w += 2 * n + static_cast<size_t>(kMgLdsCells / 64) * n;
       if (a) a->inv_off = static_cast<int>(w);
       w += n * n;
     }
@@ -222,6 +226,8 @@ int build_mg(erem_ctx* c) {
   h.lds_bytes = mg_lds_layout(h, lc, &a) * sizeof(double);
   for (int k = 0; k < a.nlev; ++k) a.lev[k] = h.lev[lc + k];
   h.coarse_threads = std::min(1024, ((a.n0 + 63) / 64) * 64);
+  // the coarse kernel gives each thread at most one cell of its first level
+  if (h.coarse_threads < a.n0) return fail(c, EREM_EDEVICE, "coarse multigrid level larger than one workgroup");
   return EREM_OK;
 }
 
@@ -242,9 +248,9 @@ const std::vector<double>& divided_differences(erem_ctx* c, double hc, double hg
 int read_reduce(erem_ctx* c) {
   HIP_TRY(c, hipMemcpyAsync(c->h_red, c->red, sizeof(AsmReduce), hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
-  c->alpha = ord_decode(c->h_red->lo);
-  c->beta = ord_decode(c->h_red->hi);
-  c->tmax = ord_decode(c->h_red->tmax);
+  c->alpha = slot_min(c->h_red->lo);
+  c->beta = slot_max(c->h_red->hi);
+  c->tmax = slot_max(c->h_red->tmax);
   return EREM_OK;
 }
 
@@ -590,6 +596,7 @@ int pcg_inner(erem_ctx* c, double inner_tol, int budget, int* iters, bool* done)
   if (c->use_mg) HIP_TRY(c, mg_apply(c->mg, c->pr, c->pz, c->pcg, 0, c->stream));
   // Multigrid iterations are few: poll the device after a handful of them.
   const int chunk = c->use_mg ? 8 : 64;
+  const bool fuse = c->use_mg && mg_fuses_cg(c->mg);
   int it = 0;
   *done = false;
   if (c->prof) {
@@ -606,9 +613,17 @@ int pcg_inner(erem_ctx* c, double inner_tol, int budget, int* iters, bool* done)
       if (timed) HIP_TRY(c, hipEventRecord(c->ev[4 * j], c->stream));
       HIP_TRY(c, launch_pcg_a(d, c->tx, c->ty, c->tz, c->pz, pold, pnew, c->pq, c->pcg, it, c->stream));
       if (timed) HIP_TRY(c, hipEventRecord(c->ev[4 * j + 1], c->stream));
-      HIP_TRY(c, launch_pcg_b(d, c->pdelta, c->pr, c->pz, pnew, c->pq, c->pdiag, c->pcg, it, jac, c->stream));
-      if (timed) HIP_TRY(c, hipEventRecord(c->ev[4 * j + 2], c->stream));
-      if (c->use_mg) HIP_TRY(c, mg_apply(c->mg, c->pr, c->pz, c->pcg, (it + 1) & 3, c->stream));
+      if (fuse) {
+        // the update runs inside the first down leg; r alternates between
+        // two buffers (neighbouring tiles read the old one)
+        const CgFuse cg{c->pdelta, (it & 1) ? c->pr : c->pr2, pnew, c->pq, it};
+        if (timed) HIP_TRY(c, hipEventRecord(c->ev[4 * j + 2], c->stream));
+        HIP_TRY(c, mg_apply(c->mg, (it & 1) ? c->pr2 : c->pr, c->pz, c->pcg, (it + 1) & 3, c->stream, &cg));
+      } else {
+        HIP_TRY(c, launch_pcg_b(d, c->pdelta, c->pr, c->pz, pnew, c->pq, c->pdiag, c->pcg, it, jac, c->stream));
+        if (timed) HIP_TRY(c, hipEventRecord(c->ev[4 * j + 2], c->stream));
+        if (c->use_mg) HIP_TRY(c, mg_apply(c->mg, c->pr, c->pz, c->pcg, (it + 1) & 3, c->stream));
+      }
       if (timed) HIP_TRY(c, hipEventRecord(c->ev[4 * j + 3], c->stream));
     }
     HIP_TRY(c, hipMemcpyAsync(c->h_pcg, c->pcg, sizeof(PcgState), hipMemcpyDeviceToHost, c->stream));
@@ -621,9 +636,11 @@ int pcg_inner(erem_ctx* c, double inner_tol, int budget, int* iters, bool* done)
       for (int j = 0; j < ran; ++j) {
         if ((it0 + j) % c->prof != 0) continue;
         c->t_pcg_a += elapsed_ms(c->ev[4 * j], c->ev[4 * j + 1]);
-        c->t_pcg_b += elapsed_ms(c->ev[4 * j + 1], c->ev[4 * j + 2]);
         ++c->n_pcg_a;
-        ++c->n_pcg_b;
+        if (!fuse) {
+          c->t_pcg_b += elapsed_ms(c->ev[4 * j + 1], c->ev[4 * j + 2]);
+          ++c->n_pcg_b;
+        }
         if (c->use_mg) {
           c->t_mg += elapsed_ms(c->ev[4 * j + 2], c->ev[4 * j + 3]);
           ++c->n_mg;
@@ -733,6 +750,7 @@ int erem_create(const erem_grid* g, void* stream, erem_ctx** out) {
   rc |= dev_alloc(c, &c->w, n);
   rc |= dev_alloc(c, &c->pres, n);
   rc |= dev_alloc(c, &c->pr, n);
+  rc |= dev_alloc(c, &c->pr2, n);
   rc |= dev_alloc(c, &c->pz, n);
   rc |= dev_alloc(c, &c->pp0, n);
   rc |= dev_alloc(c, &c->pp1, n);
@@ -963,7 +981,7 @@ int erem_phi1_apply(erem_ctx* c, double h, const double* d_v, double* d_out, con
   HIP_TRY(c, launch_absmax(c->d, d_v, c->red, c->stream));
   rc = read_reduce(c);
   if (rc) return rc;
-  const double vmax = ord_decode(c->h_red->vmax);
+  const double vmax = slot_max(c->h_red->vmax);
   const double scal = o->tol_a + o->tol_r * h * vmax;
   if (vmax == 0.0) {
     HIP_TRY(c, hipMemsetAsync(d_out, 0, sizeof(double) * c->d.N, c->stream));
@@ -1034,7 +1052,7 @@ int erem_step_frozen(erem_ctx* c, double h, double* d_T, const erem_opts* o, ere
   HIP_TRY(c, launch_absmax(c->d, d_T, c->red, c->stream));
   rc = read_reduce(c);
   if (rc) return rc;
-  return step_core(c, h, d_T, o, stats, ord_decode(c->h_red->vmax));
+  return step_core(c, h, d_T, o, stats, slot_max(c->h_red->vmax));
 }
 
 int erem_profile(erem_ctx* c, int32_t enable) {

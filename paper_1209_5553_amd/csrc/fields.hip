@@ -41,16 +41,6 @@ __device__ inline void block_sum(double (&v)[NV]) {
   }
 }
 
-// Sum of the kSlots partial sums at base, by one wavefront (kSlots == 64):
-// every lane loads one slot; a butterfly sums them and lane 0's result is
-// broadcast so that every lane takes the same decisions.
-static_assert(kSlots == 64, "one slot per lane");
-__device__ inline double wave_slot_sum(const double* base) {
-  double s = base[threadIdx.x & 63];
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-  return __shfl(s, 0, 64);  // lane 0's rounding for every lane
-}
-
 __device__ inline double rho_of(double T, const Phys& ph) {
   return ph.law == 1 ? 1000.0 * (1.0 - 3.0e-4 * (T - 20.0)) : ph.rho0;
 }
@@ -142,12 +132,17 @@ __global__ __launch_bounds__(kThreads) void k_face_fluxes(Dims d, Phys ph, const
 }
 
 __global__ void k_reset_reduce(AsmReduce* r) {
-  if (threadIdx.x == 0) {
-    r->lo = ord_encode(INFINITY);
-    r->hi = ord_encode(-INFINITY);
-    r->tmax = ord_encode(0.0);
-    r->vmax = ord_encode(0.0);
+  for (int k = threadIdx.x; k < kSlots; k += blockDim.x) {
+    r->lo[k] = ord_encode(INFINITY);
+    r->hi[k] = ord_encode(-INFINITY);
+    r->tmax[k] = ord_encode(0.0);
+    r->vmax[k] = ord_encode(0.0);
   }
+}
+
+// slot of this block's atomics in AsmReduce
+__device__ inline int red_slot() {
+  return (blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z)) & (kSlots - 1);
 }
 
 // ---------------------------------------------------------------------------
@@ -270,9 +265,10 @@ __global__ __launch_bounds__(kThreads) void k_assemble(Dims d, Phys ph, const do
       sh[1][0] = fmax(sh[1][0], sh[1][w]);
       sh[2][0] = fmax(sh[2][0], sh[2][w]);
     }
-    atomicMin(&red->lo, ord_encode(sh[0][0]));
-    atomicMax(&red->hi, ord_encode(sh[1][0]));
-    atomicMax(&red->tmax, ord_encode(sh[2][0]));
+    const int k = red_slot();
+    atomicMin(&red->lo[k], ord_encode(sh[0][0]));
+    atomicMax(&red->hi[k], ord_encode(sh[1][0]));
+    atomicMax(&red->tmax[k], ord_encode(sh[2][0]));
   }
 }
 
@@ -306,13 +302,14 @@ __global__ __launch_bounds__(kThreads) void k_gershgorin(Dims d, const double* _
       sh[0][0] = fmin(sh[0][0], sh[0][w]);
       sh[1][0] = fmax(sh[1][0], sh[1][w]);
     }
-    atomicMin(&red->lo, ord_encode(sh[0][0]));
-    atomicMax(&red->hi, ord_encode(sh[1][0]));
+    const int k = red_slot();
+    atomicMin(&red->lo[k], ord_encode(sh[0][0]));
+    atomicMax(&red->hi[k], ord_encode(sh[1][0]));
   }
 }
 
 __global__ void k_reset_vmax(AsmReduce* r) {
-  if (threadIdx.x == 0) r->vmax = ord_encode(0.0);
+  for (int k = threadIdx.x; k < kSlots; k += blockDim.x) r->vmax[k] = ord_encode(0.0);
 }
 
 __global__ __launch_bounds__(kThreads) void k_absmax(Dims d, const double* __restrict__ v, AsmReduce* red) {
@@ -328,7 +325,7 @@ __global__ __launch_bounds__(kThreads) void k_absmax(Dims d, const double* __res
   __syncthreads();
   if (t == 0) {
     for (int w = 1; w < kThreads / 64; ++w) sh[0] = fmax(sh[0], sh[w]);
-    atomicMax(&red->vmax, ord_encode(sh[0]));
+    atomicMax(&red->vmax[red_slot()], ord_encode(sh[0]));
   }
 }
 

@@ -47,9 +47,25 @@ struct MgHierarchy {
   MgCoarseArgs coarse;
 };
 
+// Conjugate-gradient update of iteration it folded into the first down leg
+// of a 2D hierarchy: alpha = (r.z) / (p.q); x += alpha p; r_new = r - alpha q
+// (r_new in its own buffer: neighbouring tiles still read r); r_new . r_new
+// into the CG ring.
+struct CgFuse {
+  double* x;
+  double* r_new;
+  const double* p;
+  const double* q;
+  int it;
+};
+
 hipError_t mg_setup(const MgHierarchy& h, hipStream_t s);
+// z = M^{-1} r.  With cg (only where mg_fuses_cg), r is the residual before
+// the update and z = M^{-1} r_new.
 hipError_t mg_apply(const MgHierarchy& h, const double* r, double* z, PcgState* st, int rz_slot,
-                    hipStream_t s);
+                    hipStream_t s, const CgFuse* cg = nullptr);
+// True when the finest level is 2D and runs the global-memory legs.
+inline bool mg_fuses_cg(const MgHierarchy& h) { return h.lc > 0 && h.lev[0].nz == 1; }
 hipError_t mg_set_lds_limit(int bytes);
 
 }  // namespace erem

@@ -94,11 +94,13 @@ __global__ __launch_bounds__(kThreads) void k_mg_coarsen(MgLevelDev F, MgLevelDe
 }
 
 // Dense inverse of the bottom-level operator (SPD, diagonally dominant, so
-// Gauss-Jordan without pivoting is stable), one workgroup, in place in LDS.
+// Gauss-Jordan without pivoting is stable), one workgroup of 1024 threads
+// holding the matrix in registers (assembled in LDS).
+static_assert(kMgBottomCells <= 64, "the bottom inverse maps 64 rows x 16 column groups of 4 onto 1024 threads");
 __global__ __launch_bounds__(1024) void k_mg_bottom_inverse(MgLevelDev L, double* __restrict__ inv) {
   __shared__ double M[kMgBottomCells * kMgBottomCells];
-  __shared__ double prow[kMgBottomCells];
-  __shared__ double pcol[kMgBottomCells];
+  __shared__ double prow[2][kMgBottomCells];
+  __shared__ double pcol[2][kMgBottomCells];
   const int n = L.nx * L.ny * L.nz;
   for (int j = threadIdx.x; j < n * n; j += blockDim.x) M[j] = 0.0;
   __syncthreads();
@@ -118,26 +120,45 @@ __global__ __launch_bounds__(1024) void k_mg_bottom_inverse(MgLevelDev L, double
     if (z + 1 < L.nz) M[c * n + c + L.nx * L.ny] = -L.tz[fzi(L.nx, L.ny, x, y, z + 1)];
   }
   __syncthreads();
+  // Gauss-Jordan in place, no pivoting (the operator is SPD).  Thread t keeps
+  // row t / 16, columns 4 (t % 16) .. 4 (t % 16) + 3 in registers; the pivot
+  // row and column go through LDS, double-buffered so that one barrier per
+  // pivot suffices.  Rows and columns past n carry values that are never
+  // stored, so the update runs without branches (selects only).
+  const int t = threadIdx.x;
+  const int i = t >> 4, j0 = (t & 15) * 4;
+  double m[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) m[u] = (i < n && j0 + u < n) ? M[i * n + j0 + u] : 0.0;
   for (int k = 0; k < n; ++k) {
-    const double piv = 1.0 / M[k * n + k];
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
-      prow[j] = (j == k) ? piv : M[k * n + j] * piv;  // new pivot row
-      pcol[j] = M[j * n + k];                          // old pivot column
+    const int b = k & 1;
+    if (i == k) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u) prow[b][j0 + u] = m[u];
+    }
+    if ((k >> 2) == (t & 15)) {
+      const int u = k & 3;
+      pcol[b][i] = u == 0 ? m[0] : u == 1 ? m[1] : u == 2 ? m[2] : m[3];
     }
     __syncthreads();
-    for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-      const int i = e / n, j = e - i * n;
-      if (i == k) {
-        M[e] = prow[j];
-      } else if (j == k) {
-        M[e] = -pcol[i] * piv;
-      } else {
-        M[e] -= pcol[i] * prow[j];
-      }
+    const double piv = 1.0 / prow[b][k];
+    const double ci = pcol[b][i];
+    double rj[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) rj[u] = prow[b][j0 + u];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = j0 + u;
+      const double pr = j == k ? piv : rj[u] * piv;  // new pivot row
+      const double upd = m[u] - ci * pr;
+      m[u] = i == k ? pr : (j == k ? -ci * piv : upd);
     }
-    __syncthreads();
   }
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) inv[e] = M[e];
+  if (i < n) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (j0 + u < n) inv[i * n + j0 + u] = m[u];
+  }
 }
 
 // Cell index and the neighbour sum of one level; the neighbour order (-x, +x,
@@ -296,11 +317,18 @@ __device__ inline double nb_sum_tile(const TileFaces& F, int nx, int ny, int gx,
   return s;
 }
 
+// With CG, the conjugate-gradient update of the iteration is folded in:
+// alpha = (r.z) / (p.q) from the slot sums, r <- r - alpha q on the tile and
+// its halo (the halo values recomputed, the tile's written), x <- x + alpha p
+// and the partial sums of r.r, as a separate update kernel would do.
+template <bool CG>
 __global__ __launch_bounds__(kThreads) void k_mg_down_restrict_2d(MgLevelDev F, MgLevelDev C,
                                                         const double* __restrict__ b, double* __restrict__ xout,
-                                                        double* __restrict__ bc, const PcgState* st) {
+                                                        double* __restrict__ bc, PcgState* st, CgFuse cg) {
   const bool stop = pcg_done(st);
   __shared__ double sb[kH2][kW2], sd[kH2][kW2], sx1[kH2][kW2], sx2[kH1][kW1];
+  __shared__ double sq[CG ? kH2 : 1][CG ? kW2 : 1];
+  __shared__ double alpha_sh;
   __shared__ TileFaces tf;
   const int nx = F.nx, ny = F.ny;
   const int x0 = blockIdx.x * kBX, y0 = blockIdx.y * kTY;
@@ -313,11 +341,63 @@ __global__ __launch_bounds__(kThreads) void k_mg_down_restrict_2d(MgLevelDev F, 
     const double bj = in ? b[j] : 0.0, dj = in ? F.diag[j] : 1.0;
     sb[ly][lx] = bj;
     sd[ly][lx] = dj;
-    sx1[ly][lx] = kOmega * bj / dj;  // first sweep from zero
+    if (CG) {
+      sq[ly][lx] = in ? cg.q[j] : 0.0;
+    } else {
+      sx1[ly][lx] = kOmega * bj / dj;  // first sweep from zero
+    }
+  }
+  // the tile's own cells (two rows per thread) for the x update
+  const int ox = x0 + threadIdx.x;
+  double xo[2] = {0.0, 0.0}, po[2] = {0.0, 0.0};
+  if (CG) {
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int oy = y0 + 2 * threadIdx.y + r;
+      if (ox < nx && oy < ny) {
+        xo[r] = cg.x[ox + nx * oy];
+        po[r] = cg.p[ox + nx * oy];
+      }
+    }
   }
   load_tile_faces(F, x0, y0, tid, tf);
+  if (CG && tid < 64 && !stop) {  // the first wavefront decides alpha
+    const int it = cg.it;
+    const double alpha = wave_slot_sum(st->rz + (it & 3) * kSlots) / wave_slot_sum(st->pq + (it & 3) * kSlots);
+    if (tid == 0) alpha_sh = alpha;
+    if (blockIdx.x == 0 && blockIdx.y == 0) st->pq[((it + 1) & 3) * kSlots + tid] = 0.0;
+  }
   if (stop) return;
   __syncthreads();
+  if (CG) {
+    const double alpha = alpha_sh;
+    for (int k = tid; k < kH2 * kW2; k += kThreads) {
+      const int ly = k / kW2, lx = k - ly * kW2;
+      const double rn = sb[ly][lx] - alpha * sq[ly][lx];  // zero outside the grid stays zero
+      sb[ly][lx] = rn;
+      sx1[ly][lx] = kOmega * rn / sd[ly][lx];  // first sweep from zero
+    }
+    __syncthreads();
+    double rr = 0.0;
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      const int ly = 2 * threadIdx.y + r, oy = y0 + ly;
+      if (ox < nx && oy < ny) {
+        const double rn = sb[ly + 2][threadIdx.x + 2];
+        cg.r_new[ox + nx * oy] = rn;
+        cg.x[ox + nx * oy] = xo[r] + alpha * po[r];
+        rr += rn * rn;
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) rr += __shfl_down(rr, off, 64);
+    __shared__ double sh[kThreads / 64];
+    if ((tid & 63) == 0) sh[tid >> 6] = rr;
+    __syncthreads();
+    if (tid == 0) {
+      const int bid = blockIdx.x + gridDim.x * blockIdx.y;
+      atomicAdd(&st->rr[((cg.it + 1) & 3) * kSlots + (bid & (kSlots - 1))], sh[0] + sh[1] + sh[2] + sh[3]);
+    }
+  }
   for (int k = tid; k < kH1 * kW1; k += kThreads) {
     const int ly = k / kW1, lx = k - ly * kW1;
     const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
@@ -415,11 +495,12 @@ __global__ __launch_bounds__(kThreads) void k_mg_up_smooth_2d(MgLevelDev F, MgLe
 }
 
 // ---------------------------------------------------------------------------
-// Coarse levels in one workgroup, everything in LDS: one V-cycle over the
-// levels first..bottom-1 with the exact dense solve on the bottom level,
+// Coarse levels in one workgroup, everything in LDS: a.ncyc V-cycles over
+// the levels first..bottom-1 with the exact dense solve on the bottom level,
 // from x = 0, on rhs b (global).  Writes x to out; with rz_slot >= 0 also
-// b . out into the CG ring.  LDS per smoothed level: faces, diagonal and
-// three vectors; bottom: two vectors and the inverse; plus the rhs copy.
+// b . out into the CG ring.  LDS per smoothed level: faces, diagonal, its
+// inverse and three vectors; bottom: two vectors, the partial products of
+// the dense solve and the inverse.
 // ---------------------------------------------------------------------------
 struct LdsLevel {
   double *tx, *ty, *tz, *diag, *B, *E, *T, *dinv;
@@ -436,8 +517,6 @@ __device__ inline void lds_level(const MgCoarseArgs& a, double* smem, int l, Lds
   S.dinv = smem + a.off[l][7];
 }
 
-// sweeps damped-Jacobi sweeps on one LDS level (E in, E out; T is scratch;
-// the roles swap after every sweep, so sweeps must be even).
 // (x, y, z) of cell c of a level
 __device__ inline void cell_xyz(const MgLevelDev& L, int c, int& x, int& y, int& z) {
   if (L.nz == 1) {
@@ -454,18 +533,59 @@ __device__ inline void cell_xyz(const MgLevelDev& L, int c, int& x, int& y, int&
 }
 
 // Neighbour sum of cell c of an LDS level with values v(j, x, y, z) of the
-// neighbour j at (x, y, z)
+// neighbour j at (x, y, z).  Every face index is valid (boundary faces are
+// stored); a missing neighbour is replaced by the cell itself and its term
+// dropped by a select, so all loads issue without branches and wait once.
 template <class V>
 __device__ inline double lds_nb_sum(const MgLevelDev& L, const LdsLevel& S, int x, int y, int z, int c, V&& v) {
   const int nx = L.nx, ny = L.ny, nz = L.nz;
-  double s = 0.0;
-  if (x > 0) s += S.tx[fxi(nx, ny, x, y, z)] * v(c - 1, x - 1, y, z);
-  if (x + 1 < nx) s += S.tx[fxi(nx, ny, x + 1, y, z)] * v(c + 1, x + 1, y, z);
-  if (y > 0) s += S.ty[fyi(nx, ny, x, y, z)] * v(c - nx, x, y - 1, z);
-  if (y + 1 < ny) s += S.ty[fyi(nx, ny, x, y + 1, z)] * v(c + nx, x, y + 1, z);
-  if (z > 0) s += S.tz[fzi(nx, ny, x, y, z)] * v(c - nx * ny, x, y, z - 1);
-  if (z + 1 < nz) s += S.tz[fzi(nx, ny, x, y, z + 1)] * v(c + nx * ny, x, y, z + 1);
+  const bool hw = x > 0, he = x + 1 < nx, hs = y > 0, hn = y + 1 < ny;
+  const double tw = S.tx[fxi(nx, ny, x, y, z)], te = S.tx[fxi(nx, ny, x + 1, y, z)];
+  const double ts = S.ty[fyi(nx, ny, x, y, z)], tn = S.ty[fyi(nx, ny, x, y + 1, z)];
+  const double vw = v(hw ? c - 1 : c, hw ? x - 1 : x, y, z);
+  const double ve = v(he ? c + 1 : c, he ? x + 1 : x, y, z);
+  const double vs = v(hs ? c - nx : c, x, hs ? y - 1 : y, z);
+  const double vn = v(hn ? c + nx : c, x, hn ? y + 1 : y, z);
+  double s = (hw ? tw * vw : 0.0) + (he ? te * ve : 0.0) + (hs ? ts * vs : 0.0) + (hn ? tn * vn : 0.0);
+  if (nz > 1) {  // uniform: 2D levels keep no z faces in LDS
+    const bool hb = z > 0, ht = z + 1 < nz;
+    const double tb = S.tz[fzi(nx, ny, x, y, z)], tt = S.tz[fzi(nx, ny, x, y, z + 1)];
+    const double vb = v(hb ? c - nx * ny : c, x, y, hb ? z - 1 : z);
+    const double vt = v(ht ? c + nx * ny : c, x, y, ht ? z + 1 : z);
+    s += (hb ? tb * vb : 0.0) + (ht ? tt * vt : 0.0);
+  }
   return s;
+}
+
+// One smoothed level's faces and diagonal (and 1/diagonal) into LDS, every
+// load issued before the first store.  Two face values and one diagonal
+// value per thread cover the level: it has at most blockDim cells and at
+// most twice as many faces per direction.
+__device__ inline void lds_load_level(const MgLevelDev& L, const LdsLevel& S) {
+  const int bd = blockDim.x, t = threadIdx.x;
+  const int n = L.nx * L.ny * L.nz;
+  const int nfx = (L.nx + 1) * L.ny * L.nz, nfy = L.nx * (L.ny + 1) * L.nz;
+  const int nfz = L.nz > 1 ? L.nx * L.ny * (L.nz + 1) : 0;  // 2D: z faces never read
+  double fx[2], fy[2], fz[2];
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int j = t + u * bd;
+    fx[u] = j < nfx ? L.tx[j] : 0.0;
+    fy[u] = j < nfy ? L.ty[j] : 0.0;
+    fz[u] = j < nfz ? L.tz[j] : 0.0;
+  }
+  const double dg = t < n ? L.diag[t] : 1.0;
+#pragma unroll
+  for (int u = 0; u < 2; ++u) {
+    const int j = t + u * bd;
+    if (j < nfx) S.tx[j] = fx[u];
+    if (j < nfy) S.ty[j] = fy[u];
+    if (j < nfz) S.tz[j] = fz[u];
+  }
+  if (t < n) {
+    S.diag[t] = dg;
+    S.dinv[t] = 1.0 / dg;  // the sweeps multiply; one division per cell here
+  }
 }
 
 __global__ __launch_bounds__(1024) void k_mg_coarse_lds(MgCoarseArgs a, const double* __restrict__ bglob,
@@ -474,31 +594,34 @@ __global__ __launch_bounds__(1024) void k_mg_coarse_lds(MgCoarseArgs a, const do
   const bool stop = pcg_done(st);  // checked once the level loads are in flight
   extern __shared__ double smem[];
   const int nl = a.nlev;          // levels in LDS, the last one is the bottom
-  // load faces / diagonals of the smoothed levels, the bottom inverse, the rhs
+  const int bd = blockDim.x, t = threadIdx.x;
+  LdsLevel S0;
+  lds_level(a, smem, 0, S0);
+  const int n0 = a.n0;
+  const double b0 = t < n0 ? bglob[t] : 0.0;
+  // faces / diagonals of the smoothed levels, the bottom inverse, the rhs
   for (int l = 0; l + 1 < nl; ++l) {
-    const MgLevelDev& L = a.lev[l];
     LdsLevel S;
     lds_level(a, smem, l, S);
-    const int n = L.nx * L.ny * L.nz;
-    const int nfx = (L.nx + 1) * L.ny * L.nz, nfy = L.nx * (L.ny + 1) * L.nz;
-    const int nfz = L.nz > 1 ? L.nx * L.ny * (L.nz + 1) : 0;  // 2D: z faces never read
-    for (int j = threadIdx.x; j < nfx; j += blockDim.x) S.tx[j] = L.tx[j];
-    for (int j = threadIdx.x; j < nfy; j += blockDim.x) S.ty[j] = L.ty[j];
-    for (int j = threadIdx.x; j < nfz; j += blockDim.x) S.tz[j] = L.tz[j];
-    for (int j = threadIdx.x; j < n; j += blockDim.x) {
-      const double dg = L.diag[j];
-      S.diag[j] = dg;
-      S.dinv[j] = 1.0 / dg;  // the sweeps multiply; one division per cell here
-    }
+    lds_load_level(a.lev[l], S);
   }
   const MgLevelDev& Lb = a.lev[nl - 1];
   const int nb = Lb.nx * Lb.ny * Lb.nz;
   double* Binv = smem + a.inv_off;
-  for (int j = threadIdx.x; j < nb * nb; j += blockDim.x) Binv[j] = binv[j];
-  LdsLevel S0;
-  lds_level(a, smem, 0, S0);
-  const int n0 = a.n0;
-  for (int j = threadIdx.x; j < n0; j += blockDim.x) S0.B[j] = bglob[j];
+  for (int j0 = 0; j0 < nb * nb; j0 += 4 * bd) {
+    double r[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = j0 + t + u * bd;
+      r[u] = j < nb * nb ? binv[j] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = j0 + t + u * bd;
+      if (j < nb * nb) Binv[j] = r[u];
+    }
+  }
+  if (t < n0) S0.B[t] = b0;
   if (stop) return;
   __syncthreads();
   // a.ncyc V-cycles on the first LDS level: each later one starts from the
@@ -506,11 +629,12 @@ __global__ __launch_bounds__(1024) void k_mg_coarse_lds(MgCoarseArgs a, const do
   for (int cyc = 0; cyc < a.ncyc; ++cyc) {
     if (cyc > 0) {
       const MgLevelDev& F = a.lev[0];
-      for (int c = threadIdx.x; c < n0; c += blockDim.x) {
+      auto ev = [&](int j, int, int, int) { return S0.E[j]; };
+      for (int c = t; c < n0; c += bd) {
         int x, y, z;
         cell_xyz(F, c, x, y, z);
         const double e = S0.E[c];
-        S0.B[c] += offdiag_sum(F.nx, F.ny, F.nz, S0.tx, S0.ty, S0.tz, S0.E, x, y, z, c) - S0.diag[c] * e;
+        S0.B[c] += lds_nb_sum(F, S0, x, y, z, c, ev) - S0.diag[c] * e;
         out[c] = (cyc > 1 ? out[c] : 0.0) + e;
       }
       __syncthreads();
@@ -527,7 +651,7 @@ __global__ __launch_bounds__(1024) void k_mg_coarse_lds(MgCoarseArgs a, const do
       {
         const int n = F.nx * F.ny * F.nz;
         auto x1 = [&](int j, int, int, int) { return kOmega * S.B[j] * S.dinv[j]; };
-        for (int c = threadIdx.x; c < n; c += blockDim.x) {
+        for (int c = t; c < n; c += bd) {
           int x, y, z;
           cell_xyz(F, c, x, y, z);
           const double di = S.dinv[c];
@@ -537,33 +661,59 @@ __global__ __launch_bounds__(1024) void k_mg_coarse_lds(MgCoarseArgs a, const do
         }
         __syncthreads();
       }
+      // restricted residual: the sum over the (up to) 2 x 2 (x 2) fine cells
+      // of each coarse cell; a fine index past the edge is clamped and its
+      // term dropped
       const int nc = C.nx * C.ny * C.nz;
-      for (int c = threadIdx.x; c < nc; c += blockDim.x) {
+      auto ev = [&](int j, int, int, int) { return S.E[j]; };
+      auto res = [&](int x, int y, int z) {
+        const int i = x + F.nx * (y + F.ny * z);
+        return S.B[i] - S.diag[i] * S.E[i] + lds_nb_sum(F, S, x, y, z, i, ev);
+      };
+      for (int c = t; c < nc; c += bd) {
         int X0, Y0, Z0;
         cell_xyz(C, c, X0, Y0, Z0);
-        const int x1 = min(2 * X0 + 1, F.nx - 1), y1 = min(2 * Y0 + 1, F.ny - 1);
-        const int z0 = F.nz > 1 ? 2 * Z0 : 0, z1 = F.nz > 1 ? min(2 * Z0 + 1, F.nz - 1) : 0;
-        double acc = 0.0;
-        for (int z = z0; z <= z1; ++z)
-          for (int y = 2 * Y0; y <= y1; ++y)
-            for (int x = 2 * X0; x <= x1; ++x) {
-              const int i = x + F.nx * (y + F.ny * z);
-              acc += S.B[i] - S.diag[i] * S.E[i] + offdiag_sum(F.nx, F.ny, F.nz, S.tx, S.ty, S.tz, S.E, x, y, z, i);
-            }
+        const int x0 = 2 * X0, y0 = 2 * Y0;
+        const bool hx = x0 + 1 < F.nx, hy = y0 + 1 < F.ny;
+        const int x1 = hx ? x0 + 1 : x0, y1 = hy ? y0 + 1 : y0;
+        double acc;
+        if (F.nz > 1) {
+          const int z0 = 2 * Z0;
+          const bool hz = z0 + 1 < F.nz;
+          const int z1 = hz ? z0 + 1 : z0;
+          const double r000 = res(x0, y0, z0), r100 = res(x1, y0, z0), r010 = res(x0, y1, z0), r110 = res(x1, y1, z0);
+          const double r001 = res(x0, y0, z1), r101 = res(x1, y0, z1), r011 = res(x0, y1, z1), r111 = res(x1, y1, z1);
+          acc = r000 + (hx ? r100 : 0.0) + (hy ? r010 : 0.0) + (hx && hy ? r110 : 0.0);
+          if (hz) acc += r001 + (hx ? r101 : 0.0) + (hy ? r011 : 0.0) + (hx && hy ? r111 : 0.0);
+        } else {
+          const double r00 = res(x0, y0, 0), r10 = res(x1, y0, 0), r01 = res(x0, y1, 0), r11 = res(x1, y1, 0);
+          acc = r00 + (hx ? r10 : 0.0) + (hy ? r01 : 0.0) + (hx && hy ? r11 : 0.0);
+        }
         SC.B[c] = acc;
       }
       __syncthreads();
     }
-    // bottom: E = inverse * B
+    // bottom: E = inverse * B, the columns split over the wavefronts (partial
+    // products in T), then summed per row.  The inverse of the symmetric
+    // bottom operator is symmetric: it is read by columns so that
+    // consecutive threads hit consecutive banks.
     {
       LdsLevel S;
       lds_level(a, smem, nl - 1, S);
-      for (int r = threadIdx.x; r < nb; r += blockDim.x) {
+      const int groups = (bd + 63) >> 6;
+      const int chunk = (nb + groups - 1) / groups;
+      const int r = t & 63, g = t >> 6;
+      if (r < nb) {
+        const int j0 = g * chunk, j1 = min(nb, j0 + chunk);
         double acc = 0.0;
-        // the inverse of the symmetric bottom operator is symmetric: read it
-        // by columns so that consecutive threads hit consecutive banks
-        for (int j = 0; j < nb; ++j) acc += Binv[j * nb + r] * S.B[j];
-        S.E[r] = acc;
+        for (int j = j0; j < j1; ++j) acc += Binv[j * nb + r] * S.B[j];
+        S.T[g * nb + r] = acc;
+      }
+      __syncthreads();
+      if (t < nb) {
+        double acc = 0.0;
+        for (int k = 0; k < groups; ++k) acc += S.T[k * nb + t];
+        S.E[t] = acc;
       }
       __syncthreads();
     }
@@ -580,7 +730,7 @@ __global__ __launch_bounds__(1024) void k_mg_coarse_lds(MgCoarseArgs a, const do
       auto xc = [&](int j, int x, int y, int z) {
         return S.E[j] + a.omega_c * SC.E[(x >> 1) + C.nx * ((y >> 1) + C.ny * (z >> cz))];
       };
-      for (int c = threadIdx.x; c < n; c += blockDim.x) {
+      for (int c = t; c < n; c += bd) {
         int x, y, z;
         cell_xyz(F, c, x, y, z);
         const double di = S.dinv[c];
@@ -590,7 +740,7 @@ __global__ __launch_bounds__(1024) void k_mg_coarse_lds(MgCoarseArgs a, const do
       __syncthreads();
       // second sweep: E = T + w (B - A T) / D
       auto tv = [&](int j, int, int, int) { return S.T[j]; };
-      for (int c = threadIdx.x; c < n; c += blockDim.x) {
+      for (int c = t; c < n; c += bd) {
         int x, y, z;
         cell_xyz(F, c, x, y, z);
         const double di = S.dinv[c];
@@ -601,7 +751,7 @@ __global__ __launch_bounds__(1024) void k_mg_coarse_lds(MgCoarseArgs a, const do
     }
   }
   double part = 0.0;
-  for (int c = threadIdx.x; c < n0; c += blockDim.x) {
+  for (int c = t; c < n0; c += bd) {
     const double v = (a.ncyc > 1 ? out[c] : 0.0) + S0.E[c];
     out[c] = v;
     part += bglob[c] * v;
@@ -609,11 +759,11 @@ __global__ __launch_bounds__(1024) void k_mg_coarse_lds(MgCoarseArgs a, const do
   if (rz_slot < 0) return;
   for (int off = 32; off > 0; off >>= 1) part += __shfl_down(part, off, 64);
   __shared__ double sh[16];
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = part;
+  if ((t & 63) == 0) sh[t >> 6] = part;
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (t == 0) {
     double s = 0.0;
-    for (int w = 0; w < static_cast<int>(blockDim.x + 63) / 64; ++w) s += sh[w];
+    for (int w = 0; w < (bd + 63) / 64; ++w) s += sh[w];
     atomicAdd(&st->rz[rz_slot * kSlots], s);
   }
 }
@@ -633,7 +783,9 @@ hipError_t mg_setup(const MgHierarchy& h, hipStream_t s) {
 
 // z = M^{-1} r on the finest level; with rz_slot >= 0 also accumulates r . z
 // into the CG ring.
-hipError_t mg_apply(const MgHierarchy& h, const double* r, double* z, PcgState* st, int rz_slot, hipStream_t s) {
+hipError_t mg_apply(const MgHierarchy& h, const double* r, double* z, PcgState* st, int rz_slot, hipStream_t s,
+                    const CgFuse* cg) {
+  if (cg && !mg_fuses_cg(h)) return hipErrorInvalidValue;
   const int lc = h.lc;
   auto grid_of = [](const MgLevelDev& L) {
     return dim3((L.nx + kBX - 1) / kBX, (L.ny + kBY - 1) / kBY, L.nz);
@@ -644,7 +796,10 @@ hipError_t mg_apply(const MgHierarchy& h, const double* r, double* z, PcgState* 
     const double* b = l == 0 ? r : F.b;
     if (F.nz == 1) {
       const dim3 g((F.nx + kBX - 1) / kBX, (F.ny + kTY - 1) / kTY, 1);
-      hipLaunchKernelGGL(k_mg_down_restrict_2d, g, cell_block(), 0, s, F, C, b, F.x, C.b, st);
+      if (l == 0 && cg)
+        hipLaunchKernelGGL(k_mg_down_restrict_2d<true>, g, cell_block(), 0, s, F, C, b, F.x, C.b, st, *cg);
+      else
+        hipLaunchKernelGGL(k_mg_down_restrict_2d<false>, g, cell_block(), 0, s, F, C, b, F.x, C.b, st, CgFuse{});
     } else {
       const dim3 g((F.nx + kBX - 1) / kBX, (F.ny + kBY - 1) / kBY, C.nz);
       hipLaunchKernelGGL(k_mg_down_restrict, g, cell_block(), 0, s, F, C, b, F.x, C.b, st);
@@ -661,7 +816,7 @@ hipError_t mg_apply(const MgHierarchy& h, const double* r, double* z, PcgState* 
   for (int l = lc - 1; l >= 0; --l) {
     const MgLevelDev& F = h.lev[l];
     const MgLevelDev& C = h.lev[l + 1];
-    const double* b = l == 0 ? r : F.b;
+    const double* b = l == 0 ? (cg ? cg->r_new : r) : F.b;
     const double* ec = l + 1 == lc ? C.x : C.y;
     double* out = l == 0 ? z : F.y;
     if (F.nz == 1) {
