@@ -61,6 +61,7 @@ struct erem_ctx {
   DivDiffCache dd;
   int last_m = 0;          // degree used by the previous evaluation
   // profiling (HIP events around each Leja term and PCG half-iteration)
+  int pcg_last = 0;  // iterations of the last converged CG solve (poll placement)
   int prof = 0;  // per-launch event timing: 0 off, n > 0 one launch in n
   std::vector<hipEvent_t> ev;
   double t_leja = 0.0, t_pcg_a = 0.0, t_pcg_b = 0.0, t_mg = 0.0;

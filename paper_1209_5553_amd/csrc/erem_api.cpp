@@ -594,17 +594,21 @@ int pcg_inner(erem_ctx* c, double inner_tol, int budget, int* iters, bool* done)
   HIP_TRY(c, launch_pcg_start_rhs(d, c->tx, c->ty, c->tz, c->prhs, c->pdelta, c->pr, c->pz, c->pp0, c->pdiag,
                                   c->pcg, jac, c->stream));
   if (c->use_mg) HIP_TRY(c, mg_apply(c->mg, c->pr, c->pz, c->pcg, 0, c->stream));
-  // Multigrid iterations are few: poll the device after a handful of them.
-  const int chunk = c->use_mg ? 8 : 64;
+  // Iterations after convergence still launch (their kernels return at
+  // entry), so the host polls where the solve is expected to end: with
+  // multigrid the first poll follows the previous solve's count plus the
+  // test iteration (at most 24), then every two iterations.
+  const int first_chunk = c->use_mg ? (c->pcg_last > 0 ? std::min(c->pcg_last + 1, 24) : 8) : 64;
+  const int chunk = c->use_mg ? 2 : 64;
   const bool fuse = c->use_mg && mg_fuses_cg(c->mg);
   int it = 0;
   *done = false;
   if (c->prof) {
-    const int rc = ensure_events(c, 4 * chunk);
+    const int rc = ensure_events(c, 4 * std::max(first_chunk, chunk));
     if (rc) return rc;
   }
   while (it < budget) {
-    const int n = std::min(chunk, budget - it);
+    const int n = std::min(it == 0 ? first_chunk : chunk, budget - it);
     const int it0 = it;
     for (int j = 0; j < n; ++j, ++it) {
       double* pold = (it & 1) ? c->pp1 : c->pp0;
@@ -650,6 +654,7 @@ int pcg_inner(erem_ctx* c, double inner_tol, int budget, int* iters, bool* done)
     if (fin) { *done = true; it = c->h_pcg->it_done; break; }
   }
   *iters = it;
+  if (*done) c->pcg_last = it;
   return EREM_OK;
 }
 
