@@ -18,7 +18,7 @@ hipError_t launch_adj_scale(const Dims& d, const double* ubar, double scale, dou
 //   jbar[dir][i] += inv_g * s_in[i] * q_prev[neighbour(i, dir)]
 hipError_t launch_adj_rev_term(const Dims& d, const double* coef, const double* s_in, const double* q_prev,
                                const double* ubar, double yscale, double inv_g, double shift_k, double* jbar,
-                               double* s_out, hipStream_t s);
+                               double* s_out, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
 // End of a reversed substep with rbar = s_0: wbar += rbar; when u is given
 // (substeps after the first), ubar += J^T rbar and jbar[dir][i] += rbar[i] u[nb].

@@ -348,9 +348,9 @@ hipError_t launch_adj_scale(const Dims& d, const double* ubar, double scale, dou
 
 hipError_t launch_adj_rev_term(const Dims& d, const double* coef, const double* s_in, const double* q_prev,
                                const double* ubar, double yscale, double inv_g, double shift_k, double* jbar,
-                               double* s_out, hipStream_t s) {
-  hipLaunchKernelGGL(k_adj_rev_term, grid2(d), block2(), 0, s, d, coef, s_in, q_prev, ubar, yscale, inv_g,
-                     shift_k, jbar, s_out);
+                               double* s_out, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  launch_timed(k_adj_rev_term, grid2(d), block2(), 0, s, e0, e1, d, coef, s_in, q_prev, ubar, yscale, inv_g,
+               shift_k, jbar, s_out);
   return hipGetLastError();
 }
 

@@ -283,10 +283,9 @@ int erem_coupled_step_adjoint(erem_ctx* c, double h, const double* d_T, double p
         q = c->adj_seg + static_cast<size_t>(kk - a * S) * N;
       }
       const bool timed = c->prof && k % c->prof == 0;
-      if (timed) HIP_TRY(c, hipEventRecord(c->ev[2 * (m - k)], c->stream));
       HIP_TRY(c, launch_adj_rev_term(d, c->coef, sin, q, c->adj_ubar, delta * dk[kk], inv_g, shift[k], c->adj_jbar,
-                                     sout, c->stream));
-      if (timed) HIP_TRY(c, hipEventRecord(c->ev[2 * (m - k) + 1], c->stream));
+                                     sout, c->stream, timed ? c->ev[2 * (m - k)] : nullptr,
+                                     timed ? c->ev[2 * (m - k) + 1] : nullptr));
       std::swap(sin, sout);
     }
     if (c->prof) {

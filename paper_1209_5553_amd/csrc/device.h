@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 #include <cstdint>
 
 namespace erem {
@@ -108,10 +109,22 @@ hipError_t launch_face_fluxes_dd(const Dims& d, const Phys& ph, const double* ph
                                  hipStream_t s);
 hipError_t launch_pcg_a(const Dims& d, const double* tx, const double* ty, const double* tz,
                         const double* z, const double* pold, double* pnew, double* q,
-                        PcgState* st, int it, hipStream_t s);
+                        PcgState* st, int it, hipStream_t s, hipEvent_t e0 = nullptr,
+                        hipEvent_t e1 = nullptr);
 hipError_t launch_pcg_b(const Dims& d, double* x, double* r, double* z, const double* pnew,
                         const double* q, const double* diag, PcgState* st, int it,
-                        int jacobi, hipStream_t s);
+                        int jacobi, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+
+// Launch; with events (sampled timing) they record the kernel's own start
+// and stop, without the queue's gaps around it.
+template <typename K, typename... A>
+inline void launch_timed(K kernel, dim3 grid, dim3 block, unsigned shmem, hipStream_t s, hipEvent_t e0,
+                         hipEvent_t e1, A... args) {
+  if (e0)
+    hipExtLaunchKernelGGL(kernel, grid, block, shmem, s, e0, e1, 0, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, shmem, s, args...);
+}
 
 // Sum of the kSlots partial sums at base, by one wavefront (kSlots == 64):
 // every lane loads one slot; a butterfly sums them and lane 0's result is

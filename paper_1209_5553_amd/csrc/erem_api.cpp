@@ -310,12 +310,11 @@ int leja_run(erem_ctx* c, const LejaBufs<V>& B, const double* v, double delta, i
     for (int k = 1, launch = 0; k <= K; ++launch) {
       const int nt = leja_terms_per_launch(d, k, K);
       const bool timed = evj && launch % c->prof == 0;
-      if (timed) HIP_TRY(c, hipEventRecord(evj[2 * (k - 1)], c->stream));
+      hipEvent_t e0 = timed ? evj[2 * (k - 1)] : nullptr, e1 = timed ? evj[2 * (k - 1) + 1] : nullptr;
       if (nt > 1)
-        HIP_TRY(c, launch_leja_terms<V>(d, c->cf, B.coef, cur, oth, B.p, st, c->part, k, nt, c->stream));
+        HIP_TRY(c, launch_leja_terms<V>(d, c->cf, B.coef, cur, oth, B.p, st, c->part, k, nt, c->stream, e0, e1));
       else
-        HIP_TRY(c, launch_leja_term<V>(d, c->cf, B.coef, cur, oth, B.p, st, c->part, k, c->stream));
-      if (timed) HIP_TRY(c, hipEventRecord(evj[2 * (k - 1) + 1], c->stream));
+        HIP_TRY(c, launch_leja_term<V>(d, c->cf, B.coef, cur, oth, B.p, st, c->part, k, c->stream, e0, e1));
       std::swap(cur, oth);
       k += nt;
       const int last = k - 1;
@@ -604,7 +603,7 @@ int pcg_inner(erem_ctx* c, double inner_tol, int budget, int* iters, bool* done)
   int it = 0;
   *done = false;
   if (c->prof) {
-    const int rc = ensure_events(c, 4 * std::max(first_chunk, chunk));
+    const int rc = ensure_events(c, 6 * std::max(first_chunk, chunk));
     if (rc) return rc;
   }
   while (it < budget) {
@@ -614,21 +613,24 @@ int pcg_inner(erem_ctx* c, double inner_tol, int budget, int* iters, bool* done)
       double* pold = (it & 1) ? c->pp1 : c->pp0;
       double* pnew = (it & 1) ? c->pp0 : c->pp1;
       const bool timed = c->prof && it % c->prof == 0;  // sampled iterations
-      if (timed) HIP_TRY(c, hipEventRecord(c->ev[4 * j], c->stream));
-      HIP_TRY(c, launch_pcg_a(d, c->tx, c->ty, c->tz, c->pz, pold, pnew, c->pq, c->pcg, it, c->stream));
-      if (timed) HIP_TRY(c, hipEventRecord(c->ev[4 * j + 1], c->stream));
+      // six events per iteration: kernel-level ones for pcg_a (0, 1) and
+      // pcg_b (4, 5), ones around the preconditioner application (2, 3)
+      hipEvent_t* ev = &c->ev[6 * j];
+      HIP_TRY(c, launch_pcg_a(d, c->tx, c->ty, c->tz, c->pz, pold, pnew, c->pq, c->pcg, it, c->stream,
+                              timed ? ev[0] : nullptr, timed ? ev[1] : nullptr));
       if (fuse) {
         // the update runs inside the first down leg; r alternates between
         // two buffers (neighbouring tiles read the old one)
         const CgFuse cg{c->pdelta, (it & 1) ? c->pr : c->pr2, pnew, c->pq, it};
-        if (timed) HIP_TRY(c, hipEventRecord(c->ev[4 * j + 2], c->stream));
+        if (timed) HIP_TRY(c, hipEventRecord(ev[2], c->stream));
         HIP_TRY(c, mg_apply(c->mg, (it & 1) ? c->pr2 : c->pr, c->pz, c->pcg, (it + 1) & 3, c->stream, &cg));
       } else {
-        HIP_TRY(c, launch_pcg_b(d, c->pdelta, c->pr, c->pz, pnew, c->pq, c->pdiag, c->pcg, it, jac, c->stream));
-        if (timed) HIP_TRY(c, hipEventRecord(c->ev[4 * j + 2], c->stream));
+        HIP_TRY(c, launch_pcg_b(d, c->pdelta, c->pr, c->pz, pnew, c->pq, c->pdiag, c->pcg, it, jac, c->stream,
+                                timed ? ev[4] : nullptr, timed ? ev[5] : nullptr));
+        if (timed) HIP_TRY(c, hipEventRecord(ev[2], c->stream));
         if (c->use_mg) HIP_TRY(c, mg_apply(c->mg, c->pr, c->pz, c->pcg, (it + 1) & 3, c->stream));
       }
-      if (timed) HIP_TRY(c, hipEventRecord(c->ev[4 * j + 3], c->stream));
+      if (timed) HIP_TRY(c, hipEventRecord(ev[3], c->stream));
     }
     HIP_TRY(c, hipMemcpyAsync(c->h_pcg, c->pcg, sizeof(PcgState), hipMemcpyDeviceToHost, c->stream));
     HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -639,14 +641,15 @@ int pcg_inner(erem_ctx* c, double inner_tol, int budget, int* iters, bool* done)
       const int ran = fin ? c->h_pcg->it_done - it0 : n;
       for (int j = 0; j < ran; ++j) {
         if ((it0 + j) % c->prof != 0) continue;
-        c->t_pcg_a += elapsed_ms(c->ev[4 * j], c->ev[4 * j + 1]);
+        const hipEvent_t* ev = &c->ev[6 * j];
+        c->t_pcg_a += elapsed_ms(ev[0], ev[1]);
         ++c->n_pcg_a;
         if (!fuse) {
-          c->t_pcg_b += elapsed_ms(c->ev[4 * j + 1], c->ev[4 * j + 2]);
+          c->t_pcg_b += elapsed_ms(ev[4], ev[5]);
           ++c->n_pcg_b;
         }
         if (c->use_mg) {
-          c->t_mg += elapsed_ms(c->ev[4 * j + 2], c->ev[4 * j + 3]);
+          c->t_mg += elapsed_ms(ev[2], ev[3]);
           ++c->n_mg;
         }
       }

@@ -831,14 +831,16 @@ hipError_t launch_face_fluxes_dd(const Dims& d, const Phys& ph, const double* ph
 }
 
 hipError_t launch_pcg_a(const Dims& d, const double* tx, const double* ty, const double* tz, const double* z,
-                        const double* pold, double* pnew, double* q, PcgState* st, int it, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_a, cell_grid(d), cell_block(), 0, s, d, tx, ty, tz, z, pold, pnew, q, st, it);
+                        const double* pold, double* pnew, double* q, PcgState* st, int it, hipStream_t s,
+                        hipEvent_t e0, hipEvent_t e1) {
+  launch_timed(k_pcg_a, cell_grid(d), cell_block(), 0, s, e0, e1, d, tx, ty, tz, z, pold, pnew, q, st, it);
   return hipGetLastError();
 }
 
 hipError_t launch_pcg_b(const Dims& d, double* x, double* r, double* z, const double* pnew, const double* q,
-                        const double* diag, PcgState* st, int it, int jacobi, hipStream_t s) {
-  hipLaunchKernelGGL(k_pcg_b, cell_grid(d), cell_block(), 0, s, d, x, r, z, pnew, q, diag, st, it, jacobi);
+                        const double* diag, PcgState* st, int it, int jacobi, hipStream_t s, hipEvent_t e0,
+                        hipEvent_t e1) {
+  launch_timed(k_pcg_b, cell_grid(d), cell_block(), 0, s, e0, e1, d, x, r, z, pnew, q, diag, st, it, jacobi);
   return hipGetLastError();
 }
 

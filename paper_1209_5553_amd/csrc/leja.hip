@@ -110,34 +110,41 @@ __global__ __launch_bounds__(kThreads) void k_leja_term(Dims d, const LejaCoef* 
 }
 
 // NT Newton terms in one pass (2D), NT = 2 or 4: q_{k-1} is staged in LDS on
-// the block's 64 x 4 tile plus a halo of NT cells and the stencil on the tile
-// plus a halo of NT - 1; term k + t is then computed on the tile plus a halo
-// of NT - 1 - t, so the last one lands on the tile.  p gets d_k q_k, then
-// d_{k+1} q_{k+1}, ... (the order of single passes); the intermediate q's
-// never go to memory.  Per-block partial sums of every term's q^2 go to the
-// term's ring slot.
-template <int NT, class V>
-__global__ __launch_bounds__(kThreads) void k_leja_terms(Dims d, const LejaCoef* __restrict__ cf,
+// the block's 64 x TY tile plus a halo of NT cells and the stencil on the
+// tile plus a halo of NT - 1; term k + t is then computed on the tile plus a
+// halo of NT - 1 - t, so the last one lands on the tile.  p gets d_k q_k,
+// then d_{k+1} q_{k+1}, ... (the order of single passes); the intermediate
+// q's never go to memory.  Each thread owns TY / 4 cells of the tile (rows
+// threadIdx.y, threadIdx.y + 4, ...).  The per-block partial sums of every
+// term's q^2 go to the term's ring slot in the slot layout of the one-term
+// kernel (one slot per 64 x 4 band): the block's sum in the slot of its first
+// band, zeros in the slots of its other bands, so the check kernel reduces
+// the same number of slots in the same order.
+template <int NT, int TY, int BY, class V>
+__global__ __launch_bounds__(kBX * BY) void k_leja_terms(Dims d, const LejaCoef* __restrict__ cf,
                                                const V* __restrict__ coef, const V* __restrict__ qin,
                                                V* __restrict__ qout, V* __restrict__ p,
                                                const LejaState* __restrict__ st, double* __restrict__ part, int nb,
                                                int k) {
+  static_assert(TY % BY == 0 && TY % kBY == 0, "whole thread rows and 64 x 4 bands per tile");
+  constexpr int NTH = kBX * BY;                     // threads
+  constexpr int R = TY / BY;                        // own cells per thread
   constexpr int H = NT - 1;                         // halo of the stencil / intermediates
-  constexpr int WQ = kBX + 2 * NT, HQ = kBY + 2 * NT;
-  constexpr int WI = kBX + 2 * H, HI = kBY + 2 * H;
+  constexpr int WQ = kBX + 2 * NT, HQ = TY + 2 * NT;
+  constexpr int WI = kBX + 2 * H, HI = TY + 2 * H;
   __shared__ V sq[HQ][WQ];           // q_{k-1}, halo NT
   __shared__ V sc[5][HI][WI];        // stencil, halo NT - 1
   __shared__ V sb[2][HI][WI];        // intermediates, halo NT - 1
   const bool stopped = *(volatile const int*)&st->stopped >= 0;
   const int nx = d.nx, ny = d.ny, N = d.N;
-  const int x0 = blockIdx.x * kBX, y0 = blockIdx.y * kBY;
+  const int x0 = blockIdx.x * kBX, y0 = blockIdx.y * TY;
   const int tid = threadIdx.x + threadIdx.y * kBX;
-  for (int e = tid; e < HQ * WQ; e += kThreads) {
+  for (int e = tid; e < HQ * WQ; e += NTH) {
     const int ly = e / WQ, lx = e - ly * WQ;
     const int gx = x0 - NT + lx, gy = y0 - NT + ly;
     sq[ly][lx] = (gx >= 0 && gx < nx && gy >= 0 && gy < ny) ? qin[gx + nx * gy] : V(0);
   }
-  for (int e = tid; e < HI * WI; e += kThreads) {
+  for (int e = tid; e < HI * WI; e += NTH) {
     const int ly = e / WI, lx = e - ly * WI;
     const int gx = x0 - H + lx, gy = y0 - H + ly;
     const bool in = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
@@ -145,22 +152,25 @@ __global__ __launch_bounds__(kThreads) void k_leja_terms(Dims d, const LejaCoef*
 #pragma unroll
     for (int c = 0; c < 5; ++c) sc[c][ly][lx] = in ? coef[c * N + j] : V(0);
   }
-  const int gx = x0 + threadIdx.x, gy = y0 + threadIdx.y;
-  const bool own = gx < nx && gy < ny;
-  const int i = gx + nx * gy;
-  V acc = own ? p[i] : V(0);
+  const int gx = x0 + threadIdx.x;
+  V acc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int gy = y0 + threadIdx.y + BY * r;
+    acc[r] = (gx < nx && gy < ny) ? p[gx + nx * gy] : V(0);
+  }
   if (stopped) return;  // stop test already passed
   __syncthreads();
   const V ig = to_v<V>(cf->inv_g);
   double a[NT];
-  V last = V(0);
+  V last[R];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     const int h = H - t;  // halo of the region computed in this phase
     const V sh = to_v<V>(cf->shift[k + t]);
-    const int w = kBX + 2 * h, hh = kBY + 2 * h;
+    const int w = kBX + 2 * h, hh = TY + 2 * h;
     V(*out)[WI] = sb[t & 1];
-    for (int e = tid; e < w * hh; e += kThreads) {
+    for (int e = tid; e < w * hh; e += NTH) {
       const int ry = e / w, rx = e - ry * w;
       const int iy = ry + t, ix = rx + t;  // position in the halo-H buffers
       V qc, qw, qe, qs, qn;
@@ -186,16 +196,27 @@ __global__ __launch_bounds__(kThreads) void k_leja_terms(Dims d, const LejaCoef*
       out[iy][ix] = jq * ig - sh * qc;  // zero outside the grid (stencil and q are)
     }
     __syncthreads();
-    const V qo = out[threadIdx.y + H][threadIdx.x + H];
-    acc += to_v<V>(cf->dk[k + t]) * qo;
-    a[t] = own ? static_cast<double>(qo) * static_cast<double>(qo) : 0.0;
-    last = qo;
+    const V dk = to_v<V>(cf->dk[k + t]);
+    double sq2 = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int ly = threadIdx.y + BY * r;
+      const V qo = out[ly + H][threadIdx.x + H];
+      acc[r] += dk * qo;
+      if (gx < nx && y0 + ly < ny) sq2 += static_cast<double>(qo) * static_cast<double>(qo);
+      last[r] = qo;
+    }
+    a[t] = sq2;
   }
-  if (own) {
-    p[i] = acc;
-    qout[i] = last;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int gy = y0 + threadIdx.y + BY * r;
+    if (gx < nx && gy < ny) {
+      p[gx + nx * gy] = acc[r];
+      qout[gx + nx * gy] = last[r];
+    }
   }
-  __shared__ double red[NT][kThreads / 64];
+  __shared__ double red[NT][BY];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
     double v = a[t];
@@ -203,7 +224,20 @@ __global__ __launch_bounds__(kThreads) void k_leja_terms(Dims d, const LejaCoef*
     if ((tid & 63) == 0) red[t][tid >> 6] = v;
   }
   __syncthreads();
-  if (tid < NT) part[((k + tid) % kLejaRing) * nb + block_id()] = red[tid][0] + red[tid][1] + red[tid][2] + red[tid][3];
+  // slot layout of the one-term kernel: band b of this tile is global band
+  // blockIdx.y * R + b, slot blockIdx.x + gridDim.x * band
+  constexpr int NB = TY / kBY;  // 64 x 4 bands per tile
+  const int nbands = (ny + kBY - 1) / kBY;
+  for (int e = tid; e < NT * NB; e += NTH) {
+    const int t = e / NB, b = e - t * NB;
+    const int band = blockIdx.y * NB + b;
+    if (band < nbands) {
+      double sum = 0.0;
+      if (b == 0)
+        for (int w = 0; w < BY; ++w) sum += red[t][w];
+      part[((k + t) % kLejaRing) * nb + blockIdx.x + gridDim.x * band] = sum;
+    }
+  }
 }
 
 // Reduce the partials of terms k1..k2 (in order), record their sums and
@@ -284,27 +318,30 @@ hipError_t launch_leja_init(const Dims& d, const LejaCoef* cf, const double* v, 
 
 template <class V>
 hipError_t launch_leja_term(const Dims& d, const LejaCoef* cf, const V* coef, const V* qin, V* qout, V* p,
-                            const LejaState* st, double* part, int k, hipStream_t s) {
+                            const LejaState* st, double* part, int k, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   const int nb = leja_num_blocks(d);
   if (d.dim == 3)
-    hipLaunchKernelGGL((k_leja_term<3, V>), cell_grid(d), cell_block(), 0, s, d, cf, coef, qin, qout, p, st, part,
-                       nb, k);
+    launch_timed(k_leja_term<3, V>, cell_grid(d), cell_block(), 0, s, e0, e1, d, cf, coef, qin, qout, p, st, part,
+                 nb, k);
   else
-    hipLaunchKernelGGL((k_leja_term<2, V>), cell_grid(d), cell_block(), 0, s, d, cf, coef, qin, qout, p, st, part,
-                       nb, k);
+    launch_timed(k_leja_term<2, V>, cell_grid(d), cell_block(), 0, s, e0, e1, d, cf, coef, qin, qout, p, st, part,
+                 nb, k);
   return hipGetLastError();
 }
 
 template <class V>
 hipError_t launch_leja_terms(const Dims& d, const LejaCoef* cf, const V* coef, const V* qin, V* qout, V* p,
-                             const LejaState* st, double* part, int k, int nterms, hipStream_t s) {
+                             const LejaState* st, double* part, int k, int nterms, hipStream_t s, hipEvent_t e0,
+                             hipEvent_t e1) {
   if (d.dim != 2) return hipErrorInvalidValue;
+  const dim3 g((d.nx + kBX - 1) / kBX, (d.ny + kLejaTileRows - 1) / kLejaTileRows, 1);
+  const dim3 blk(kBX, kLejaThreadRows, 1);
   if (nterms == 4)
-    hipLaunchKernelGGL((k_leja_terms<4, V>), cell_grid(d), cell_block(), 0, s, d, cf, coef, qin, qout, p, st, part,
-                       leja_num_blocks(d), k);
+    launch_timed(k_leja_terms<4, kLejaTileRows, kLejaThreadRows, V>, g, blk, 0, s, e0, e1, d, cf, coef, qin, qout, p,
+                 st, part, leja_num_blocks(d), k);
   else if (nterms == 2)
-    hipLaunchKernelGGL((k_leja_terms<2, V>), cell_grid(d), cell_block(), 0, s, d, cf, coef, qin, qout, p, st, part,
-                       leja_num_blocks(d), k);
+    launch_timed(k_leja_terms<2, kLejaTileRows, kLejaThreadRows, V>, g, blk, 0, s, e0, e1, d, cf, coef, qin, qout, p,
+                 st, part, leja_num_blocks(d), k);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -335,15 +372,17 @@ template hipError_t launch_leja_init<double>(const Dims&, const LejaCoef*, const
 template hipError_t launch_leja_init<float>(const Dims&, const LejaCoef*, const double*, float*, float*, double*,
                                             hipStream_t);
 template hipError_t launch_leja_term<double>(const Dims&, const LejaCoef*, const double*, const double*, double*,
-                                             double*, const LejaState*, double*, int, hipStream_t);
+                                             double*, const LejaState*, double*, int, hipStream_t, hipEvent_t,
+                                             hipEvent_t);
 template hipError_t launch_leja_term<float>(const Dims&, const LejaCoef*, const float*, const float*, float*, float*,
-                                            const LejaState*, double*, int, hipStream_t);
+                                            const LejaState*, double*, int, hipStream_t, hipEvent_t, hipEvent_t);
 template hipError_t launch_substep_update<double>(const Dims&, double*, const double*, double, int, hipStream_t);
 template hipError_t launch_substep_update<float>(const Dims&, double*, const float*, double, int, hipStream_t);
 
 template hipError_t launch_leja_terms<double>(const Dims&, const LejaCoef*, const double*, const double*, double*,
-                                              double*, const LejaState*, double*, int, int, hipStream_t);
+                                              double*, const LejaState*, double*, int, int, hipStream_t, hipEvent_t,
+                                              hipEvent_t);
 template hipError_t launch_leja_terms<float>(const Dims&, const LejaCoef*, const float*, const float*, float*, float*,
-                                             const LejaState*, double*, int, int, hipStream_t);
+                                             const LejaState*, double*, int, int, hipStream_t, hipEvent_t, hipEvent_t);
 
 }  // namespace erem
