@@ -46,15 +46,16 @@ PCG_B_BYTES = {2: 48, 3: 48}    # read x, p_new, r, q; write x, r (multigrid-pre
 # read b, diag, faces and the iterate and write one vector each (~180 B);
 # the coarser levels add a third of that (2 x 2 aggregation).
 MG_BYTES = {2: 240, 3: 240}
-# On 2D grids the CG update (x += alpha p, r_new = r - alpha q, r.r) runs in
-# the first down leg of the V-cycle: it adds reads of x, p, q and writes of x
-# and r_new to the cycle (r itself is the cycle's right-hand side).
-CG_FUSED_BYTES = 40
+# On 2D grids a whole Chronopoulos-Gear CG iteration runs inside the finest
+# legs of the V-cycle: the first down leg reads w, s_old, z, p, x and writes
+# r_new, s, p, x (r itself is the cycle's right-hand side); the last up leg
+# also writes w = A z.
+CG_FUSED_BYTES = 80
 
 
 def mg_bytes(times, dim):
     """Algorithmic bytes per cell of one preconditioner application."""
-    fused = times["pcg_b_launches"] == 0 and times["mg_cycles"] > 0
+    fused = times["pcg_a_launches"] == 0 and times["mg_cycles"] > 0
     return MG_BYTES[dim] + (CG_FUSED_BYTES if fused else 0)
 
 

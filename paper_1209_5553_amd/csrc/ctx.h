@@ -33,6 +33,7 @@ struct erem_ctx {
   double *coef = nullptr, *F = nullptr;
   double *qa = nullptr, *qb = nullptr, *pacc = nullptr, *u = nullptr, *w = nullptr;
   double *pres = nullptr, *pr = nullptr, *pr2 = nullptr, *pz = nullptr, *pp0 = nullptr, *pp1 = nullptr;
+  double *pw = nullptr, *ps0 = nullptr, *ps1 = nullptr;  // Chronopoulos-Gear w = A z and s
   double *pq = nullptr, *pdiag = nullptr, *pres_lo = nullptr, *pdelta = nullptr, *prhs = nullptr;
   double* part = nullptr;  // Leja block partial sums (ring of kLejaRing terms)
   // FP32 copies for the mixed-precision Leja passes (allocated on first use)

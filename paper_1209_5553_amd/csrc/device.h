@@ -67,6 +67,8 @@ struct PcgState {
   double rz[4 * kSlots];
   double rr[4 * kSlots];
   double pq[4 * kSlots];
+  double wz[4 * kSlots];  // w.z (Chronopoulos-Gear form)
+  double alpha[4];        // step lengths (Chronopoulos-Gear form)
 };
 
 inline dim3 cell_grid(const Dims& d) {

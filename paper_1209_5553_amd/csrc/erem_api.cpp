@@ -70,7 +70,7 @@ int check_opts(erem_ctx* c, const erem_opts* o) {
 void free_all(erem_ctx* c) {
   double** bufs[] = {&c->logk, &c->poro, &c->tx, &c->ty, &c->tz, &c->fx, &c->fy, &c->fz,
                      &c->coef, &c->F, &c->qa, &c->qb, &c->pacc, &c->u, &c->w, &c->pres,
-                     &c->pr, &c->pr2, &c->pz, &c->pp0, &c->pp1, &c->pq, &c->pdiag,
+                     &c->pr, &c->pr2, &c->pw, &c->ps0, &c->ps1, &c->pz, &c->pp0, &c->pp1, &c->pq, &c->pdiag,
                      &c->pres_lo, &c->pdelta, &c->prhs, &c->part};
   for (double** b : bufs)
     if (*b) { (void)hipFree(*b); *b = nullptr; }
@@ -592,14 +592,21 @@ int pcg_inner(erem_ctx* c, double inner_tol, int budget, int* iters, bool* done)
   const int jac = c->use_mg ? 0 : 1;
   HIP_TRY(c, launch_pcg_start_rhs(d, c->tx, c->ty, c->tz, c->prhs, c->pdelta, c->pr, c->pz, c->pp0, c->pdiag,
                                   c->pcg, jac, c->stream));
-  if (c->use_mg) HIP_TRY(c, mg_apply(c->mg, c->pr, c->pz, c->pcg, 0, c->stream));
+  // 2D multigrid: Chronopoulos-Gear iterations folded into the finest legs
+  // (no separate CG kernels); otherwise pcg_a, pcg_b and the preconditioner.
+  const bool fuse = c->use_mg && mg_fuses_cg(c->mg);
+  if (fuse) {
+    const CgFuse cg0{0, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, c->pw};
+    HIP_TRY(c, mg_apply(c->mg, c->pr, c->pz, c->pcg, 0, c->stream, &cg0));
+  } else if (c->use_mg) {
+    HIP_TRY(c, mg_apply(c->mg, c->pr, c->pz, c->pcg, 0, c->stream));
+  }
   // Iterations after convergence still launch (their kernels return at
   // entry), so the host polls where the solve is expected to end: with
   // multigrid the first poll follows the previous solve's count plus the
   // test iteration (at most 24), then every two iterations.
   const int first_chunk = c->use_mg ? (c->pcg_last > 0 ? std::min(c->pcg_last + 1, 24) : 8) : 64;
   const int chunk = c->use_mg ? 2 : 64;
-  const bool fuse = c->use_mg && mg_fuses_cg(c->mg);
   int it = 0;
   *done = false;
   if (c->prof) {
@@ -616,15 +623,16 @@ int pcg_inner(erem_ctx* c, double inner_tol, int budget, int* iters, bool* done)
       // six events per iteration: kernel-level ones for pcg_a (0, 1) and
       // pcg_b (4, 5), ones around the preconditioner application (2, 3)
       hipEvent_t* ev = &c->ev[6 * j];
-      HIP_TRY(c, launch_pcg_a(d, c->tx, c->ty, c->tz, c->pz, pold, pnew, c->pq, c->pcg, it, c->stream,
-                              timed ? ev[0] : nullptr, timed ? ev[1] : nullptr));
       if (fuse) {
-        // the update runs inside the first down leg; r alternates between
-        // two buffers (neighbouring tiles read the old one)
-        const CgFuse cg{c->pdelta, (it & 1) ? c->pr : c->pr2, pnew, c->pq, it};
+        // r and s alternate between two buffers (neighbouring tiles read
+        // the old ones); p, x, z and w are updated in place
+        const CgFuse cg{1, it, c->pdelta, (it & 1) ? c->pr : c->pr2, c->pz, c->pw, c->pp0,
+                        (it & 1) ? c->ps1 : c->ps0, (it & 1) ? c->ps0 : c->ps1, c->pw};
         if (timed) HIP_TRY(c, hipEventRecord(ev[2], c->stream));
         HIP_TRY(c, mg_apply(c->mg, (it & 1) ? c->pr2 : c->pr, c->pz, c->pcg, (it + 1) & 3, c->stream, &cg));
       } else {
+        HIP_TRY(c, launch_pcg_a(d, c->tx, c->ty, c->tz, c->pz, pold, pnew, c->pq, c->pcg, it, c->stream,
+                                timed ? ev[0] : nullptr, timed ? ev[1] : nullptr));
         HIP_TRY(c, launch_pcg_b(d, c->pdelta, c->pr, c->pz, pnew, c->pq, c->pdiag, c->pcg, it, jac, c->stream,
                                 timed ? ev[4] : nullptr, timed ? ev[5] : nullptr));
         if (timed) HIP_TRY(c, hipEventRecord(ev[2], c->stream));
@@ -642,9 +650,9 @@ int pcg_inner(erem_ctx* c, double inner_tol, int budget, int* iters, bool* done)
       for (int j = 0; j < ran; ++j) {
         if ((it0 + j) % c->prof != 0) continue;
         const hipEvent_t* ev = &c->ev[6 * j];
-        c->t_pcg_a += elapsed_ms(ev[0], ev[1]);
-        ++c->n_pcg_a;
         if (!fuse) {
+          c->t_pcg_a += elapsed_ms(ev[0], ev[1]);
+          ++c->n_pcg_a;
           c->t_pcg_b += elapsed_ms(ev[4], ev[5]);
           ++c->n_pcg_b;
         }
@@ -759,6 +767,9 @@ int erem_create(const erem_grid* g, void* stream, erem_ctx** out) {
   rc |= dev_alloc(c, &c->pres, n);
   rc |= dev_alloc(c, &c->pr, n);
   rc |= dev_alloc(c, &c->pr2, n);
+  rc |= dev_alloc(c, &c->pw, n);
+  rc |= dev_alloc(c, &c->ps0, n);
+  rc |= dev_alloc(c, &c->ps1, n);
   rc |= dev_alloc(c, &c->pz, n);
   rc |= dev_alloc(c, &c->pp0, n);
   rc |= dev_alloc(c, &c->pp1, n);

@@ -47,21 +47,29 @@ struct MgHierarchy {
   MgCoarseArgs coarse;
 };
 
-// Conjugate-gradient update of iteration it folded into the first down leg
-// of a 2D hierarchy: alpha = (r.z) / (p.q); x += alpha p; r_new = r - alpha q
-// (r_new in its own buffer: neighbouring tiles still read r); r_new . r_new
-// into the CG ring.
+// Chronopoulos-Gear conjugate gradients folded into the finest legs of a
+// 2D hierarchy.  With update, the first down leg runs iteration it (stop
+// test; alpha, beta from the ring; s = w + beta s_old; r_new = r - alpha s;
+// p = z + beta p; x += alpha p; r_new . r_new into the ring) and the cycle
+// preconditions r_new; the last up leg also forms w_out = A z and puts r.z
+// and w.z into the ring slot.  r_new and s_new are separate buffers from r
+// and s_old: neighbouring tiles still read the old values.
 struct CgFuse {
+  int update;          // run iteration it in the first down leg
+  int it;
   double* x;
   double* r_new;
-  const double* p;
-  const double* q;
-  int it;
+  const double* z;     // z_it (read)
+  const double* w;     // w_it = A z_it (read)
+  double* p;           // p_{it-1} in, p_it out (own cells)
+  const double* s_old;
+  double* s_new;
+  double* w_out;       // w of the new z
 };
 
 hipError_t mg_setup(const MgHierarchy& h, hipStream_t s);
-// z = M^{-1} r.  With cg (only where mg_fuses_cg), r is the residual before
-// the update and z = M^{-1} r_new.
+// z = M^{-1} r.  With cg (only where mg_fuses_cg): see CgFuse; with
+// cg->update, r is the residual before the update and z = M^{-1} r_new.
 hipError_t mg_apply(const MgHierarchy& h, const double* r, double* z, PcgState* st, int rz_slot,
                     hipStream_t s, const CgFuse* cg = nullptr);
 // True when the finest level is 2D and runs the global-memory legs.

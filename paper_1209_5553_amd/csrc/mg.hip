@@ -283,56 +283,66 @@ constexpr int kH2 = kTY + 4;
 constexpr int kW1 = kBX + 2;     // with a halo of one
 constexpr int kH1 = kTY + 2;
 
-// Faces of the halo-one region: x faces of its rows (face gx of cell gx is
-// its -x face) and y faces of its columns.
-struct TileFaces {
-  double tx[kH1][kW1 + 1];
-  double ty[kH1 + 1][kW1];
+// Faces of the halo-H region: x faces of its rows (face gx of cell gx is its
+// -x face) and y faces of its columns.
+template <int H>
+struct TileFacesH {
+  double tx[kTY + 2 * H][kBX + 2 * H + 1];
+  double ty[kTY + 2 * H + 1][kBX + 2 * H];
 };
+using TileFaces = TileFacesH<1>;
 
-__device__ inline void load_tile_faces(const MgLevelDev& L, int x0, int y0, int tid, TileFaces& F) {
+template <int H>
+__device__ inline void load_tile_faces(const MgLevelDev& L, int x0, int y0, int tid, TileFacesH<H>& F) {
+  constexpr int W = kBX + 2 * H, HH = kTY + 2 * H;
   const int nx = L.nx, ny = L.ny;
-  for (int k = tid; k < kH1 * (kW1 + 1); k += kThreads) {
-    const int ly = k / (kW1 + 1), lx = k - ly * (kW1 + 1);
-    const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
+  for (int k = tid; k < HH * (W + 1); k += kThreads) {
+    const int ly = k / (W + 1), lx = k - ly * (W + 1);
+    const int gx = x0 - H + lx, gy = y0 - H + ly;
     F.tx[ly][lx] = (gx >= 0 && gx <= nx && gy >= 0 && gy < ny) ? L.tx[fxi(nx, ny, gx, gy, 0)] : 0.0;
   }
-  for (int k = tid; k < (kH1 + 1) * kW1; k += kThreads) {
-    const int ly = k / kW1, lx = k - ly * kW1;
-    const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
+  for (int k = tid; k < (HH + 1) * W; k += kThreads) {
+    const int ly = k / W, lx = k - ly * W;
+    const int gx = x0 - H + lx, gy = y0 - H + ly;
     F.ty[ly][lx] = (gx >= 0 && gx < nx && gy >= 0 && gy <= ny) ? L.ty[fyi(nx, ny, gx, gy, 0)] : 0.0;
   }
 }
 
-// Neighbour sum of the halo-one cell (l1x, l1y) at (gx, gy), values v in a
+// Neighbour sum of the halo-H cell (lx, ly) at (gx, gy), values v in a
 // region whose element (sy, sx) is that cell.
-template <int W>
-__device__ inline double nb_sum_tile(const TileFaces& F, int nx, int ny, int gx, int gy, int l1x, int l1y,
+template <int W, int H>
+__device__ inline double nb_sum_tile(const TileFacesH<H>& F, int nx, int ny, int gx, int gy, int lx, int ly,
                                      const double (*v)[W], int sy, int sx) {
   double s = 0.0;
-  if (gx > 0) s += F.tx[l1y][l1x] * v[sy][sx - 1];
-  if (gx + 1 < nx) s += F.tx[l1y][l1x + 1] * v[sy][sx + 1];
-  if (gy > 0) s += F.ty[l1y][l1x] * v[sy - 1][sx];
-  if (gy + 1 < ny) s += F.ty[l1y + 1][l1x] * v[sy + 1][sx];
+  if (gx > 0) s += F.tx[ly][lx] * v[sy][sx - 1];
+  if (gx + 1 < nx) s += F.tx[ly][lx + 1] * v[sy][sx + 1];
+  if (gy > 0) s += F.ty[ly][lx] * v[sy - 1][sx];
+  if (gy + 1 < ny) s += F.ty[ly + 1][lx] * v[sy + 1][sx];
   return s;
 }
 
-// With CG, the conjugate-gradient update of the iteration is folded in:
-// alpha = (r.z) / (p.q) from the slot sums, r <- r - alpha q on the tile and
-// its halo (the halo values recomputed, the tile's written), x <- x + alpha p
-// and the partial sums of r.r, as a separate update kernel would do.
+// With CG, iteration it of Chronopoulos-Gear conjugate gradients (one
+// reduction phase per iteration) is folded in front of the leg.  From the
+// slot sums of the previous leg pair: the stop test on ||r_it||, then
+// beta = g_it / g_{it-1}, alpha = g_it / (d_it - beta g_it / alpha_{it-1})
+// with g = r.z, d = w.z, w = A z (alpha = g_0 / d_0, beta = 0 at it = 0);
+// s = w + beta s_old and r_new = r - alpha s on the tile and its halo (the
+// halo values recomputed, the tile's written); p = z + beta p and
+// x += alpha p on the tile; the partial sums of r_new . r_new.
 template <bool CG>
 __global__ __launch_bounds__(kThreads) void k_mg_down_restrict_2d(MgLevelDev F, MgLevelDev C,
                                                         const double* __restrict__ b, double* __restrict__ xout,
                                                         double* __restrict__ bc, PcgState* st, CgFuse cg) {
   const bool stop = pcg_done(st);
   __shared__ double sb[kH2][kW2], sd[kH2][kW2], sx1[kH2][kW2], sx2[kH1][kW1];
-  __shared__ double sq[CG ? kH2 : 1][CG ? kW2 : 1];
-  __shared__ double alpha_sh;
+  __shared__ double sw[CG ? kH2 : 1][CG ? kW2 : 1], ss[CG ? kH2 : 1][CG ? kW2 : 1];
+  __shared__ double alpha_sh, beta_sh;
+  __shared__ int stop_sh;
   __shared__ TileFaces tf;
   const int nx = F.nx, ny = F.ny;
   const int x0 = blockIdx.x * kBX, y0 = blockIdx.y * kTY;
   const int tid = threadIdx.x + threadIdx.y * kBX;
+  const int it = cg.it;
   for (int k = tid; k < kH2 * kW2; k += kThreads) {
     const int ly = k / kW2, lx = k - ly * kW2;
     const int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
@@ -342,38 +352,74 @@ __global__ __launch_bounds__(kThreads) void k_mg_down_restrict_2d(MgLevelDev F, 
     sb[ly][lx] = bj;
     sd[ly][lx] = dj;
     if (CG) {
-      sq[ly][lx] = in ? cg.q[j] : 0.0;
+      sw[ly][lx] = in ? cg.w[j] : 0.0;
+      ss[ly][lx] = (in && it > 0) ? cg.s_old[j] : 0.0;
     } else {
       sx1[ly][lx] = kOmega * bj / dj;  // first sweep from zero
     }
   }
-  // the tile's own cells (two rows per thread) for the x update
+  // the tile's own cells (two rows per thread) for the p and x updates
   const int ox = x0 + threadIdx.x;
-  double xo[2] = {0.0, 0.0}, po[2] = {0.0, 0.0};
+  double xo[2] = {0.0, 0.0}, po[2] = {0.0, 0.0}, zo[2] = {0.0, 0.0};
   if (CG) {
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
       const int oy = y0 + 2 * threadIdx.y + r;
       if (ox < nx && oy < ny) {
         xo[r] = cg.x[ox + nx * oy];
-        po[r] = cg.p[ox + nx * oy];
+        zo[r] = cg.z[ox + nx * oy];
+        if (it > 0) po[r] = cg.p[ox + nx * oy];
       }
     }
   }
   load_tile_faces(F, x0, y0, tid, tf);
-  if (CG && tid < 64 && !stop) {  // the first wavefront decides alpha
-    const int it = cg.it;
-    const double alpha = wave_slot_sum(st->rz + (it & 3) * kSlots) / wave_slot_sum(st->pq + (it & 3) * kSlots);
-    if (tid == 0) alpha_sh = alpha;
-    if (blockIdx.x == 0 && blockIdx.y == 0) st->pq[((it + 1) & 3) * kSlots + tid] = 0.0;
+  if (CG && tid < 64) {  // the first wavefront decides for the block
+    int halt = stop ? 1 : 0;
+    double alpha = 0.0, beta = 0.0;
+    const double rr = wave_slot_sum(st->rr + (it & 3) * kSlots);
+    const double bb = wave_slot_sum(st->bb_sl);
+    const double g1 = wave_slot_sum(st->rz + (it & 3) * kSlots);
+    const double d1 = wave_slot_sum(st->wz + (it & 3) * kSlots);
+    const double g0 = wave_slot_sum(st->rz + ((it - 1) & 3) * kSlots);
+    const bool lead = blockIdx.x == 0 && blockIdx.y == 0;
+    if (halt) {
+      // an earlier iteration converged
+    } else if (!isfinite(rr)) {
+      halt = 1;
+      if (lead && tid == 0) { st->nonfinite = 1; st->done = 1; st->it_done = it; }
+    } else if (rr <= st->tol2 * bb) {
+      halt = 1;
+      if (lead && tid == 0) { st->done = 1; st->it_done = it; st->bb = bb; }
+    } else if (it > 0) {
+      beta = g1 / g0;
+      alpha = g1 / (d1 - beta * g1 / st->alpha[(it - 1) & 3]);
+    } else {
+      alpha = g1 / d1;
+    }
+    if (tid == 0) {
+      stop_sh = halt;
+      alpha_sh = alpha;
+      beta_sh = beta;
+    }
+    if (!halt && lead) {
+      if (tid == 0) st->alpha[it & 3] = alpha;
+      // clear the slots two iterations ahead (nobody reads them now)
+      st->rz[((it + 2) & 3) * kSlots + tid] = 0.0;
+      st->rr[((it + 2) & 3) * kSlots + tid] = 0.0;
+      st->wz[((it + 2) & 3) * kSlots + tid] = 0.0;
+    }
   }
-  if (stop) return;
-  __syncthreads();
   if (CG) {
-    const double alpha = alpha_sh;
+    // block (0, 0) may set the stop flag while this kernel runs, so every
+    // wavefront follows the first one's decision, not its own read
+    __syncthreads();
+    if (stop_sh) return;
+    const double alpha = alpha_sh, beta = beta_sh;
     for (int k = tid; k < kH2 * kW2; k += kThreads) {
       const int ly = k / kW2, lx = k - ly * kW2;
-      const double rn = sb[ly][lx] - alpha * sq[ly][lx];  // zero outside the grid stays zero
+      const double sv = sw[ly][lx] + beta * ss[ly][lx];  // zero outside the grid stays zero
+      const double rn = sb[ly][lx] - alpha * sv;
+      ss[ly][lx] = sv;
       sb[ly][lx] = rn;
       sx1[ly][lx] = kOmega * rn / sd[ly][lx];  // first sweep from zero
     }
@@ -383,9 +429,13 @@ __global__ __launch_bounds__(kThreads) void k_mg_down_restrict_2d(MgLevelDev F, 
     for (int r = 0; r < 2; ++r) {
       const int ly = 2 * threadIdx.y + r, oy = y0 + ly;
       if (ox < nx && oy < ny) {
+        const int j = ox + nx * oy;
         const double rn = sb[ly + 2][threadIdx.x + 2];
-        cg.r_new[ox + nx * oy] = rn;
-        cg.x[ox + nx * oy] = xo[r] + alpha * po[r];
+        const double pn = zo[r] + beta * po[r];
+        cg.r_new[j] = rn;
+        cg.s_new[j] = ss[ly + 2][threadIdx.x + 2];
+        cg.p[j] = pn;
+        cg.x[j] = xo[r] + alpha * pn;
         rr += rn * rn;
       }
     }
@@ -395,8 +445,11 @@ __global__ __launch_bounds__(kThreads) void k_mg_down_restrict_2d(MgLevelDev F, 
     __syncthreads();
     if (tid == 0) {
       const int bid = blockIdx.x + gridDim.x * blockIdx.y;
-      atomicAdd(&st->rr[((cg.it + 1) & 3) * kSlots + (bid & (kSlots - 1))], sh[0] + sh[1] + sh[2] + sh[3]);
+      atomicAdd(&st->rr[((it + 1) & 3) * kSlots + (bid & (kSlots - 1))], sh[0] + sh[1] + sh[2] + sh[3]);
     }
+  } else {
+    if (stop) return;
+    __syncthreads();
   }
   for (int k = tid; k < kH1 * kW1; k += kThreads) {
     const int ly = k / kW1, lx = k - ly * kW1;
@@ -491,6 +544,103 @@ __global__ __launch_bounds__(kThreads) void k_mg_up_smooth_2d(MgLevelDev F, MgLe
   if (tid == 0) {
     const int bid = blockIdx.x + gridDim.x * blockIdx.y;
     atomicAdd(&st->rz[rz_slot * kSlots + (bid & (kSlots - 1))], sh[0] + sh[1] + sh[2] + sh[3]);
+  }
+}
+
+// Finest up leg for Chronopoulos-Gear conjugate gradients: as above, with
+// the second sweep also on the halo-one ring so that w = A z follows on the
+// tile (z = out, w = w_out); the partial sums of r.z and w.z go to the CG
+// ring slot.  Halos grow by one: x + w_c e on halo three, the first sweep on
+// halo two.
+constexpr int kW3 = kBX + 6;
+constexpr int kH3 = kTY + 6;
+
+__global__ __launch_bounds__(kThreads) void k_mg_up_smooth_2d_cg(MgLevelDev F, MgLevelDev C,
+                                                        const double* __restrict__ b,
+                                                        const double* __restrict__ xv,
+                                                        const double* __restrict__ ec, double omega_c,
+                                                        double* __restrict__ out, double* __restrict__ w_out,
+                                                        PcgState* st, int slot) {
+  const bool stop = pcg_done(st);
+  __shared__ double sxc[kH3][kW3], sb[kH2][kW2], sd[kH2][kW2], sys[kH2][kW2], se[kH1][kW1];
+  __shared__ TileFacesH<2> tf;
+  const int nx = F.nx, ny = F.ny;
+  const int x0 = blockIdx.x * kBX, y0 = blockIdx.y * kTY;
+  const int tid = threadIdx.x + threadIdx.y * kBX;
+  for (int k = tid; k < kH3 * kW3; k += kThreads) {
+    const int ly = k / kW3, lx = k - ly * kW3;
+    const int gx = x0 - 3 + lx, gy = y0 - 3 + ly;
+    double v = 0.0;
+    if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) v = xv[gx + nx * gy] + omega_c * ec[(gx >> 1) + C.nx * (gy >> 1)];
+    sxc[ly][lx] = v;
+  }
+  for (int k = tid; k < kH2 * kW2; k += kThreads) {
+    const int ly = k / kW2, lx = k - ly * kW2;
+    const int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
+    const bool in = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+    const int j = gx + nx * gy;
+    sb[ly][lx] = in ? b[j] : 0.0;
+    sd[ly][lx] = in ? F.diag[j] : 1.0;
+  }
+  load_tile_faces(F, x0, y0, tid, tf);
+  if (stop) return;
+  __syncthreads();
+  // first sweep on halo two
+  for (int k = tid; k < kH2 * kW2; k += kThreads) {
+    const int ly = k / kW2, lx = k - ly * kW2;
+    const int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
+    double v = 0.0;
+    if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+      const double D = sd[ly][lx];
+      const double xi = sxc[ly + 1][lx + 1];
+      v = xi + kOmega * (sb[ly][lx] - D * xi + nb_sum_tile<kW3>(tf, nx, ny, gx, gy, lx, ly, sxc, ly + 1, lx + 1)) / D;
+    }
+    sys[ly][lx] = v;
+  }
+  __syncthreads();
+  // second sweep on halo one
+  for (int k = tid; k < kH1 * kW1; k += kThreads) {
+    const int ly = k / kW1, lx = k - ly * kW1;
+    const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
+    double v = 0.0;
+    if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
+      const double D = sd[ly + 1][lx + 1];
+      const double yi = sys[ly + 1][lx + 1];
+      v = yi + kOmega * (sb[ly + 1][lx + 1] - D * yi +
+                         nb_sum_tile<kW2>(tf, nx, ny, gx, gy, lx + 1, ly + 1, sys, ly + 1, lx + 1)) / D;
+    }
+    se[ly][lx] = v;
+  }
+  __syncthreads();
+  const int gx = x0 + threadIdx.x;
+  double g = 0.0, dz = 0.0;
+  for (int r = 0; r < 2; ++r) {
+    const int ly = 2 * threadIdx.y + r;
+    const int gy = y0 + ly;
+    if (gx < nx && gy < ny) {
+      const double z = se[ly + 1][threadIdx.x + 1];
+      const double w = sd[ly + 2][threadIdx.x + 2] * z -
+                       nb_sum_tile<kW1>(tf, nx, ny, gx, gy, threadIdx.x + 2, ly + 2, se, ly + 1, threadIdx.x + 1);
+      out[gx + nx * gy] = z;
+      w_out[gx + nx * gy] = w;
+      g += sb[ly + 2][threadIdx.x + 2] * z;
+      dz += w * z;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    g += __shfl_down(g, off, 64);
+    dz += __shfl_down(dz, off, 64);
+  }
+  __shared__ double sh[2][kThreads / 64];
+  if ((tid & 63) == 0) {
+    sh[0][tid >> 6] = g;
+    sh[1][tid >> 6] = dz;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const int sl = slot * kSlots + ((blockIdx.x + gridDim.x * blockIdx.y) & (kSlots - 1));
+    atomicAdd(&st->rz[sl], sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3]);
+    atomicAdd(&st->wz[sl], sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3]);
   }
 }
 
@@ -796,7 +946,7 @@ hipError_t mg_apply(const MgHierarchy& h, const double* r, double* z, PcgState* 
     const double* b = l == 0 ? r : F.b;
     if (F.nz == 1) {
       const dim3 g((F.nx + kBX - 1) / kBX, (F.ny + kTY - 1) / kTY, 1);
-      if (l == 0 && cg)
+      if (l == 0 && cg && cg->update)
         hipLaunchKernelGGL(k_mg_down_restrict_2d<true>, g, cell_block(), 0, s, F, C, b, F.x, C.b, st, *cg);
       else
         hipLaunchKernelGGL(k_mg_down_restrict_2d<false>, g, cell_block(), 0, s, F, C, b, F.x, C.b, st, CgFuse{});
@@ -816,13 +966,17 @@ hipError_t mg_apply(const MgHierarchy& h, const double* r, double* z, PcgState* 
   for (int l = lc - 1; l >= 0; --l) {
     const MgLevelDev& F = h.lev[l];
     const MgLevelDev& C = h.lev[l + 1];
-    const double* b = l == 0 ? (cg ? cg->r_new : r) : F.b;
+    const double* b = l == 0 ? (cg && cg->update ? cg->r_new : r) : F.b;
     const double* ec = l + 1 == lc ? C.x : C.y;
     double* out = l == 0 ? z : F.y;
     if (F.nz == 1) {
       const dim3 g((F.nx + kBX - 1) / kBX, (F.ny + kTY - 1) / kTY, 1);
-      hipLaunchKernelGGL(k_mg_up_smooth_2d, g, cell_block(), 0, s, F, C, b, F.x, ec, h.omega_c, out, st,
-                         l == 0 ? rz_slot : -1);
+      if (l == 0 && cg)
+        hipLaunchKernelGGL(k_mg_up_smooth_2d_cg, g, cell_block(), 0, s, F, C, b, F.x, ec, h.omega_c, out, cg->w_out,
+                           st, rz_slot);
+      else
+        hipLaunchKernelGGL(k_mg_up_smooth_2d, g, cell_block(), 0, s, F, C, b, F.x, ec, h.omega_c, out, st,
+                           l == 0 ? rz_slot : -1);
     } else {
       hipLaunchKernelGGL(k_mg_up_smooth, grid_of(F), cell_block(), 0, s, F, C, b, F.x, ec, h.omega_c, out, st,
                          l == 0 ? rz_slot : -1);
