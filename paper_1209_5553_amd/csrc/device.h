@@ -117,6 +117,25 @@ hipError_t launch_pcg_b(const Dims& d, double* x, double* r, double* z, const do
                         const double* q, const double* diag, PcgState* st, int it,
                         int jacobi, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 
+// Tile index of this block for grids whose neighbouring tiles share data:
+// the hardware deals consecutive workgroups to the eight XCDs in turn
+// (workgroup b to XCD b % 8), so tiles are handed out so that each XCD takes
+// one contiguous range of them (x fastest), and the halos of a tile's
+// neighbours are mostly in the same XCD's L2.  A bijection of the block
+// index; only the placement changes.
+#ifndef EREM_XCD_REMAP
+#define EREM_XCD_REMAP 1
+#endif
+constexpr int kXcds = 8;
+__device__ inline int xcd_tile_id() {
+  const int nbk = gridDim.x * gridDim.y * gridDim.z;
+  const int b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+  if (!EREM_XCD_REMAP) return b;
+  const int q = nbk / kXcds, r = nbk % kXcds;
+  const int x = b % kXcds, k = b / kXcds;
+  return x * q + (x < r ? x : r) + k;
+}
+
 // Launch; with events (sampled timing) they record the kernel's own start
 // and stop, without the queue's gaps around it.
 template <typename K, typename... A>

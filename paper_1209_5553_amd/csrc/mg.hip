@@ -340,7 +340,8 @@ __global__ __launch_bounds__(kThreads) void k_mg_down_restrict_2d(MgLevelDev F, 
   __shared__ int stop_sh;
   __shared__ TileFaces tf;
   const int nx = F.nx, ny = F.ny;
-  const int x0 = blockIdx.x * kBX, y0 = blockIdx.y * kTY;
+  const int tile = xcd_tile_id();  // 2D grid: tile = bx + gridDim.x * by
+  const int x0 = (tile % gridDim.x) * kBX, y0 = (tile / gridDim.x) * kTY;
   const int tid = threadIdx.x + threadIdx.y * kBX;
   const int it = cg.it;
   for (int k = tid; k < kH2 * kW2; k += kThreads) {
@@ -381,7 +382,7 @@ __global__ __launch_bounds__(kThreads) void k_mg_down_restrict_2d(MgLevelDev F, 
     const double g1 = wave_slot_sum(st->rz + (it & 3) * kSlots);
     const double d1 = wave_slot_sum(st->wz + (it & 3) * kSlots);
     const double g0 = wave_slot_sum(st->rz + ((it - 1) & 3) * kSlots);
-    const bool lead = blockIdx.x == 0 && blockIdx.y == 0;
+    const bool lead = tile == 0;
     if (halt) {
       // an earlier iteration converged
     } else if (!isfinite(rr)) {
@@ -489,7 +490,8 @@ __global__ __launch_bounds__(kThreads) void k_mg_up_smooth_2d(MgLevelDev F, MgLe
   __shared__ double sxc[kH2][kW2], sb[kH1][kW1], sd[kH1][kW1], sys[kH1][kW1];
   __shared__ TileFaces tf;
   const int nx = F.nx, ny = F.ny;
-  const int x0 = blockIdx.x * kBX, y0 = blockIdx.y * kTY;
+  const int tile = xcd_tile_id();  // 2D grid: tile = bx + gridDim.x * by
+  const int x0 = (tile % gridDim.x) * kBX, y0 = (tile / gridDim.x) * kTY;
   const int tid = threadIdx.x + threadIdx.y * kBX;
   for (int k = tid; k < kH2 * kW2; k += kThreads) {
     const int ly = k / kW2, lx = k - ly * kW2;
@@ -565,7 +567,8 @@ __global__ __launch_bounds__(kThreads) void k_mg_up_smooth_2d_cg(MgLevelDev F, M
   __shared__ double sxc[kH3][kW3], sb[kH2][kW2], sd[kH2][kW2], sys[kH2][kW2], se[kH1][kW1];
   __shared__ TileFacesH<2> tf;
   const int nx = F.nx, ny = F.ny;
-  const int x0 = blockIdx.x * kBX, y0 = blockIdx.y * kTY;
+  const int tile = xcd_tile_id();  // 2D grid: tile = bx + gridDim.x * by
+  const int x0 = (tile % gridDim.x) * kBX, y0 = (tile / gridDim.x) * kTY;
   const int tid = threadIdx.x + threadIdx.y * kBX;
   for (int k = tid; k < kH3 * kW3; k += kThreads) {
     const int ly = k / kW3, lx = k - ly * kW3;
