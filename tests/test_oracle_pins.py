@@ -132,6 +132,35 @@ def test_tpfa_two_cells_hand_example():
     assert np.allclose(fx.ravel(), gd["flux"], rtol=1e-14)
 
 
+def test_strip_flux_is_the_series_closed_form():
+    """One row of cells is a chain of resistances 1/tau in series between the
+    two Dirichlet faces: every face carries (p_left - p_right) / sum(1/tau).
+    A long strip with a strong permeability contrast is ill-conditioned for
+    the pressure, so this pins the flux accuracy of the pressure solve."""
+    g = ph.Grid(700, 1)
+    rng = np.random.default_rng(11)
+    k = np.exp(2.0 * rng.standard_normal(g.n))
+    tr = ph.tpfa_transmissibilities(k, g)
+    p_left, p_right = 6.0e4, 0.0
+    p = ph.solve_pressure(tr, g, p_left, p_right)
+    fx, _, _ = ph.face_fluxes(p, tr, g, p_left, p_right)
+    res = (1.0 / np.asarray(tr["t_left"], dtype=np.longdouble).ravel()).sum() \
+        + (1.0 / np.asarray(tr["tx"], dtype=np.longdouble).ravel()).sum() \
+        + (1.0 / np.asarray(tr["t_right"], dtype=np.longdouble).ravel()).sum()
+    q = float((p_left - p_right) / res)
+    # the strip's condition number (~1e10) bounds the flux accuracy of a
+    # solve at ~1e-11; a dropped or misplaced boundary term costs O(1)
+    assert np.abs(fx.ravel() - q).max() <= 1e-10 * abs(q)
+    # the refined residual is at the extended-precision floor
+    A, rhs = ph.pressure_matrix(tr, g, p_left, p_right)
+    A = A.tocsr()
+    rows = np.repeat(np.arange(g.n), np.diff(A.indptr))
+    Ap = np.zeros(g.n, dtype=np.longdouble)
+    np.add.at(Ap, rows, A.data.astype(np.longdouble) * p[A.indices])
+    scale = (np.abs(A).astype(np.longdouble) @ np.abs(p)).max()
+    assert np.abs(rhs - Ap).max() <= 64 * np.finfo(np.longdouble).eps * scale
+
+
 def test_layered_pressure_is_linear_and_fluxes_analytic():
     """Mobility depending on z only: each layer carries k A dp/(nx dx) and
     the TPFA pressure is linear in x (no transverse flow)."""
