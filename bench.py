@@ -129,7 +129,7 @@ def gpu_run(prob, coupled, steps, warmup, rtol_p, mixed=False):
 
 def cpu_baseline(prob, coupled, nsteps, gpu_snaps):
     """The oracle as it stands, on a bounded sample: the first `nsteps` steps
-    of the same workload (tier-B sparse action; SuperLU pressure)."""
+    of the same workload (tier-B sparse action; SuperLU pressure with extended-precision refinement)."""
     from threadpoolctl import threadpool_limits
 
     from oracle import erem as oerem
@@ -146,7 +146,7 @@ def cpu_baseline(prob, coupled, nsteps, gpu_snaps):
         t1 = time.perf_counter()
     out = {"value": nsteps / (t1 - t0), "unit": "steps/s", "cores": 1, "kind": "oracle",
            "sample": f"first {nsteps} steps of the same workload from T0 "
-                     f"({'SuperLU pressure + ' if coupled else ''}substepped Taylor action of the "
+                     f"({'SuperLU pressure refined in extended precision + ' if coupled else ''}substepped Taylor action of the "
                      f"augmented exponential, FP64, 1 thread)",
            "seconds": t1 - t0}
     if nsteps in gpu_snaps:
@@ -319,7 +319,7 @@ def bench_adjoint(args):
             oerem.coupled_step(prob, np.asarray(prob.T0, dtype=np.float64), tier="taylor")
             t1 = time.perf_counter()
         line["cpu_baseline"] = {"value": 1.0 / (t1 - t0), "unit": "steps/s", "cores": 1, "kind": "oracle",
-                                "sample": "1 forward coupled step of the same workload (SuperLU pressure + "
+                                "sample": "1 forward coupled step of the same workload (SuperLU pressure refined in extended precision + "
                                           "substepped Taylor action, FP64, 1 thread); the oracle's dense "
                                           "adjoint is limited to grids of a few hundred cells",
                                 "seconds": t1 - t0}
