@@ -319,7 +319,7 @@ def bench_adjoint(args):
             oerem.coupled_step(prob, np.asarray(prob.T0, dtype=np.float64), tier="taylor")
             t1 = time.perf_counter()
         line["cpu_baseline"] = {"value": 1.0 / (t1 - t0), "unit": "steps/s", "cores": 1, "kind": "oracle",
-                                "sample": "1 forward coupled step of the same workload (SuperLU pressure refined in extended precision + "
+                                "sample": "1 forward coupled step of the same workload (SuperLU pressure + "
                                           "substepped Taylor action, FP64, 1 thread); the oracle's dense "
                                           "adjoint is limited to grids of a few hundred cells",
                                 "seconds": t1 - t0}
