@@ -204,8 +204,9 @@ def bench_batch(args, mixed):
         "config": {"workload": desc, "cells": int(b.ntot), "problems": nprob, "steps_per_launch": nst,
                    "step_unit": "one EREM step of all realisations", "tile_shape": shape,
                    "tol_r": 1e-7 if mixed else 1e-12, "precision": args.precision},
-        "roofline": {"kernel": "k_batch_blocks", "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+        "roofline": {"kernel": "k_batch_fused" if shape == 4 else "k_batch_blocks", "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
+                     "traffic": _traffic("batch256", args.precision, "k_batch_fused" if shape == 4 else "k_batch_blocks"),
                      "avg_launch_us": round(avg_s * 1e6, 1), "launches": len(ms),
                      "bytes_per_launch": float(np.mean(byts)),
                      "bytes_rule": f"Newton terms only: sum over problems of terms x cells x "
@@ -326,14 +327,32 @@ def bench_adjoint(args):
     return line
 
 
-def _roof(kern, name):
+# Bytes moved between L2 and memory per launch unit (the unit of "achieved":
+# one V-cycle, one Newton term, one batch launch), from rocprofv3 --pmc runs
+# of FETCH_SIZE and WRITE_SIZE on these kernels, scaled by what the counters
+# read for a plain 512 MiB copy (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0).  They
+# describe the kernels as measured: reset an entry to None when its kernel
+# changes.
+TRAFFIC = {
+    ("coupled512", "fp64", "mg_vcycle"): 51.82e6,
+    ("coupled512", "fp64", "leja_term"): 5.29e6,     # a 4-term launch moves 21.15 MB
+    ("layered128", "fp64", "leja_term"): 186.49e6,
+    ("batch256", "fp64", "k_batch_fused"): 485.5e9,
+}
+
+
+def _traffic(workload, precision, kernel):
+    return TRAFFIC.get((workload, precision, kernel))
+
+
+def _roof(kern, name, traffic=None):
     ms, n, bytes_per = kern[name]
     if n == 0:
         return None
     avg_s = ms / n * 1e-3
     ach = bytes_per / avg_s / 1e9
     return {"kernel": name, "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
             "avg_launch_us": round(avg_s * 1e6, 3), "launches": n, "bytes_per_launch": bytes_per,
             "share_of_kernel_time": round(ms / max(sum(v[0] for v in kern.values()), 1e-30), 4)}
 
@@ -383,7 +402,7 @@ def main():
     dominant = max(kern, key=lambda k: kern[k][0])
 
     def roof(name):
-        return _roof(kern, name)
+        return _roof(kern, name, _traffic(args.workload, args.precision, name))
 
     steps_s = args.steps / res["elapsed"]
     line = {
