@@ -218,11 +218,14 @@ int build_mg(erem_ctx* c) {
   a.n0 = L0.nx * L0.ny * L0.nz;
   a.nu = 2;
   a.omega_c = h.omega_c;
-  // The LDS levels cost a few microseconds per V-cycle against tens for a
-  // CG iteration on the grid: three cycles there (an approximate coarse
-  // solve) cut the CG iterations on 256^2 - 512^2 log-normal fields by about
-  // a third.  Repeated cycles keep the preconditioner symmetric.
+  // The LDS levels cost a few microseconds per cycle against tens for a CG
+  // iteration on the grid: two cycles there, each solving the second level's
+  // coarse problem by two V-cycles, come as close to an exact coarse solve
+  // as the CG iteration count can tell on 512^2 log-normal fields (12
+  // iterations against 21 with one V-cycle).  Repeated cycles keep the
+  // preconditioner symmetric.
   a.ncyc = a.nlev > 1 ? kMgTopCycles : 1;
+  a.ncyc1 = a.nlev > 2 ? kMgSubCycles : 1;
   h.lds_bytes = mg_lds_layout(h, lc, &a) * sizeof(double);
   for (int k = 0; k < a.nlev; ++k) a.lev[k] = h.lev[lc + k];
   h.coarse_threads = std::min(1024, ((a.n0 + 63) / 64) * 64);

@@ -10,9 +10,13 @@ namespace erem {
 constexpr int kMgMaxLevels = 16;
 constexpr int kMgLdsCells = 1024;   // levels at or below this size run in one workgroup
 #ifndef EREM_MG_TOP_CYCLES
-#define EREM_MG_TOP_CYCLES 3
+#define EREM_MG_TOP_CYCLES 2
 #endif
-constexpr int kMgTopCycles = EREM_MG_TOP_CYCLES;  // V-cycles per coarse solve on the first LDS level
+#ifndef EREM_MG_SUB_CYCLES
+#define EREM_MG_SUB_CYCLES 2
+#endif
+constexpr int kMgTopCycles = EREM_MG_TOP_CYCLES;  // cycles per coarse solve on the first LDS level
+constexpr int kMgSubCycles = EREM_MG_SUB_CYCLES;  // V-cycles under the second LDS level per visit
 constexpr int kMgBottomCells = 64;  // bottom level, solved with a dense inverse
 
 // One level: faces in the fine-grid layout (x faces (nz, ny, nx+1), y faces
@@ -29,7 +33,8 @@ struct MgCoarseArgs {
   int n0;                      // cells of the first of them
   int nu;                      // Jacobi sweeps before and after the coarse correction (the kernels do two)
   int inv_off;                 // LDS offset of the bottom inverse
-  int ncyc;                    // V-cycles on the first LDS level (1 when it is the bottom)
+  int ncyc;                    // cycles on the first LDS level (1 when it is the bottom)
+  int ncyc1;                   // V-cycles of the second level's coarse problem per visit (1 when it is the bottom)
   double omega_c;              // coarse-correction relaxation
   int off[kMgMaxLevels][8];    // LDS offsets: tx, ty, tz, diag, B, E, T, 1/diag per level
   MgLevelDev lev[kMgMaxLevels];

@@ -741,6 +741,149 @@ __device__ inline void lds_load_level(const MgLevelDev& L, const LdsLevel& S) {
   }
 }
 
+// Phases of the LDS levels; each ends with a barrier.
+// Down leg of level l: two damped-Jacobi sweeps from zero in one pass (E = x2,
+// the first sweep's x1 = w B / D recomputed at the neighbours), then the
+// restricted residual into the B of level l + 1: the sum over the (up to)
+// 2 x 2 (x 2) fine cells of each coarse cell, a fine index past the edge
+// clamped and its term dropped.
+__device__ inline void lds_down(const MgCoarseArgs& a, double* smem, int l) {
+  const int bd = blockDim.x, t = threadIdx.x;
+  const MgLevelDev& F = a.lev[l];
+  const MgLevelDev& C = a.lev[l + 1];
+  LdsLevel S, SC;
+  lds_level(a, smem, l, S);
+  lds_level(a, smem, l + 1, SC);
+  {
+    const int n = F.nx * F.ny * F.nz;
+    auto x1 = [&](int j, int, int, int) { return kOmega * S.B[j] * S.dinv[j]; };
+    for (int c = t; c < n; c += bd) {
+      int x, y, z;
+      cell_xyz(F, c, x, y, z);
+      const double di = S.dinv[c];
+      const double bi = S.B[c];
+      const double xi = kOmega * bi * di;
+      S.E[c] = xi + kOmega * ((bi + lds_nb_sum(F, S, x, y, z, c, x1)) * di - xi);
+    }
+    __syncthreads();
+  }
+  const int nc = C.nx * C.ny * C.nz;
+  auto ev = [&](int j, int, int, int) { return S.E[j]; };
+  auto res = [&](int x, int y, int z) {
+    const int i = x + F.nx * (y + F.ny * z);
+    return S.B[i] - S.diag[i] * S.E[i] + lds_nb_sum(F, S, x, y, z, i, ev);
+  };
+  for (int c = t; c < nc; c += bd) {
+    int X0, Y0, Z0;
+    cell_xyz(C, c, X0, Y0, Z0);
+    const int x0 = 2 * X0, y0 = 2 * Y0;
+    const bool hx = x0 + 1 < F.nx, hy = y0 + 1 < F.ny;
+    const int x1 = hx ? x0 + 1 : x0, y1 = hy ? y0 + 1 : y0;
+    double acc;
+    if (F.nz > 1) {
+      const int z0 = 2 * Z0;
+      const bool hz = z0 + 1 < F.nz;
+      const int z1 = hz ? z0 + 1 : z0;
+      const double r000 = res(x0, y0, z0), r100 = res(x1, y0, z0), r010 = res(x0, y1, z0), r110 = res(x1, y1, z0);
+      const double r001 = res(x0, y0, z1), r101 = res(x1, y0, z1), r011 = res(x0, y1, z1), r111 = res(x1, y1, z1);
+      acc = r000 + (hx ? r100 : 0.0) + (hy ? r010 : 0.0) + (hx && hy ? r110 : 0.0);
+      if (hz) acc += r001 + (hx ? r101 : 0.0) + (hy ? r011 : 0.0) + (hx && hy ? r111 : 0.0);
+    } else {
+      const double r00 = res(x0, y0, 0), r10 = res(x1, y0, 0), r01 = res(x0, y1, 0), r11 = res(x1, y1, 0);
+      acc = r00 + (hx ? r10 : 0.0) + (hy ? r01 : 0.0) + (hx && hy ? r11 : 0.0);
+    }
+    SC.B[c] = acc;
+  }
+  __syncthreads();
+}
+
+// Up leg of level l: coarse correction folded into the first sweep,
+// T = y(E + w_c e[parent]), then E = T + w (B - A T) / D.
+__device__ inline void lds_up(const MgCoarseArgs& a, double* smem, int l) {
+  const int bd = blockDim.x, t = threadIdx.x;
+  const MgLevelDev& F = a.lev[l];
+  const MgLevelDev& C = a.lev[l + 1];
+  LdsLevel S, SC;
+  lds_level(a, smem, l, S);
+  lds_level(a, smem, l + 1, SC);
+  const int n = F.nx * F.ny * F.nz;
+  const int cz = F.nz > 1 ? 1 : 0;
+  auto xc = [&](int j, int x, int y, int z) {
+    return S.E[j] + a.omega_c * SC.E[(x >> 1) + C.nx * ((y >> 1) + C.ny * (z >> cz))];
+  };
+  for (int c = t; c < n; c += bd) {
+    int x, y, z;
+    cell_xyz(F, c, x, y, z);
+    const double di = S.dinv[c];
+    const double v = xc(c, x, y, z);
+    S.T[c] = v + kOmega * ((S.B[c] + lds_nb_sum(F, S, x, y, z, c, xc)) * di - v);
+  }
+  __syncthreads();
+  auto tv = [&](int j, int, int, int) { return S.T[j]; };
+  for (int c = t; c < n; c += bd) {
+    int x, y, z;
+    cell_xyz(F, c, x, y, z);
+    const double di = S.dinv[c];
+    const double v = S.T[c];
+    S.E[c] = v + kOmega * ((S.B[c] + lds_nb_sum(F, S, x, y, z, c, tv)) * di - v);
+  }
+  __syncthreads();
+}
+
+// Bottom: E = inverse * B, the columns split over the wavefronts (partial
+// products in T), then summed per row.  The inverse of the symmetric bottom
+// operator is symmetric: it is read by columns so that consecutive threads
+// hit consecutive banks.
+__device__ inline void lds_bottom(const MgCoarseArgs& a, double* smem, const double* Binv, int nb) {
+  const int bd = blockDim.x, t = threadIdx.x;
+  LdsLevel S;
+  lds_level(a, smem, a.nlev - 1, S);
+  const int groups = (bd + 63) >> 6;
+  const int chunk = (nb + groups - 1) / groups;
+  const int r = t & 63, g = t >> 6;
+  if (r < nb) {
+    const int j0 = g * chunk, j1 = min(nb, j0 + chunk);
+    double acc = 0.0;
+    for (int j = j0; j < j1; ++j) acc += Binv[j * nb + r] * S.B[j];
+    S.T[g * nb + r] = acc;
+  }
+  __syncthreads();
+  if (t < nb) {
+    double acc = 0.0;
+    for (int k = 0; k < groups; ++k) acc += S.T[k * nb + t];
+    S.E[t] = acc;
+  }
+  __syncthreads();
+}
+
+// Residual of level l for the correction so far: B <- B - A E (in place: a
+// cell writes only its own B, the neighbours' E are only read).  Thread t
+// owns cell t (the level has at most blockDim cells); returns E of that cell.
+__device__ inline double lds_residual(const MgCoarseArgs& a, double* smem, int l) {
+  const int t = threadIdx.x;
+  const MgLevelDev& F = a.lev[l];
+  LdsLevel S;
+  lds_level(a, smem, l, S);
+  const int n = F.nx * F.ny * F.nz;
+  double e = 0.0;
+  if (t < n) {
+    auto ev = [&](int j, int, int, int) { return S.E[j]; };
+    int x, y, z;
+    cell_xyz(F, t, x, y, z);
+    e = S.E[t];
+    S.B[t] += lds_nb_sum(F, S, x, y, z, t, ev) - S.diag[t] * e;
+  }
+  __syncthreads();
+  return e;
+}
+
+// Coarse levels in one workgroup, everything in LDS: a.ncyc cycles on the
+// first level; inside each, the coarse problem of the second level is solved
+// by a.ncyc1 V-cycles over the levels below it (a W-shaped cycle with two
+// visits under the first level), with the exact dense solve on the bottom
+// level.  Later cycles on a level start from the residual the earlier ones
+// left, and the corrections add up.  From x = 0, on rhs b (global); writes x
+// to out; with rz_slot >= 0 also b . out into the CG ring.
 __global__ __launch_bounds__(1024) void k_mg_coarse_lds(MgCoarseArgs a, const double* __restrict__ bglob,
                                               const double* __restrict__ binv, double* __restrict__ out,
                                               PcgState* st, int rz_slot) {
@@ -777,137 +920,35 @@ __global__ __launch_bounds__(1024) void k_mg_coarse_lds(MgCoarseArgs a, const do
   if (t < n0) S0.B[t] = b0;
   if (stop) return;
   __syncthreads();
-  // a.ncyc V-cycles on the first LDS level: each later one starts from the
-  // residual B - A E the earlier ones left, and the corrections add up in out
+  double x0 = 0.0;  // accumulated correction of the first level, cell t
   for (int cyc = 0; cyc < a.ncyc; ++cyc) {
-    if (cyc > 0) {
-      const MgLevelDev& F = a.lev[0];
-      auto ev = [&](int j, int, int, int) { return S0.E[j]; };
-      for (int c = t; c < n0; c += bd) {
-        int x, y, z;
-        cell_xyz(F, c, x, y, z);
-        const double e = S0.E[c];
-        S0.B[c] += lds_nb_sum(F, S0, x, y, z, c, ev) - S0.diag[c] * e;
-        out[c] = (cyc > 1 ? out[c] : 0.0) + e;
-      }
+    if (cyc > 0) x0 += lds_residual(a, smem, 0);
+    if (nl == 1) {
+      lds_bottom(a, smem, Binv, nb);
+      continue;
+    }
+    lds_down(a, smem, 0);
+    double x1 = 0.0;  // accumulated correction of the second level, cell t
+    for (int c1 = 0; c1 < a.ncyc1; ++c1) {
+      if (c1 > 0) x1 += lds_residual(a, smem, 1);
+      for (int l = 1; l + 1 < nl; ++l) lds_down(a, smem, l);
+      lds_bottom(a, smem, Binv, nb);
+      for (int l = nl - 2; l >= 1; --l) lds_up(a, smem, l);
+    }
+    if (a.ncyc1 > 1) {
+      LdsLevel S1;
+      lds_level(a, smem, 1, S1);
+      const MgLevelDev& L1 = a.lev[1];
+      if (t < L1.nx * L1.ny * L1.nz) S1.E[t] += x1;
       __syncthreads();
     }
-    // down
-    for (int l = 0; l + 1 < nl; ++l) {
-      const MgLevelDev& F = a.lev[l];
-      const MgLevelDev& C = a.lev[l + 1];
-      LdsLevel S, SC;
-      lds_level(a, smem, l, S);
-      lds_level(a, smem, l + 1, SC);
-      // two damped-Jacobi sweeps from zero in one pass: E = x2, the first
-      // sweep's x1 = w B / D recomputed at the neighbours
-      {
-        const int n = F.nx * F.ny * F.nz;
-        auto x1 = [&](int j, int, int, int) { return kOmega * S.B[j] * S.dinv[j]; };
-        for (int c = t; c < n; c += bd) {
-          int x, y, z;
-          cell_xyz(F, c, x, y, z);
-          const double di = S.dinv[c];
-          const double bi = S.B[c];
-          const double xi = kOmega * bi * di;
-          S.E[c] = xi + kOmega * ((bi + lds_nb_sum(F, S, x, y, z, c, x1)) * di - xi);
-        }
-        __syncthreads();
-      }
-      // restricted residual: the sum over the (up to) 2 x 2 (x 2) fine cells
-      // of each coarse cell; a fine index past the edge is clamped and its
-      // term dropped
-      const int nc = C.nx * C.ny * C.nz;
-      auto ev = [&](int j, int, int, int) { return S.E[j]; };
-      auto res = [&](int x, int y, int z) {
-        const int i = x + F.nx * (y + F.ny * z);
-        return S.B[i] - S.diag[i] * S.E[i] + lds_nb_sum(F, S, x, y, z, i, ev);
-      };
-      for (int c = t; c < nc; c += bd) {
-        int X0, Y0, Z0;
-        cell_xyz(C, c, X0, Y0, Z0);
-        const int x0 = 2 * X0, y0 = 2 * Y0;
-        const bool hx = x0 + 1 < F.nx, hy = y0 + 1 < F.ny;
-        const int x1 = hx ? x0 + 1 : x0, y1 = hy ? y0 + 1 : y0;
-        double acc;
-        if (F.nz > 1) {
-          const int z0 = 2 * Z0;
-          const bool hz = z0 + 1 < F.nz;
-          const int z1 = hz ? z0 + 1 : z0;
-          const double r000 = res(x0, y0, z0), r100 = res(x1, y0, z0), r010 = res(x0, y1, z0), r110 = res(x1, y1, z0);
-          const double r001 = res(x0, y0, z1), r101 = res(x1, y0, z1), r011 = res(x0, y1, z1), r111 = res(x1, y1, z1);
-          acc = r000 + (hx ? r100 : 0.0) + (hy ? r010 : 0.0) + (hx && hy ? r110 : 0.0);
-          if (hz) acc += r001 + (hx ? r101 : 0.0) + (hy ? r011 : 0.0) + (hx && hy ? r111 : 0.0);
-        } else {
-          const double r00 = res(x0, y0, 0), r10 = res(x1, y0, 0), r01 = res(x0, y1, 0), r11 = res(x1, y1, 0);
-          acc = r00 + (hx ? r10 : 0.0) + (hy ? r01 : 0.0) + (hx && hy ? r11 : 0.0);
-        }
-        SC.B[c] = acc;
-      }
-      __syncthreads();
-    }
-    // bottom: E = inverse * B, the columns split over the wavefronts (partial
-    // products in T), then summed per row.  The inverse of the symmetric
-    // bottom operator is symmetric: it is read by columns so that
-    // consecutive threads hit consecutive banks.
-    {
-      LdsLevel S;
-      lds_level(a, smem, nl - 1, S);
-      const int groups = (bd + 63) >> 6;
-      const int chunk = (nb + groups - 1) / groups;
-      const int r = t & 63, g = t >> 6;
-      if (r < nb) {
-        const int j0 = g * chunk, j1 = min(nb, j0 + chunk);
-        double acc = 0.0;
-        for (int j = j0; j < j1; ++j) acc += Binv[j * nb + r] * S.B[j];
-        S.T[g * nb + r] = acc;
-      }
-      __syncthreads();
-      if (t < nb) {
-        double acc = 0.0;
-        for (int k = 0; k < groups; ++k) acc += S.T[k * nb + t];
-        S.E[t] = acc;
-      }
-      __syncthreads();
-    }
-    // up
-    for (int l = nl - 2; l >= 0; --l) {
-      const MgLevelDev& F = a.lev[l];
-      const MgLevelDev& C = a.lev[l + 1];
-      LdsLevel S, SC;
-      lds_level(a, smem, l, S);
-      lds_level(a, smem, l + 1, SC);
-      const int n = F.nx * F.ny * F.nz;
-      const int cz = F.nz > 1 ? 1 : 0;
-      // coarse correction folded into the first sweep: T = y(E + w_c e[parent])
-      auto xc = [&](int j, int x, int y, int z) {
-        return S.E[j] + a.omega_c * SC.E[(x >> 1) + C.nx * ((y >> 1) + C.ny * (z >> cz))];
-      };
-      for (int c = t; c < n; c += bd) {
-        int x, y, z;
-        cell_xyz(F, c, x, y, z);
-        const double di = S.dinv[c];
-        const double v = xc(c, x, y, z);
-        S.T[c] = v + kOmega * ((S.B[c] + lds_nb_sum(F, S, x, y, z, c, xc)) * di - v);
-      }
-      __syncthreads();
-      // second sweep: E = T + w (B - A T) / D
-      auto tv = [&](int j, int, int, int) { return S.T[j]; };
-      for (int c = t; c < n; c += bd) {
-        int x, y, z;
-        cell_xyz(F, c, x, y, z);
-        const double di = S.dinv[c];
-        const double v = S.T[c];
-        S.E[c] = v + kOmega * ((S.B[c] + lds_nb_sum(F, S, x, y, z, c, tv)) * di - v);
-      }
-      __syncthreads();
-    }
+    lds_up(a, smem, 0);
   }
   double part = 0.0;
-  for (int c = t; c < n0; c += bd) {
-    const double v = (a.ncyc > 1 ? out[c] : 0.0) + S0.E[c];
-    out[c] = v;
-    part += bglob[c] * v;
+  if (t < n0) {
+    const double v = x0 + S0.E[t];
+    out[t] = v;
+    part = b0 * v;
   }
   if (rz_slot < 0) return;
   for (int off = 32; off > 0; off >>= 1) part += __shfl_down(part, off, 64);
