@@ -97,7 +97,9 @@ def gpu_run(prob, coupled, steps, warmup, rtol_p, mixed=False):
 
     def one_step():
         if coupled:
-            sp = ctx.pressure_and_fluxes(T, rtol=rtol_p, p=p, warm=state["n"] > 0)
+            # the pressure stays resident in the context: after the first
+            # step each solve starts from the previous double-double pressure
+            sp = ctx.pressure_and_fluxes(T, rtol=rtol_p, p=p if state["n"] == 0 else None, warm=state["n"] > 0)
             state["pcg"] += sp["iterations"]
         state["last"] = ctx.step(prob.h, T, opts)
         state["n"] += 1
@@ -334,7 +336,7 @@ def bench_adjoint(args):
 # describe the kernels as measured: reset an entry to None when its kernel
 # changes.
 TRAFFIC = {
-    ("coupled512", "fp64", "mg_vcycle"): 51.82e6,
+    ("coupled512", "fp64", "mg_vcycle"): None,       # legs changed since the counter runs
     ("coupled512", "fp64", "leja_term"): 5.29e6,     # a 4-term launch moves 21.15 MB
     ("layered128", "fp64", "leja_term"): 186.49e6,
     ("batch256", "fp64", "k_batch_fused"): 485.5e9,

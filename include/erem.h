@@ -133,9 +133,11 @@ int erem_assemble_transmissibilities(erem_ctx* ctx, const double* d_T);
  * preconditioned conjugate gradients to relative residual rtol (at most
  * max_iter iterations), then the face mass fluxes F = tau (p_i - p_j)
  * (Darcy's law, Eq. darcy, g = 0).  d_p (N, may be NULL) is read as the
- * initial guess when warm != 0 and receives the pressure.  stats (may be
- * NULL) gets iterations and the final relative residual.  ENOCONV if rtol
- * is not reached. */
+ * initial guess when warm != 0 and receives the pressure; with warm != 0 and
+ * d_p NULL the context's own (double-double) pressure of the last solve is
+ * the initial guess, and no copy is made.  stats (may be NULL) gets
+ * iterations and the final relative residual.  ENOCONV if rtol is not
+ * reached. */
 int erem_solve_pressure(erem_ctx* ctx, double rtol, int32_t max_iter, int32_t warm,
                         double* d_p, erem_stats* stats);
 

@@ -18,6 +18,15 @@ constexpr int kMgLdsCells = 1024;   // levels at or below this size run in one w
 constexpr int kMgTopCycles = EREM_MG_TOP_CYCLES;  // cycles per coarse solve on the first LDS level
 constexpr int kMgSubCycles = EREM_MG_SUB_CYCLES;  // V-cycles under the second LDS level per visit
 constexpr int kMgBottomCells = 64;  // bottom level, solved with a dense inverse
+#ifndef EREM_MG_SWEEPS
+#define EREM_MG_SWEEPS 3
+#endif
+#ifndef EREM_MG_LDS_SWEEPS
+#define EREM_MG_LDS_SWEEPS 2
+#endif
+constexpr int kMgSweeps = EREM_MG_SWEEPS;         // damped-Jacobi sweeps each way, 2D grid levels
+constexpr int kMgLdsSweeps = EREM_MG_LDS_SWEEPS;  // the same on the LDS levels (even)
+static_assert(kMgLdsSweeps % 2 == 0 && kMgLdsSweeps >= 2, "LDS sweeps come in pairs");
 
 // One level: faces in the fine-grid layout (x faces (nz, ny, nx+1), y faces
 // (nz, ny+1, nx), z faces (nz+1, ny, nx)), diagonal, and work vectors.

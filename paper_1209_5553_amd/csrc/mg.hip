@@ -278,10 +278,6 @@ __global__ __launch_bounds__(kThreads) void k_mg_up_smooth(MgLevelDev F, MgLevel
 // from LDS.  Same arithmetic, in the same order, as the generic forms above.
 // ---------------------------------------------------------------------------
 constexpr int kTY = 8;           // tile rows (two per thread)
-constexpr int kW2 = kBX + 4;     // tile width with a halo of two
-constexpr int kH2 = kTY + 4;
-constexpr int kW1 = kBX + 2;     // with a halo of one
-constexpr int kH1 = kTY + 2;
 
 // Faces of the halo-H region: x faces of its rows (face gx of cell gx is its
 // -x face) and y faces of its columns.
@@ -321,6 +317,42 @@ __device__ inline double nb_sum_tile(const TileFacesH<H>& F, int nx, int ny, int
   return s;
 }
 
+// Tile arrays of the 2D legs: the 64 x 8 tile plus a halo of H cells.
+template <int H>
+struct Halo {
+  static constexpr int W = kBX + 2 * H;
+  static constexpr int R = kTY + 2 * H;
+};
+
+// One damped-Jacobi sweep, out = x + w (B - D x + sum t x_nb) / D, on the
+// tile plus a halo of h (cells outside the grid get zero); arrays in
+// halo-HA coordinates, faces of the halo-HF region (HF >= h, HA > h).
+template <int HA, int HF>
+__device__ inline void tile_sweep(int h, const TileFacesH<HF>& tf, const MgLevelDev& F, int x0, int y0, int tid,
+                                  const double (*sb)[Halo<HA>::W], const double (*sd)[Halo<HA>::W],
+                                  const double (*xin)[Halo<HA>::W], double (*xo)[Halo<HA>::W]) {
+  constexpr int W = Halo<HA>::W;
+  const int w = kBX + 2 * h, hh = kTY + 2 * h;
+  for (int k = tid; k < w * hh; k += kThreads) {
+    const int ry = k / w, rx = k - ry * w;
+    const int ly = ry + HA - h, lx = rx + HA - h;
+    const int gx = x0 - HA + lx, gy = y0 - HA + ly;
+    double v = 0.0;
+    if (gx >= 0 && gx < F.nx && gy >= 0 && gy < F.ny) {
+      const double D = sd[ly][lx];
+      const double xi = xin[ly][lx];
+      v = xi + kOmega * (sb[ly][lx] - D * xi +
+                         nb_sum_tile<W>(tf, F.nx, F.ny, gx, gy, lx - (HA - HF), ly - (HA - HF), xin, ly, lx)) / D;
+    }
+    xo[ly][lx] = v;
+  }
+}
+
+// Down leg of a 2D level, fused: NU damped-Jacobi sweeps from zero (the
+// first, x1 = w B / D, needs no neighbours; sweep k runs on the tile plus a
+// halo of NU - k + 1 so that the neighbours' values are recomputed instead of
+// exchanged), then the restricted residual of the tile's aggregates.
+//
 // With CG, iteration it of Chronopoulos-Gear conjugate gradients (one
 // reduction phase per iteration) is folded in front of the leg.  From the
 // slot sums of the previous leg pair: the stop test on ||r_it||, then
@@ -329,24 +361,27 @@ __device__ inline double nb_sum_tile(const TileFacesH<H>& F, int nx, int ny, int
 // s = w + beta s_old and r_new = r - alpha s on the tile and its halo (the
 // halo values recomputed, the tile's written); p = z + beta p and
 // x += alpha p on the tile; the partial sums of r_new . r_new.
-template <bool CG>
+template <int NU, bool CG>
 __global__ __launch_bounds__(kThreads) void k_mg_down_restrict_2d(MgLevelDev F, MgLevelDev C,
                                                         const double* __restrict__ b, double* __restrict__ xout,
                                                         double* __restrict__ bc, PcgState* st, CgFuse cg) {
+  static_assert(NU >= 2, "two sweeps at least");
+  constexpr int HA = NU;  // b, D (and the CG vectors) on the tile plus NU
+  constexpr int W = Halo<HA>::W, R = Halo<HA>::R;
   const bool stop = pcg_done(st);
-  __shared__ double sb[kH2][kW2], sd[kH2][kW2], sx1[kH2][kW2], sx2[kH1][kW1];
-  __shared__ double sw[CG ? kH2 : 1][CG ? kW2 : 1], ss[CG ? kH2 : 1][CG ? kW2 : 1];
+  __shared__ double sb[R][W], sd[R][W], sx[2][R][W];
+  __shared__ double sw[CG ? R : 1][CG ? W : 1], ss[CG ? R : 1][CG ? W : 1];
   __shared__ double alpha_sh, beta_sh;
   __shared__ int stop_sh;
-  __shared__ TileFaces tf;
+  __shared__ TileFacesH<NU - 1> tf;
   const int nx = F.nx, ny = F.ny;
   const int tile = xcd_tile_id();  // 2D grid: tile = bx + gridDim.x * by
   const int x0 = (tile % gridDim.x) * kBX, y0 = (tile / gridDim.x) * kTY;
   const int tid = threadIdx.x + threadIdx.y * kBX;
   const int it = cg.it;
-  for (int k = tid; k < kH2 * kW2; k += kThreads) {
-    const int ly = k / kW2, lx = k - ly * kW2;
-    const int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
+  for (int k = tid; k < R * W; k += kThreads) {
+    const int ly = k / W, lx = k - ly * W;
+    const int gx = x0 - HA + lx, gy = y0 - HA + ly;
     const bool in = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
     const int j = gx + nx * gy;
     const double bj = in ? b[j] : 0.0, dj = in ? F.diag[j] : 1.0;
@@ -356,7 +391,7 @@ __global__ __launch_bounds__(kThreads) void k_mg_down_restrict_2d(MgLevelDev F, 
       sw[ly][lx] = in ? cg.w[j] : 0.0;
       ss[ly][lx] = (in && it > 0) ? cg.s_old[j] : 0.0;
     } else {
-      sx1[ly][lx] = kOmega * bj / dj;  // first sweep from zero
+      sx[0][ly][lx] = kOmega * bj / dj;  // first sweep from zero
     }
   }
   // the tile's own cells (two rows per thread) for the p and x updates
@@ -416,13 +451,13 @@ __global__ __launch_bounds__(kThreads) void k_mg_down_restrict_2d(MgLevelDev F, 
     __syncthreads();
     if (stop_sh) return;
     const double alpha = alpha_sh, beta = beta_sh;
-    for (int k = tid; k < kH2 * kW2; k += kThreads) {
-      const int ly = k / kW2, lx = k - ly * kW2;
+    for (int k = tid; k < R * W; k += kThreads) {
+      const int ly = k / W, lx = k - ly * W;
       const double sv = sw[ly][lx] + beta * ss[ly][lx];  // zero outside the grid stays zero
       const double rn = sb[ly][lx] - alpha * sv;
       ss[ly][lx] = sv;
       sb[ly][lx] = rn;
-      sx1[ly][lx] = kOmega * rn / sd[ly][lx];  // first sweep from zero
+      sx[0][ly][lx] = kOmega * rn / sd[ly][lx];  // first sweep from zero
     }
     __syncthreads();
     double rr = 0.0;
@@ -431,10 +466,10 @@ __global__ __launch_bounds__(kThreads) void k_mg_down_restrict_2d(MgLevelDev F, 
       const int ly = 2 * threadIdx.y + r, oy = y0 + ly;
       if (ox < nx && oy < ny) {
         const int j = ox + nx * oy;
-        const double rn = sb[ly + 2][threadIdx.x + 2];
+        const double rn = sb[ly + HA][threadIdx.x + HA];
         const double pn = zo[r] + beta * po[r];
         cg.r_new[j] = rn;
-        cg.s_new[j] = ss[ly + 2][threadIdx.x + 2];
+        cg.s_new[j] = ss[ly + HA][threadIdx.x + HA];
         cg.p[j] = pn;
         cg.x[j] = xo[r] + alpha * pn;
         rr += rn * rn;
@@ -452,29 +487,23 @@ __global__ __launch_bounds__(kThreads) void k_mg_down_restrict_2d(MgLevelDev F, 
     if (stop) return;
     __syncthreads();
   }
-  for (int k = tid; k < kH1 * kW1; k += kThreads) {
-    const int ly = k / kW1, lx = k - ly * kW1;
-    const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
-    double v = 0.0;
-    if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
-      const double D = sd[ly + 1][lx + 1];
-      const double xi = sx1[ly + 1][lx + 1];
-      v = xi + kOmega * (sb[ly + 1][lx + 1] - D * xi + nb_sum_tile<kW2>(tf, nx, ny, gx, gy, lx, ly, sx1, ly + 1, lx + 1)) / D;
-      if (lx >= 1 && lx <= kBX && ly >= 1 && ly <= kTY) xout[gx + nx * gy] = v;
-    }
-    sx2[ly][lx] = v;
+#pragma unroll
+  for (int k = 2; k <= NU; ++k) {
+    tile_sweep<HA, NU - 1>(NU - k + 1, tf, F, x0, y0, tid, sb, sd, sx[(k - 2) & 1], sx[(k - 1) & 1]);
+    __syncthreads();
   }
-  __syncthreads();
+  const double(*fin)[W] = sx[(NU - 1) & 1];
   const int gx = x0 + threadIdx.x;
   double acc = 0.0;
   for (int r = 0; r < 2; ++r) {
     const int ly = 2 * threadIdx.y + r;
     const int gy = y0 + ly;
     if (gx < nx && gy < ny) {
-      const int l1x = threadIdx.x + 1, l1y = ly + 1;
-      const double xi = sx2[l1y][l1x];
-      acc += sb[l1y + 1][l1x + 1] - sd[l1y + 1][l1x + 1] * xi +
-             nb_sum_tile<kW1>(tf, nx, ny, gx, gy, l1x, l1y, sx2, l1y, l1x);
+      const int sy = ly + HA, sxx = threadIdx.x + HA;
+      const double xi = fin[sy][sxx];
+      xout[gx + nx * gy] = xi;
+      acc += sb[sy][sxx] - sd[sy][sxx] * xi +
+             nb_sum_tile<W>(tf, nx, ny, gx, gy, sxx - (HA - (NU - 1)), sy - (HA - (NU - 1)), fin, sy, sxx);
     }
   }
   acc += __shfl_xor(acc, 1, 64);
@@ -482,157 +511,66 @@ __global__ __launch_bounds__(kThreads) void k_mg_down_restrict_2d(MgLevelDev F, 
   if ((threadIdx.x & 1) == 0 && gx < nx && gy < ny) bc[(gx >> 1) + C.nx * (gy >> 1)] = acc;
 }
 
+// Up leg of a 2D level, fused: the coarse correction v = x + w_c e[parent]
+// on the tile plus a halo of HU, then NU damped-Jacobi sweeps on shrinking
+// halos; the last lands on the tile (out = z) and, with rz_slot >= 0, b . z
+// goes to the CG ring.  With CG (the finest level of the Chronopoulos-Gear
+// form) every halo is one larger, so that the last sweep also covers the
+// halo-one ring and w = A z follows on the tile (w_out); the partial sums of
+// r.z and w.z go to the ring slot.
+template <int NU, bool CG>
 __global__ __launch_bounds__(kThreads) void k_mg_up_smooth_2d(MgLevelDev F, MgLevelDev C, const double* __restrict__ b,
-                                                    const double* __restrict__ xv, const double* __restrict__ ec,
-                                                    double omega_c, double* __restrict__ out, PcgState* st,
-                                                    int rz_slot) {
+                                                     const double* __restrict__ xv, const double* __restrict__ ec,
+                                                     double omega_c, double* __restrict__ out,
+                                                     double* __restrict__ w_out, PcgState* st, int rz_slot) {
+  constexpr int HU = NU + (CG ? 1 : 0);
+  constexpr int W = Halo<HU>::W, R = Halo<HU>::R;
   const bool stop = pcg_done(st);
-  __shared__ double sxc[kH2][kW2], sb[kH1][kW1], sd[kH1][kW1], sys[kH1][kW1];
-  __shared__ TileFaces tf;
+  __shared__ double sxc[R][W], sb[R][W], sd[R][W], sy[2][R][W];
+  __shared__ TileFacesH<HU - 1> tf;
   const int nx = F.nx, ny = F.ny;
   const int tile = xcd_tile_id();  // 2D grid: tile = bx + gridDim.x * by
   const int x0 = (tile % gridDim.x) * kBX, y0 = (tile / gridDim.x) * kTY;
   const int tid = threadIdx.x + threadIdx.y * kBX;
-  for (int k = tid; k < kH2 * kW2; k += kThreads) {
-    const int ly = k / kW2, lx = k - ly * kW2;
-    const int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
-    double v = 0.0;
-    if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) v = xv[gx + nx * gy] + omega_c * ec[(gx >> 1) + C.nx * (gy >> 1)];
-    sxc[ly][lx] = v;
-  }
-  for (int k = tid; k < kH1 * kW1; k += kThreads) {
-    const int ly = k / kW1, lx = k - ly * kW1;
-    const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
+  for (int k = tid; k < R * W; k += kThreads) {
+    const int ly = k / W, lx = k - ly * W;
+    const int gx = x0 - HU + lx, gy = y0 - HU + ly;
     const bool in = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
     const int j = gx + nx * gy;
+    sxc[ly][lx] = in ? xv[j] + omega_c * ec[(gx >> 1) + C.nx * (gy >> 1)] : 0.0;
     sb[ly][lx] = in ? b[j] : 0.0;
     sd[ly][lx] = in ? F.diag[j] : 1.0;
   }
   load_tile_faces(F, x0, y0, tid, tf);
   if (stop) return;
   __syncthreads();
-  for (int k = tid; k < kH1 * kW1; k += kThreads) {
-    const int ly = k / kW1, lx = k - ly * kW1;
-    const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
-    double v = 0.0;
-    if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
-      const double D = sd[ly][lx];
-      const double xi = sxc[ly + 1][lx + 1];
-      v = xi + kOmega * (sb[ly][lx] - D * xi + nb_sum_tile<kW2>(tf, nx, ny, gx, gy, lx, ly, sxc, ly + 1, lx + 1)) / D;
-    }
-    sys[ly][lx] = v;
+#pragma unroll
+  for (int k = 1; k <= NU; ++k) {
+    tile_sweep<HU, HU - 1>(HU - k, tf, F, x0, y0, tid, sb, sd, k == 1 ? sxc : sy[(k - 2) & 1], sy[(k - 1) & 1]);
+    __syncthreads();
   }
-  __syncthreads();
-  const int gx = x0 + threadIdx.x;
-  double part = 0.0;
-  for (int r = 0; r < 2; ++r) {
-    const int ly = 2 * threadIdx.y + r;
-    const int gy = y0 + ly;
-    if (gx < nx && gy < ny) {
-      const int l1x = threadIdx.x + 1, l1y = ly + 1;
-      const double D = sd[l1y][l1x];
-      const double yi = sys[l1y][l1x];
-      const double bi = sb[l1y][l1x];
-      const double v = yi + kOmega * (bi - D * yi + nb_sum_tile<kW1>(tf, nx, ny, gx, gy, l1x, l1y, sys, l1y, l1x)) / D;
-      out[gx + nx * gy] = v;
-      part += bi * v;
-    }
-  }
-  if (rz_slot < 0) return;
-  for (int off = 32; off > 0; off >>= 1) part += __shfl_down(part, off, 64);
-  __shared__ double sh[kThreads / 64];
-  if ((tid & 63) == 0) sh[tid >> 6] = part;
-  __syncthreads();
-  if (tid == 0) {
-    const int bid = blockIdx.x + gridDim.x * blockIdx.y;
-    atomicAdd(&st->rz[rz_slot * kSlots + (bid & (kSlots - 1))], sh[0] + sh[1] + sh[2] + sh[3]);
-  }
-}
-
-// Finest up leg for Chronopoulos-Gear conjugate gradients: as above, with
-// the second sweep also on the halo-one ring so that w = A z follows on the
-// tile (z = out, w = w_out); the partial sums of r.z and w.z go to the CG
-// ring slot.  Halos grow by one: x + w_c e on halo three, the first sweep on
-// halo two.
-constexpr int kW3 = kBX + 6;
-constexpr int kH3 = kTY + 6;
-
-__global__ __launch_bounds__(kThreads) void k_mg_up_smooth_2d_cg(MgLevelDev F, MgLevelDev C,
-                                                        const double* __restrict__ b,
-                                                        const double* __restrict__ xv,
-                                                        const double* __restrict__ ec, double omega_c,
-                                                        double* __restrict__ out, double* __restrict__ w_out,
-                                                        PcgState* st, int slot) {
-  const bool stop = pcg_done(st);
-  __shared__ double sxc[kH3][kW3], sb[kH2][kW2], sd[kH2][kW2], sys[kH2][kW2], se[kH1][kW1];
-  __shared__ TileFacesH<2> tf;
-  const int nx = F.nx, ny = F.ny;
-  const int tile = xcd_tile_id();  // 2D grid: tile = bx + gridDim.x * by
-  const int x0 = (tile % gridDim.x) * kBX, y0 = (tile / gridDim.x) * kTY;
-  const int tid = threadIdx.x + threadIdx.y * kBX;
-  for (int k = tid; k < kH3 * kW3; k += kThreads) {
-    const int ly = k / kW3, lx = k - ly * kW3;
-    const int gx = x0 - 3 + lx, gy = y0 - 3 + ly;
-    double v = 0.0;
-    if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) v = xv[gx + nx * gy] + omega_c * ec[(gx >> 1) + C.nx * (gy >> 1)];
-    sxc[ly][lx] = v;
-  }
-  for (int k = tid; k < kH2 * kW2; k += kThreads) {
-    const int ly = k / kW2, lx = k - ly * kW2;
-    const int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
-    const bool in = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-    const int j = gx + nx * gy;
-    sb[ly][lx] = in ? b[j] : 0.0;
-    sd[ly][lx] = in ? F.diag[j] : 1.0;
-  }
-  load_tile_faces(F, x0, y0, tid, tf);
-  if (stop) return;
-  __syncthreads();
-  // first sweep on halo two
-  for (int k = tid; k < kH2 * kW2; k += kThreads) {
-    const int ly = k / kW2, lx = k - ly * kW2;
-    const int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
-    double v = 0.0;
-    if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
-      const double D = sd[ly][lx];
-      const double xi = sxc[ly + 1][lx + 1];
-      v = xi + kOmega * (sb[ly][lx] - D * xi + nb_sum_tile<kW3>(tf, nx, ny, gx, gy, lx, ly, sxc, ly + 1, lx + 1)) / D;
-    }
-    sys[ly][lx] = v;
-  }
-  __syncthreads();
-  // second sweep on halo one
-  for (int k = tid; k < kH1 * kW1; k += kThreads) {
-    const int ly = k / kW1, lx = k - ly * kW1;
-    const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
-    double v = 0.0;
-    if (gx >= 0 && gx < nx && gy >= 0 && gy < ny) {
-      const double D = sd[ly + 1][lx + 1];
-      const double yi = sys[ly + 1][lx + 1];
-      v = yi + kOmega * (sb[ly + 1][lx + 1] - D * yi +
-                         nb_sum_tile<kW2>(tf, nx, ny, gx, gy, lx + 1, ly + 1, sys, ly + 1, lx + 1)) / D;
-    }
-    se[ly][lx] = v;
-  }
-  __syncthreads();
+  const double(*fin)[W] = sy[(NU - 1) & 1];
   const int gx = x0 + threadIdx.x;
   double g = 0.0, dz = 0.0;
   for (int r = 0; r < 2; ++r) {
     const int ly = 2 * threadIdx.y + r;
     const int gy = y0 + ly;
     if (gx < nx && gy < ny) {
-      const double z = se[ly + 1][threadIdx.x + 1];
-      const double w = sd[ly + 2][threadIdx.x + 2] * z -
-                       nb_sum_tile<kW1>(tf, nx, ny, gx, gy, threadIdx.x + 2, ly + 2, se, ly + 1, threadIdx.x + 1);
+      const int syy = ly + HU, sxx = threadIdx.x + HU;
+      const double z = fin[syy][sxx];
       out[gx + nx * gy] = z;
-      w_out[gx + nx * gy] = w;
-      g += sb[ly + 2][threadIdx.x + 2] * z;
-      dz += w * z;
+      g += sb[syy][sxx] * z;
+      if (CG) {
+        const double w = sd[syy][sxx] * z - nb_sum_tile<W>(tf, nx, ny, gx, gy, sxx - 1, syy - 1, fin, syy, sxx);
+        w_out[gx + nx * gy] = w;
+        dz += w * z;
+      }
     }
   }
+  if (rz_slot < 0) return;
   for (int off = 32; off > 0; off >>= 1) {
     g += __shfl_down(g, off, 64);
-    dz += __shfl_down(dz, off, 64);
+    if (CG) dz += __shfl_down(dz, off, 64);
   }
   __shared__ double sh[2][kThreads / 64];
   if ((tid & 63) == 0) {
@@ -641,9 +579,9 @@ __global__ __launch_bounds__(kThreads) void k_mg_up_smooth_2d_cg(MgLevelDev F, M
   }
   __syncthreads();
   if (tid == 0) {
-    const int sl = slot * kSlots + ((blockIdx.x + gridDim.x * blockIdx.y) & (kSlots - 1));
+    const int sl = rz_slot * kSlots + ((blockIdx.x + gridDim.x * blockIdx.y) & (kSlots - 1));
     atomicAdd(&st->rz[sl], sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3]);
-    atomicAdd(&st->wz[sl], sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3]);
+    if (CG) atomicAdd(&st->wz[sl], sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3]);
   }
 }
 
@@ -747,6 +685,21 @@ __device__ inline void lds_load_level(const MgLevelDev& L, const LdsLevel& S) {
 // restricted residual into the B of level l + 1: the sum over the (up to)
 // 2 x 2 (x 2) fine cells of each coarse cell, a fine index past the edge
 // clamped and its term dropped.
+// One damped-Jacobi sweep of an LDS level from xin into xo (different arrays).
+__device__ inline void lds_sweep(const MgLevelDev& F, const LdsLevel& S, const double* xin, double* xo) {
+  const int bd = blockDim.x, t = threadIdx.x;
+  const int n = F.nx * F.ny * F.nz;
+  auto xv = [&](int j, int, int, int) { return xin[j]; };
+  for (int c = t; c < n; c += bd) {
+    int x, y, z;
+    cell_xyz(F, c, x, y, z);
+    const double di = S.dinv[c];
+    const double v = xin[c];
+    xo[c] = v + kOmega * ((S.B[c] + lds_nb_sum(F, S, x, y, z, c, xv)) * di - v);
+  }
+  __syncthreads();
+}
+
 __device__ inline void lds_down(const MgCoarseArgs& a, double* smem, int l) {
   const int bd = blockDim.x, t = threadIdx.x;
   const MgLevelDev& F = a.lev[l];
@@ -766,6 +719,10 @@ __device__ inline void lds_down(const MgCoarseArgs& a, double* smem, int l) {
       S.E[c] = xi + kOmega * ((bi + lds_nb_sum(F, S, x, y, z, c, x1)) * di - xi);
     }
     __syncthreads();
+  }
+  for (int k = 2; k < kMgLdsSweeps; k += 2) {  // further sweeps in pairs, ending in E
+    lds_sweep(F, S, S.E, S.T);
+    lds_sweep(F, S, S.T, S.E);
   }
   const int nc = C.nx * C.ny * C.nz;
   auto ev = [&](int j, int, int, int) { return S.E[j]; };
@@ -819,15 +776,11 @@ __device__ inline void lds_up(const MgCoarseArgs& a, double* smem, int l) {
     S.T[c] = v + kOmega * ((S.B[c] + lds_nb_sum(F, S, x, y, z, c, xc)) * di - v);
   }
   __syncthreads();
-  auto tv = [&](int j, int, int, int) { return S.T[j]; };
-  for (int c = t; c < n; c += bd) {
-    int x, y, z;
-    cell_xyz(F, c, x, y, z);
-    const double di = S.dinv[c];
-    const double v = S.T[c];
-    S.E[c] = v + kOmega * ((S.B[c] + lds_nb_sum(F, S, x, y, z, c, tv)) * di - v);
+  lds_sweep(F, S, S.T, S.E);
+  for (int k = 2; k < kMgLdsSweeps; k += 2) {  // further sweeps in pairs, ending in E
+    lds_sweep(F, S, S.E, S.T);
+    lds_sweep(F, S, S.T, S.E);
   }
-  __syncthreads();
 }
 
 // Bottom: E = inverse * B, the columns split over the wavefronts (partial
@@ -991,9 +944,11 @@ hipError_t mg_apply(const MgHierarchy& h, const double* r, double* z, PcgState* 
     if (F.nz == 1) {
       const dim3 g((F.nx + kBX - 1) / kBX, (F.ny + kTY - 1) / kTY, 1);
       if (l == 0 && cg && cg->update)
-        hipLaunchKernelGGL(k_mg_down_restrict_2d<true>, g, cell_block(), 0, s, F, C, b, F.x, C.b, st, *cg);
+        hipLaunchKernelGGL((k_mg_down_restrict_2d<kMgSweeps, true>), g, cell_block(), 0, s, F, C, b, F.x, C.b, st,
+                           *cg);
       else
-        hipLaunchKernelGGL(k_mg_down_restrict_2d<false>, g, cell_block(), 0, s, F, C, b, F.x, C.b, st, CgFuse{});
+        hipLaunchKernelGGL((k_mg_down_restrict_2d<kMgSweeps, false>), g, cell_block(), 0, s, F, C, b, F.x, C.b, st,
+                           CgFuse{});
     } else {
       const dim3 g((F.nx + kBX - 1) / kBX, (F.ny + kBY - 1) / kBY, C.nz);
       hipLaunchKernelGGL(k_mg_down_restrict, g, cell_block(), 0, s, F, C, b, F.x, C.b, st);
@@ -1016,11 +971,11 @@ hipError_t mg_apply(const MgHierarchy& h, const double* r, double* z, PcgState* 
     if (F.nz == 1) {
       const dim3 g((F.nx + kBX - 1) / kBX, (F.ny + kTY - 1) / kTY, 1);
       if (l == 0 && cg)
-        hipLaunchKernelGGL(k_mg_up_smooth_2d_cg, g, cell_block(), 0, s, F, C, b, F.x, ec, h.omega_c, out, cg->w_out,
-                           st, rz_slot);
+        hipLaunchKernelGGL((k_mg_up_smooth_2d<kMgSweeps, true>), g, cell_block(), 0, s, F, C, b, F.x, ec, h.omega_c,
+                           out, cg->w_out, st, rz_slot);
       else
-        hipLaunchKernelGGL(k_mg_up_smooth_2d, g, cell_block(), 0, s, F, C, b, F.x, ec, h.omega_c, out, st,
-                           l == 0 ? rz_slot : -1);
+        hipLaunchKernelGGL((k_mg_up_smooth_2d<kMgSweeps, false>), g, cell_block(), 0, s, F, C, b, F.x, ec, h.omega_c,
+                           out, nullptr, st, l == 0 ? rz_slot : -1);
     } else {
       hipLaunchKernelGGL(k_mg_up_smooth, grid_of(F), cell_block(), 0, s, F, C, b, F.x, ec, h.omega_c, out, st,
                          l == 0 ? rz_slot : -1);
