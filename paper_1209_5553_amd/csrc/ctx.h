@@ -21,11 +21,6 @@ struct DivDiffCache {
 struct erem_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
-  // side stream (non-blocking, default priority) for the multigrid bottom
-  // inverse, which overlaps the start of the solve; join before its first use
-  hipStream_t side = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
-  bool inv_pending = false;
   erem::Dims d{};
   erem::Phys ph{};
   bool rock_set = false, fluid_set = false, bc_set = false;

@@ -50,10 +50,6 @@ double elapsed_ms(hipEvent_t a, hipEvent_t b) {
 }
 
 constexpr int kProfSubsteps = 8;  // profiled substeps per evaluation
-#ifndef EREM_SIDE_STREAM
-#define EREM_SIDE_STREAM 1
-#endif
-constexpr bool kSideStream = EREM_SIDE_STREAM != 0;  // bottom inverse on the side stream
 
 int check_opts(erem_ctx* c, const erem_opts* o) {
   if (!o) return fail(c, EREM_EINVAL, "opts is NULL");
@@ -603,10 +599,6 @@ int pcg_inner(erem_ctx* c, double inner_tol, int budget, int* iters, bool* done)
   // 2D multigrid: Chronopoulos-Gear iterations folded into the finest legs
   // (no separate CG kernels); otherwise pcg_a, pcg_b and the preconditioner.
   const bool fuse = c->use_mg && mg_fuses_cg(c->mg);
-  if (c->inv_pending) {  // the bottom inverse of this setup, from the side stream
-    HIP_TRY(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
-    c->inv_pending = false;
-  }
   if (fuse) {
     const CgFuse cg0{0, 0, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, c->pw};
     HIP_TRY(c, mg_apply(c->mg, c->pr, c->pz, c->pcg, 0, c->stream, &cg0));
@@ -685,10 +677,7 @@ int spd_solve(erem_ctx* c, const double* b, double* x, double rtol, int max_iter
   const Dims& d = c->d;
   if (d.dim != 2) return fail(c, EREM_EINVAL, "the general right-hand-side solve supports 2D grids");
   HIP_TRY(c, hipMemsetAsync(x, 0, sizeof(double) * d.N, c->stream));
-  if (c->use_mg) {
-    HIP_TRY(c, mg_setup(c->mg, c->stream, kSideStream ? c->side : nullptr, c->ev_fork, c->ev_join));
-    c->inv_pending = true;
-  }
+  if (c->use_mg) HIP_TRY(c, mg_setup(c->mg, c->stream));
   int total = 0;
   bool ok = false;
   for (int outer = 0; outer < 12; ++outer) {
@@ -753,14 +742,6 @@ int erem_create(const erem_grid* g, void* stream, erem_ctx** out) {
   if (!c) return EREM_ENOMEM;
   c->stream = static_cast<hipStream_t>(stream);
   if (hipGetDevice(&c->device) != hipSuccess) { delete c; return EREM_EDEVICE; }
-  if (hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) != hipSuccess) {
-    if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
-    if (c->side) (void)hipStreamDestroy(c->side);
-    delete c;
-    return EREM_EDEVICE;
-  }
   c->d.nx = static_cast<int>(g->nx);
   c->d.ny = static_cast<int>(g->ny);
   c->d.nz = static_cast<int>(g->nz);
@@ -858,10 +839,6 @@ int erem_create(const erem_grid* g, void* stream, erem_ctx** out) {
 int erem_destroy(erem_ctx* c) {
   if (!c) return EREM_EINVAL;
   (void)hipStreamSynchronize(c->stream);
-  (void)hipStreamSynchronize(c->side);
-  (void)hipEventDestroy(c->ev_fork);
-  (void)hipEventDestroy(c->ev_join);
-  (void)hipStreamDestroy(c->side);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   c->ev.clear();
   free_mg(c);
@@ -937,10 +914,7 @@ int erem_solve_pressure(erem_ctx* c, double rtol, int32_t max_iter, int32_t warm
   int total = 0;
   bool ok = false;
   double relres = NAN;
-  if (c->use_mg) {
-    HIP_TRY(c, mg_setup(c->mg, c->stream, kSideStream ? c->side : nullptr, c->ev_fork, c->ev_join));
-    c->inv_pending = true;
-  }
+  if (c->use_mg) HIP_TRY(c, mg_setup(c->mg, c->stream));
   for (int outer = 0; outer < 8; ++outer) {
     HIP_TRY(c, launch_pcg_reset(c->pcg, 0.0, c->stream));
     HIP_TRY(c, launch_dd_residual(d, c->ph, c->tx, c->ty, c->tz, c->pres, c->pres_lo, c->prhs, c->pcg, c->stream));

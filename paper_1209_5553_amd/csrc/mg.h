@@ -81,10 +81,7 @@ struct CgFuse {
   double* w_out;       // w of the new z
 };
 
-// Coarse operators on s, then the bottom inverse: on side after s reaches
-// fork (join recorded after it), or on s when side is null.
-hipError_t mg_setup(const MgHierarchy& h, hipStream_t s, hipStream_t side = nullptr, hipEvent_t fork = nullptr,
-                    hipEvent_t join = nullptr);
+hipError_t mg_setup(const MgHierarchy& h, hipStream_t s);
 // z = M^{-1} r.  With cg (only where mg_fuses_cg): see CgFuse; with
 // cg->update, r is the residual before the update and z = M^{-1} r_new.
 hipError_t mg_apply(const MgHierarchy& h, const double* r, double* z, PcgState* st, int rz_slot,

@@ -917,21 +917,12 @@ __global__ __launch_bounds__(1024) void k_mg_coarse_lds(MgCoarseArgs a, const do
 
 }  // namespace
 
-hipError_t mg_setup(const MgHierarchy& h, hipStream_t s, hipStream_t side, hipEvent_t fork, hipEvent_t join) {
+hipError_t mg_setup(const MgHierarchy& h, hipStream_t s) {
   for (int l = 1; l <= h.lb; ++l) {
     const MgLevelDev& F = h.lev[l - 1];
     const MgLevelDev& C = h.lev[l];
     const dim3 grid((C.nx + kBX - 1) / kBX, (C.ny + kBY - 1) / kBY, C.nz);
     hipLaunchKernelGGL(k_mg_coarsen, grid, cell_block(), 0, s, F, C);
-  }
-  if (side) {
-    hipError_t e = hipEventRecord(fork, s);
-    if (e == hipSuccess) e = hipStreamWaitEvent(side, fork, 0);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(k_mg_bottom_inverse, dim3(1), dim3(1024), 0, side, h.lev[h.lb], h.binv);
-    e = hipGetLastError();
-    if (e == hipSuccess) e = hipEventRecord(join, side);
-    return e;
   }
   hipLaunchKernelGGL(k_mg_bottom_inverse, dim3(1), dim3(1024), 0, s, h.lev[h.lb], h.binv);
   return hipGetLastError();
