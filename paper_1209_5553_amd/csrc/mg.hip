@@ -23,6 +23,22 @@ namespace {
 
 constexpr double kOmega = 0.8;
 
+// Weights of the sweeps on the 2D grid levels: with EREM_MG_CHEB the
+// reciprocals of the Chebyshev points of [lmax / 3, lmax] for lmax = 2 (the
+// Gershgorin bound of D^-1 A for these operators), i.e. the smoother is the
+// degree-kMgSweeps Chebyshev polynomial in D^-1 A; otherwise damped Jacobi.
+// Any order gives the same polynomial, so the cycle stays symmetric.
+#ifndef EREM_MG_CHEB
+#define EREM_MG_CHEB 1
+#endif
+template <int NU>
+__device__ inline double sweep_weight(int k) {
+  if (!EREM_MG_CHEB) return kOmega;
+  const double lmax = 2.0, lmin = lmax / 3.0;
+  const double z = 0.5 * (lmax + lmin) + 0.5 * (lmax - lmin) * cos(M_PI * (2 * k + 1) / (2.0 * NU));
+  return 1.0 / z;
+}
+
 __device__ inline int fxi(int nx, int ny, int x, int y, int z) { return (z * ny + y) * (nx + 1) + x; }
 __device__ inline int fyi(int nx, int ny, int x, int y, int z) { return (z * (ny + 1) + y) * nx + x; }
 __device__ inline int fzi(int nx, int ny, int x, int y, int z) { return (z * ny + y) * nx + x; }
@@ -330,7 +346,7 @@ struct Halo {
 template <int HA, int HF>
 __device__ inline void tile_sweep(int h, const TileFacesH<HF>& tf, const MgLevelDev& F, int x0, int y0, int tid,
                                   const double (*sb)[Halo<HA>::W], const double (*sd)[Halo<HA>::W],
-                                  const double (*xin)[Halo<HA>::W], double (*xo)[Halo<HA>::W]) {
+                                  const double (*xin)[Halo<HA>::W], double (*xo)[Halo<HA>::W], double om) {
   constexpr int W = Halo<HA>::W;
   const int w = kBX + 2 * h, hh = kTY + 2 * h;
   for (int k = tid; k < w * hh; k += kThreads) {
@@ -341,8 +357,8 @@ __device__ inline void tile_sweep(int h, const TileFacesH<HF>& tf, const MgLevel
     if (gx >= 0 && gx < F.nx && gy >= 0 && gy < F.ny) {
       const double D = sd[ly][lx];
       const double xi = xin[ly][lx];
-      v = xi + kOmega * (sb[ly][lx] - D * xi +
-                         nb_sum_tile<W>(tf, F.nx, F.ny, gx, gy, lx - (HA - HF), ly - (HA - HF), xin, ly, lx)) / D;
+      v = xi + om * (sb[ly][lx] - D * xi +
+                     nb_sum_tile<W>(tf, F.nx, F.ny, gx, gy, lx - (HA - HF), ly - (HA - HF), xin, ly, lx)) / D;
     }
     xo[ly][lx] = v;
   }
@@ -391,7 +407,7 @@ __global__ __launch_bounds__(kThreads) void k_mg_down_restrict_2d(MgLevelDev F, 
       sw[ly][lx] = in ? cg.w[j] : 0.0;
       ss[ly][lx] = (in && it > 0) ? cg.s_old[j] : 0.0;
     } else {
-      sx[0][ly][lx] = kOmega * bj / dj;  // first sweep from zero
+      sx[0][ly][lx] = sweep_weight<NU>(0) * bj / dj;  // first sweep from zero
     }
   }
   // the tile's own cells (two rows per thread) for the p and x updates
@@ -457,7 +473,7 @@ __global__ __launch_bounds__(kThreads) void k_mg_down_restrict_2d(MgLevelDev F, 
       const double rn = sb[ly][lx] - alpha * sv;
       ss[ly][lx] = sv;
       sb[ly][lx] = rn;
-      sx[0][ly][lx] = kOmega * rn / sd[ly][lx];  // first sweep from zero
+      sx[0][ly][lx] = sweep_weight<NU>(0) * rn / sd[ly][lx];  // first sweep from zero
     }
     __syncthreads();
     double rr = 0.0;
@@ -489,7 +505,8 @@ __global__ __launch_bounds__(kThreads) void k_mg_down_restrict_2d(MgLevelDev F, 
   }
 #pragma unroll
   for (int k = 2; k <= NU; ++k) {
-    tile_sweep<HA, NU - 1>(NU - k + 1, tf, F, x0, y0, tid, sb, sd, sx[(k - 2) & 1], sx[(k - 1) & 1]);
+    tile_sweep<HA, NU - 1>(NU - k + 1, tf, F, x0, y0, tid, sb, sd, sx[(k - 2) & 1], sx[(k - 1) & 1],
+                           sweep_weight<NU>(k - 1));
     __syncthreads();
   }
   const double(*fin)[W] = sx[(NU - 1) & 1];
@@ -546,7 +563,8 @@ __global__ __launch_bounds__(kThreads) void k_mg_up_smooth_2d(MgLevelDev F, MgLe
   __syncthreads();
 #pragma unroll
   for (int k = 1; k <= NU; ++k) {
-    tile_sweep<HU, HU - 1>(HU - k, tf, F, x0, y0, tid, sb, sd, k == 1 ? sxc : sy[(k - 2) & 1], sy[(k - 1) & 1]);
+    tile_sweep<HU, HU - 1>(HU - k, tf, F, x0, y0, tid, sb, sd, k == 1 ? sxc : sy[(k - 2) & 1], sy[(k - 1) & 1],
+                           sweep_weight<NU>(NU - k));
     __syncthreads();
   }
   const double(*fin)[W] = sy[(NU - 1) & 1];
