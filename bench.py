@@ -337,9 +337,9 @@ def bench_adjoint(args):
 # changes.
 TRAFFIC = {
     ("coupled512", "fp64", "mg_vcycle"): None,       # legs changed since the counter runs
-    ("coupled512", "fp64", "leja_term"): 5.29e6,     # a 4-term launch moves 21.15 MB
+    ("coupled512", "fp64", "leja_term"): None,       # kernel changed since the counter runs
     ("layered128", "fp64", "leja_term"): 186.49e6,
-    ("batch256", "fp64", "k_batch_fused"): 485.5e9,
+    ("batch256", "fp64", "k_batch_fused"): None,     # kernel changed since the counter runs
 }
 
 

@@ -228,6 +228,12 @@ __global__ __launch_bounds__(NT) void k_batch_blocks(BatchArgs a) {
 constexpr int kFX = 64, kFY = 16, kFThreads = kFX * kFY;
 constexpr int kFWQ = kFX + 8, kFHQ = kFY + 8;   // q_{k-1}: halo 4
 constexpr int kFWI = kFX + 6, kFHI = kFY + 6;   // stencil, intermediates: halo 3
+static_assert(kFHQ * kFWQ <= 2 * kFThreads && kFHI * kFWI <= 2 * kFThreads, "two staged values per thread");
+#ifndef EREM_BATCH_LOAD_GROUPS
+#define EREM_BATCH_LOAD_GROUPS 2
+#endif
+constexpr int kFLoadGroups = EREM_BATCH_LOAD_GROUPS;  // 1 or 2
+static_assert(kFLoadGroups == 1 || kFLoadGroups == 2, "one or two load groups");
 
 template <class V>
 constexpr size_t fused_lds_bytes() {
@@ -305,23 +311,55 @@ __global__ __launch_bounds__(kFThreads) void k_batch_fused(BatchArgs a) {
           double part[4] = {0.0, 0.0, 0.0, 0.0};
           for (int y0 = 0; y0 < ny; y0 += kFY)
             for (int x0 = 0; x0 < nx; x0 += kFX) {
-              for (int e = tid; e < kFHQ * kFWQ; e += kFThreads) {
-                const int ry = e / kFWQ, rx = e - ry * kFWQ;
-                const int gx = x0 - 4 + rx, gy = y0 - 4 + ry;
-                sq[ry][rx] = (gx >= 0 && gx < nx && gy >= 0 && gy < ny) ? qin[o + gx + nx * gy] : V(0);
-              }
-              for (int e = tid; e < kFHI * kFWI; e += kFThreads) {
-                const int ry = e / kFWI, rx = e - ry * kFWI;
-                const int gx = x0 - 3 + rx, gy = y0 - 3 + ry;
-                const bool in = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-                const long long ci = o + gx + nx * gy;
-#pragma unroll
-                for (int d = 0; d < 5; ++d) sc[d][ry][rx] = in ? cV[d * Ntot + ci] : V(0);
-              }
+              // the tile's loads are issued in groups before their LDS
+              // stores (q with the first half of the stencil, then the
+              // second half), so the tile waits for a few memory latencies
+              // instead of one per loop trip
               const int gx = x0 + lx, gy = y0 + ly;
               const bool own = gx < nx && gy < ny;
               const long long i = o + gx + nx * gy;
-              V acc = own ? pv[i] : V(0);
+              V acc;
+#pragma unroll
+              for (int grp = 0; grp < kFLoadGroups; ++grp) {
+                constexpr int UG = 2 / kFLoadGroups;  // stencil values per thread and group
+                V rq[2], rc[5][UG];
+                if (grp == 0) {
+#pragma unroll
+                  for (int u = 0; u < 2; ++u) {
+                    const int e = tid + u * kFThreads;
+                    const int ry = e / kFWQ, rx = e - ry * kFWQ;
+                    const int qx = x0 - 4 + rx, qy = y0 - 4 + ry;
+                    rq[u] = (e < kFHQ * kFWQ && qx >= 0 && qx < nx && qy >= 0 && qy < ny) ? qin[o + qx + nx * qy]
+                                                                                        : V(0);
+                  }
+                  acc = own ? pv[i] : V(0);
+                }
+#pragma unroll
+                for (int uu = 0; uu < UG; ++uu) {
+                  const int e = tid + (grp * UG + uu) * kFThreads;
+                  const int ry = e / kFWI, rx = e - ry * kFWI;
+                  const int cx = x0 - 3 + rx, cy = y0 - 3 + ry;
+                  const bool in = e < kFHI * kFWI && cx >= 0 && cx < nx && cy >= 0 && cy < ny;
+                  const long long ci = o + cx + nx * cy;
+#pragma unroll
+                  for (int d = 0; d < 5; ++d) rc[d][uu] = in ? cV[d * Ntot + ci] : V(0);
+                }
+                if (grp == 0) {
+#pragma unroll
+                  for (int u = 0; u < 2; ++u) {
+                    const int e = tid + u * kFThreads;
+                    if (e < kFHQ * kFWQ) sq[e / kFWQ][e % kFWQ] = rq[u];
+                  }
+                }
+#pragma unroll
+                for (int uu = 0; uu < UG; ++uu) {
+                  const int e = tid + (grp * UG + uu) * kFThreads;
+                  if (e < kFHI * kFWI) {
+#pragma unroll
+                    for (int d = 0; d < 5; ++d) sc[d][e / kFWI][e % kFWI] = rc[d][uu];
+                  }
+                }
+              }
               __syncthreads();
               V last = V(0);
 #pragma unroll

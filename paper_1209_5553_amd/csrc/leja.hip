@@ -145,18 +145,26 @@ __global__ __launch_bounds__(kBX * BY) void k_leja_terms(Dims d, const LejaCoef*
   const int bx = blockIdx.x, by = blockIdx.y;
   const int x0 = bx * kBX, y0 = by * TY;
   const int tid = threadIdx.x + threadIdx.y * kBX;
-  for (int e = tid; e < HQ * WQ; e += NTH) {
+  // every load of the tile is issued (into registers) before the first LDS
+  // store, so the tile waits for one memory latency instead of one per trip
+  constexpr int UQ = (HQ * WQ + NTH - 1) / NTH, UI = (HI * WI + NTH - 1) / NTH;
+  V rq[UQ], rc[5][UI];
+#pragma unroll
+  for (int u = 0; u < UQ; ++u) {
+    const int e = tid + u * NTH;
     const int ly = e / WQ, lx = e - ly * WQ;
     const int gx = x0 - NT + lx, gy = y0 - NT + ly;
-    sq[ly][lx] = (gx >= 0 && gx < nx && gy >= 0 && gy < ny) ? qin[gx + nx * gy] : V(0);
+    rq[u] = (e < HQ * WQ && gx >= 0 && gx < nx && gy >= 0 && gy < ny) ? qin[gx + nx * gy] : V(0);
   }
-  for (int e = tid; e < HI * WI; e += NTH) {
+#pragma unroll
+  for (int u = 0; u < UI; ++u) {
+    const int e = tid + u * NTH;
     const int ly = e / WI, lx = e - ly * WI;
     const int gx = x0 - H + lx, gy = y0 - H + ly;
-    const bool in = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+    const bool in = e < HI * WI && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
     const int j = gx + nx * gy;
 #pragma unroll
-    for (int c = 0; c < 5; ++c) sc[c][ly][lx] = in ? coef[c * N + j] : V(0);
+    for (int c = 0; c < 5; ++c) rc[c][u] = in ? coef[c * N + j] : V(0);
   }
   const int gx = x0 + threadIdx.x;
   V acc[R];
@@ -164,6 +172,19 @@ __global__ __launch_bounds__(kBX * BY) void k_leja_terms(Dims d, const LejaCoef*
   for (int r = 0; r < R; ++r) {
     const int gy = y0 + threadIdx.y + BY * r;
     acc[r] = (gx < nx && gy < ny) ? p[gx + nx * gy] : V(0);
+  }
+#pragma unroll
+  for (int u = 0; u < UQ; ++u) {
+    const int e = tid + u * NTH;
+    if (e < HQ * WQ) sq[e / WQ][e % WQ] = rq[u];
+  }
+#pragma unroll
+  for (int u = 0; u < UI; ++u) {
+    const int e = tid + u * NTH;
+    if (e < HI * WI) {
+#pragma unroll
+      for (int c = 0; c < 5; ++c) sc[c][e / WI][e % WI] = rc[c][u];
+    }
   }
   if (stopped) return;  // stop test already passed
   __syncthreads();

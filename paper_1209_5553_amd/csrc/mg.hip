@@ -304,21 +304,46 @@ struct TileFacesH {
 };
 using TileFaces = TileFacesH<1>;
 
+// Faces of a tile staged through registers: fetch issues every load (a
+// fixed number per thread), store writes them to LDS, so the loads of all
+// the tile's operands are in flight together instead of one loop trip after
+// another.
 template <int H>
-__device__ inline void load_tile_faces(const MgLevelDev& L, int x0, int y0, int tid, TileFacesH<H>& F) {
-  constexpr int W = kBX + 2 * H, HH = kTY + 2 * H;
-  const int nx = L.nx, ny = L.ny;
-  for (int k = tid; k < HH * (W + 1); k += kThreads) {
-    const int ly = k / (W + 1), lx = k - ly * (W + 1);
-    const int gx = x0 - H + lx, gy = y0 - H + ly;
-    F.tx[ly][lx] = (gx >= 0 && gx <= nx && gy >= 0 && gy < ny) ? L.tx[fxi(nx, ny, gx, gy, 0)] : 0.0;
+struct FaceRegs {
+  static constexpr int W = kBX + 2 * H, HH = kTY + 2 * H;
+  static constexpr int NX = HH * (W + 1), NY = (HH + 1) * W;
+  static constexpr int UX = (NX + kThreads - 1) / kThreads, UY = (NY + kThreads - 1) / kThreads;
+  double tx[UX], ty[UY];
+  __device__ inline void fetch(const MgLevelDev& L, int x0, int y0, int tid) {
+    const int nx = L.nx, ny = L.ny;
+#pragma unroll
+    for (int u = 0; u < UX; ++u) {
+      const int k = tid + u * kThreads;
+      const int ly = k / (W + 1), lx = k - ly * (W + 1);
+      const int gx = x0 - H + lx, gy = y0 - H + ly;
+      tx[u] = (k < NX && gx >= 0 && gx <= nx && gy >= 0 && gy < ny) ? L.tx[fxi(nx, ny, gx, gy, 0)] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < UY; ++u) {
+      const int k = tid + u * kThreads;
+      const int ly = k / W, lx = k - ly * W;
+      const int gx = x0 - H + lx, gy = y0 - H + ly;
+      ty[u] = (k < NY && gx >= 0 && gx < nx && gy >= 0 && gy <= ny) ? L.ty[fyi(nx, ny, gx, gy, 0)] : 0.0;
+    }
   }
-  for (int k = tid; k < (HH + 1) * W; k += kThreads) {
-    const int ly = k / W, lx = k - ly * W;
-    const int gx = x0 - H + lx, gy = y0 - H + ly;
-    F.ty[ly][lx] = (gx >= 0 && gx < nx && gy >= 0 && gy <= ny) ? L.ty[fyi(nx, ny, gx, gy, 0)] : 0.0;
+  __device__ inline void store(TileFacesH<H>& F, int tid) const {
+#pragma unroll
+    for (int u = 0; u < UX; ++u) {
+      const int k = tid + u * kThreads;
+      if (k < NX) F.tx[k / (W + 1)][k % (W + 1)] = tx[u];
+    }
+#pragma unroll
+    for (int u = 0; u < UY; ++u) {
+      const int k = tid + u * kThreads;
+      if (k < NY) F.ty[k / W][k % W] = ty[u];
+    }
   }
-}
+};
 
 // Neighbour sum of the halo-H cell (lx, ly) at (gx, gy), values v in a
 // region whose element (sy, sx) is that cell.
@@ -395,21 +420,27 @@ __global__ __launch_bounds__(kThreads) void k_mg_down_restrict_2d(MgLevelDev F, 
   const int x0 = (tile % gridDim.x) * kBX, y0 = (tile / gridDim.x) * kTY;
   const int tid = threadIdx.x + threadIdx.y * kBX;
   const int it = cg.it;
-  for (int k = tid; k < R * W; k += kThreads) {
+  // every load of the tile is issued (into registers) before the first LDS
+  // store: the cells' b, D (and w, s) on the tile plus NU, the faces, the
+  // tile's own x, z, p
+  constexpr int U = (R * W + kThreads - 1) / kThreads;
+  double rb[U], rd[U], rw[CG ? U : 1], rs[CG ? U : 1];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int k = tid + u * kThreads;
     const int ly = k / W, lx = k - ly * W;
     const int gx = x0 - HA + lx, gy = y0 - HA + ly;
-    const bool in = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+    const bool in = k < R * W && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
     const int j = gx + nx * gy;
-    const double bj = in ? b[j] : 0.0, dj = in ? F.diag[j] : 1.0;
-    sb[ly][lx] = bj;
-    sd[ly][lx] = dj;
+    rb[u] = in ? b[j] : 0.0;
+    rd[u] = in ? F.diag[j] : 1.0;
     if (CG) {
-      sw[ly][lx] = in ? cg.w[j] : 0.0;
-      ss[ly][lx] = (in && it > 0) ? cg.s_old[j] : 0.0;
-    } else {
-      sx[0][ly][lx] = sweep_weight<NU>(0) * bj / dj;  // first sweep from zero
+      rw[u] = in ? cg.w[j] : 0.0;
+      rs[u] = (in && it > 0) ? cg.s_old[j] : 0.0;
     }
   }
+  FaceRegs<NU - 1> fr;
+  fr.fetch(F, x0, y0, tid);
   // the tile's own cells (two rows per thread) for the p and x updates
   const int ox = x0 + threadIdx.x;
   double xo[2] = {0.0, 0.0}, po[2] = {0.0, 0.0}, zo[2] = {0.0, 0.0};
@@ -424,7 +455,21 @@ __global__ __launch_bounds__(kThreads) void k_mg_down_restrict_2d(MgLevelDev F, 
       }
     }
   }
-  load_tile_faces(F, x0, y0, tid, tf);
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int k = tid + u * kThreads;
+    if (k >= R * W) continue;
+    const int ly = k / W, lx = k - ly * W;
+    sb[ly][lx] = rb[u];
+    sd[ly][lx] = rd[u];
+    if (CG) {
+      sw[ly][lx] = rw[u];
+      ss[ly][lx] = rs[u];
+    } else {
+      sx[0][ly][lx] = sweep_weight<NU>(0) * rb[u] / rd[u];  // first sweep from zero
+    }
+  }
+  fr.store(tf, tid);
   if (CG && tid < 64) {  // the first wavefront decides for the block
     int halt = stop ? 1 : 0;
     double alpha = 0.0, beta = 0.0;
@@ -549,16 +594,35 @@ __global__ __launch_bounds__(kThreads) void k_mg_up_smooth_2d(MgLevelDev F, MgLe
   const int tile = xcd_tile_id();  // 2D grid: tile = bx + gridDim.x * by
   const int x0 = (tile % gridDim.x) * kBX, y0 = (tile / gridDim.x) * kTY;
   const int tid = threadIdx.x + threadIdx.y * kBX;
-  for (int k = tid; k < R * W; k += kThreads) {
+  // every load of the tile is issued (into registers) before the first LDS store
+  constexpr int U = (R * W + kThreads - 1) / kThreads;
+  double rx[U], re[U], rb[U], rd[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int k = tid + u * kThreads;
+    const int ly = k / W, lx = k - ly * W;
+    const int gx = x0 - HU + lx, gy = y0 - HU + ly;
+    const bool in = k < R * W && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+    const int j = gx + nx * gy;
+    rx[u] = in ? xv[j] : 0.0;
+    re[u] = in ? ec[(gx >> 1) + C.nx * (gy >> 1)] : 0.0;
+    rb[u] = in ? b[j] : 0.0;
+    rd[u] = in ? F.diag[j] : 1.0;
+  }
+  FaceRegs<HU - 1> fr;
+  fr.fetch(F, x0, y0, tid);
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int k = tid + u * kThreads;
+    if (k >= R * W) continue;
     const int ly = k / W, lx = k - ly * W;
     const int gx = x0 - HU + lx, gy = y0 - HU + ly;
     const bool in = gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-    const int j = gx + nx * gy;
-    sxc[ly][lx] = in ? xv[j] + omega_c * ec[(gx >> 1) + C.nx * (gy >> 1)] : 0.0;
-    sb[ly][lx] = in ? b[j] : 0.0;
-    sd[ly][lx] = in ? F.diag[j] : 1.0;
+    sxc[ly][lx] = in ? rx[u] + omega_c * re[u] : 0.0;
+    sb[ly][lx] = rb[u];
+    sd[ly][lx] = rd[u];
   }
-  load_tile_faces(F, x0, y0, tid, tf);
+  fr.store(tf, tid);
   if (stop) return;
   __syncthreads();
 #pragma unroll
