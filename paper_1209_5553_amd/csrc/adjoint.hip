@@ -29,14 +29,37 @@ __device__ inline int fxi(const Dims& d, int x, int y) { return y * (d.nx + 1) +
 __device__ inline int fyi(const Dims& d, int x, int y) { return y * d.nx + x; }
 
 // J^T s at cell (x, y): the coefficient of each neighbour's row toward i.
+// Neighbour indices of cell i, the cell itself where the neighbour is
+// missing: every load below is in bounds and issued without a branch, and
+// the missing neighbours' terms are dropped by a select.
+struct Nbrs {
+  bool hw, he, hs, hn;
+  int w, e, s, n;
+};
+__device__ inline Nbrs nbrs(const Dims& d, int x, int y, int i) {
+  Nbrs b;
+  b.hw = x > 0;
+  b.he = x + 1 < d.nx;
+  b.hs = y > 0;
+  b.hn = y + 1 < d.ny;
+  b.w = b.hw ? i - 1 : i;
+  b.e = b.he ? i + 1 : i;
+  b.s = b.hs ? i - d.nx : i;
+  b.n = b.hn ? i + d.nx : i;
+  return b;
+}
+
 __device__ inline double jt_apply(const Dims& d, const double* __restrict__ coef, const double* __restrict__ s,
                                   int x, int y, int i) {
   const int N = d.N;
+  const Nbrs b = nbrs(d, x, y, i);
+  const double tw = coef[2 * N + b.w] * s[b.w], te = coef[N + b.e] * s[b.e];
+  const double ts = coef[4 * N + b.s] * s[b.s], tn = coef[3 * N + b.n] * s[b.n];
   double v = coef[i] * s[i];
-  if (x > 0) v += coef[2 * N + i - 1] * s[i - 1];
-  if (x + 1 < d.nx) v += coef[N + i + 1] * s[i + 1];
-  if (y > 0) v += coef[4 * N + i - d.nx] * s[i - d.nx];
-  if (y + 1 < d.ny) v += coef[3 * N + i + d.nx] * s[i + d.nx];
+  v += b.hw ? tw : 0.0;
+  v += b.he ? te : 0.0;
+  v += b.hs ? ts : 0.0;
+  v += b.hn ? tn : 0.0;
   return v;
 }
 
@@ -119,14 +142,23 @@ __global__ __launch_bounds__(kThreads) void k_adj_rev_term(Dims d, const double*
                                                  double* __restrict__ jbar, double* __restrict__ s_out) {
   CELL_INDEX
   const int N = d.N;
+  // every load first (jbar too), then the stores: the loads issue together
+  const Nbrs b = nbrs(d, x, y, i);
   const double si = s_in[i];
-  s_out[i] = yscale * ubar[i] + inv_g * jt_apply(d, coef, s_in, x, y, i) - shift_k * si;
+  const double jt = jt_apply(d, coef, s_in, x, y, i);
+  const double ub = ubar[i];
+  const double qc = q[i], qw = q[b.w], qe = q[b.e], qs = q[b.s], qn = q[b.n];
+  double jb[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) jb[k] = jbar[k * N + i];
+  s_out[i] = yscale * ub + inv_g * jt - shift_k * si;
   const double g = inv_g * si;
-  jbar[i] += g * q[i];
-  if (x > 0) jbar[N + i] += g * q[i - 1];
-  if (x + 1 < d.nx) jbar[2 * N + i] += g * q[i + 1];
-  if (y > 0) jbar[3 * N + i] += g * q[i - d.nx];
-  if (y + 1 < d.ny) jbar[4 * N + i] += g * q[i + d.nx];
+  // a missing neighbour's entry of jbar is never read; it gets 0 added
+  jbar[i] = jb[0] + g * qc;
+  jbar[N + i] = jb[1] + (b.hw ? g * qw : 0.0);
+  jbar[2 * N + i] = jb[2] + (b.he ? g * qe : 0.0);
+  jbar[3 * N + i] = jb[3] + (b.hs ? g * qs : 0.0);
+  jbar[4 * N + i] = jb[4] + (b.hn ? g * qn : 0.0);
 }
 
 __global__ __launch_bounds__(kThreads) void k_adj_substep(Dims d, const double* __restrict__ coef,
@@ -136,14 +168,25 @@ __global__ __launch_bounds__(kThreads) void k_adj_substep(Dims d, const double* 
   CELL_INDEX
   const int N = d.N;
   const double ri = r[i];
-  wbar[i] += ri;
+  const double wb = wbar[i];
   if (u) {
-    ubar[i] += jt_apply(d, coef, r, x, y, i);
-    jbar[i] += ri * u[i];
-    if (x > 0) jbar[N + i] += ri * u[i - 1];
-    if (x + 1 < d.nx) jbar[2 * N + i] += ri * u[i + 1];
-    if (y > 0) jbar[3 * N + i] += ri * u[i - d.nx];
-    if (y + 1 < d.ny) jbar[4 * N + i] += ri * u[i + d.nx];
+    // every load first (jbar too), then the stores
+    const Nbrs b = nbrs(d, x, y, i);
+    const double jt = jt_apply(d, coef, r, x, y, i);
+    const double ub = ubar[i];
+    const double uc = u[i], uw = u[b.w], ue = u[b.e], us = u[b.s], un = u[b.n];
+    double jb[5];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) jb[k] = jbar[k * N + i];
+    wbar[i] = wb + ri;
+    ubar[i] = ub + jt;
+    jbar[i] = jb[0] + ri * uc;
+    jbar[N + i] = jb[1] + (b.hw ? ri * uw : 0.0);
+    jbar[2 * N + i] = jb[2] + (b.he ? ri * ue : 0.0);
+    jbar[3 * N + i] = jb[3] + (b.hs ? ri * us : 0.0);
+    jbar[4 * N + i] = jb[4] + (b.hn ? ri * un : 0.0);
+  } else {
+    wbar[i] = wb + ri;
   }
 }
 

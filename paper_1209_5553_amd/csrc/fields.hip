@@ -169,65 +169,64 @@ __global__ __launch_bounds__(kThreads) void k_assemble(Dims d, Phys ph, const do
     const double tcb = ph.lam * ax / (0.5 * d.dx);
     const double cf = ph.c_f;
     const double Ti = T[i];
+    // every load first (the cell itself where a neighbour is missing; the
+    // face arrays hold the boundary faces), the arithmetic after
+    const int pl = d.nx * d.ny;
+    const bool hw = x > 0, he = x + 1 < d.nx, hs = y > 0, hn = y + 1 < d.ny;
+    const bool hb = d.dim == 3 && z > 0, ht = d.dim == 3 && z + 1 < d.nz;
+    const double Tw = T[hw ? i - 1 : i], Te = T[he ? i + 1 : i];
+    const double Ts = T[hs ? i - d.nx : i], Tn = T[hn ? i + d.nx : i];
+    const double Tb = T[hb ? i - pl : i], Tt = T[ht ? i + pl : i];
+    const double fw = fx[fx_idx(d, x, y, z)], fe = fx[fx_idx(d, x + 1, y, z)];
+    const double fs = fy[fy_idx(d, x, y, z)], fn = fy[fy_idx(d, x, y + 1, z)];
+    const double fb = d.dim == 3 ? fz[fz_idx(d, x, y, z)] : 0.0;
+    const double ft = d.dim == 3 ? fz[fz_idx(d, x, y, z + 1)] : 0.0;
+    const double phi = poro[i];
     double diag = 0.0, b = 0.0, R = 0.0;
     double a[7] = {0, 0, 0, 0, 0, 0, 0};
-    // -x face
-    {
-      const double f = fx[fx_idx(d, x, y, z)];  // > 0 enters the cell
-      if (x > 0) {
-        a[1] = tcx + cf * fmax(f, 0.0);
-        diag -= tcx + cf * fmax(-f, 0.0);
-        R += a[1] * T[i - 1];
-      } else {
-        if (ph.dirichlet_left) {
-          diag -= tcb;
-          b += tcb * ph.T_left;
-        }
-        if (f > 0.0) b += cf * f * ph.T_left; else diag -= cf * (-f);
+    // -x face (flux > 0 enters the cell)
+    if (hw) {
+      a[1] = tcx + cf * fmax(fw, 0.0);
+      diag -= tcx + cf * fmax(-fw, 0.0);
+      R += a[1] * Tw;
+    } else {
+      if (ph.dirichlet_left) {
+        diag -= tcb;
+        b += tcb * ph.T_left;
       }
+      if (fw > 0.0) b += cf * fw * ph.T_left; else diag -= cf * (-fw);
     }
-    // +x face
-    {
-      const double f = fx[fx_idx(d, x + 1, y, z)];  // > 0 leaves the cell
-      if (x + 1 < d.nx) {
-        a[2] = tcx + cf * fmax(-f, 0.0);
-        diag -= tcx + cf * fmax(f, 0.0);
-        R += a[2] * T[i + 1];
-      } else {
-        if (f >= 0.0) diag -= cf * f; else b += cf * (-f) * ph.T_right;
-      }
+    // +x face (flux > 0 leaves the cell)
+    if (he) {
+      a[2] = tcx + cf * fmax(-fe, 0.0);
+      diag -= tcx + cf * fmax(fe, 0.0);
+      R += a[2] * Te;
+    } else {
+      if (fe >= 0.0) diag -= cf * fe; else b += cf * (-fe) * ph.T_right;
     }
     // -y / +y faces (closed boundaries carry nothing)
-    if (y > 0) {
-      const double f = fy[fy_idx(d, x, y, z)];
-      a[3] = tcy + cf * fmax(f, 0.0);
-      diag -= tcy + cf * fmax(-f, 0.0);
-      R += a[3] * T[i - d.nx];
+    if (hs) {
+      a[3] = tcy + cf * fmax(fs, 0.0);
+      diag -= tcy + cf * fmax(-fs, 0.0);
+      R += a[3] * Ts;
     }
-    if (y + 1 < d.ny) {
-      const double f = fy[fy_idx(d, x, y + 1, z)];
-      a[4] = tcy + cf * fmax(-f, 0.0);
-      diag -= tcy + cf * fmax(f, 0.0);
-      R += a[4] * T[i + d.nx];
+    if (hn) {
+      a[4] = tcy + cf * fmax(-fn, 0.0);
+      diag -= tcy + cf * fmax(fn, 0.0);
+      R += a[4] * Tn;
     }
-    if (d.dim == 3) {
-      const int pl = d.nx * d.ny;
-      if (z > 0) {
-        const double f = fz[fz_idx(d, x, y, z)];
-        a[5] = tcz + cf * fmax(f, 0.0);
-        diag -= tcz + cf * fmax(-f, 0.0);
-        R += a[5] * T[i - pl];
-      }
-      if (z + 1 < d.nz) {
-        const double f = fz[fz_idx(d, x, y, z + 1)];
-        a[6] = tcz + cf * fmax(-f, 0.0);
-        diag -= tcz + cf * fmax(f, 0.0);
-        R += a[6] * T[i + pl];
-      }
+    if (hb) {
+      a[5] = tcz + cf * fmax(fb, 0.0);
+      diag -= tcz + cf * fmax(-fb, 0.0);
+      R += a[5] * Tb;
+    }
+    if (ht) {
+      a[6] = tcz + cf * fmax(-ft, 0.0);
+      diag -= tcz + cf * fmax(ft, 0.0);
+      R += a[6] * Tt;
     }
     R += diag * Ti + b;
     const double V = d.dx * d.dy * d.dz;
-    const double phi = poro[i];
     const double C = phi * rho_of(Ti, ph) * cf + (1.0 - phi) * ph.rhoc_s;
     const double dC = phi * drho_of(ph) * cf;
     const double inv = 1.0 / (V * C);
@@ -528,17 +527,24 @@ __global__ __launch_bounds__(kThreads) void k_dd_residual(Dims d, Phys ph, const
     const int i = x + d.nx * (y + d.ny * z);
     const int pl = d.nx * d.ny;
     const FaceT f = load_faces(d, tx, ty, tz, x, y, z);
+    // neighbour pressures first (the cell itself where a neighbour is
+    // missing), so that every load issues before the arithmetic
+    const bool hw = x > 0, he = x + 1 < d.nx, hs = y > 0, hn = y + 1 < d.ny, hb = z > 0, ht = z + 1 < d.nz;
+    const int iw = hw ? i - 1 : i, ie = he ? i + 1 : i, is = hs ? i - d.nx : i, in = hn ? i + d.nx : i;
+    const int ib = hb ? i - pl : i, it = ht ? i + pl : i;
     const DD pi{phi[i], plo[i]};
+    const DD pw{phi[iw], plo[iw]}, pe{phi[ie], plo[ie]}, ps{phi[is], plo[is]}, pn{phi[in], plo[in]};
+    const DD pb{phi[ib], plo[ib]}, pt{phi[it], plo[it]};
     DD acc{0.0, 0.0};  // sum t (p_i - p_nb)
     double bi = 0.0;
-    if (x > 0) acc = dd_add(acc, dd_mul(dd_sub(pi, DD{phi[i - 1], plo[i - 1]}), f.w));
-    else { acc = dd_add(acc, dd_mul(dd_sub(pi, DD{ph.p_left, 0.0}), f.w)); bi += f.w * ph.p_left; }
-    if (x + 1 < d.nx) acc = dd_add(acc, dd_mul(dd_sub(pi, DD{phi[i + 1], plo[i + 1]}), f.e));
-    else { acc = dd_add(acc, dd_mul(dd_sub(pi, DD{ph.p_right, 0.0}), f.e)); bi += f.e * ph.p_right; }
-    if (y > 0) acc = dd_add(acc, dd_mul(dd_sub(pi, DD{phi[i - d.nx], plo[i - d.nx]}), f.s));
-    if (y + 1 < d.ny) acc = dd_add(acc, dd_mul(dd_sub(pi, DD{phi[i + d.nx], plo[i + d.nx]}), f.n));
-    if (z > 0) acc = dd_add(acc, dd_mul(dd_sub(pi, DD{phi[i - pl], plo[i - pl]}), f.b));
-    if (z + 1 < d.nz) acc = dd_add(acc, dd_mul(dd_sub(pi, DD{phi[i + pl], plo[i + pl]}), f.t));
+    acc = dd_add(acc, dd_mul(dd_sub(pi, hw ? pw : DD{ph.p_left, 0.0}), f.w));
+    if (!hw) bi += f.w * ph.p_left;
+    acc = dd_add(acc, dd_mul(dd_sub(pi, he ? pe : DD{ph.p_right, 0.0}), f.e));
+    if (!he) bi += f.e * ph.p_right;
+    if (hs) acc = dd_add(acc, dd_mul(dd_sub(pi, ps), f.s));
+    if (hn) acc = dd_add(acc, dd_mul(dd_sub(pi, pn), f.n));
+    if (hb) acc = dd_add(acc, dd_mul(dd_sub(pi, pb), f.b));
+    if (ht) acc = dd_add(acc, dd_mul(dd_sub(pi, pt), f.t));
     // residual of sum t (p_i - p_nb) = 0 with Dirichlet neighbours folded in
     const double ri = -(acc.hi + acc.lo);
     r[i] = ri;
