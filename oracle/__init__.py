@@ -14,8 +14,10 @@ physics : water laws, TPFA transmissibilities, steady pressure, face fluxes,
           upwind heat operator, G(T) and its Jacobian J (Sec. 2, Sec. 3.1).
 phi     : phi1 scalar, dense exponential by Taylor scaling-and-squaring,
           phi1 action by the augmented-matrix exponential (tier A) and by a
-          substepped Taylor action (tier B) (Sec. 3.2.2, Sec. 4).
-erem    : the EREM step and the coupled sequential step (Eq. EERM, Sec. 3.2.2).
+          substepped Taylor action (tier B) (Sec. 3.2.2, Sec. 4); phi2 and
+          the non-autonomous increment in the same two tiers (Sec. 3.2.3).
+erem    : the EREM step and the coupled sequential step (Eq. EERM, Sec. 3.2.2);
+          the non-autonomous EREM step (Eq. nEERMg, Sec. 3.2.3).
 adjoint : dense reverse-mode sensitivities of the EREM step map.
 
 Parity status of each function is stated in its docstring; none is unpinned

@@ -16,6 +16,8 @@ resulting face fluxes frozen.
 """
 from __future__ import annotations
 
+import copy
+
 import numpy as np
 
 from . import physics as ph
@@ -96,3 +98,65 @@ def run_coupled(problem, nsteps=None, h=None, tier: str = "dense"):
     for _ in range(nsteps):
         T, _ = coupled_step(problem, T, h, tier)
     return T
+
+
+# --------------------------------------------------------------------------
+# Non-autonomous EREM (Sec. 3.2.3, Eq. nEERMg)
+# --------------------------------------------------------------------------
+
+def _at_boundary(problem, T_left, T_right):
+    """A copy of the problem record with the boundary temperatures replaced."""
+    q = copy.copy(problem)
+    q.T_left = float(T_left)
+    q.T_right = float(T_right)
+    return q
+
+
+def time_derivative(disc: Discretisation, T, dT_left, dT_right):
+    """D_t G(T, t) when the boundary temperatures move at the rates dT_left,
+    dT_right.  R(T, t) = A T + b(t) and b is linear and homogeneous in
+    (T_left, T_right) (Sec. 3.1 boundary fluxes), so D_t b is the boundary
+    vector assembled with the rates in place of the temperatures, and
+    D_t G = D_t b / (V C(T)) (the capacity does not depend on t)."""
+    prob = disc.prob
+    _, bt = ph.heat_operator(disc.fluxes, disc.g, prob.lam, prob.c_f, dT_left, dT_right,
+                             getattr(prob, "dirichlet_left", True))
+    return bt / (disc.g.volume * disc.model.capacity(np.asarray(T, dtype=np.float64)))
+
+
+def nonautonomous_step(problem, T, h, T_left, T_right, dT_left, dT_right, fluxes,
+                       tier: str = "dense"):
+    """One step of Eq. nEERMg for the frozen-flux heat model whose boundary
+    temperatures at t_n are (T_left, T_right), moving at (dT_left, dT_right):
+
+        T^{n+1} = T^n + h phi1(h J) G(T^n, t_n) + h^2 phi2(h J) D_t G(T^n, t_n),
+        J = D_T G(T^n, t_n).
+    """
+    T = np.asarray(T, dtype=np.float64)
+    disc = Discretisation(_at_boundary(problem, T_left, T_right), T, fluxes=fluxes)
+    model = disc.model
+    G = model.G(T)
+    Gt = time_derivative(disc, T, dT_left, dT_right)
+    if tier == "dense":
+        inc = phimod.nonautonomous_action_dense(model.J(T), G, Gt, h)
+    else:
+        inc = phimod.nonautonomous_action_taylor(model.J_sparse(T), G, Gt, h)
+    return T + inc
+
+
+def run_nonautonomous(problem, schedule, nsteps=None, h=None, t0: float = 0.0,
+                      tier: str = "dense", fluxes=None):
+    """Steps of Eq. nEERMg from problem.T0 at t0; ``schedule(t)`` returns
+    (T_left, T_right, dT_left/dt, dT_right/dt) at time t.  The face fluxes are
+    those of the pressure solved once at T0 (as in run_linear) unless given."""
+    nsteps = problem.nsteps if nsteps is None else nsteps
+    h = problem.h if h is None else h
+    T = np.asarray(problem.T0, dtype=np.float64).copy()
+    if fluxes is None:
+        fluxes = Discretisation(problem, T).fluxes
+    t = t0
+    for _ in range(nsteps):
+        Tl, Tr, dTl, dTr = schedule(t)
+        T = nonautonomous_step(problem, T, h, Tl, Tr, dTl, dTr, fluxes, tier)
+        t += h
+    return T, fluxes

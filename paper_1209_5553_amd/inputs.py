@@ -173,6 +173,41 @@ def adjoint_problem(n: int = 256, seed: int = 0, nsteps: int = 20, structured_T0
                    nsteps=nsteps)
 
 
+def injector_problem(n: int = 512, seed: int = 0, nsteps: int = 20,
+                     name: str | None = None) -> Problem:
+    """2D n x n heat transport with a fixed Darcy field and a time-varying
+    injection temperature (the non-autonomous workload): the permeability of
+    the coupled workload (sigma_logK = 2, correlation 16 cells, same seed),
+    constant fluid laws, the coupled pressure drop (Peclet ~ 100); the
+    injection temperature follows InjectorSchedule()."""
+    rng = np.random.default_rng(seed)
+    logk = lognormal_field(rng, (n, n), 2.0, 16.0)
+    N = n * n
+    return Problem(name=name or f"injector2d_{n}", nx=n, ny=n, nz=1, logk=logk,
+                   poro=_uniform(N, POROSITY), T0=_uniform(N, T_INITIAL),
+                   law=LAW_CONSTANT, p_left=DP_COUPLED, nsteps=nsteps)
+
+
+@dataclasses.dataclass(frozen=True)
+class InjectorSchedule:
+    """Boundary temperatures at time t for the non-autonomous problems and
+    their exact time derivatives: the injected temperature
+    T_left(t) = mean + swing sin(2 pi t / period) + ramp t (20 C to 80 C over
+    a period of 20 steps by default), T_right constant.  Calling it returns
+    (T_left, T_right, dT_left/dt, dT_right/dt)."""
+    mean: float = 50.0
+    swing: float = 30.0
+    period: float = 20 * STEP_H
+    ramp: float = 0.0
+    T_right: float = T_INITIAL
+
+    def __call__(self, t: float):
+        w = 2.0 * np.pi / self.period
+        Tl = self.mean + self.swing * np.sin(w * t) + self.ramp * t
+        dTl = self.swing * w * np.cos(w * t) + self.ramp
+        return float(Tl), float(self.T_right), float(dTl), 0.0
+
+
 def producer_ring(nx: int, ny: int, block: int = 4, ring: int = 2):
     """Flat indices of the producer block and ``ring`` cells around it
     (inside the grid), for checks of d/dT0 where it is not negligible."""
