@@ -74,6 +74,12 @@ def make_workload(name):
         prob = inputs.linear_problem(32)
         desc = "linear 2D 32x32 heat transport, fixed Darcy field, EREM-Leja, h=1e6 s"
         return prob, desc, False
+    if name == "injector512":
+        prob = inputs.injector_problem(512)
+        desc = ("non-autonomous 2D 512x512 heat transport, fixed Darcy field (sigma_logK=2, corr 16, "
+                "Pe~100), injection temperature 50+30 sin(2 pi t / 20h) C: EREM-Leja with the phi2 "
+                "term (Eq. nEERMg), h=1e6 s")
+        return prob, desc, False
     if name == "layered128":
         prob = inputs.layered3d_problem(128)
         desc = "linear 3D 128^3 7-point heat transport, layered K (3 decades), EREM-Leja, h=1e6 s"
@@ -81,7 +87,13 @@ def make_workload(name):
     raise SystemExit(f"unknown workload {name}")
 
 
-def gpu_run(prob, coupled, steps, warmup, rtol_p, mixed=False):
+def schedule_of(name):
+    """Boundary schedule of a non-autonomous workload, else None."""
+    from paper_1209_5553_amd import inputs
+    return inputs.InjectorSchedule() if name == "injector512" else None
+
+
+def gpu_run(prob, coupled, steps, warmup, rtol_p, mixed=False, sched=None):
     import torch
     from paper_1209_5553_amd.api import EremContext, make_opts
 
@@ -101,7 +113,11 @@ def gpu_run(prob, coupled, steps, warmup, rtol_p, mixed=False):
             # step each solve starts from the previous double-double pressure
             sp = ctx.pressure_and_fluxes(T, rtol=rtol_p, p=p if state["n"] == 0 else None, warm=state["n"] > 0)
             state["pcg"] += sp["iterations"]
-        state["last"] = ctx.step(prob.h, T, opts)
+        if sched is not None:
+            # boundary temperatures and their rates at t_n = n h
+            state["last"] = ctx.step_nonautonomous(prob.h, T, *sched(state["n"] * prob.h), opts)
+        else:
+            state["last"] = ctx.step(prob.h, T, opts)
         state["n"] += 1
 
     snapshots = {}
@@ -129,7 +145,7 @@ def gpu_run(prob, coupled, steps, warmup, rtol_p, mixed=False):
                 T_final=T.cpu().numpy())
 
 
-def cpu_baseline(prob, coupled, nsteps, gpu_snaps):
+def cpu_baseline(prob, coupled, nsteps, gpu_snaps, sched=None):
     """The oracle as it stands, on a bounded sample: the first `nsteps` steps
     of the same workload (tier-B sparse action; SuperLU pressure with extended-precision refinement)."""
     from threadpoolctl import threadpool_limits
@@ -141,6 +157,8 @@ def cpu_baseline(prob, coupled, nsteps, gpu_snaps):
         if coupled:
             for _ in range(nsteps):
                 T, _ = oerem.coupled_step(prob, T, tier="taylor")
+        elif sched is not None:
+            T, _ = oerem.run_nonautonomous(prob, sched, nsteps=nsteps, tier="taylor")
         else:
             tier = "dense" if prob.n <= 4096 else "taylor"
             layered = prob.nz > 1
@@ -149,7 +167,7 @@ def cpu_baseline(prob, coupled, nsteps, gpu_snaps):
     out = {"value": nsteps / (t1 - t0), "unit": "steps/s", "cores": 1, "kind": "oracle",
            "sample": f"first {nsteps} steps of the same workload from T0 "
                      f"({'SuperLU pressure refined in extended precision + ' if coupled else ''}substepped Taylor action of the "
-                     f"augmented exponential, FP64, 1 thread)",
+                     f"augmented exponential{' with the two extra rows of the phi2 term' if sched else ''}, FP64, 1 thread)",
            "seconds": t1 - t0}
     if nsteps in gpu_snaps:
         Tg = gpu_snaps[nsteps]
@@ -365,7 +383,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="coupled512",
-                    choices=["coupled512", "linear32", "layered128", "batch256", "adjoint256"])
+                    choices=["coupled512", "linear32", "layered128", "injector512", "batch256", "adjoint256"])
     ap.add_argument("--adjoint-start", default="uniform", choices=["uniform", "structured"])
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -390,7 +408,8 @@ def main():
 
     prob, desc, coupled = make_workload(args.workload)
     log(f"workload {args.workload}: {desc}; N={prob.n}")
-    res = gpu_run(prob, coupled, args.steps, args.warmup, args.pressure_rtol, mixed=mixed)
+    sched = schedule_of(args.workload)
+    res = gpu_run(prob, coupled, args.steps, args.warmup, args.pressure_rtol, mixed=mixed, sched=sched)
     dim = prob.dim
     N = prob.n
     t = res["times"]
@@ -424,7 +443,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         log(f"cpu baseline: {args.cpu_steps} oracle step(s)")
-        line["cpu_baseline"] = cpu_baseline(prob, coupled, args.cpu_steps, res["snapshots"])
+        line["cpu_baseline"] = cpu_baseline(prob, coupled, args.cpu_steps, res["snapshots"], sched)
     print(json.dumps(line), flush=True)
 
 

@@ -196,6 +196,25 @@ int erem_step(erem_ctx* ctx, double h, double* d_T, const erem_opts* opts, erem_
 int erem_step_frozen(erem_ctx* ctx, double h, double* d_T, const erem_opts* opts,
                      erem_stats* stats);
 
+/* One step of the non-autonomous EREM scheme (Sec. 3.2.3, Eq. nEERMg) in
+ * place, for boundary temperatures that change in time: T_left on x = 0 and
+ * T_right on x = nx (the values at t_n), changing at the rates dT_left_dt and
+ * dT_right_dt [K/s] at t_n.  Sets the context's boundary temperatures to
+ * T_left and T_right (they stay so), forms J and G at d_T with the current
+ * fluxes, D_t G (b is linear in the boundary temperatures, so D_t G is the
+ * boundary vector with the rates in their place, over V C(T)), and sets
+ *   d_T <- d_T + h phi1(h J) G + h^2 phi2(h J) D_t G.
+ * With s substeps of delta = h / s (the rule of erem_step) it integrates
+ * u' = J u + G + t D_t G exactly up to the tolerance:
+ *   u <- u + delta phi1(delta J) (G + t_j D_t G + J u) + delta^2 phi2(delta J) D_t G,
+ * the last term one Newton-Leja pass with the divided differences of phi2,
+ * computed once per step.  Leja method only (EREM_EINVAL for Krylov);
+ * EREM_EINVAL for non-finite temperatures or rates.  stats->m_total counts
+ * the Newton terms of every pass, the phi2 pass included. */
+int erem_step_nonautonomous(erem_ctx* ctx, double h, double T_left, double T_right,
+                            double dT_left_dt, double dT_right_dt, double* d_T,
+                            const erem_opts* opts, erem_stats* stats);
+
 /* ---- sequential coupled step and its adjoint (2D grids) ----
  *
  * The coupled step of Sec. 3.2.2 (pressure first, then temperature): TPFA
@@ -336,6 +355,13 @@ int erem_leja_points(int32_t n, double* out);
  * (diagonal xi, subdiagonal 1) (Sec. 4.2), through the exponential of the
  * augmented lower-bidiagonal matrix by Taylor scaling-and-squaring. */
 int erem_phi1_divided_differences(double hc, double hg, const double* xi, int32_t n,
+                                  double* out);
+
+/* The same for g(xi) = phi2(hc + hg xi), phi2(z) = (e^z - 1 - z) / z^2
+ * (Sec. 3.2.3): the first column of phi2(hc I + hg L), read off the
+ * exponential of the bidiagonal matrix augmented by two leading rows and
+ * columns.  Same argument rules as erem_phi1_divided_differences. */
+int erem_phi2_divided_differences(double hc, double hg, const double* xi, int32_t n,
                                   double* out);
 
 #ifdef __cplusplus

@@ -98,6 +98,8 @@ SIGNATURES = {
     "erem_phi1_apply": (c_int32, [_P, c_double, _P, _P, POINTER(Opts), POINTER(Stats)]),
     "erem_step": (c_int32, [_P, c_double, _P, POINTER(Opts), POINTER(Stats)]),
     "erem_step_frozen": (c_int32, [_P, c_double, _P, POINTER(Opts), POINTER(Stats)]),
+    "erem_step_nonautonomous": (c_int32, [_P, c_double, c_double, c_double, c_double, c_double, _P,
+                                          POINTER(Opts), POINTER(Stats)]),
     "erem_coupled_step": (c_int32, [_P, c_double, _P, c_double, POINTER(Opts), POINTER(Tape),
                                     POINTER(Tape), POINTER(Stats)]),
     "erem_coupled_step_adjoint": (c_int32, [_P, c_double, _P, c_double, POINTER(Opts), POINTER(Tape),
@@ -116,6 +118,7 @@ SIGNATURES = {
     "erem_profile_read": (c_int32, [_P, POINTER(KernelTimes)]),
     "erem_leja_points": (c_int32, [c_int32, _PD]),
     "erem_phi1_divided_differences": (c_int32, [c_double, c_double, _PD, c_int32, _PD]),
+    "erem_phi2_divided_differences": (c_int32, [c_double, c_double, _PD, c_int32, _PD]),
 }
 
 _lib = None

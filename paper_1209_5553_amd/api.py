@@ -49,6 +49,16 @@ def phi1_divided_differences(hc: float, hg: float, xi) -> np.ndarray:
     return out
 
 
+def phi2_divided_differences(hc: float, hg: float, xi) -> np.ndarray:
+    xi = np.ascontiguousarray(xi, dtype=np.float64)
+    out = np.zeros(xi.size, dtype=np.float64)
+    rc = nat.load().erem_phi2_divided_differences(hc, hg, xi.ctypes.data_as(nat._PD), xi.size,
+                                                  out.ctypes.data_as(nat._PD))
+    if rc != 0:
+        raise EremError(rc, "erem_phi2_divided_differences")
+    return out
+
+
 class EremContext:
     """One grid's EREM state on one HIP device (see include/erem.h)."""
 
@@ -190,6 +200,18 @@ class EremContext:
         st = nat.Stats()
         self._check(self.lib.erem_step(self.handle, h, self._ptr(T, self.n, "T"), ctypes.byref(o),
                                        ctypes.byref(st)), "erem_step")
+        return st.as_dict()
+
+    def step_nonautonomous(self, h: float, T, T_left: float, T_right: float, dT_left_dt: float,
+                           dT_right_dt: float, opts: nat.Opts | None = None):
+        """One non-autonomous EREM step in place on T
+        (erem_step_nonautonomous): boundary temperatures at t_n and their
+        rates; the context keeps T_left and T_right afterwards."""
+        o = opts if opts is not None else make_opts()
+        st = nat.Stats()
+        self._check(self.lib.erem_step_nonautonomous(
+            self.handle, h, T_left, T_right, dT_left_dt, dT_right_dt, self._ptr(T, self.n, "T"),
+            ctypes.byref(o), ctypes.byref(st)), "erem_step_nonautonomous")
         return st.as_dict()
 
     def coupled_step(self, h: float, T, p_rtol: float = 1e-16, opts: nat.Opts | None = None,

@@ -31,6 +31,8 @@ struct erem_ctx {
   double *tx = nullptr, *ty = nullptr, *tz = nullptr;
   double *fx = nullptr, *fy = nullptr, *fz = nullptr;
   double *coef = nullptr, *F = nullptr;
+  // non-autonomous step: D_t G and the phi2 term (allocated on first use)
+  double *gt = nullptr, *zt = nullptr;
   double *qa = nullptr, *qb = nullptr, *pacc = nullptr, *u = nullptr, *w = nullptr;
   double *pres = nullptr, *pr = nullptr, *pr2 = nullptr, *pz = nullptr, *pp0 = nullptr, *pp1 = nullptr;
   double *pw = nullptr, *ps0 = nullptr, *ps1 = nullptr;  // Chronopoulos-Gear w = A z and s
@@ -59,7 +61,7 @@ struct erem_ctx {
   erem::PcgState* h_pcg = nullptr;
 
   std::vector<double> xi;  // Leja points
-  DivDiffCache dd;
+  DivDiffCache dd, dd2;  // phi1 and phi2 divided differences
   int last_m = 0;          // degree used by the previous evaluation
   // profiling (HIP events around each Leja term and PCG half-iteration)
   int pcg_last = 0;  // iterations of the last converged CG solve (poll placement)
@@ -115,7 +117,7 @@ int ensure_events(erem_ctx* c, size_t n);  // event pool of at least n events (p
 double elapsed_ms(hipEvent_t a, hipEvent_t b);
 int ndir(const erem_ctx* c);
 int read_reduce(erem_ctx* c);
-const std::vector<double>& divided_differences(erem_ctx* c, double hc, double hg, int n);
+const std::vector<double>& divided_differences(erem_ctx* c, double hc, double hg, int n, int ell = 1);
 // x <- A^{-1} b for the TPFA pressure matrix A (Dirichlet x faces folded into
 // the diagonal, no right-hand side from the boundary values): conjugate
 // gradients with the context's preconditioner, refined in FP64 until

@@ -89,8 +89,13 @@ hipError_t launch_assemble(const Dims& d, const Phys& ph, const double* poro, co
                            double* F, AsmReduce* red, hipStream_t s);
 hipError_t launch_absmax(const Dims& d, const double* v, AsmReduce* red, hipStream_t s);
 hipError_t launch_gershgorin(const Dims& d, const double* coef, AsmReduce* red, hipStream_t s);
+// w = v + tg g + J u (g null: w = v + J u)
 hipError_t launch_stencil_axpy(const Dims& d, const double* coef, const double* v,
-                               const double* u, double* w, hipStream_t s);
+                               const double* u, double* w, hipStream_t s,
+                               const double* g = nullptr, double tg = 0.0);
+// Gt = D_t G for boundary temperature rates dTl (x = 0) and dTr (x = nx)
+hipError_t launch_time_rate(const Dims& d, const Phys& ph, const double* poro, const double* fx,
+                            const double* T, double dTl, double dTr, double* Gt, hipStream_t s);
 hipError_t launch_axpby(const Dims& d, double* y, double a, const double* x, double b,
                         hipStream_t s);
 hipError_t launch_pcg_reset(PcgState* st, double tol2, hipStream_t s);

@@ -71,7 +71,7 @@ void free_all(erem_ctx* c) {
   double** bufs[] = {&c->logk, &c->poro, &c->tx, &c->ty, &c->tz, &c->fx, &c->fy, &c->fz,
                      &c->coef, &c->F, &c->qa, &c->qb, &c->pacc, &c->u, &c->w, &c->pres,
                      &c->pr, &c->pr2, &c->pw, &c->ps0, &c->ps1, &c->pz, &c->pp0, &c->pp1, &c->pq, &c->pdiag,
-                     &c->pres_lo, &c->pdelta, &c->prhs, &c->part};
+                     &c->pres_lo, &c->pdelta, &c->prhs, &c->part, &c->gt, &c->zt};
   for (double** b : bufs)
     if (*b) { (void)hipFree(*b); *b = nullptr; }
   if (c->cf) (void)hipFree(c->cf);
@@ -235,12 +235,13 @@ int build_mg(erem_ctx* c) {
   return EREM_OK;
 }
 
-// Divided differences for (hc, hg) with at least n coefficients (cached).
-const std::vector<double>& divided_differences(erem_ctx* c, double hc, double hg, int n) {
-  DivDiffCache& dd = c->dd;
+// Divided differences of phi_ell (ell = 1, 2) for (hc, hg) with at least n
+// coefficients (cached per ell).
+const std::vector<double>& divided_differences(erem_ctx* c, double hc, double hg, int n, int ell) {
+  DivDiffCache& dd = ell == 2 ? c->dd2 : c->dd;
   if (!(dd.hc == hc && dd.hg == hg && dd.n >= n)) {
     dd.d.assign(n, 0.0);
-    phi1_divided_differences(hc, hg, c->xi.data(), n, dd.d.data());
+    phi_divided_differences(ell, hc, hg, c->xi.data(), n, dd.d.data());
     dd.hc = hc;
     dd.hg = hg;
     dd.n = n;
@@ -294,18 +295,32 @@ int leja_terms_per_launch(const Dims& d, int k, int K) {
   return k + 1 <= K ? 2 : 1;
 }
 
+// One Newton-Leja evaluation over s substeps: its coefficient block, its s
+// stop-state slots, the vector that accumulates the substep increments and,
+// for the non-autonomous step, the time source g and the fixed phi2 term zt.
+struct LejaPass {
+  const LejaCoef* cf;
+  LejaState* states;
+  double* out;
+  const double* g;   // source of substep j is v + (j delta) g + J u_j; null: v + J u_j
+  const double* zt;  // added to out after every substep; null: nothing
+  hipEvent_t* ev;    // 2 K events per timed substep (the first nprof), or null
+  int nprof;
+};
+
 template <class V>
-int leja_run(erem_ctx* c, const LejaBufs<V>& B, const double* v, double delta, int s, int K, int nprof) {
+int leja_run(erem_ctx* c, const LejaBufs<V>& B, const LejaPass& P, const double* v, double delta, int s,
+             int K) {
   const Dims& d = c->d;
   for (int j = 0; j < s; ++j) {
-    LejaState* st = c->states + j;
+    LejaState* st = P.states + j;
     const double* src = v;
     if (j > 0) {
-      HIP_TRY(c, launch_stencil_axpy(d, c->coef, v, c->u, c->w, c->stream));
+      HIP_TRY(c, launch_stencil_axpy(d, c->coef, v, P.out, c->w, c->stream, P.g, j * delta));
       src = c->w;
     }
-    HIP_TRY(c, launch_leja_init<V>(d, c->cf, src, B.qa, B.p, c->part, c->stream));
-    hipEvent_t* evj = j < nprof ? &c->ev[static_cast<size_t>(j) * 2 * K] : nullptr;
+    HIP_TRY(c, launch_leja_init<V>(d, P.cf, src, B.qa, B.p, c->part, c->stream));
+    hipEvent_t* evj = j < P.nprof ? &P.ev[static_cast<size_t>(j) * 2 * K] : nullptr;
     int prev = -1;  // last term already checked
     V* cur = B.qa;  // latest q
     V* oth = B.qb;
@@ -316,20 +331,35 @@ int leja_run(erem_ctx* c, const LejaBufs<V>& B, const double* v, double delta, i
       const bool timed = evj && launch % c->prof == 0;
       hipEvent_t e0 = timed ? evj[2 * (k - 1)] : nullptr, e1 = timed ? evj[2 * (k - 1) + 1] : nullptr;
       if (nt > 1)
-        HIP_TRY(c, launch_leja_terms<V>(d, c->cf, B.coef, cur, oth, B.p, st, c->part, k, nt, c->stream, e0, e1));
+        HIP_TRY(c, launch_leja_terms<V>(d, P.cf, B.coef, cur, oth, B.p, st, c->part, k, nt, c->stream, e0, e1));
       else
-        HIP_TRY(c, launch_leja_term<V>(d, c->cf, B.coef, cur, oth, B.p, st, c->part, k, c->stream, e0, e1));
+        HIP_TRY(c, launch_leja_term<V>(d, P.cf, B.coef, cur, oth, B.p, st, c->part, k, c->stream, e0, e1));
       std::swap(cur, oth);
       k += nt;
       const int last = k - 1;
       if (last % kCheckEvery == 0 || last == K) {
-        HIP_TRY(c, launch_leja_check(d, c->cf, st, c->part, prev + 1, last, c->stream));
+        HIP_TRY(c, launch_leja_check(d, P.cf, st, c->part, prev + 1, last, c->stream));
         prev = last;
       }
     }
-    HIP_TRY(c, launch_substep_update<V>(d, c->u, B.p, delta, j == 0 ? 1 : 0, c->stream));
+    HIP_TRY(c, launch_substep_update<V>(d, P.out, B.p, delta, j == 0 ? 1 : 0, c->stream, P.zt));
   }
   return EREM_OK;
+}
+
+// Newton coefficients of one pass: the divided differences dv of
+// phi_ell(delta (c + gamma xi)), the shifts c/gamma + xi_{k-1}, and the
+// stop-test factors |w dv_k| / (sqrt(N) scal), w the weight of the pass's
+// polynomial in the increment (delta for phi1, delta^2 for phi2).
+void fill_coef(LejaCoef* hc, const std::vector<double>& dv, int n, double cc, double gg, double w,
+               const std::vector<double>& xi, double rootN, double scal, int p_order) {
+  hc->inv_g = 1.0 / gg;
+  hc->thresh = std::pow(10.0, -p_order);
+  for (int k = 0; k < n; ++k) {
+    hc->dk[k] = dv[k];
+    hc->shift[k] = (k > 0) ? cc / gg + xi[k - 1] : 0.0;
+    hc->estf[k] = std::fabs(w * dv[k]) / (rootN * scal);
+  }
 }
 
 // u <- h phi1(h J) v by s Leja substeps of delta = h/s, each an exact
@@ -337,43 +367,52 @@ int leja_run(erem_ctx* c, const LejaBufs<V>& B, const double* v, double delta, i
 //   u_{j+1} = u_j + delta phi1(delta J) (v + J u_j)   (Sec. 4.2 splitting).
 // Returns EREM_OK, EREM_ENOCONV (some substep did not stop within K terms)
 // or an error.  `m_used` receives the summed degree actually applied.
-int leja_hphi1(erem_ctx* c, double h, const double* v, double scal, int s, int K,
+int leja_hphi1(erem_ctx* c, double h, const double* v, const double* g, double scal, int s, int K,
                const erem_opts* o, int* m_used, double* est_last) {
   const double a = c->alpha, b = c->beta;
   const double cc = 0.5 * (a + b);
   const double gg = 0.25 * (b - a);
   const double delta = h / s;
   const int n = K + 1;
-  const std::vector<double>& dv = divided_differences(c, delta * cc, delta * gg, n);
-  LejaCoef* hc = c->h_cf;
-  hc->inv_g = 1.0 / gg;
-  hc->thresh = std::pow(10.0, -o->p_order);
+  const bool na = g != nullptr;  // non-autonomous: one phi2 pass first, in slot s
+  const int npass = s + (na ? 1 : 0);
   const double rootN = std::sqrt(static_cast<double>(c->d.N));
-  for (int k = 0; k < n; ++k) {
-    hc->dk[k] = dv[k];
-    hc->shift[k] = (k > 0) ? cc / gg + c->xi[k - 1] : 0.0;
-    hc->estf[k] = std::fabs(delta * dv[k]) / (rootN * scal);
-  }
+  fill_coef(c->h_cf, divided_differences(c, delta * cc, delta * gg, n, 1), n, cc, gg, delta, c->xi, rootN,
+            scal, o->p_order);
+  if (na)
+    fill_coef(c->h_cf + 1, divided_differences(c, delta * cc, delta * gg, n, 2), n, cc, gg, delta * delta,
+              c->xi, rootN, scal, o->p_order);
   const size_t cf_bytes = offsetof(LejaCoef, shift) + 3 * sizeof(double) * (kMaxTerms + 1);
-  HIP_TRY(c, hipMemcpyAsync(c->cf, hc, cf_bytes, hipMemcpyHostToDevice, c->stream));
-  HIP_TRY(c, launch_leja_reset(c->states, s, K, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->cf, c->h_cf, na ? 2 * sizeof(LejaCoef) : cf_bytes, hipMemcpyHostToDevice,
+                            c->stream));
+  HIP_TRY(c, launch_leja_reset(c->states, npass, K, c->stream));
   const int nprof = c->prof ? std::min(s, kProfSubsteps) : 0;
-  if (nprof) {
-    const int rc = ensure_events(c, static_cast<size_t>(nprof) * 2 * K);
+  if (c->prof) {
+    const int rc = ensure_events(c, static_cast<size_t>(nprof + 1) * 2 * K);
     if (rc) return rc;
   }
+  hipEvent_t* ev = c->prof ? c->ev.data() : nullptr;
+  // phi2 pass: zt = delta^2 phi2(delta J) g, the same vector on every
+  // substep; then the phi1 substeps with the time source and zt added
+  const LejaPass p2{c->cf + 1, c->states + s, c->zt, nullptr, nullptr, ev ? ev + static_cast<size_t>(nprof) * 2 * K : nullptr,
+                    c->prof ? 1 : 0};
+  const LejaPass p1{c->cf, c->states, c->u, g, na ? c->zt : nullptr, ev, nprof};
   int rc;
   if (o->precision == EREM_PREC_MIXED) {
     rc = ensure_mixed(c);
     if (rc) return rc;
-    rc = leja_run<float>(c, LejaBufs<float>{c->coef32, c->qa32, c->qb32, c->p32}, v, delta, s, K, nprof);
+    const LejaBufs<float> B{c->coef32, c->qa32, c->qb32, c->p32};
+    if (na) rc = leja_run<float>(c, B, p2, g, delta * delta, 1, K);
+    if (!rc) rc = leja_run<float>(c, B, p1, v, delta, s, K);
   } else {
-    rc = leja_run<double>(c, LejaBufs<double>{c->coef, c->qa, c->qb, c->pacc}, v, delta, s, K, nprof);
+    const LejaBufs<double> B{c->coef, c->qa, c->qb, c->pacc};
+    if (na) rc = leja_run<double>(c, B, p2, g, delta * delta, 1, K);
+    if (!rc) rc = leja_run<double>(c, B, p1, v, delta, s, K);
   }
   if (rc) return rc;
-  // Read the stop state of every substep.
+  // Read the stop state of every pass.
   const size_t hdr = offsetof(LejaState, sums);
-  for (int j = 0; j < s; ++j)
+  for (int j = 0; j < npass; ++j)
     HIP_TRY(c, hipMemcpyAsync(reinterpret_cast<char*>(c->h_states + j),
                               reinterpret_cast<const char*>(c->states + j),
                               hdr + sizeof(double) * (K + 1), hipMemcpyDeviceToHost, c->stream));
@@ -381,18 +420,23 @@ int leja_hphi1(erem_ctx* c, double h, const double* v, double scal, int s, int K
   int total = 0;
   double last = 0.0;
   c->applied.assign(s, 0);
-  for (int j = 0; j < s; ++j) {
+  for (int j = 0; j < npass; ++j) {
     const LejaState& st = c->h_states[j];
     if (st.nonfinite) return fail(c, EREM_ENONFINITE, "non-finite Leja term norm");
     if (st.stopped < 0) return EREM_ENOCONV;
     // the stop test ran after every kCheckEvery terms: the terms up to the
     // end of the group in which it passed were applied
     const int applied = std::min(K, ((st.stopped + kCheckEvery - 1) / kCheckEvery) * kCheckEvery);
-    c->applied[j] = applied;
     total += applied;
-    last = hc->estf[st.stopped] * std::sqrt(st.sums[st.stopped]);
-    if (j < nprof) {
-      const hipEvent_t* evj = &c->ev[static_cast<size_t>(j) * 2 * K];
+    if (j < s) c->applied[j] = applied;
+    // estimate of the last phi1 substep and of the phi2 pass
+    if (j + 1 >= s) {
+      const LejaCoef& hcf = c->h_cf[j < s ? 0 : 1];
+      last = std::max(last, hcf.estf[st.stopped] * std::sqrt(st.sums[st.stopped]));
+    }
+    const int timed_slot = j < s ? (j < nprof ? j : -1) : (c->prof ? nprof : -1);
+    if (timed_slot >= 0) {
+      const hipEvent_t* evj = &c->ev[static_cast<size_t>(timed_slot) * 2 * K];
       for (int k = 1, launch = 0; k <= applied; ++launch) {
         const int nt = leja_terms_per_launch(c->d, k, K);
         if (launch % c->prof == 0) {
@@ -526,37 +570,44 @@ int krylov_hphi1(erem_ctx* c, double h, const double* v, double scal, const erem
   return EREM_OK;
 }
 
-// Full phi1 evaluation with the substep / restart policy.  On success c->u
-// holds h phi1(h J) v.
-int hphi1_eval(erem_ctx* c, double h, const double* v, double scal, const erem_opts* o, erem_stats* stats) {
+// Full evaluation with the substep / restart policy.  On success c->u holds
+// h phi1(h J) v, plus h^2 phi2(h J) g when g is not null (the increment of
+// the non-autonomous step, Sec. 3.2.3, Eq. nEERMg; Leja method only).
+int hphi1_eval(erem_ctx* c, double h, const double* v, const double* g, double scal, const erem_opts* o,
+               erem_stats* stats) {
   const double width = c->beta - c->alpha;
   const double mag = std::max(std::fabs(c->alpha), std::fabs(c->beta));
   if (!std::isfinite(width)) return fail(c, EREM_ENONFINITE, "non-finite Gershgorin interval");
   if (stats) { stats->alpha = c->alpha; stats->beta = c->beta; stats->restarts = 0; }
   if (width <= 1e-14 * mag || width == 0.0) {
     // Degenerate interval: J = c I (all Gershgorin radii zero, equal
-    // diagonal), so h phi1(h J) v = h phi1(h c) v exactly.
+    // diagonal), so h phi1(h J) v = h phi1(h c) v exactly, and likewise
+    // h^2 phi2(h J) g = h^2 phi2(h c) g.
     const double z = h * 0.5 * (c->alpha + c->beta);
     const double f = (z == 0.0) ? h : h * (std::expm1(z) / z);
     HIP_TRY(c, launch_axpby(c->d, c->u, 0.0, v, f, c->stream));
+    if (g) HIP_TRY(c, launch_axpby(c->d, c->u, 1.0, g, h * h * phi2_scalar(z), c->stream));
     c->applied.clear();
     if (stats) { stats->m_total = 0; stats->substeps = 1; stats->est_err = 0.0; }
     return EREM_OK;
   }
   if (o->method == EREM_METHOD_KRYLOV) return krylov_hphi1(c, h, v, scal, o, stats);
+  // the non-autonomous evaluation keeps one stop-state slot for its phi2 pass
+  const int smax = std::min(o->max_substeps, g ? c->nstates - 1 : c->nstates);
   int s = 1;
   if (o->rho_max > 0.0) s = std::max(1, static_cast<int>(std::ceil(h * width / o->rho_max)));
-  if (s > o->max_substeps) s = o->max_substeps;
-  if (s > c->nstates) s = c->nstates;
+  if (s > smax) s = smax;
   int K = o->chunk > 0 ? std::min(o->chunk, o->m_max)
                        : (c->last_m > 0 ? std::min(o->m_max, c->last_m + 8) : o->m_max);
   int restarts = 0;
   for (;;) {
     int m_used = 0;
     double est = 0.0;
-    const int rc = leja_hphi1(c, h, v, scal, s, K, o, &m_used, &est);
+    const int rc = leja_hphi1(c, h, v, g, scal, s, K, o, &m_used, &est);
     if (rc == EREM_OK) {
-      c->last_m = (m_used + s - 1) / s;
+      int m1 = 0;  // phi1 terms
+      for (int a : c->applied) m1 += a;
+      c->last_m = (m1 + s - 1) / s;
       if (stats) {
         stats->m_total = m_used;
         stats->substeps = s;
@@ -569,7 +620,7 @@ int hphi1_eval(erem_ctx* c, double h, const double* v, double scal, const erem_o
     ++restarts;
     if (K < o->m_max) {
       K = o->m_max;
-    } else if (2 * s <= std::min(o->max_substeps, c->nstates)) {
+    } else if (2 * s <= smax) {
       s *= 2;
     } else {
       return fail(c, EREM_ENOCONV, "phi1 did not converge within m_max terms and max_substeps substeps");
@@ -784,12 +835,12 @@ int erem_create(const erem_grid* g, void* stream, erem_ctx** out) {
   rc |= dev_alloc(c, &c->prhs, n);
   rc |= dev_alloc(c, &c->part, static_cast<size_t>(kLejaRing) * leja_num_blocks(c->d));
   c->nstates = 64;
-  rc |= dev_alloc(c, &c->cf, 1);
+  rc |= dev_alloc(c, &c->cf, 2);  // phi1 and phi2 coefficient blocks
   rc |= dev_alloc(c, &c->states, c->nstates);
   rc |= dev_alloc(c, &c->red, 1);
   rc |= dev_alloc(c, &c->pcg, 1);
   if (rc == EREM_OK) {
-    if (hipHostMalloc(reinterpret_cast<void**>(&c->h_cf), sizeof(LejaCoef), hipHostMallocDefault) != hipSuccess ||
+    if (hipHostMalloc(reinterpret_cast<void**>(&c->h_cf), 2 * sizeof(LejaCoef), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&c->h_states), sizeof(LejaState) * c->nstates, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&c->h_red), sizeof(AsmReduce), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&c->h_pcg), sizeof(PcgState), hipHostMallocDefault) != hipSuccess)
@@ -1012,7 +1063,7 @@ int erem_phi1_apply(erem_ctx* c, double h, const double* d_v, double* d_out, con
     if (stats) { std::memset(stats, 0, sizeof(*stats)); stats->alpha = c->alpha; stats->beta = c->beta; }
     return EREM_OK;
   }
-  rc = hphi1_eval(c, h, d_v, scal, o, stats);
+  rc = hphi1_eval(c, h, d_v, nullptr, scal, o, stats);
   if (rc) return rc;
   HIP_TRY(c, launch_axpby(c->d, d_out, 0.0, c->u, 1.0 / h, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
@@ -1043,12 +1094,14 @@ int step_checks(erem_ctx* c, double h, double* d_T, const erem_opts* o) {
   return EREM_OK;
 }
 
-// T += h phi1(h J) F with the context's J, F and interval; tmax = ||T||_inf.
-int step_core(erem_ctx* c, double h, double* d_T, const erem_opts* o, erem_stats* stats, double tmax) {
+// T += h phi1(h J) F (+ h^2 phi2(h J) g when g is not null) with the
+// context's J, F and interval; tmax = ||T||_inf.
+int step_core(erem_ctx* c, double h, double* d_T, const erem_opts* o, erem_stats* stats, double tmax,
+              const double* g = nullptr) {
   if (!std::isfinite(tmax)) return fail(c, EREM_ENONFINITE, "non-finite temperature");
   const double scal = o->tol_a + o->tol_r * tmax;
   if (!(scal > 0)) return fail(c, EREM_EINVAL, "error scale is zero (tol_a = 0 and T = 0)");
-  int rc = hphi1_eval(c, h, c->F, scal, o, stats);
+  int rc = hphi1_eval(c, h, c->F, g, scal, o, stats);
   if (rc) return rc;
   HIP_TRY(c, launch_axpby(c->d, d_T, 1.0, c->u, 1.0, c->stream));
   return EREM_OK;
@@ -1065,6 +1118,29 @@ int erem_step(erem_ctx* c, double h, double* d_T, const erem_opts* o, erem_stats
   rc = read_reduce(c);
   if (rc) return rc;
   return step_core(c, h, d_T, o, stats, c->tmax);
+}
+
+int erem_step_nonautonomous(erem_ctx* c, double h, double T_left, double T_right, double dT_left_dt,
+                            double dT_right_dt, double* d_T, const erem_opts* o, erem_stats* stats) {
+  if (!c) return EREM_EINVAL;
+  int rc = step_checks(c, h, d_T, o);
+  if (rc) return rc;
+  if (o->method != EREM_METHOD_LEJA) return fail(c, EREM_EINVAL, "the non-autonomous step runs with the Leja method");
+  if (!std::isfinite(T_left) || !std::isfinite(T_right) || !std::isfinite(dT_left_dt) || !std::isfinite(dT_right_dt))
+    return fail(c, EREM_EINVAL, "boundary temperatures and their rates must be finite");
+  if (!c->gt) {
+    rc = dev_alloc(c, &c->gt, c->d.N);
+    if (!rc) rc = dev_alloc(c, &c->zt, c->d.N);
+    if (rc) return EREM_ENOMEM;
+  }
+  c->ph.T_left = T_left;
+  c->ph.T_right = T_right;
+  rc = erem_form_jacobian(c, d_T);
+  if (rc) return rc;
+  HIP_TRY(c, launch_time_rate(c->d, c->ph, c->poro, c->fx, d_T, dT_left_dt, dT_right_dt, c->gt, c->stream));
+  rc = read_reduce(c);
+  if (rc) return rc;
+  return step_core(c, h, d_T, o, stats, c->tmax, c->gt);
 }
 
 int erem_step_frozen(erem_ctx* c, double h, double* d_T, const erem_opts* o, erem_stats* stats) {
@@ -1115,6 +1191,14 @@ int erem_leja_points(int32_t n, double* out) {
   std::vector<double> v;
   if (!leja_points(n, v)) return EREM_EINVAL;
   std::copy(v.begin(), v.end(), out);
+  return EREM_OK;
+}
+
+int erem_phi2_divided_differences(double hc, double hg, const double* xi, int32_t n, double* out) {
+  if (n < 0 || n > kMaxTerms + 1 || (n > 0 && (!xi || !out))) return EREM_EINVAL;
+  if (!std::isfinite(hc) || !std::isfinite(hg)) return EREM_EINVAL;
+  if (n == 0) return EREM_OK;
+  phi_divided_differences(2, hc, hg, xi, n, out);
   return EREM_OK;
 }
 

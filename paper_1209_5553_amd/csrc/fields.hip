@@ -345,15 +345,51 @@ __device__ inline double stencil_apply(const Dims& d, const double* __restrict__
   return s;
 }
 
+// w = v + tg g + J u  (g may be null: w = v + J u)
 __global__ __launch_bounds__(kThreads) void k_stencil_axpy(Dims d, const double* __restrict__ coef,
                                                  const double* __restrict__ v, const double* __restrict__ u,
-                                                 double* __restrict__ w) {
+                                                 double* __restrict__ w, const double* __restrict__ g,
+                                                 double tg) {
   const int x = blockIdx.x * kBX + threadIdx.x;
   const int y = blockIdx.y * kBY + threadIdx.y;
   const int z = blockIdx.z;
   if (x >= d.nx || y >= d.ny) return;
   const int i = x + d.nx * (y + d.ny * z);
-  w[i] = v[i] + stencil_apply(d, coef, u, x, y, z, i);
+  double a = v[i];
+  if (g) a += tg * g[i];
+  w[i] = a + stencil_apply(d, coef, u, x, y, z, i);
+}
+
+// ---------------------------------------------------------------------------
+// D_t G for boundary temperatures moving at the rates dTl (x = 0) and dTr
+// (x = nx): b enters R linearly and is itself linear in T_left and T_right,
+// so D_t b is the boundary part of the assembly with the rates in place of
+// the temperatures, and D_t G = D_t b / (V C(T)) (the non-autonomous step,
+// Sec. 3.2.3, Eq. nEERMg).  Zero away from the two x boundaries.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_time_rate(Dims d, Phys ph, const double* __restrict__ poro,
+                                              const double* __restrict__ fx, const double* __restrict__ T,
+                                              double dTl, double dTr, double* __restrict__ Gt) {
+  const int x = blockIdx.x * kBX + threadIdx.x;
+  const int y = blockIdx.y * kBY + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= d.nx || y >= d.ny) return;
+  const int i = x + d.nx * (y + d.ny * z);
+  const double cf = ph.c_f;
+  double bt = 0.0;
+  if (x == 0) {
+    const double fw = fx[fx_idx(d, 0, y, z)];
+    if (ph.dirichlet_left) bt += ph.lam * (d.dy * d.dz) / (0.5 * d.dx) * dTl;
+    if (fw > 0.0) bt += cf * fw * dTl;
+  }
+  if (x + 1 == d.nx) {
+    const double fe = fx[fx_idx(d, x + 1, y, z)];
+    if (fe < 0.0) bt += cf * (-fe) * dTr;
+  }
+  const double phi = poro[i];
+  const double V = d.dx * d.dy * d.dz;
+  const double C = phi * rho_of(T[i], ph) * cf + (1.0 - phi) * ph.rhoc_s;
+  Gt[i] = bt * (1.0 / (V * C));
 }
 
 // y <- a*y + b*x
@@ -787,8 +823,14 @@ hipError_t launch_absmax(const Dims& d, const double* v, AsmReduce* red, hipStre
 }
 
 hipError_t launch_stencil_axpy(const Dims& d, const double* coef, const double* v, const double* u,
-                               double* w, hipStream_t s) {
-  hipLaunchKernelGGL(k_stencil_axpy, cell_grid(d), cell_block(), 0, s, d, coef, v, u, w);
+                               double* w, hipStream_t s, const double* g, double tg) {
+  hipLaunchKernelGGL(k_stencil_axpy, cell_grid(d), cell_block(), 0, s, d, coef, v, u, w, g, tg);
+  return hipGetLastError();
+}
+
+hipError_t launch_time_rate(const Dims& d, const Phys& ph, const double* poro, const double* fx,
+                            const double* T, double dTl, double dTr, double* Gt, hipStream_t s) {
+  hipLaunchKernelGGL(k_time_rate, cell_grid(d), cell_block(), 0, s, d, ph, poro, fx, T, dTl, dTr, Gt);
   return hipGetLastError();
 }
 

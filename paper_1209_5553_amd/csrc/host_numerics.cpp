@@ -92,18 +92,21 @@ bool leja_points(int n, std::vector<double>& out) {
   return true;
 }
 
-void phi1_divided_differences(double hc, double hg, const double* xi, int n, double* out) {
-  // Augmented lower-bidiagonal matrix of order M = n + 1:
-  //   diag = (0, hc + hg xi_0, ..., hc + hg xi_{n-1}),
-  //   subdiag = (1, hg, ..., hg).
-  // exp of it is [[1, 0], [phi1(L) e_1, e^L]], L = hc I + hg Lhat, and
-  // phi1(L) e_1 holds the divided differences of phi1(hc + hg xi).
-  const int M = n + 1;
-  std::vector<double> dg(M), sd(M, 0.0);
-  dg[0] = 0.0;
-  for (int k = 0; k < n; ++k) dg[k + 1] = hc + hg * xi[k];
-  if (M > 1) sd[1] = 1.0;                 // A[1][0]
-  for (int k = 2; k < M; ++k) sd[k] = hg;  // A[k][k-1]
+void phi_divided_differences(int ell, double hc, double hg, const double* xi, int n, double* out) {
+  // Augmented lower-bidiagonal matrix of order M = n + ell:
+  //   diag = (0 (ell times), hc + hg xi_0, ..., hc + hg xi_{n-1}),
+  //   subdiag = (1 (ell times), hg, ..., hg).
+  // Its exponential's first column is (1, 1, .., 1/(ell-1)!, phi_ell(L) e_1)
+  // with L = hc I + hg Lhat: the first ell unknowns of y' = A y, y(0) = e_1,
+  // are s^j / j!, which feed the last block as the forcing s^(ell-1)/(ell-1)!
+  // e_1, whose response at s = 1 is phi_ell(L) e_1 by the integral
+  // definition of phi_ell.  phi_ell(L) e_1 holds the divided differences of
+  // phi_ell(hc + hg xi).
+  const int M = n + ell;
+  std::vector<double> dg(M, 0.0), sd(M, 0.0);
+  for (int k = 0; k < n; ++k) dg[k + ell] = hc + hg * xi[k];
+  for (int k = 1; k <= ell && k < M; ++k) sd[k] = 1.0;  // A[k][k-1]
+  for (int k = ell + 1; k < M; ++k) sd[k] = hg;
   double nrm = 0.0;                        // 1-norm: max column sum
   for (int j = 0; j < M; ++j) {
     const double c = std::fabs(dg[j]) + (j + 1 < M ? std::fabs(sd[j + 1]) : 0.0);
@@ -144,7 +147,24 @@ void phi1_divided_differences(double hc, double hg, const double* xi, int n, dou
       std::swap(E, T);
     }
   }
-  for (int k = 0; k < n; ++k) out[k] = E[(k + 1) * M + 0];
+  for (int k = 0; k < n; ++k) out[k] = E[(k + ell) * M + 0];
+}
+
+void phi1_divided_differences(double hc, double hg, const double* xi, int n, double* out) {
+  phi_divided_differences(1, hc, hg, xi, n, out);
+}
+
+double phi2_scalar(double z) {
+  if (std::fabs(z) < 1.0) {
+    // sum_{k>=0} z^k / (k+2)!: terms fall by |z| / (k+3) each
+    double acc = 0.0, term = 0.5;
+    for (int k = 0; k < 25; ++k) {
+      acc += term;
+      term *= z / (k + 3);
+    }
+    return acc;
+  }
+  return (std::expm1(z) - z) / (z * z);
 }
 
 void dense_expm(int n, const double* A, double* E) {

@@ -16,6 +16,14 @@ bool leja_points(int n, std::vector<double>& out);
 // read off exp([[0, 0], [e_1, hc I + hg L]]).
 void phi1_divided_differences(double hc, double hg, const double* xi, int n, double* out);
 
+// The same for g(xi) = phi_ell(hc + hg xi), ell = 1 or 2 (phi_2 of the
+// non-autonomous step, Sec. 3.2.3): first column of phi_ell(hc I + hg L),
+// read off the exponential of the bidiagonal matrix augmented by ell rows.
+void phi_divided_differences(int ell, double hc, double hg, const double* xi, int n, double* out);
+
+// phi2(z) = (e^z - 1 - z) / z^2 (Sec. 3.2.3), by its series for |z| < 1.
+double phi2_scalar(double z);
+
 // Dense exponential of an n x n row-major matrix by Taylor scaling-and-squaring.
 void dense_expm(int n, const double* A, double* E);
 

@@ -37,9 +37,10 @@ hipError_t launch_leja_terms(const Dims& d, const LejaCoef* cf, const V* coef, c
                              hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_leja_check(const Dims& d, const LejaCoef* cf, LejaState* st, const double* part,
                              int k1, int k2, hipStream_t s);
+// u = (first ? 0 : u) + delta p (+ zt when zt is not null)
 template <class V>
 hipError_t launch_substep_update(const Dims& d, double* u, const V* p, double delta, int first,
-                                 hipStream_t s);
+                                 hipStream_t s, const double* zt = nullptr);
 hipError_t launch_cast_f32(const double* a, float* b, long long n, hipStream_t s);
 
 }  // namespace erem

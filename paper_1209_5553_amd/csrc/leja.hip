@@ -304,17 +304,20 @@ __global__ __launch_bounds__(kCheckThreads) void k_leja_check(const LejaCoef* __
   }
 }
 
-// u = (first ? 0 : u) + delta * p  (FP64 update of the substep increment)
+// u = (first ? 0 : u) + delta * p (+ zt)  (FP64 update of the substep
+// increment; zt, when not null, is a fixed vector added on every substep)
 template <class V>
 __global__ __launch_bounds__(kThreads) void k_substep_update(Dims d, double* __restrict__ u, const V* __restrict__ p,
-                                                   double delta, int first) {
+                                                   double delta, int first, const double* __restrict__ zt) {
   const int x = blockIdx.x * kBX + threadIdx.x;
   const int y = blockIdx.y * kBY + threadIdx.y;
   const int z = blockIdx.z;
   if (x >= d.nx || y >= d.ny) return;
   const int i = x + d.nx * (y + d.ny * z);
   const double pi = static_cast<double>(p[i]);
-  u[i] = first ? delta * pi : u[i] + delta * pi;
+  double r = first ? delta * pi : u[i] + delta * pi;
+  if (zt) r += zt[i];
+  u[i] = r;
 }
 
 __global__ void k_cast_f32(const double* __restrict__ a, float* __restrict__ b, long long n) {
@@ -381,8 +384,9 @@ hipError_t launch_leja_check(const Dims& d, const LejaCoef* cf, LejaState* st, c
 }
 
 template <class V>
-hipError_t launch_substep_update(const Dims& d, double* u, const V* p, double delta, int first, hipStream_t s) {
-  hipLaunchKernelGGL(k_substep_update<V>, cell_grid(d), cell_block(), 0, s, d, u, p, delta, first);
+hipError_t launch_substep_update(const Dims& d, double* u, const V* p, double delta, int first, hipStream_t s,
+                                 const double* zt) {
+  hipLaunchKernelGGL(k_substep_update<V>, cell_grid(d), cell_block(), 0, s, d, u, p, delta, first, zt);
   return hipGetLastError();
 }
 
@@ -403,8 +407,10 @@ template hipError_t launch_leja_term<double>(const Dims&, const LejaCoef*, const
                                              hipEvent_t);
 template hipError_t launch_leja_term<float>(const Dims&, const LejaCoef*, const float*, const float*, float*, float*,
                                             const LejaState*, double*, int, hipStream_t, hipEvent_t, hipEvent_t);
-template hipError_t launch_substep_update<double>(const Dims&, double*, const double*, double, int, hipStream_t);
-template hipError_t launch_substep_update<float>(const Dims&, double*, const float*, double, int, hipStream_t);
+template hipError_t launch_substep_update<double>(const Dims&, double*, const double*, double, int, hipStream_t,
+                                                  const double*);
+template hipError_t launch_substep_update<float>(const Dims&, double*, const float*, double, int, hipStream_t,
+                                                 const double*);
 
 template hipError_t launch_leja_terms<double>(const Dims&, const LejaCoef*, const double*, const double*, double*,
                                               double*, const LejaState*, double*, int, int, hipStream_t, hipEvent_t,

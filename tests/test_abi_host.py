@@ -150,3 +150,48 @@ def test_host_numerics_argument_validation(lib):
     assert lib.erem_leja_points(5000, out.ctypes.data_as(nat._PD)) == -1
     assert lib.erem_phi1_divided_differences(float("nan"), 1.0, out.ctypes.data_as(nat._PD), 4,
                                              out.ctypes.data_as(nat._PD)) == -1
+
+
+def _dd2_reference(hc, hg, xi, n, dps=80):
+    """Divided differences of g(x) = phi2(hc + hg x), phi2(z) =
+    (e^z - 1 - z)/z^2 (Sec. 3.2.3), by the recursive definition in 80 digits
+    (series where the closed form would cancel)."""
+    mpmath.mp.dps = dps
+
+    def g(x):
+        z = mpmath.mpf(hc) + mpmath.mpf(hg) * x
+        if abs(z) < mpmath.mpf("1e-20"):
+            return sum(z ** k / mpmath.factorial(k + 2) for k in range(6))
+        return (mpmath.expm1(z) - z) / (z * z)
+
+    pts = [mpmath.mpf(float(v)) for v in xi[:n]]
+    table = [g(p) for p in pts]
+    out = [table[0]]
+    for k in range(1, n):
+        table = [(table[i + 1] - table[i]) / (pts[i + k] - pts[i]) for i in range(n - k)]
+        out.append(table[0])
+    return np.array([float(v) for v in out])
+
+
+@pytest.mark.parametrize("hc,hg", [(-128.0, 64.0), (-3.7, 1.9), (-0.5, 0.25), (-30.0, 16.0)])
+def test_phi2_divided_differences_against_high_precision_recursion(hc, hg):
+    n = 40
+    xi = _leja(n)
+    got = np.zeros(n)
+    assert nat.load().erem_phi2_divided_differences(hc, hg, xi.ctypes.data_as(nat._PD), n,
+                                                    got.ctypes.data_as(nat._PD)) == 0
+    ref = _dd2_reference(hc, hg, xi, n)
+    scale = np.abs(ref).max()
+    assert np.abs(got - ref).max() <= 4e-14 * scale, np.abs(got - ref).max() / scale
+
+
+def test_phi2_divided_differences_degenerate_interval():
+    """hg = 0: d_0 = phi2(hc), the rest 0."""
+    xi = _leja(8)
+    got = np.zeros(8)
+    nat.load().erem_phi2_divided_differences(-3.0, 0.0, xi.ctypes.data_as(nat._PD), 8,
+                                             got.ctypes.data_as(nat._PD))
+    assert got[0] == pytest.approx((math.expm1(-3.0) + 3.0) / 9.0, rel=1e-15)
+    assert np.all(got[1:] == 0.0)
+    assert nat.load().erem_phi2_divided_differences(1.0, float("inf"), xi.ctypes.data_as(nat._PD), 8,
+                                                    got.ctypes.data_as(nat._PD)) == -1

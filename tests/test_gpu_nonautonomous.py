@@ -1,0 +1,141 @@
+"""GPU parity of the non-autonomous EREM step (Sec. 3.2.3, Eq. nEERMg)
+through the C ABI against the CPU oracle.
+
+The injection temperature follows the workload's schedule (a 20 C - 80 C
+sine of period 20 steps); every step passes the boundary temperatures at t_n
+and their rates.  Tolerance: 1e-10 relative (max norm) on the increment
+T^n - T^0, as for the autonomous step.
+"""
+import numpy as np
+import pytest
+
+from oracle import erem as oerem
+from paper_1209_5553_amd import inputs
+
+from gpu_util import rel_inf
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _say(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+
+
+def _run_gpu(torch, prob, sched, nsteps, t0=0.0, opts=None):
+    from paper_1209_5553_amd.api import EremContext
+    ctx = EremContext.from_problem(prob, device="cuda:0")
+    T = torch.as_tensor(prob.T0, dtype=torch.float64, device="cuda:0").clone()
+    ctx.pressure_and_fluxes(T, rtol=1e-16)      # fluxes of the pressure at T0, as in the oracle
+    t = t0
+    stats = []
+    for _ in range(nsteps):
+        Tl, Tr, dTl, dTr = sched(t)
+        stats.append(ctx.step_nonautonomous(prob.h, T, Tl, Tr, dTl, dTr, opts))
+        t += prob.h
+    torch.cuda.synchronize()
+    return T.cpu().numpy(), stats, ctx
+
+
+def _ragged_problem(nx, ny, seed):
+    rng = np.random.default_rng(seed)
+    logk = inputs.lognormal_field(rng, (ny, nx), 1.0, 4.0)
+    N = nx * ny
+    return inputs.Problem(name=f"ragged_{nx}x{ny}", nx=nx, ny=ny, nz=1, logk=logk,
+                          poro=np.full(N, inputs.POROSITY), T0=np.full(N, inputs.T_INITIAL),
+                          p_left=inputs.DP_COUPLED)
+
+
+def _water_problem(n, seed):
+    prob = inputs.coupled_problem(n, seed=seed)
+    rng = np.random.default_rng(seed + 100)
+    prob.T0 = 20.0 + 60.0 * rng.random(prob.n)
+    return prob
+
+
+CASES = {
+    "linear 24x24 from t=0": (lambda: inputs.linear_problem(24, seed=3), 0.0, 4),
+    "water laws 20x20, random T0, from t=5e6": (lambda: _water_problem(20, 4), 5.0e6, 3),
+    "ragged 70x33 (several tiles, ragged tails)": (lambda: _ragged_problem(70, 33, 5), 2.0e6, 3),
+    "3D layered 10^3": (lambda: inputs.layered3d_problem(10, seed=6), 1.0e6, 3),
+    "injector 64x64, rising ramp": (lambda: inputs.injector_problem(64, seed=7), 0.0, 5),
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_nonautonomous_steps_match_oracle(torch_mod, case):
+    make, t0, nsteps = CASES[case]
+    prob = make()
+    sched = inputs.InjectorSchedule(ramp=2e-6) if "ramp" in case else inputs.InjectorSchedule()
+    _say(f"non-autonomous {case}: N={prob.n}, {nsteps} steps")
+    got, stats, _ = _run_gpu(torch_mod, prob, sched, nsteps, t0)
+    _say(f"  stats {stats[-1]}")
+    tier = "dense" if prob.n <= 700 else "taylor"
+    ref, _ = oerem.run_nonautonomous(prob, sched, nsteps=nsteps, t0=t0, tier=tier)
+    err = rel_inf(got - prob.T0, ref - prob.T0)
+    _say(f"  rel err of the increment {err:.3e}")
+    assert err <= TOL
+
+
+def test_zero_rates_give_the_autonomous_step_bit_for_bit(torch_mod):
+    """With both rates 0 the phi2 term vanishes and every phi1 substep is the
+    one of erem_step: the two entry points agree bit for bit."""
+    torch = torch_mod
+    from paper_1209_5553_amd.api import EremContext
+    prob = inputs.linear_problem(40, seed=8)
+    ctx = EremContext.from_problem(prob, device="cuda:0")
+    ctx.pressure_and_fluxes(rtol=1e-16)
+    Ta = torch.as_tensor(prob.T0, dtype=torch.float64, device="cuda:0").clone()
+    Tb = Ta.clone()
+    for _ in range(3):
+        sa = ctx.step(prob.h, Ta)
+        sb = ctx.step_nonautonomous(prob.h, Tb, prob.T_left, prob.T_right, 0.0, 0.0)
+    _say(f"autonomous {sa}; non-autonomous, zero rates {sb}")
+    assert torch.equal(Ta, Tb)
+
+
+def test_mixed_precision_close_to_fp64(torch_mod):
+    from paper_1209_5553_amd.api import make_opts
+    prob = inputs.injector_problem(96, seed=9)
+    sched = inputs.InjectorSchedule()
+    T64, _, _ = _run_gpu(torch_mod, prob, sched, 3)
+    T32, st, _ = _run_gpu(torch_mod, prob, sched, 3, opts=make_opts(precision=1, tol_r=1e-7))
+    err = rel_inf(T32 - prob.T0, T64 - prob.T0)
+    _say(f"mixed vs fp64 increment: {err:.3e} ({st[-1]})")
+    assert err <= 1e-5
+
+
+def test_full_size_injector_512(torch_mod):
+    """The 512 x 512 injector workload, two steps from t = 0, against the
+    substepped Taylor oracle on every cell."""
+    prob = inputs.injector_problem(512)
+    sched = inputs.InjectorSchedule()
+    got, stats, _ = _run_gpu(torch_mod, prob, sched, 2)
+    _say(f"injector 512^2: {stats}")
+    ref, _ = oerem.run_nonautonomous(prob, sched, nsteps=2, tier="taylor")
+    err = rel_inf(got - prob.T0, ref - prob.T0)
+    _say(f"  rel err of the increment {err:.3e}")
+    assert err <= TOL
+
+
+def test_bad_arguments_are_rejected(torch_mod):
+    torch = torch_mod
+    from paper_1209_5553_amd.api import EremContext, EremError, make_opts
+    prob = inputs.linear_problem(16, seed=10)
+    ctx = EremContext.from_problem(prob, device="cuda:0")
+    ctx.pressure_and_fluxes(rtol=1e-16)
+    T = torch.as_tensor(prob.T0, dtype=torch.float64, device="cuda:0").clone()
+    with pytest.raises(EremError):
+        ctx.step_nonautonomous(prob.h, T, 50.0, 20.0, float("nan"), 0.0)
+    with pytest.raises(EremError):
+        ctx.step_nonautonomous(prob.h, T, 50.0, 20.0, 1e-6, 0.0, make_opts(method=1))
+    torch.cuda.synchronize()
+    assert torch.equal(T.cpu(), torch.as_tensor(prob.T0))
