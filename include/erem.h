@@ -215,6 +215,48 @@ int erem_step_nonautonomous(erem_ctx* ctx, double h, double T_left, double T_rig
                             double dT_left_dt, double dT_right_dt, double* d_T,
                             const erem_opts* opts, erem_stats* stats);
 
+/* ---- comparison schemes: Rosenbrock-type methods and theta-Euler ----
+ *
+ * The linear systems of these schemes, (I/(tau gamma) - J) k = rhs, are
+ * solved by BiCGSTAB (the paper's solver, Sec. 3.2.3) with Jacobi right
+ * preconditioning, M = diag(sigma - J_ii), from x = 0 to the relative
+ * residual rtol (recursive residual).  EREM_ENOCONV on breakdown or when
+ * the iteration limit is reached. */
+
+/* x = (sigma I - J)^{-1} b for the J of the last erem_form_jacobian or
+ * erem_set_jacobian; sigma > 0, rtol in (0, 1), max_iter >= 1.  d_b and d_x
+ * (N values each, device) must not alias.  stats->iterations: BiCGSTAB
+ * iterations. */
+int erem_shifted_solve(erem_ctx* ctx, double sigma, const double* d_b, double* d_x, double rtol,
+                       int32_t max_iter, erem_stats* stats);
+
+#define EREM_ROSM_1 0     /* ROSM(1), Eq. ROS with gamma = 1 */
+#define EREM_ROSM_HALF 1  /* ROSM(1/2), Eq. ROS with gamma = 1/2 */
+#define EREM_ROS2 2       /* ROS2(1), Eq. ROSMh with Table ros2 */
+#define EREM_ROS3P 3      /* ROS3p, Eq. ROSMh with Table ros3 */
+
+/* One Rosenbrock-type step in place on d_T for the autonomous heat model
+ * with the current fluxes (Eq. ROSMh, D_t f = 0): J and G are formed at d_T,
+ * then for each stage i
+ *   (I/(h gamma) - J) k_i = G(T + sum_{j<i} a_ij k_j) - sum_{j<i} (c_ij / h) k_j
+ * and d_T <- d_T + sum_i b_i k_i; ROSM(gamma) is the one-stage case
+ * T + h (I - h gamma J)^{-1} G(T) (Eq. ROS).  lin_rtol: relative residual of
+ * every stage solve.  stats->substeps: stages; stats->iterations: BiCGSTAB
+ * iterations summed over the stages.  The context keeps J and G of the
+ * start of the step. */
+int erem_step_rosenbrock(erem_ctx* ctx, double h, int32_t scheme, double* d_T, double lin_rtol,
+                         erem_stats* stats);
+
+/* One theta-Euler step in place (Eq. temscheme): X = T^{n+1} solves
+ *   X - h theta G(X) - h (1 - theta) G(T^n) - T^n = 0
+ * by Newton's method from X_0 = T^n, (I - h theta J(X_k)) dX = -F(X_k), until
+ * max|dX| <= newton_rtol max|T^n| (at most max_newton iterations, else
+ * EREM_ENOCONV with d_T unchanged).  theta in [0, 1]; theta = 0 is the
+ * explicit Euler step.  stats->substeps: Newton iterations;
+ * stats->iterations: BiCGSTAB iterations summed over them. */
+int erem_step_theta(erem_ctx* ctx, double h, double theta, double* d_T, double newton_rtol,
+                    double lin_rtol, int32_t max_newton, erem_stats* stats);
+
 /* ---- sequential coupled step and its adjoint (2D grids) ----
  *
  * The coupled step of Sec. 3.2.2 (pressure first, then temperature): TPFA
@@ -332,6 +374,8 @@ typedef struct {
     int64_t mg_cycles;
     double adj_rev_ms;          /* reverse Newton-Leja term kernel (adjoint) */
     int64_t adj_rev_launches;
+    double bicg_ms;             /* BiCGSTAB iteration (its three kernels) */
+    int64_t bicg_iterations;
 } erem_kernel_times;
 
 /* Per-launch event timing: enable = 0 turns it off, enable = n > 0 times one

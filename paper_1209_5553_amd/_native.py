@@ -48,7 +48,8 @@ class KernelTimes(ctypes.Structure):
                 ("pcg_a_ms", c_double), ("pcg_a_launches", c_int64),
                 ("pcg_b_ms", c_double), ("pcg_b_launches", c_int64),
                 ("mg_ms", c_double), ("mg_cycles", c_int64),
-                ("adj_rev_ms", c_double), ("adj_rev_launches", c_int64)]
+                ("adj_rev_ms", c_double), ("adj_rev_launches", c_int64),
+                ("bicg_ms", c_double), ("bicg_iterations", c_int64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -100,6 +101,9 @@ SIGNATURES = {
     "erem_step_frozen": (c_int32, [_P, c_double, _P, POINTER(Opts), POINTER(Stats)]),
     "erem_step_nonautonomous": (c_int32, [_P, c_double, c_double, c_double, c_double, c_double, _P,
                                           POINTER(Opts), POINTER(Stats)]),
+    "erem_shifted_solve": (c_int32, [_P, c_double, _P, _P, c_double, c_int32, POINTER(Stats)]),
+    "erem_step_rosenbrock": (c_int32, [_P, c_double, c_int32, _P, c_double, POINTER(Stats)]),
+    "erem_step_theta": (c_int32, [_P, c_double, c_double, _P, c_double, c_double, c_int32, POINTER(Stats)]),
     "erem_coupled_step": (c_int32, [_P, c_double, _P, c_double, POINTER(Opts), POINTER(Tape),
                                     POINTER(Tape), POINTER(Stats)]),
     "erem_coupled_step_adjoint": (c_int32, [_P, c_double, _P, c_double, POINTER(Opts), POINTER(Tape),

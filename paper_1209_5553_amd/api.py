@@ -214,6 +214,33 @@ class EremContext:
             ctypes.byref(o), ctypes.byref(st)), "erem_step_nonautonomous")
         return st.as_dict()
 
+    ROS_SCHEMES = {"rosm1": 0, "rosm05": 1, "ros2": 2, "ros3p": 3}
+
+    def shifted_solve(self, sigma: float, b, x, rtol: float = 1e-13, max_iter: int = 10000):
+        """x = (sigma I - J)^{-1} b for the context's J (erem_shifted_solve)."""
+        st = nat.Stats()
+        self._check(self.lib.erem_shifted_solve(self.handle, sigma, self._ptr(b, self.n, "b"),
+                                                self._ptr(x, self.n, "x"), rtol, max_iter, ctypes.byref(st)),
+                    "erem_shifted_solve")
+        return st.as_dict()
+
+    def step_rosenbrock(self, h: float, T, scheme: str = "ros2", lin_rtol: float = 1e-13):
+        """One Rosenbrock-type step in place (erem_step_rosenbrock); scheme
+        one of rosm1, rosm05, ros2, ros3p."""
+        st = nat.Stats()
+        self._check(self.lib.erem_step_rosenbrock(self.handle, h, self.ROS_SCHEMES[scheme],
+                                                  self._ptr(T, self.n, "T"), lin_rtol, ctypes.byref(st)),
+                    "erem_step_rosenbrock")
+        return st.as_dict()
+
+    def step_theta(self, h: float, T, theta: float = 0.5, newton_rtol: float = 1e-13,
+                   lin_rtol: float = 1e-13, max_newton: int = 30):
+        """One theta-Euler step with Newton's method in place (erem_step_theta)."""
+        st = nat.Stats()
+        self._check(self.lib.erem_step_theta(self.handle, h, theta, self._ptr(T, self.n, "T"), newton_rtol,
+                                             lin_rtol, max_newton, ctypes.byref(st)), "erem_step_theta")
+        return st.as_dict()
+
     def coupled_step(self, h: float, T, p_rtol: float = 1e-16, opts: nat.Opts | None = None,
                      tape: nat.Tape | None = None, record: bool = True):
         """One sequential coupled step in place on T (erem_coupled_step).

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "device.h"
+#include "rosenbrock.h"
 #include "erem.h"
 #include "mg.h"
 
@@ -33,6 +34,16 @@ struct erem_ctx {
   double *coef = nullptr, *F = nullptr;
   // non-autonomous step: D_t G and the phi2 term (allocated on first use)
   double *gt = nullptr, *zt = nullptr;
+  // shifted solves (BiCGSTAB) and the Rosenbrock / theta-Euler stages
+  // (allocated on first use): solver vectors, stage vectors k_1..k_3, the
+  // stage state Y, G(Y), the right-hand side, and a scratch stencil
+  double *bc_r = nullptr, *bc_rhat = nullptr, *bc_p0 = nullptr, *bc_p1 = nullptr, *bc_v0 = nullptr,
+         *bc_v1 = nullptr, *bc_s = nullptr, *bc_t = nullptr;
+  double *rs_k0 = nullptr, *rs_k1 = nullptr, *rs_k2 = nullptr, *rs_y = nullptr, *rs_g = nullptr,
+         *rs_rhs = nullptr, *rs_coef = nullptr;
+  erem::BicgState* bicg = nullptr;
+  erem::BicgState* h_bicg = nullptr;
+  int bicg_last = 0;  // iterations of the last converged solve (poll placement)
   double *qa = nullptr, *qb = nullptr, *pacc = nullptr, *u = nullptr, *w = nullptr;
   double *pres = nullptr, *pr = nullptr, *pr2 = nullptr, *pz = nullptr, *pp0 = nullptr, *pp1 = nullptr;
   double *pw = nullptr, *ps0 = nullptr, *ps1 = nullptr;  // Chronopoulos-Gear w = A z and s
@@ -71,6 +82,8 @@ struct erem_ctx {
   long long n_leja = 0, n_pcg_a = 0, n_pcg_b = 0, n_mg = 0;
   double t_adj = 0.0;
   long long n_adj = 0;
+  double t_bicg = 0.0;
+  long long n_bicg = 0;
   // multigrid preconditioner of the pressure operator
   erem::MgHierarchy mg;
   bool use_mg = true;

@@ -71,13 +71,19 @@ void free_all(erem_ctx* c) {
   double** bufs[] = {&c->logk, &c->poro, &c->tx, &c->ty, &c->tz, &c->fx, &c->fy, &c->fz,
                      &c->coef, &c->F, &c->qa, &c->qb, &c->pacc, &c->u, &c->w, &c->pres,
                      &c->pr, &c->pr2, &c->pw, &c->ps0, &c->ps1, &c->pz, &c->pp0, &c->pp1, &c->pq, &c->pdiag,
-                     &c->pres_lo, &c->pdelta, &c->prhs, &c->part, &c->gt, &c->zt};
+                     &c->pres_lo, &c->pdelta, &c->prhs, &c->part, &c->gt, &c->zt,
+                     &c->bc_r, &c->bc_rhat, &c->bc_p0, &c->bc_p1, &c->bc_v0, &c->bc_v1, &c->bc_s, &c->bc_t,
+                     &c->rs_k0, &c->rs_k1, &c->rs_k2, &c->rs_y, &c->rs_g, &c->rs_rhs, &c->rs_coef};
   for (double** b : bufs)
     if (*b) { (void)hipFree(*b); *b = nullptr; }
   if (c->cf) (void)hipFree(c->cf);
   if (c->states) (void)hipFree(c->states);
   if (c->red) (void)hipFree(c->red);
   if (c->pcg) (void)hipFree(c->pcg);
+  if (c->bicg) (void)hipFree(c->bicg);
+  if (c->h_bicg) (void)hipHostFree(c->h_bicg);
+  c->bicg = nullptr;
+  c->h_bicg = nullptr;
   if (c->h_cf) (void)hipHostFree(c->h_cf);
   if (c->h_states) (void)hipHostFree(c->h_states);
   if (c->h_red) (void)hipHostFree(c->h_red);
@@ -1158,8 +1164,8 @@ int erem_profile(erem_ctx* c, int32_t enable) {
   if (!c) return EREM_EINVAL;
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   c->prof = enable > 0 ? enable : 0;
-  c->t_leja = c->t_pcg_a = c->t_pcg_b = c->t_mg = c->t_adj = 0.0;
-  c->n_leja = c->n_pcg_a = c->n_pcg_b = c->n_mg = c->n_adj = 0;
+  c->t_leja = c->t_pcg_a = c->t_pcg_b = c->t_mg = c->t_adj = c->t_bicg = 0.0;
+  c->n_leja = c->n_pcg_a = c->n_pcg_b = c->n_mg = c->n_adj = c->n_bicg = 0;
   return EREM_OK;
 }
 
@@ -1175,6 +1181,8 @@ int erem_profile_read(erem_ctx* c, erem_kernel_times* out) {
   out->mg_cycles = c->n_mg;
   out->adj_rev_ms = c->t_adj;
   out->adj_rev_launches = c->n_adj;
+  out->bicg_ms = c->t_bicg;
+  out->bicg_iterations = c->n_bicg;
   return EREM_OK;
 }
 

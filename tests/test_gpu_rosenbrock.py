@@ -1,0 +1,159 @@
+"""GPU parity of the comparison schemes through the C ABI against the CPU
+oracle: the BiCGSTAB shifted solve (sigma I - J) x = b against a sparse LU
+solve, the Rosenbrock-type steps ROSM(1), ROSM(1/2), ROS2(1), ROS3p (Eq. ROS,
+Eq. ROSMh, Tables ros2 and ros3) and theta-Euler with Newton's method
+(Eq. temscheme).  Tolerance: 1e-10 relative (max norm) on T^n - T^0, with
+every linear solve run to a relative residual of 1e-13."""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from oracle import erem as oerem
+from oracle import rosenbrock as oros
+from paper_1209_5553_amd import inputs
+
+from gpu_util import rel_inf
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+TABLES = {"rosm1": oros.rosm_table(1.0), "rosm05": oros.rosm_table(0.5), "ros2": oros.ROS2, "ros3p": oros.ROS3P}
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _say(msg):
+    print(f"[gpu-test] {msg}", flush=True)
+
+
+def _ctx(torch, prob):
+    from paper_1209_5553_amd.api import EremContext
+    ctx = EremContext.from_problem(prob, device="cuda:0")
+    T = torch.as_tensor(prob.T0, dtype=torch.float64, device="cuda:0").clone()
+    ctx.pressure_and_fluxes(T, rtol=1e-16)
+    return ctx, T
+
+
+def _water_problem(n, seed):
+    prob = inputs.coupled_problem(n, seed=seed)
+    prob.T0 = 20.0 + 60.0 * np.random.default_rng(seed + 50).random(prob.n)
+    return prob
+
+
+def _ragged_problem(nx, ny, seed):
+    rng = np.random.default_rng(seed)
+    logk = inputs.lognormal_field(rng, (ny, nx), 1.0, 4.0)
+    N = nx * ny
+    return inputs.Problem(name=f"ragged_{nx}x{ny}", nx=nx, ny=ny, nz=1, logk=logk,
+                          poro=np.full(N, inputs.POROSITY), T0=np.full(N, inputs.T_INITIAL),
+                          p_left=inputs.DP_COUPLED)
+
+
+def test_shifted_solve_matches_sparse_lu(torch_mod):
+    """(sigma I - J) x = b with the GPU's J against scipy's LU of the oracle's
+    J, for the sigmas of ROS2(1) and ROSM(1/2) at h = 1e6 s, 2D and 3D."""
+    torch = torch_mod
+    for prob in (_water_problem(24, 1), inputs.layered3d_problem(8, seed=2)):
+        ctx, T = _ctx(torch, prob)
+        ctx.form_jacobian(T)
+        disc = oerem.Discretisation(prob, prob.T0)
+        J = disc.model.J_sparse(prob.T0)
+        b = np.random.default_rng(3).standard_normal(prob.n) * 1e-6
+        bd = torch.as_tensor(b, device="cuda:0")
+        for sigma in (1.0 / (prob.h * oros.ROS2.gamma), 2.0 / prob.h):
+            x = torch.empty_like(bd)
+            st = ctx.shifted_solve(sigma, bd, x, rtol=1e-13)
+            ref = spla.spsolve(sp.csc_matrix(sigma * sp.identity(prob.n) - J), b)
+            err = rel_inf(x.cpu().numpy(), ref)
+            _say(f"{prob.name} sigma={sigma:.3e}: {st['iterations']} iterations, rel err {err:.2e}")
+            assert err <= 1e-11
+
+
+CASES = {
+    "linear 24x24": (lambda: inputs.linear_problem(24, seed=3), 3),
+    "water laws 20x20, random T0": (lambda: _water_problem(20, 4), 3),
+    "ragged 70x33": (lambda: _ragged_problem(70, 33, 5), 2),
+    "3D layered 8^3": (lambda: inputs.layered3d_problem(8, seed=6), 2),
+}
+
+
+@pytest.mark.parametrize("scheme", list(TABLES))
+@pytest.mark.parametrize("case", list(CASES))
+def test_rosenbrock_steps_match_oracle(torch_mod, case, scheme):
+    torch = torch_mod
+    make, nsteps = CASES[case]
+    prob = make()
+    ctx, T = _ctx(torch, prob)
+    for _ in range(nsteps):
+        st = ctx.step_rosenbrock(prob.h, T, scheme, lin_rtol=1e-13)
+    torch.cuda.synchronize()
+    ref, _ = oros.run_rosenbrock(prob, TABLES[scheme], nsteps=nsteps)
+    err = rel_inf(T.cpu().numpy() - prob.T0, ref - prob.T0)
+    _say(f"{scheme} {case}: {st}, rel err {err:.2e}")
+    assert err <= TOL
+
+
+@pytest.mark.parametrize("theta", [0.5, 1.0, 0.0])
+@pytest.mark.parametrize("case", ["linear 24x24", "water laws 20x20, random T0", "3D layered 8^3"])
+def test_theta_euler_steps_match_oracle(torch_mod, case, theta):
+    torch = torch_mod
+    make, nsteps = CASES[case]
+    prob = make()
+    ctx, T = _ctx(torch, prob)
+    for _ in range(nsteps):
+        st = ctx.step_theta(prob.h, T, theta)
+    torch.cuda.synchronize()
+    if theta == 0.0:
+        # explicit Euler: T + h G(T), unstable at this h but a plain definition
+        disc = oerem.Discretisation(prob, prob.T0)
+        fl = disc.fluxes
+        ref = prob.T0.copy()
+        ode = oros.HeatODE(prob, fl)
+        for n in range(nsteps):
+            ref = ref + prob.h * ode.f(ref, 0.0)
+    else:
+        ref, _, its = oros.run_theta_euler(prob, theta, nsteps=nsteps)
+    err = rel_inf(T.cpu().numpy() - prob.T0, ref - prob.T0)
+    _say(f"theta={theta} {case}: {st}, rel err {err:.2e}")
+    assert err <= TOL
+
+
+def test_full_size_coupled_512_ros2_and_theta(torch_mod):
+    """The 512 x 512 coupled workload's first temperature step (fluxes of the
+    pressure at T0) by ROS2(1) and by Crank-Nicolson, on every cell."""
+    torch = torch_mod
+    prob = inputs.coupled_problem(512)
+    fl = oerem.Discretisation(prob, prob.T0).fluxes
+    for name, run in (("ros2", lambda ctx, T: ctx.step_rosenbrock(prob.h, T, "ros2")),
+                      ("theta 1/2", lambda ctx, T: ctx.step_theta(prob.h, T, 0.5))):
+        ctx, T = _ctx(torch, prob)
+        st = run(ctx, T)
+        torch.cuda.synchronize()
+        if name == "ros2":
+            ref, _ = oros.run_rosenbrock(prob, oros.ROS2, nsteps=1, fluxes=fl)
+        else:
+            ref, _, _ = oros.run_theta_euler(prob, 0.5, nsteps=1, fluxes=fl)
+        err = rel_inf(T.cpu().numpy() - prob.T0, ref - prob.T0)
+        _say(f"512^2 {name}: {st}, rel err {err:.2e}")
+        assert err <= TOL
+
+
+def test_bad_arguments_are_rejected(torch_mod):
+    torch = torch_mod
+    from paper_1209_5553_amd.api import EremError
+    prob = inputs.linear_problem(16, seed=9)
+    ctx, T = _ctx(torch, prob)
+    T0 = T.clone()
+    assert ctx.lib.erem_step_rosenbrock(ctx.handle, prob.h, 7, ctx._ptr(T, ctx.n, "T"), 1e-13, None) == -1
+    with pytest.raises(EremError):
+        ctx.step_theta(prob.h, T, 1.5)
+    with pytest.raises(EremError):
+        ctx.step_rosenbrock(prob.h, T, "ros2", lin_rtol=0.0)
+    torch.cuda.synchronize()
+    assert torch.equal(T, T0)
