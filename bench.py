@@ -41,6 +41,12 @@ PROFILE_STRIDE = 4
 LEJA_BYTES = {2: {"f64": 72, "f32": 36}, 3: {"f64": 88, "f32": 44}}
 PCG_A_BYTES = {2: 48, 3: 64}    # read z, p_old, face transmissibilities; write p_new, q
 PCG_B_BYTES = {2: 48, 3: 48}    # read x, p_new, r, q; write x, r (multigrid-preconditioned)
+# One BiCGSTAB iteration of the comparison schemes (three kernels): K1 reads
+# r, p, v (with halos), the stencil and rhat and writes p, v; K2 reads r, v
+# and the stencil and writes s, t; K3 reads x, p, s, t, the diagonal and rhat
+# and writes x, r.
+BICG_BYTES = {2: 88 + 72 + 64, 3: 104 + 88 + 64}
+SCHEMES = ("erem", "rosm1", "rosm05", "ros2", "ros3p", "theta05", "theta1")
 # One multigrid V-cycle per finest cell: on the finest level the four passes
 # (two-sweep smoothing, residual + restriction, prolongation + sweep, sweep)
 # read b, diag, faces and the iterate and write one vector each (~180 B);
@@ -93,7 +99,7 @@ def schedule_of(name):
     return inputs.InjectorSchedule() if name == "injector512" else None
 
 
-def gpu_run(prob, coupled, steps, warmup, rtol_p, mixed=False, sched=None):
+def gpu_run(prob, coupled, steps, warmup, rtol_p, mixed=False, sched=None, scheme="erem"):
     import torch
     from paper_1209_5553_amd.api import EremContext, make_opts
 
@@ -116,6 +122,10 @@ def gpu_run(prob, coupled, steps, warmup, rtol_p, mixed=False, sched=None):
         if sched is not None:
             # boundary temperatures and their rates at t_n = n h
             state["last"] = ctx.step_nonautonomous(prob.h, T, *sched(state["n"] * prob.h), opts)
+        elif scheme.startswith("theta"):
+            state["last"] = ctx.step_theta(prob.h, T, 0.5 if scheme == "theta05" else 1.0)
+        elif scheme != "erem":
+            state["last"] = ctx.step_rosenbrock(prob.h, T, scheme)
         else:
             state["last"] = ctx.step(prob.h, T, opts)
         state["n"] += 1
@@ -130,22 +140,24 @@ def gpu_run(prob, coupled, steps, warmup, rtol_p, mixed=False, sched=None):
     ctx.profile(True, stride=PROFILE_STRIDE)
     state["pcg"] = 0
     m_total = 0
+    lin_total = 0
     t0 = time.perf_counter()
     for _ in range(steps):
         one_step()
         m_total += state["last"]["m_total"]
+        lin_total += state["last"]["iterations"]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     times = ctx.profile_read()
     ctx.profile(False)
     log(f"timed {steps} steps in {t1 - t0:.3f} s; kernel times {times}")
     snaps = {k: v.cpu().numpy() for k, v in snapshots.items()}
-    return dict(elapsed=t1 - t0, times=times, m_per_step=m_total / steps,
+    return dict(elapsed=t1 - t0, times=times, m_per_step=m_total / steps, lin_per_step=lin_total / steps,
                 pcg_per_step=state["pcg"] / steps, last=state["last"], snapshots=snaps,
                 T_final=T.cpu().numpy())
 
 
-def cpu_baseline(prob, coupled, nsteps, gpu_snaps, sched=None):
+def cpu_baseline(prob, coupled, nsteps, gpu_snaps, sched=None, scheme="erem"):
     """The oracle as it stands, on a bounded sample: the first `nsteps` steps
     of the same workload (tier-B sparse action; SuperLU pressure with extended-precision refinement)."""
     from threadpoolctl import threadpool_limits
@@ -154,7 +166,11 @@ def cpu_baseline(prob, coupled, nsteps, gpu_snaps, sched=None):
     with threadpool_limits(limits=1):
         T = np.asarray(prob.T0, dtype=np.float64).copy()
         t0 = time.perf_counter()
-        if coupled:
+        if coupled and scheme != "erem":
+            from oracle import rosenbrock as oros
+            for _ in range(nsteps):
+                T = oros.coupled_step_scheme(prob, T, scheme)
+        elif coupled:
             for _ in range(nsteps):
                 T, _ = oerem.coupled_step(prob, T, tier="taylor")
         elif sched is not None:
@@ -166,8 +182,11 @@ def cpu_baseline(prob, coupled, nsteps, gpu_snaps, sched=None):
         t1 = time.perf_counter()
     out = {"value": nsteps / (t1 - t0), "unit": "steps/s", "cores": 1, "kind": "oracle",
            "sample": f"first {nsteps} steps of the same workload from T0 "
-                     f"({'SuperLU pressure refined in extended precision + ' if coupled else ''}substepped Taylor action of the "
-                     f"augmented exponential{' with the two extra rows of the phi2 term' if sched else ''}, FP64, 1 thread)",
+                     f"({'SuperLU pressure refined in extended precision + ' if coupled else ''}"
+                     + (f"{scheme} with sparse LU stage solves" if scheme != "erem" else
+                        f"substepped Taylor action of the augmented exponential"
+                        f"{' with the two extra rows of the phi2 term' if sched else ''}")
+                     + ", FP64, 1 thread)",
            "seconds": t1 - t0}
     if nsteps in gpu_snaps:
         Tg = gpu_snaps[nsteps]
@@ -359,6 +378,8 @@ TRAFFIC = {
     ("injector512", "fp64", "leja_term"): 6.15e6,    # the same kernel on the same grid: 24.60 MB
     ("layered128", "fp64", "leja_term"): 186.49e6,
     ("batch256", "fp64", "k_batch_fused"): 486.8e9,
+    # one BiCGSTAB iteration (three kernels) of the comparison schemes
+    ("coupled512", "fp64", "bicg_iteration"): 65.23e6,
 }
 
 
@@ -390,6 +411,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pressure-rtol", type=float, default=1e-16)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--scheme", default="erem", choices=list(SCHEMES),
+                    help="temperature scheme of the coupled workloads: EREM or a comparison scheme "
+                         "(ROSM(1), ROSM(1/2), ROS2(1), ROS3p, theta-Euler 1/2 or 1 with Newton)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -410,7 +434,10 @@ def main():
     prob, desc, coupled = make_workload(args.workload)
     log(f"workload {args.workload}: {desc}; N={prob.n}")
     sched = schedule_of(args.workload)
-    res = gpu_run(prob, coupled, args.steps, args.warmup, args.pressure_rtol, mixed=mixed, sched=sched)
+    if args.scheme != "erem" and (not coupled or mixed):
+        raise SystemExit("comparison schemes run on the coupled workloads in FP64")
+    res = gpu_run(prob, coupled, args.steps, args.warmup, args.pressure_rtol, mixed=mixed, sched=sched,
+                  scheme=args.scheme)
     dim = prob.dim
     N = prob.n
     t = res["times"]
@@ -420,6 +447,7 @@ def main():
         "pcg_a": (t["pcg_a_ms"], t["pcg_a_launches"], PCG_A_BYTES[dim] * N),
         "pcg_b": (t["pcg_b_ms"], t["pcg_b_launches"], PCG_B_BYTES[dim] * N),
         "mg_vcycle": (t["mg_ms"], t["mg_cycles"], mg_bytes(t, dim) * N),
+        "bicg_iteration": (t["bicg_ms"], t["bicg_iterations"], BICG_BYTES[dim] * N),
     }
     dominant = max(kern, key=lambda k: kern[k][0])
 
@@ -427,24 +455,30 @@ def main():
         return _roof(kern, name, _traffic(args.workload, args.precision, name))
 
     steps_s = args.steps / res["elapsed"]
+    erem = args.scheme == "erem"
+    metric = METRIC if erem else (f"{args.scheme} coupled steps/s (comparison scheme) & BiCGSTAB iteration GB/s "
+                                  f"(% of HBM peak) at 1e-10 rel. err vs FP64 oracle")
     line = {
-        "metric": METRIC, "value": round(steps_s, 3), "unit": "steps/s", "n_gpus": 1,
+        "metric": metric, "value": round(steps_s, 3), "unit": "steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(1e3 * res["elapsed"] / args.steps, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+f64" if mixed else "f64",
         "data": "synthetic (seeded generators)",
         "config": {"workload": desc, "grid": [prob.nx, prob.ny, prob.nz], "cells": N, "h_s": prob.h,
-                   "tol_r": 1e-7 if mixed else 1e-12, "precision": args.precision, "pressure_rtol": args.pressure_rtol if coupled else None},
+                   "tol_r": 1e-7 if mixed else 1e-12, "precision": args.precision, "pressure_rtol": args.pressure_rtol if coupled else None,
+                   "scheme": args.scheme},
         "roofline": roof(dominant),
-        "leja": roof("leja_term"),
+        "leja": roof("leja_term") if erem else None,
+        "bicg": None if erem else roof("bicg_iteration"),
         "leja_terms_per_step": res["m_per_step"],
+        "bicg_iterations_per_step": None if erem else res["lin_per_step"],
         "substeps": res["last"]["substeps"],
         "pcg_iterations_per_step": res["pcg_per_step"],
-        "interval_hJ": [res["last"]["alpha"] * prob.h, res["last"]["beta"] * prob.h],
+        "interval_hJ": [res["last"]["alpha"] * prob.h, res["last"]["beta"] * prob.h] if erem else None,
     }
     if not args.no_cpu_baseline:
         log(f"cpu baseline: {args.cpu_steps} oracle step(s)")
-        line["cpu_baseline"] = cpu_baseline(prob, coupled, args.cpu_steps, res["snapshots"], sched)
+        line["cpu_baseline"] = cpu_baseline(prob, coupled, args.cpu_steps, res["snapshots"], sched, args.scheme)
     print(json.dumps(line), flush=True)
 
 

@@ -203,3 +203,18 @@ def run_theta_euler(problem, theta: float, nsteps=None, h=None, fluxes=None, rto
         T, it = theta_euler_step(ode.f, ode.jac, T, n * h, h, theta, rtol=rtol)
         its.append(it)
     return T, fluxes, its
+
+
+def coupled_step_scheme(problem, T, scheme: str, h=None):
+    """The sequential coupled step (Sec. 3.2.2) with a comparison scheme for
+    the temperature: steady pressure at T^n, then one step of ROSM(1)
+    ('rosm1'), ROSM(1/2) ('rosm05'), ROS2(1) ('ros2'), ROS3p ('ros3p') or
+    theta-Euler ('theta05', 'theta1') with the fluxes frozen."""
+    h = problem.h if h is None else h
+    fl = oerem.Discretisation(problem, T).fluxes
+    ode = HeatODE(problem, fl)
+    tables = {"rosm1": rosm_table(1.0), "rosm05": rosm_table(0.5), "ros2": ROS2, "ros3p": ROS3P}
+    if scheme in tables:
+        return rosenbrock_step(ode.f, ode.jac, None, T, 0.0, h, tables[scheme])
+    theta = {"theta05": 0.5, "theta1": 1.0}[scheme]
+    return theta_euler_step(ode.f, ode.jac, T, 0.0, h, theta)[0]
