@@ -19,6 +19,9 @@ phi     : phi1 scalar, dense exponential by Taylor scaling-and-squaring,
 erem    : the EREM step and the coupled sequential step (Eq. EERM, Sec. 3.2.2);
           the non-autonomous EREM step (Eq. nEERMg, Sec. 3.2.3).
 adjoint : dense reverse-mode sensitivities of the EREM step map.
+compressible : the transient pressure ODE (Eq. masscon4, Eq. spaceheat3)
+          and its EREM step (Eq. EERM1); the sequential temperature and
+          pressure step (Sec. 3.2.2).
 rosenbrock : the comparison schemes: ROSM(gamma), ROS2(1), ROS3p (Eq. ROS,
           Eq. ROSMh, Tables ros2 and ros3) and theta-Euler with Newton
           (Eq. temscheme), all with exact sparse solves.

@@ -188,6 +188,39 @@ def injector_problem(n: int = 512, seed: int = 0, nsteps: int = 20,
                    law=LAW_CONSTANT, p_left=DP_COUPLED, nsteps=nsteps)
 
 
+# Compressible (transient-pressure) workload: the paper's bulk rock
+# compressibility (Sec. 5, first experiment) and the compressibility of water.
+ALPHA_B = 1.0e-7          # [1/Pa]
+BETA_F = 4.5e-10          # [1/Pa]
+DARCY = 9.869233e-13      # [m^2]
+
+
+def compressible_problem(n: int = 50, seed: int = 0, nsteps: int = 20,
+                         name: str | None = None) -> Problem:
+    """3D n^3 sequential problem with a transient pressure (compressible rock
+    and fluid), standing in for the paper's first reservoir (Sec. 5):
+    1 km x 1 km x 0.1 km (cells 1000/n x 1000/n x 100/n m), two layers - the
+    upper half (z index >= n/2) K = 0.01 D, phi = 0.2, the lower half
+    K = 0.1 D, phi = 0.4 - each with a log-normal perturbation (sigma 0.5,
+    correlation 2 cells) of its permeability; water laws; T0 = 60 C at z = 0
+    rising 3 C per 10 m; injection at 10 C through x = 0 with p_left = 1 MPa,
+    p_right = 0 (Dirichlet faces stand in for the wells); h = 2e4 s.  The
+    initial pressure is the steady pressure at T0 (as in the paper)."""
+    rng = np.random.default_rng(seed)
+    dx, dz = 1000.0 / n, 100.0 / n
+    pert = lognormal_field(rng, (n, n, n), 0.5, 2.0, mean_k=1.0).reshape(n, n, n)
+    zc = np.arange(n)
+    upper = (zc >= n // 2)[:, None, None]
+    k = np.where(upper, 0.01 * DARCY, 0.1 * DARCY) * np.exp(pert)
+    poro = np.where(upper, 0.2, 0.4) * np.ones((n, n, n))
+    zm = (zc + 0.5) * dz
+    T0 = np.broadcast_to((60.0 + 0.3 * zm)[:, None, None], (n, n, n))
+    return Problem(name=name or f"compressible3d_{n}", nx=n, ny=n, nz=n,
+                   logk=np.log(k).ravel().astype(np.float64), poro=poro.ravel().astype(np.float64),
+                   T0=T0.ravel().astype(np.float64).copy(), law=LAW_WATER, p_left=1.0e6,
+                   T_left=10.0, T_right=60.0, h=2.0e4, nsteps=nsteps, dx=dx, dy=dx, dz=dz)
+
+
 @dataclasses.dataclass(frozen=True)
 class InjectorSchedule:
     """Boundary temperatures at time t for the non-autonomous problems and
