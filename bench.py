@@ -86,6 +86,12 @@ def make_workload(name):
                 "Pe~100), injection temperature 50+30 sin(2 pi t / 20h) C: EREM-Leja with the phi2 "
                 "term (Eq. nEERMg), h=1e6 s")
         return prob, desc, False
+    if name == "compressible50":
+        prob = inputs.compressible_problem(50)
+        desc = ("sequential 3D 50^3 (1 km x 1 km x 0.1 km, two layers 0.01/0.1 D, water laws) with a transient "
+                "pressure (alpha_b=1e-7, beta_f=4.5e-10 1/Pa): fluxes of p^n, EREM-Leja temperature step, "
+                "EREM pressure step (Eq. EERM1), h=2e4 s")
+        return prob, desc, False
     if name == "layered128":
         prob = inputs.layered3d_problem(128)
         desc = "linear 3D 128^3 7-point heat transport, layered K (3 decades), EREM-Leja, h=1e6 s"
@@ -99,7 +105,7 @@ def schedule_of(name):
     return inputs.InjectorSchedule() if name == "injector512" else None
 
 
-def gpu_run(prob, coupled, steps, warmup, rtol_p, mixed=False, sched=None, scheme="erem"):
+def gpu_run(prob, coupled, steps, warmup, rtol_p, mixed=False, sched=None, scheme="erem", pmethod="leja"):
     import torch
     from paper_1209_5553_amd.api import EremContext, make_opts
 
@@ -110,10 +116,26 @@ def gpu_run(prob, coupled, steps, warmup, rtol_p, mixed=False, sched=None, schem
     opts = make_opts(precision=1, tol_r=1e-7) if mixed else make_opts()
     state = {"n": 0, "last": None, "pcg": 0}
 
-    if not coupled:
+    comp = prob.name.startswith("compressible")
+    if comp:
+        from paper_1209_5553_amd import inputs
+        pc = torch.as_tensor(inputs.linear_pressure(prob), device=dev)
+        Tn = torch.empty_like(T)
+        popts = (make_opts(method=1, krylov_m=10, max_substeps=4096, tol_r=1e-14) if pmethod == "krylov"
+                 else make_opts(tol_r=1e-14, max_substeps=4096))
+    elif not coupled:
         st = ctx.pressure_and_fluxes(rtol=rtol_p)
 
     def one_step():
+        if comp:
+            # transmissibilities at T^n, fluxes of p^n, temperature, then pressure at T^n
+            Tn.copy_(T)
+            ctx.assemble_transmissibilities(T)
+            ctx.face_fluxes_from_pressure(pc)
+            state["last"] = ctx.step(prob.h, T, opts)
+            state["plast"] = ctx.step_pressure(prob.h, pc, Tn, inputs.ALPHA_B, inputs.BETA_F, popts)
+            state["n"] += 1
+            return
         if coupled:
             # the pressure stays resident in the context: after the first
             # step each solve starts from the previous double-double pressure
@@ -135,17 +157,22 @@ def gpu_run(prob, coupled, steps, warmup, rtol_p, mixed=False, sched=None, schem
         one_step()
         if state["n"] <= 3:
             snapshots[state["n"]] = T.clone()
+            if comp:
+                snapshots[("p", state["n"])] = pc.clone()
     log(f"warmup done ({warmup} steps), last stats {state['last']}")
     torch.cuda.synchronize()
     ctx.profile(True, stride=PROFILE_STRIDE)
     state["pcg"] = 0
     m_total = 0
     lin_total = 0
+    pm_total = 0
     t0 = time.perf_counter()
     for _ in range(steps):
         one_step()
         m_total += state["last"]["m_total"]
         lin_total += state["last"]["iterations"]
+        if comp:
+            pm_total += state["plast"]["m_total"]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     times = ctx.profile_read()
@@ -153,6 +180,7 @@ def gpu_run(prob, coupled, steps, warmup, rtol_p, mixed=False, sched=None, schem
     log(f"timed {steps} steps in {t1 - t0:.3f} s; kernel times {times}")
     snaps = {k: v.cpu().numpy() for k, v in snapshots.items()}
     return dict(elapsed=t1 - t0, times=times, m_per_step=m_total / steps, lin_per_step=lin_total / steps,
+                pressure_m_per_step=pm_total / steps if comp else None, plast=state.get("plast"),
                 pcg_per_step=state["pcg"] / steps, last=state["last"], snapshots=snaps,
                 T_final=T.cpu().numpy())
 
@@ -175,6 +203,11 @@ def cpu_baseline(prob, coupled, nsteps, gpu_snaps, sched=None, scheme="erem"):
                 T, _ = oerem.coupled_step(prob, T, tier="taylor")
         elif sched is not None:
             T, _ = oerem.run_nonautonomous(prob, sched, nsteps=nsteps, tier="taylor")
+        elif prob.name.startswith("compressible"):
+            from oracle import compressible as ocomp
+            from paper_1209_5553_amd import inputs
+            T, P = ocomp.run_sequential(prob, nsteps, prob.h, inputs.ALPHA_B, inputs.BETA_F,
+                                        p0=inputs.linear_pressure(prob), tier="taylor")
         else:
             tier = "dense" if prob.n <= 4096 else "taylor"
             layered = prob.nz > 1
@@ -184,10 +217,17 @@ def cpu_baseline(prob, coupled, nsteps, gpu_snaps, sched=None, scheme="erem"):
            "sample": f"first {nsteps} steps of the same workload from T0 "
                      f"({'SuperLU pressure refined in extended precision + ' if coupled else ''}"
                      + (f"{scheme} with sparse LU stage solves" if scheme != "erem" else
+                        "temperature and pressure by the substepped Taylor action of their augmented exponentials"
+                        if prob.name.startswith("compressible") else
                         f"substepped Taylor action of the augmented exponential"
                         f"{' with the two extra rows of the phi2 term' if sched else ''}")
                      + ", FP64, 1 thread)",
            "seconds": t1 - t0}
+    if ("p", nsteps) in gpu_snaps:
+        from paper_1209_5553_amd import inputs
+        p0 = inputs.linear_pressure(prob)
+        out["gpu_pressure_increment_rel_err"] = float(np.abs((gpu_snaps[("p", nsteps)] - p0) - (P - p0)).max()
+                                                      / np.abs(P - p0).max())
     if nsteps in gpu_snaps:
         Tg = gpu_snaps[nsteps]
         out["gpu_rel_err"] = float(np.abs(Tg - T).max() / np.abs(T).max())
@@ -405,12 +445,15 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="coupled512",
-                    choices=["coupled512", "linear32", "layered128", "injector512", "batch256", "adjoint256"])
+                    choices=["coupled512", "linear32", "layered128", "injector512", "compressible50", "batch256",
+                             "adjoint256"])
     ap.add_argument("--adjoint-start", default="uniform", choices=["uniform", "structured"])
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--pressure-rtol", type=float, default=1e-16)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "mixed"])
+    ap.add_argument("--pressure-method", default="leja", choices=["leja", "krylov"],
+                    help="phi1 of the transient pressure step (compressible50)")
     ap.add_argument("--scheme", default="erem", choices=list(SCHEMES),
                     help="temperature scheme of the coupled workloads: EREM or a comparison scheme "
                          "(ROSM(1), ROSM(1/2), ROS2(1), ROS3p, theta-Euler 1/2 or 1 with Newton)")
@@ -436,8 +479,10 @@ def main():
     sched = schedule_of(args.workload)
     if args.scheme != "erem" and (not coupled or mixed):
         raise SystemExit("comparison schemes run on the coupled workloads in FP64")
+    if args.workload == "compressible50":
+        args.cpu_steps = min(args.cpu_steps, 2)
     res = gpu_run(prob, coupled, args.steps, args.warmup, args.pressure_rtol, mixed=mixed, sched=sched,
-                  scheme=args.scheme)
+                  scheme=args.scheme, pmethod=args.pressure_method)
     dim = prob.dim
     N = prob.n
     t = res["times"]
@@ -472,6 +517,10 @@ def main():
         "bicg": None if erem else roof("bicg_iteration"),
         "leja_terms_per_step": res["m_per_step"],
         "bicg_iterations_per_step": None if erem else res["lin_per_step"],
+        "pressure": None if res["plast"] is None else {
+            "method": args.pressure_method, "terms_per_step": res["pressure_m_per_step"],
+            "substeps": res["plast"]["substeps"],
+            "interval_hJp": [res["plast"]["alpha"] * prob.h, res["plast"]["beta"] * prob.h]},
         "substeps": res["last"]["substeps"],
         "pcg_iterations_per_step": res["pcg_per_step"],
         "interval_hJ": [res["last"]["alpha"] * prob.h, res["last"]["beta"] * prob.h] if erem else None,

@@ -215,6 +215,33 @@ int erem_step_nonautonomous(erem_ctx* ctx, double h, double T_left, double T_rig
                             double dT_left_dt, double dT_right_dt, double* d_T,
                             const erem_opts* opts, erem_stats* stats);
 
+/* ---- transient (compressible) pressure, Eq. masscon4 / spaceheat3 ----
+ *
+ * With a slightly compressible fluid and rock the pressure obeys, per cell,
+ *   dp/dt = G4 = (b - A p) / (V rho(T) S) + (phi alpha_f / S) G2,
+ *   S = phi (beta_f + alpha_b),  alpha_f = -rho'(T) / rho(T),
+ * A p = b the TPFA pressure system of the current transmissibilities (Dirichlet
+ * x faces at p_left, p_right), G2 = dT/dt.  The sequential scheme (Sec. 3.2.2)
+ * takes, per step: transmissibilities at T^n, the face fluxes of p^n
+ * (erem_face_fluxes_from_pressure), the EREM temperature step (erem_step,
+ * which leaves G2 = G(T^n, p^n) in the context), then the EREM pressure step
+ * (Eq. EERM1, erem_step_pressure) with the T^n the caller kept. */
+
+/* Face fluxes F = t (p_i - p_j) of the given pressure d_p (N values, device)
+ * with the current transmissibilities, Dirichlet x faces included. */
+int erem_face_fluxes_from_pressure(erem_ctx* ctx, const double* d_p);
+
+/* d_p <- d_p + h phi1(h J_p) G4 (Eq. EERM1) with J_p = -diag(1/(V rho S)) A
+ * (G2 held fixed in p), at the temperature d_T (T^n; rho, alpha_f and the
+ * storage are evaluated there) and the G2 = F of the context's last
+ * erem_form_jacobian / erem_step.  alpha_b (rock) and beta_f (fluid
+ * compressibility) in 1/Pa, >= 0, not both 0.  phi1 by opts->method (the
+ * paper pairs Krylov for the pressure with Leja for the temperature); the
+ * error scale is tol_a + tol_r max|p|.  Afterwards the context's J and F are
+ * J_p and G4. */
+int erem_step_pressure(erem_ctx* ctx, double h, double* d_p, const double* d_T, double alpha_b, double beta_f,
+                       const erem_opts* opts, erem_stats* stats);
+
 /* ---- comparison schemes: Rosenbrock-type methods and theta-Euler ----
  *
  * The linear systems of these schemes, (I/(tau gamma) - J) k = rhs, are

@@ -101,6 +101,8 @@ SIGNATURES = {
     "erem_step_frozen": (c_int32, [_P, c_double, _P, POINTER(Opts), POINTER(Stats)]),
     "erem_step_nonautonomous": (c_int32, [_P, c_double, c_double, c_double, c_double, c_double, _P,
                                           POINTER(Opts), POINTER(Stats)]),
+    "erem_face_fluxes_from_pressure": (c_int32, [_P, _P]),
+    "erem_step_pressure": (c_int32, [_P, c_double, _P, _P, c_double, c_double, POINTER(Opts), POINTER(Stats)]),
     "erem_shifted_solve": (c_int32, [_P, c_double, _P, _P, c_double, c_int32, POINTER(Stats)]),
     "erem_step_rosenbrock": (c_int32, [_P, c_double, c_int32, _P, c_double, POINTER(Stats)]),
     "erem_step_theta": (c_int32, [_P, c_double, c_double, _P, c_double, c_double, c_int32, POINTER(Stats)]),

@@ -214,6 +214,21 @@ class EremContext:
             ctypes.byref(o), ctypes.byref(st)), "erem_step_nonautonomous")
         return st.as_dict()
 
+    def face_fluxes_from_pressure(self, p):
+        """Face fluxes of the given pressure (erem_face_fluxes_from_pressure)."""
+        self._check(self.lib.erem_face_fluxes_from_pressure(self.handle, self._ptr(p, self.n, "p")),
+                    "erem_face_fluxes_from_pressure")
+
+    def step_pressure(self, h: float, p, T, alpha_b: float, beta_f: float, opts: nat.Opts | None = None):
+        """EREM step of the transient pressure in place on p
+        (erem_step_pressure) at the temperature T (T^n)."""
+        o = opts if opts is not None else make_opts()
+        st = nat.Stats()
+        self._check(self.lib.erem_step_pressure(self.handle, h, self._ptr(p, self.n, "p"), self._ptr(T, self.n, "T"),
+                                                alpha_b, beta_f, ctypes.byref(o), ctypes.byref(st)),
+                    "erem_step_pressure")
+        return st.as_dict()
+
     ROS_SCHEMES = {"rosm1": 0, "rosm05": 1, "ros2": 2, "ros3p": 3}
 
     def shifted_solve(self, sigma: float, b, x, rtol: float = 1e-13, max_iter: int = 10000):

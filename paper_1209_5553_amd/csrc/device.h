@@ -93,6 +93,11 @@ hipError_t launch_gershgorin(const Dims& d, const double* coef, AsmReduce* red, 
 hipError_t launch_stencil_axpy(const Dims& d, const double* coef, const double* v,
                                const double* u, double* w, hipStream_t s,
                                const double* g = nullptr, double tg = 0.0);
+// J_p stencil, G4 over G2 (in place), Gershgorin interval and max |p| of the
+// transient pressure ODE at (T, p) with the current faces
+hipError_t launch_pressure_ode(const Dims& d, const Phys& ph, const double* poro, const double* T, const double* p,
+                               const double* tx, const double* ty, const double* tz, double alpha_b, double beta_f,
+                               double* coef, double* G, AsmReduce* red, hipStream_t s);
 // Gt = D_t G for boundary temperature rates dTl (x = 0) and dTr (x = nx)
 hipError_t launch_time_rate(const Dims& d, const Phys& ph, const double* poro, const double* fx,
                             const double* T, double dTl, double dTr, double* Gt, hipStream_t s);

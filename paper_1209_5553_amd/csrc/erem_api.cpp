@@ -1149,6 +1149,41 @@ int erem_step_nonautonomous(erem_ctx* c, double h, double T_left, double T_right
   return step_core(c, h, d_T, o, stats, c->tmax, c->gt);
 }
 
+int erem_face_fluxes_from_pressure(erem_ctx* c, const double* d_p) {
+  if (!c) return EREM_EINVAL;
+  if (!d_p) return fail(c, EREM_EINVAL, "p is NULL");
+  if (!c->trans_set) return fail(c, EREM_EINVAL, "erem_assemble_transmissibilities must come first");
+  HIP_TRY(c, launch_face_fluxes(c->d, c->ph, d_p, c->tx, c->ty, c->tz, c->fx, c->fy, c->fz, c->stream));
+  c->flux_set = true;
+  return EREM_OK;
+}
+
+int erem_step_pressure(erem_ctx* c, double h, double* d_p, const double* d_T, double alpha_b, double beta_f,
+                       const erem_opts* o, erem_stats* stats) {
+  if (!c) return EREM_EINVAL;
+  int rc = check_opts(c, o);
+  if (rc) return rc;
+  if (!d_p || !d_T) return fail(c, EREM_EINVAL, "p and T must be non-NULL");
+  if (!(h > 0) || !std::isfinite(h)) return fail(c, EREM_EINVAL, "h must be > 0");
+  if (!(alpha_b >= 0) || !(beta_f >= 0) || !(alpha_b + beta_f > 0) || !std::isfinite(alpha_b + beta_f))
+    return fail(c, EREM_EINVAL, "alpha_b and beta_f must be >= 0, finite and not both 0");
+  if (!c->trans_set) return fail(c, EREM_EINVAL, "erem_assemble_transmissibilities must come first");
+  if (!c->jac_set) return fail(c, EREM_EINVAL, "G2 = dT/dt must be in the context (erem_form_jacobian or erem_step)");
+  if (o->method == EREM_METHOD_KRYLOV && o->precision != EREM_PREC_FP64)
+    return fail(c, EREM_EINVAL, "the Krylov method runs in FP64 only");
+  HIP_TRY(c, launch_pressure_ode(c->d, c->ph, c->poro, d_T, d_p, c->tx, c->ty, c->tz, alpha_b, beta_f, c->coef,
+                                 c->F, c->red, c->stream));
+  c->coef32_valid = false;
+  rc = read_reduce(c);
+  if (rc) return rc;
+  // the pressure keeps its own Newton-degree memory (the temperature
+  // evaluations of the same steps need far fewer terms)
+  std::swap(c->last_m, c->last_m_p);
+  rc = step_core(c, h, d_p, o, stats, c->tmax);
+  std::swap(c->last_m, c->last_m_p);
+  return rc;
+}
+
 int erem_step_frozen(erem_ctx* c, double h, double* d_T, const erem_opts* o, erem_stats* stats) {
   if (!c) return EREM_EINVAL;
   int rc = step_checks(c, h, d_T, o);

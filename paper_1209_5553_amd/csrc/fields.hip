@@ -780,6 +780,90 @@ __global__ __launch_bounds__(kThreads) void k_pcg_b(Dims d, double* __restrict__
   }
 }
 
+// ---------------------------------------------------------------------------
+// The transient pressure ODE of a slightly compressible fluid in a slightly
+// compressible rock (Eq. masscon4, Eq. spaceheat3), per cell:
+//   D dp/dt = -(A p - b) + D (phi alpha_f / S) G2,   D = V rho(T) S,
+//   S = phi (beta_f + alpha_b),  alpha_f = -rho'(T) / rho(T),
+// A p = b the TPFA pressure system at the mobility of the last assembly
+// (faces, Dirichlet x faces), G2 = dT/dt.  Writes J_p = -D^{-1} A as a
+// stencil, G4 = dp/dt over G2 (in place), the Gershgorin interval of J_p
+// and max |p|.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kThreads) void k_pressure_ode(Dims d, Phys ph, const double* __restrict__ poro,
+                                                 const double* __restrict__ T, const double* __restrict__ p,
+                                                 const double* __restrict__ tx, const double* __restrict__ ty,
+                                                 const double* __restrict__ tz, double alpha_b, double beta_f,
+                                                 double* __restrict__ coef, double* G, AsmReduce* red) {
+  const int x = blockIdx.x * kBX + threadIdx.x;
+  const int y = blockIdx.y * kBY + threadIdx.y;
+  const int z = blockIdx.z;
+  double lo = INFINITY, hi = -INFINITY, pmax = 0.0;
+  if (x < d.nx && y < d.ny) {
+    const int N = d.N;
+    const int i = x + d.nx * (y + d.ny * z);
+    const int pl = d.nx * d.ny;
+    const bool has[6] = {x > 0, x + 1 < d.nx, y > 0, y + 1 < d.ny, d.dim == 3 && z > 0, d.dim == 3 && z + 1 < d.nz};
+    const int nbi[6] = {has[0] ? i - 1 : i, has[1] ? i + 1 : i, has[2] ? i - d.nx : i,
+                        has[3] ? i + d.nx : i, has[4] ? i - pl : i, has[5] ? i + pl : i};
+    const FaceT f = load_faces(d, tx, ty, tz, x, y, z);
+    const double pc = p[i];
+    double pn[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) pn[k] = p[nbi[k]];
+    const double Ti = T[i], phi = poro[i], g2 = G[i];
+    const double fk[6] = {f.w, f.e, f.s, f.n, f.b, f.t};
+    const double dg = f.w + f.e + f.s + f.n + f.b + f.t;
+    double r = -dg * pc;  // b - A p
+#pragma unroll
+    for (int k = 0; k < 6; ++k)
+      if (has[k]) r += fk[k] * pn[k];
+    if (x == 0) r += f.w * ph.p_left;
+    if (x + 1 == d.nx) r += f.e * ph.p_right;
+    const double rho = rho_of(Ti, ph);
+    const double S = phi * (beta_f + alpha_b);
+    const double inv = 1.0 / (d.dx * d.dy * d.dz * rho * S);
+    const double af = -drho_of(ph) / rho;
+    G[i] = r * inv + phi * af / S * g2;
+    const double jc = -dg * inv;
+    coef[i] = jc;
+    double rad = 0.0;
+    const int ndir = d.dim == 3 ? 7 : 5;
+    for (int k = 1; k < ndir; ++k) {
+      const double c = has[k - 1] ? fk[k - 1] * inv : 0.0;
+      coef[k * N + i] = c;
+      rad += c;
+    }
+    lo = jc - rad;
+    hi = jc + rad;
+    pmax = fabs(pc);
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    lo = fmin(lo, __shfl_down(lo, off, 64));
+    hi = fmax(hi, __shfl_down(hi, off, 64));
+    pmax = fmax(pmax, __shfl_down(pmax, off, 64));
+  }
+  __shared__ double sh[3][kThreads / 64];
+  const int t = tid_lin();
+  if ((t & 63) == 0) {
+    sh[0][t >> 6] = lo;
+    sh[1][t >> 6] = hi;
+    sh[2][t >> 6] = pmax;
+  }
+  __syncthreads();
+  if (t == 0) {
+    for (int w = 1; w < kThreads / 64; ++w) {
+      sh[0][0] = fmin(sh[0][0], sh[0][w]);
+      sh[1][0] = fmax(sh[1][0], sh[1][w]);
+      sh[2][0] = fmax(sh[2][0], sh[2][w]);
+    }
+    const int k = red_slot();
+    atomicMin(&red->lo[k], ord_encode(sh[0][0]));
+    atomicMax(&red->hi[k], ord_encode(sh[1][0]));
+    atomicMax(&red->tmax[k], ord_encode(sh[2][0]));
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -825,6 +909,15 @@ hipError_t launch_absmax(const Dims& d, const double* v, AsmReduce* red, hipStre
 hipError_t launch_stencil_axpy(const Dims& d, const double* coef, const double* v, const double* u,
                                double* w, hipStream_t s, const double* g, double tg) {
   hipLaunchKernelGGL(k_stencil_axpy, cell_grid(d), cell_block(), 0, s, d, coef, v, u, w, g, tg);
+  return hipGetLastError();
+}
+
+hipError_t launch_pressure_ode(const Dims& d, const Phys& ph, const double* poro, const double* T, const double* p,
+                               const double* tx, const double* ty, const double* tz, double alpha_b, double beta_f,
+                               double* coef, double* G, AsmReduce* red, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset_reduce, dim3(1), dim3(64), 0, s, red);
+  hipLaunchKernelGGL(k_pressure_ode, cell_grid(d), cell_block(), 0, s, d, ph, poro, T, p, tx, ty, tz, alpha_b, beta_f,
+                     coef, G, red);
   return hipGetLastError();
 }
 

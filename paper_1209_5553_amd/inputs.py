@@ -205,7 +205,9 @@ def compressible_problem(n: int = 50, seed: int = 0, nsteps: int = 20,
     correlation 2 cells) of its permeability; water laws; T0 = 60 C at z = 0
     rising 3 C per 10 m; injection at 10 C through x = 0 with p_left = 1 MPa,
     p_right = 0 (Dirichlet faces stand in for the wells); h = 2e4 s.  The
-    initial pressure is the steady pressure at T0 (as in the paper)."""
+    initial pressure is linear_pressure(): linear in x between the boundary
+    values, so the first steps relax it toward the steady pressure of the
+    heterogeneous field."""
     rng = np.random.default_rng(seed)
     dx, dz = 1000.0 / n, 100.0 / n
     pert = lognormal_field(rng, (n, n, n), 0.5, 2.0, mean_k=1.0).reshape(n, n, n)
@@ -219,6 +221,14 @@ def compressible_problem(n: int = 50, seed: int = 0, nsteps: int = 20,
                    logk=np.log(k).ravel().astype(np.float64), poro=poro.ravel().astype(np.float64),
                    T0=T0.ravel().astype(np.float64).copy(), law=LAW_WATER, p_left=1.0e6,
                    T_left=10.0, T_right=60.0, h=2.0e4, nsteps=nsteps, dx=dx, dy=dx, dz=dz)
+
+
+def linear_pressure(problem: Problem) -> np.ndarray:
+    """Initial pressure of the compressible workload: p_left + (p_right -
+    p_left) (x + 1/2) / nx at cell centres (flat, float64)."""
+    xs = (np.arange(problem.nx) + 0.5) / problem.nx
+    row = problem.p_left + (problem.p_right - problem.p_left) * xs
+    return np.broadcast_to(row, (problem.nz, problem.ny, problem.nx)).ravel().astype(np.float64).copy()
 
 
 @dataclasses.dataclass(frozen=True)
