@@ -274,6 +274,18 @@ int erem_shifted_solve(erem_ctx* ctx, double sigma, const double* d_b, double* d
 int erem_step_rosenbrock(erem_ctx* ctx, double h, int32_t scheme, double* d_T, double lin_rtol,
                          erem_stats* stats);
 
+/* The same step for boundary temperatures that change in time (Eq. ROSf,
+ * Eq. ROSMh with D_t f): T_left_stage[i], T_right_stage[i] (host arrays, one
+ * value per stage) are the boundary temperatures at the stage times
+ * t_n + alpha_i h (alpha = (0) for ROSM, (0, 1) for ROS2(1), (0, 1, 1) for
+ * ROS3p), dT_left_dt and dT_right_dt their rates at t_n.  J and G are formed
+ * at t_n, D_t f at t_n as in erem_step_nonautonomous, G of stage i at its
+ * stage time, and stage i adds h gamma_i D_t f to its right-hand side.  The
+ * context's boundary temperatures are left at the stage-0 values. */
+int erem_step_rosenbrock_nonautonomous(erem_ctx* ctx, double h, int32_t scheme, const double* T_left_stage,
+                                       const double* T_right_stage, double dT_left_dt, double dT_right_dt,
+                                       double* d_T, double lin_rtol, erem_stats* stats);
+
 /* One theta-Euler step in place (Eq. temscheme): X = T^{n+1} solves
  *   X - h theta G(X) - h (1 - theta) G(T^n) - T^n = 0
  * by Newton's method from X_0 = T^n, (I - h theta J(X_k)) dX = -F(X_k), until

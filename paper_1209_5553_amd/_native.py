@@ -105,6 +105,8 @@ SIGNATURES = {
     "erem_step_pressure": (c_int32, [_P, c_double, _P, _P, c_double, c_double, POINTER(Opts), POINTER(Stats)]),
     "erem_shifted_solve": (c_int32, [_P, c_double, _P, _P, c_double, c_int32, POINTER(Stats)]),
     "erem_step_rosenbrock": (c_int32, [_P, c_double, c_int32, _P, c_double, POINTER(Stats)]),
+    "erem_step_rosenbrock_nonautonomous": (c_int32, [_P, c_double, c_int32, _PD, _PD, c_double, c_double, _P,
+                                                     c_double, POINTER(Stats)]),
     "erem_step_theta": (c_int32, [_P, c_double, c_double, _P, c_double, c_double, c_int32, POINTER(Stats)]),
     "erem_coupled_step": (c_int32, [_P, c_double, _P, c_double, POINTER(Opts), POINTER(Tape),
                                     POINTER(Tape), POINTER(Stats)]),

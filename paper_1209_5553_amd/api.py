@@ -248,6 +248,25 @@ class EremContext:
                     "erem_step_rosenbrock")
         return st.as_dict()
 
+    ROS_ALPHA = {"rosm1": (0.0,), "rosm05": (0.0,), "ros2": (0.0, 1.0), "ros3p": (0.0, 1.0, 1.0)}
+
+    def step_rosenbrock_nonautonomous(self, h: float, T, scheme: str, T_left_stage, T_right_stage,
+                                      dT_left_dt: float, dT_right_dt: float, lin_rtol: float = 1e-13):
+        """Non-autonomous Rosenbrock-type step in place
+        (erem_step_rosenbrock_nonautonomous): boundary temperatures at the
+        stage times t_n + ROS_ALPHA[scheme][i] h and their rates at t_n."""
+        n = len(self.ROS_ALPHA[scheme])
+        tl = np.ascontiguousarray(T_left_stage, dtype=np.float64)
+        tr = np.ascontiguousarray(T_right_stage, dtype=np.float64)
+        if tl.size != n or tr.size != n:
+            raise ValueError(f"{scheme} takes {n} stage values")
+        st = nat.Stats()
+        self._check(self.lib.erem_step_rosenbrock_nonautonomous(
+            self.handle, h, self.ROS_SCHEMES[scheme], tl.ctypes.data_as(nat._PD), tr.ctypes.data_as(nat._PD),
+            dT_left_dt, dT_right_dt, self._ptr(T, self.n, "T"), lin_rtol, ctypes.byref(st)),
+            "erem_step_rosenbrock_nonautonomous")
+        return st.as_dict()
+
     def step_theta(self, h: float, T, theta: float = 0.5, newton_rtol: float = 1e-13,
                    lin_rtol: float = 1e-13, max_newton: int = 30):
         """One theta-Euler step with Newton's method in place (erem_step_theta)."""

@@ -31,23 +31,38 @@ struct RosScheme {
   double a[3][3];
   double c[3][3];
   double b[3];
+  double gam[3];    // gamma_i of the D_t f term
+  double alpha[3];  // stage times t_n + alpha_i h
 };
 
 // ROSM(gamma) is the one-stage method (I/(tau gamma) - J) k = f,
 // y+ = y + k / gamma (Eq. ROS).
+// ROSM(gamma) with a time-dependent right-hand side carries gamma tau D_t f
+// (Eq. ROSf).
 const RosScheme kSchemes[4] = {
-    {1, 1.0, {{0.0}}, {{0.0}}, {1.0}},
-    {1, 0.5, {{0.0}}, {{0.0}}, {2.0}},
+    {1, 1.0, {{0.0}}, {{0.0}}, {1.0}, {1.0}, {0.0}},
+    {1, 0.5, {{0.0}}, {{0.0}}, {2.0}, {0.5}, {0.0}},
     // Table ros2: ROS2(1)
     {2, 1.707106781186547,
      {{0.0}, {5.857864376269050e-01}},
      {{0.0}, {1.171572875253810e+00}},
-     {8.786796564403575e-01, 2.928932188134525e-01}},
+     {8.786796564403575e-01, 2.928932188134525e-01},
+     {1.707106781186547, -1.707106781186547},
+     {0.0, 1.0}},
     // Table ros3: ROS3p
     {3, 7.886751345948129e-01,
      {{0.0}, {1.267949192431123}, {1.267949192431123, 0.0}},
      {{0.0}, {1.607695154586736}, {3.464101615137755, 1.732050807568877}},
-     {2.0, 5.773502691896258e-01, 4.226497308103742e-01}},
+     {2.0, 5.773502691896258e-01, 4.226497308103742e-01},
+     {7.886751345948129e-01, -2.113248654051871e-01, -1.077350269189626},
+     {0.0, 1.0, 1.0}},
+};
+
+// Boundary data of a non-autonomous Rosenbrock step: the boundary
+// temperatures at the stage times t_n + alpha_i h and their rates at t_n.
+struct StageBc {
+  double Tl[3], Tr[3];
+  double dTl, dTr;
 };
 
 int ensure_bicg(erem_ctx* c) {
@@ -134,6 +149,81 @@ int scheme_checks(erem_ctx* c, double h, const double* d_T, double rtol) {
   return EREM_OK;
 }
 
+int ros_step(erem_ctx* c, double h, int32_t scheme, double* d_T, double lin_rtol, erem_stats* stats,
+             const StageBc* bc) {
+  int rc = scheme_checks(c, h, d_T, lin_rtol);
+  if (rc) return rc;
+  if (scheme < EREM_ROSM_1 || scheme > EREM_ROS3P) return fail(c, EREM_EINVAL, "unknown Rosenbrock scheme");
+  const RosScheme& S = kSchemes[scheme];
+  if (bc) {
+    for (int i = 0; i < S.stages; ++i)
+      if (!std::isfinite(bc->Tl[i]) || !std::isfinite(bc->Tr[i]))
+        return fail(c, EREM_EINVAL, "stage boundary temperatures must be finite");
+    if (!std::isfinite(bc->dTl) || !std::isfinite(bc->dTr)) return fail(c, EREM_EINVAL, "rates must be finite");
+  }
+  rc = ensure_bicg(c);
+  if (rc) return rc;
+  if (bc && !c->gt) {
+    rc = dev_alloc(c, &c->gt, c->d.N);
+    if (!rc) rc = dev_alloc(c, &c->zt, c->d.N);
+    if (rc) return EREM_ENOMEM;
+  }
+  if (bc) { c->ph.T_left = bc->Tl[0]; c->ph.T_right = bc->Tr[0]; }
+  rc = erem_form_jacobian(c, d_T);  // J_n and G(T^n, t_n)
+  if (rc) return rc;
+  const Dims& d = c->d;
+  // D_t f(T^n, t_n): the boundary vector with the rates, over V C
+  if (bc) HIP_TRY(c, launch_time_rate(d, c->ph, c->poro, c->fx, d_T, bc->dTl, bc->dTr, c->gt, c->stream));
+  const double sigma = 1.0 / (h * S.gamma);
+  double* k[3] = {c->rs_k0, c->rs_k1, c->rs_k2};
+  int total = 0;
+  for (int i = 0; i < S.stages; ++i) {
+    const double* rhs = c->F;
+    const double wt = bc ? h * S.gam[i] : 0.0;  // weight of D_t f
+    if (i == 0 && bc) {
+      rc = lincomb(c, c->rs_rhs, {{c->F, 1.0}, {c->gt, wt}});
+      if (rc) return rc;
+      rhs = c->rs_rhs;
+    } else if (i > 0) {
+      // Y = T + sum_j a_ij k_j, then G(Y, t_n + alpha_i h) (the scratch
+      // stencil keeps J_n)
+      if (i == 1) rc = lincomb(c, c->rs_y, {{d_T, 1.0}, {k[0], S.a[1][0]}});
+      else rc = lincomb(c, c->rs_y, {{d_T, 1.0}, {k[0], S.a[2][0]}, {k[1], S.a[2][1]}});
+      if (rc) return rc;
+      if (bc) { c->ph.T_left = bc->Tl[i]; c->ph.T_right = bc->Tr[i]; }
+      HIP_TRY(c, launch_reset_reduce(c->red, c->stream));
+      HIP_TRY(c, launch_assemble(d, c->ph, c->poro, c->fx, c->fy, c->fz, c->rs_y, c->rs_coef, c->rs_g, c->red,
+                                 c->stream));
+      // rhs = G(Y) - sum_j (c_ij / h) k_j (+ h gamma_i D_t f)
+      if (i == 1) {
+        if (bc) rc = lincomb(c, c->rs_rhs, {{c->rs_g, 1.0}, {k[0], -S.c[1][0] / h}, {c->gt, wt}});
+        else rc = lincomb(c, c->rs_rhs, {{c->rs_g, 1.0}, {k[0], -S.c[1][0] / h}});
+      } else {
+        if (bc)
+          rc = lincomb(c, c->rs_rhs, {{c->rs_g, 1.0}, {k[0], -S.c[2][0] / h}, {k[1], -S.c[2][1] / h}, {c->gt, wt}});
+        else rc = lincomb(c, c->rs_rhs, {{c->rs_g, 1.0}, {k[0], -S.c[2][0] / h}, {k[1], -S.c[2][1] / h}});
+      }
+      if (rc) return rc;
+      rhs = c->rs_rhs;
+    }
+    int it = 0;
+    rc = bicg_solve(c, sigma, rhs, k[i], lin_rtol, 10000, &it);
+    if (bc) { c->ph.T_left = bc->Tl[0]; c->ph.T_right = bc->Tr[0]; }
+    if (rc) return rc;
+    total += it;
+  }
+  if (S.stages == 1) rc = lincomb(c, d_T, {{d_T, 1.0}, {k[0], S.b[0]}});
+  else if (S.stages == 2) rc = lincomb(c, d_T, {{d_T, 1.0}, {k[0], S.b[0]}, {k[1], S.b[1]}});
+  else rc = lincomb(c, d_T, {{d_T, 1.0}, {k[0], S.b[0]}, {k[1], S.b[1]}, {k[2], S.b[2]}});
+  if (rc) return rc;
+  if (stats) {
+    *stats = erem_stats{};
+    stats->substeps = S.stages;
+    stats->iterations = total;
+  }
+  return EREM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -160,49 +250,23 @@ int erem_shifted_solve(erem_ctx* c, double sigma, const double* d_b, double* d_x
 int erem_step_rosenbrock(erem_ctx* c, double h, int32_t scheme, double* d_T, double lin_rtol,
                          erem_stats* stats) {
   if (!c) return EREM_EINVAL;
-  int rc = scheme_checks(c, h, d_T, lin_rtol);
-  if (rc) return rc;
+  return ros_step(c, h, scheme, d_T, lin_rtol, stats, nullptr);
+}
+
+int erem_step_rosenbrock_nonautonomous(erem_ctx* c, double h, int32_t scheme, const double* T_left_stage,
+                                       const double* T_right_stage, double dT_left_dt, double dT_right_dt,
+                                       double* d_T, double lin_rtol, erem_stats* stats) {
+  if (!c) return EREM_EINVAL;
+  if (!T_left_stage || !T_right_stage) return fail(c, EREM_EINVAL, "stage boundary arrays are NULL");
   if (scheme < EREM_ROSM_1 || scheme > EREM_ROS3P) return fail(c, EREM_EINVAL, "unknown Rosenbrock scheme");
-  const RosScheme& S = kSchemes[scheme];
-  rc = ensure_bicg(c);
-  if (rc) return rc;
-  rc = erem_form_jacobian(c, d_T);  // J_n and G(T^n)
-  if (rc) return rc;
-  const Dims& d = c->d;
-  const double sigma = 1.0 / (h * S.gamma);
-  double* k[3] = {c->rs_k0, c->rs_k1, c->rs_k2};
-  int total = 0;
-  for (int i = 0; i < S.stages; ++i) {
-    const double* rhs = c->F;
-    if (i > 0) {
-      // Y = T + sum_j a_ij k_j, then G(Y) (the scratch stencil keeps J_n)
-      if (i == 1) rc = lincomb(c, c->rs_y, {{d_T, 1.0}, {k[0], S.a[1][0]}});
-      else rc = lincomb(c, c->rs_y, {{d_T, 1.0}, {k[0], S.a[2][0]}, {k[1], S.a[2][1]}});
-      if (rc) return rc;
-      HIP_TRY(c, launch_reset_reduce(c->red, c->stream));
-      HIP_TRY(c, launch_assemble(d, c->ph, c->poro, c->fx, c->fy, c->fz, c->rs_y, c->rs_coef, c->rs_g, c->red,
-                                 c->stream));
-      // rhs = G(Y) - sum_j (c_ij / h) k_j
-      if (i == 1) rc = lincomb(c, c->rs_rhs, {{c->rs_g, 1.0}, {k[0], -S.c[1][0] / h}});
-      else rc = lincomb(c, c->rs_rhs, {{c->rs_g, 1.0}, {k[0], -S.c[2][0] / h}, {k[1], -S.c[2][1] / h}});
-      if (rc) return rc;
-      rhs = c->rs_rhs;
-    }
-    int it = 0;
-    rc = bicg_solve(c, sigma, rhs, k[i], lin_rtol, 10000, &it);
-    if (rc) return rc;
-    total += it;
+  StageBc bc{};
+  for (int i = 0; i < kSchemes[scheme].stages; ++i) {
+    bc.Tl[i] = T_left_stage[i];
+    bc.Tr[i] = T_right_stage[i];
   }
-  if (S.stages == 1) rc = lincomb(c, d_T, {{d_T, 1.0}, {k[0], S.b[0]}});
-  else if (S.stages == 2) rc = lincomb(c, d_T, {{d_T, 1.0}, {k[0], S.b[0]}, {k[1], S.b[1]}});
-  else rc = lincomb(c, d_T, {{d_T, 1.0}, {k[0], S.b[0]}, {k[1], S.b[1]}, {k[2], S.b[2]}});
-  if (rc) return rc;
-  if (stats) {
-    *stats = erem_stats{};
-    stats->substeps = S.stages;
-    stats->iterations = total;
-  }
-  return EREM_OK;
+  bc.dTl = dT_left_dt;
+  bc.dTr = dT_right_dt;
+  return ros_step(c, h, scheme, d_T, lin_rtol, stats, &bc);
 }
 
 int erem_step_theta(erem_ctx* c, double h, double theta, double* d_T, double newton_rtol, double lin_rtol,

@@ -157,3 +157,36 @@ def test_bad_arguments_are_rejected(torch_mod):
         ctx.step_rosenbrock(prob.h, T, "ros2", lin_rtol=0.0)
     torch.cuda.synchronize()
     assert torch.equal(T, T0)
+
+
+NA_CASES = {
+    "linear 24x24 from t=0": (lambda: inputs.linear_problem(24, seed=11), 0.0, 3),
+    "water laws 20x20, random T0, from t=5e6": (lambda: _water_problem(20, 12), 5.0e6, 2),
+    "injector 64x64, rising ramp": (lambda: inputs.injector_problem(64, seed=13), 0.0, 3),
+}
+
+
+@pytest.mark.parametrize("scheme", list(TABLES))
+@pytest.mark.parametrize("case", list(NA_CASES))
+def test_nonautonomous_rosenbrock_matches_oracle(torch_mod, case, scheme):
+    """Eq. ROSf / Eq. ROSMh with a time-varying injection temperature: stage
+    boundary values at t_n + alpha_i h, D_t f at t_n, the gamma_i column."""
+    torch = torch_mod
+    from paper_1209_5553_amd.api import EremContext
+    make, t0, nsteps = NA_CASES[case]
+    prob = make()
+    sched = inputs.InjectorSchedule(ramp=2e-6) if "ramp" in case else inputs.InjectorSchedule()
+    ctx, T = _ctx(torch, prob)
+    t = t0
+    alpha = EremContext.ROS_ALPHA[scheme]
+    for _ in range(nsteps):
+        stage = [sched(t + a * prob.h) for a in alpha]
+        _, _, dTl, dTr = sched(t)
+        st = ctx.step_rosenbrock_nonautonomous(prob.h, T, scheme, [s[0] for s in stage], [s[1] for s in stage],
+                                               dTl, dTr)
+        t += prob.h
+    torch.cuda.synchronize()
+    ref, _ = oros.run_rosenbrock(prob, TABLES[scheme], nsteps=nsteps, schedule=sched, t0=t0)
+    err = rel_inf(T.cpu().numpy() - prob.T0, ref - prob.T0)
+    _say(f"non-autonomous {scheme} {case}: {st}, rel err {err:.2e}")
+    assert err <= TOL
