@@ -137,3 +137,32 @@ def test_bad_arguments_are_rejected(torch_mod):
         ctx.step_pressure(prob.h, p, T, 0.0, 0.0)
     torch.cuda.synchronize()
     assert torch.count_nonzero(p).item() == 0
+
+
+def test_mixed_precision_pressure_close_to_fp64(torch_mod):
+    """The Newton-Leja pressure passes in FP32 (the a10 form) stay within
+    1e-5 of the FP64 GPU result on the increment."""
+    from paper_1209_5553_amd.api import make_opts
+    prob = inputs.compressible_problem(12, seed=21)
+    p0 = inputs.linear_pressure(prob)
+
+    def run(opts):
+        from paper_1209_5553_amd.api import EremContext
+        torch = torch_mod
+        ctx = EremContext.from_problem(prob, device="cuda:0")
+        T = torch.as_tensor(prob.T0, dtype=torch.float64, device="cuda:0").clone()
+        p = torch.as_tensor(p0, dtype=torch.float64, device="cuda:0").clone()
+        for _ in range(2):
+            Tn = T.clone()
+            ctx.assemble_transmissibilities(T)
+            ctx.face_fluxes_from_pressure(p)
+            ctx.step(prob.h, T)
+            st = ctx.step_pressure(prob.h, p, Tn, AB, BF, opts)
+        torch.cuda.synchronize()
+        return p.cpu().numpy(), st
+
+    p64, _ = run(make_opts(tol_r=1e-14, max_substeps=4096))
+    p32, st = run(make_opts(precision=1, tol_r=1e-7, max_substeps=4096))
+    err = rel_inf(p32 - p0, p64 - p0)
+    _say(f"mixed-precision pressure: {st}, rel err vs FP64 {err:.2e}")
+    assert err <= 1e-5
