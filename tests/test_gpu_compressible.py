@@ -166,3 +166,27 @@ def test_mixed_precision_pressure_close_to_fp64(torch_mod):
     err = rel_inf(p32 - p0, p64 - p0)
     _say(f"mixed-precision pressure: {st}, rel err vs FP64 {err:.2e}")
     assert err <= 1e-5
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (5, 1, 1), (1, 4, 3)])
+def test_compressible_degenerate_and_thin_grids(torch_mod, shape):
+    """One cell (the pressure Jacobian is a scalar: the closed form replaces
+    the Newton passes) and thin grids, the pressure by Leja; a long step
+    (h = 1e7 s) so that T and p move by more than their last bits."""
+    nx, ny, nz = shape
+    base = inputs.compressible_problem(4, seed=31)
+    rng = np.random.default_rng(nx + 10 * ny + 100 * nz)
+    N = nx * ny * nz
+    prob = inputs.Problem(name=f"thin_{nx}x{ny}x{nz}", nx=nx, ny=ny, nz=nz,
+                          logk=np.log(1e-13 * np.exp(rng.normal(0.0, 0.5, N))), poro=np.full(N, 0.3),
+                          T0=60.0 + rng.random(N), law=inputs.LAW_WATER, p_left=1.0e6, T_left=10.0,
+                          T_right=60.0, h=1.0e7, dx=base.dx, dy=base.dy, dz=base.dz)
+    p0 = inputs.linear_pressure(prob)
+    T, p, stats = _run_gpu(torch_mod, prob, p0, 2, "leja")
+    _say(f"compressible {shape}: {stats[-1][1]}")
+    Tr, pr = oc.run_sequential(prob, 2, prob.h, AB, BF, p0=p0, tier="dense")
+    eT = rel_inf(T - prob.T0, Tr - prob.T0)
+    ep = rel_inf(p - p0, pr - p0)
+    _say(f"  rel err: T {eT:.2e}, p {ep:.2e} (max |dT| {np.abs(Tr - prob.T0).max():.3e} K, "
+         f"max |dp| {np.abs(pr - p0).max():.3e} Pa)")
+    assert eT <= TOL and ep <= TOL

@@ -139,3 +139,23 @@ def test_bad_arguments_are_rejected(torch_mod):
         ctx.step_nonautonomous(prob.h, T, 50.0, 20.0, 1e-6, 0.0, make_opts(method=1))
     torch.cuda.synchronize()
     assert torch.equal(T.cpu(), torch.as_tensor(prob.T0))
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 9), (17, 1)])
+def test_nonautonomous_degenerate_and_strip_grids(torch_mod, shape):
+    """A single cell (J = c I: the closed forms h phi1(hc) and h^2 phi2(hc)
+    replace the Newton passes) and one-cell-wide strips."""
+    nx, ny = shape
+    rng = np.random.default_rng(nx * 100 + ny)
+    N = nx * ny
+    logk = np.log(1e-12) + rng.normal(0.0, 1.0, N)      # i.i.d. log-normal (no smoothing on strips)
+    prob = inputs.Problem(name=f"strip_{nx}x{ny}", nx=nx, ny=ny, nz=1, logk=logk,
+                          poro=np.full(N, inputs.POROSITY), T0=np.full(N, inputs.T_INITIAL),
+                          p_left=inputs.DP_COUPLED)
+    sched = inputs.InjectorSchedule()
+    got, stats, _ = _run_gpu(torch_mod, prob, sched, 3, 1.0e6)
+    _say(f"non-autonomous {nx}x{ny}: {stats[-1]}")
+    ref, _ = oerem.run_nonautonomous(prob, sched, nsteps=3, t0=1.0e6, tier="dense")
+    err = rel_inf(got - prob.T0, ref - prob.T0)
+    _say(f"  rel err {err:.2e}")
+    assert err <= TOL

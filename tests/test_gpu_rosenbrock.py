@@ -190,3 +190,28 @@ def test_nonautonomous_rosenbrock_matches_oracle(torch_mod, case, scheme):
     err = rel_inf(T.cpu().numpy() - prob.T0, ref - prob.T0)
     _say(f"non-autonomous {scheme} {case}: {st}, rel err {err:.2e}")
     assert err <= TOL
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 9), (17, 1)])
+def test_schemes_on_degenerate_and_strip_grids(torch_mod, shape):
+    """One cell (a scalar system: BiCGSTAB ends after one iteration) and
+    one-cell-wide strips, for ROS3p and Crank-Nicolson."""
+    torch = torch_mod
+    nx, ny = shape
+    rng = np.random.default_rng(nx * 10 + ny)
+    N = nx * ny
+    prob = inputs.Problem(name=f"strip_{nx}x{ny}", nx=nx, ny=ny, nz=1,
+                          logk=np.log(1e-12) + rng.normal(0.0, 1.0, N), poro=np.full(N, inputs.POROSITY),
+                          T0=np.full(N, inputs.T_INITIAL), p_left=inputs.DP_COUPLED)
+    for name in ("ros3p", "theta05"):
+        ctx, T = _ctx(torch, prob)
+        for _ in range(2):
+            st = ctx.step_rosenbrock(prob.h, T, "ros3p") if name == "ros3p" else ctx.step_theta(prob.h, T, 0.5)
+        torch.cuda.synchronize()
+        if name == "ros3p":
+            ref, _ = oros.run_rosenbrock(prob, oros.ROS3P, nsteps=2)
+        else:
+            ref, _, _ = oros.run_theta_euler(prob, 0.5, nsteps=2)
+        err = rel_inf(T.cpu().numpy() - prob.T0, ref - prob.T0)
+        _say(f"{name} {nx}x{ny}: {st}, rel err {err:.2e}")
+        assert err <= TOL
