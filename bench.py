@@ -9,6 +9,14 @@ EREM temperature step with the real-Leja phi1 (FP64).  Inputs are
 synthetic (seeded generators) and already resident in HBM when timing
 starts.
 
+Other workloads (--workload): linear32, layered128 (3D, --precision mixed for
+the FP32 Newton passes), injector512 (the non-autonomous step with the phi2
+term), compressible50 (the sequential step with a transient pressure,
+--pressure-method leja|krylov), batch256 (256 ragged problems per launch),
+adjoint256 (a coupled step and its adjoint).  --scheme runs the coupled
+workload with a comparison scheme instead of EREM (ROSM(1), ROSM(1/2),
+ROS2(1), ROS3p, theta-Euler 1/2 or 1 with Newton's method).
+
 Prints ONE JSON line: steps/s over the timed steps, the roofline of the
 dominant kernel (HIP-event timing of a sample of the launches inside the
 timed region, one in PROFILE_STRIDE),
