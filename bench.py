@@ -425,6 +425,7 @@ TRAFFIC = {
     ("coupled512", "fp64", "leja_term"): 6.15e6,     # a working 4-term launch moves 24.60 MB
     ("injector512", "fp64", "leja_term"): 6.15e6,    # the same kernel on the same grid: 24.60 MB
     ("layered128", "fp64", "leja_term"): 186.49e6,
+    ("compressible50", "fp64", "leja_term"): 11.34e6,   # the 3D one-term kernel on 125 000 cells
     ("batch256", "fp64", "k_batch_fused"): 486.8e9,
     # one BiCGSTAB iteration (three kernels) of the comparison schemes
     ("coupled512", "fp64", "bicg_iteration"): 65.23e6,
