@@ -190,3 +190,16 @@ def test_compressible_degenerate_and_thin_grids(torch_mod, shape):
     _say(f"  rel err: T {eT:.2e}, p {ep:.2e} (max |dT| {np.abs(Tr - prob.T0).max():.3e} K, "
          f"max |dp| {np.abs(pr - p0).max():.3e} Pa)")
     assert eT <= TOL and ep <= TOL
+
+
+def test_ten_sequential_steps_16(torch_mod):
+    """Ten sequential steps on a 16^3 compressible grid (the pressure relaxes
+    from its linear start), Krylov for the pressure as the paper pairs it."""
+    prob = inputs.compressible_problem(16, seed=16)
+    p0 = inputs.linear_pressure(prob)
+    T, p, stats = _run_gpu(torch_mod, prob, p0, 10, "krylov")
+    Tr, pr = oc.run_sequential(prob, 10, prob.h, AB, BF, p0=p0, tier="taylor")
+    eT = rel_inf(T - prob.T0, Tr - prob.T0)
+    ep = rel_inf(p - p0, pr - p0)
+    _say(f"compressible 16^3 x 10: {stats[-1][1]}, rel err T {eT:.2e}, p {ep:.2e}")
+    assert eT <= TOL and ep <= TOL

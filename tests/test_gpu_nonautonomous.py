@@ -159,3 +159,15 @@ def test_nonautonomous_degenerate_and_strip_grids(torch_mod, shape):
     err = rel_inf(got - prob.T0, ref - prob.T0)
     _say(f"  rel err {err:.2e}")
     assert err <= TOL
+
+
+def test_full_injection_period_128(torch_mod):
+    """A whole injection period (20 steps, 20 C -> 80 C -> 20 C) on a 128 x 128
+    injector grid, every cell against the substepped Taylor oracle."""
+    prob = inputs.injector_problem(128, seed=14)
+    sched = inputs.InjectorSchedule()
+    got, stats, _ = _run_gpu(torch_mod, prob, sched, 20)
+    ref, _ = oerem.run_nonautonomous(prob, sched, nsteps=20, tier="taylor")
+    err = rel_inf(got - prob.T0, ref - prob.T0)
+    _say(f"injector 128^2 x 20 steps: last {stats[-1]}, rel err {err:.2e}")
+    assert err <= TOL
