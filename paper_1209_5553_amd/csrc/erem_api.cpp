@@ -603,8 +603,11 @@ int hphi1_eval(erem_ctx* c, double h, const double* v, const double* g, double s
   int s = 1;
   if (o->rho_max > 0.0) s = std::max(1, static_cast<int>(std::ceil(h * width / o->rho_max)));
   if (s > smax) s = smax;
+  // term budget: the previous evaluation's degree per substep plus one
+  // stop-test group (the launches past the stop return at entry); a degree
+  // that outgrows it restarts the evaluation with the full budget m_max
   int K = o->chunk > 0 ? std::min(o->chunk, o->m_max)
-                       : (c->last_m > 0 ? std::min(o->m_max, c->last_m + 8) : o->m_max);
+                       : (c->last_m > 0 ? std::min(o->m_max, c->last_m + kCheckEvery) : o->m_max);
   int restarts = 0;
   for (;;) {
     int m_used = 0;
