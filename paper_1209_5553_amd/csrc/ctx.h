@@ -73,7 +73,7 @@ struct erem_ctx {
 
   std::vector<double> xi;  // Leja points
   DivDiffCache dd, dd2;  // phi1 and phi2 divided differences
-  int last_m = 0;          // degree used by the previous evaluation
+  int last_m = 0;          // largest substep degree of the previous evaluation
   int last_m_p = 0;        // the same for the transient pressure (its own degree)
   // profiling (HIP events around each Leja term and PCG half-iteration)
   int pcg_last = 0;  // iterations of the last converged CG solve (poll placement)

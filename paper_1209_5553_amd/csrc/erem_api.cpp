@@ -603,7 +603,7 @@ int hphi1_eval(erem_ctx* c, double h, const double* v, const double* g, double s
   int s = 1;
   if (o->rho_max > 0.0) s = std::max(1, static_cast<int>(std::ceil(h * width / o->rho_max)));
   if (s > smax) s = smax;
-  // term budget: the previous evaluation's degree per substep plus one
+  // term budget: the previous evaluation's largest substep degree plus one
   // stop-test group (the launches past the stop return at entry); a degree
   // that outgrows it restarts the evaluation with the full budget m_max
   int K = o->chunk > 0 ? std::min(o->chunk, o->m_max)
@@ -614,9 +614,9 @@ int hphi1_eval(erem_ctx* c, double h, const double* v, const double* g, double s
     double est = 0.0;
     const int rc = leja_hphi1(c, h, v, g, scal, s, K, o, &m_used, &est);
     if (rc == EREM_OK) {
-      int m1 = 0;  // phi1 terms
-      for (int a : c->applied) m1 += a;
-      c->last_m = (m1 + s - 1) / s;
+      int m1 = 0;  // the largest phi1 degree of a substep
+      for (int a : c->applied) m1 = std::max(m1, a);
+      c->last_m = m1;
       if (stats) {
         stats->m_total = m_used;
         stats->substeps = s;
