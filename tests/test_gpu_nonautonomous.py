@@ -171,3 +171,37 @@ def test_full_injection_period_128(torch_mod):
     err = rel_inf(got - prob.T0, ref - prob.T0)
     _say(f"injector 128^2 x 20 steps: last {stats[-1]}, rel err {err:.2e}")
     assert err <= TOL
+
+
+def _reversed_flow_problem(n, seed):
+    """Flow from x = nx to x = 0 (p_right > p_left), so the right boundary
+    is the inflow and its temperature enters b."""
+    rng = np.random.default_rng(seed)
+    logk = inputs.lognormal_field(rng, (n, n), 1.0, 4.0)
+    N = n * n
+    return inputs.Problem(name=f"reversed_{n}", nx=n, ny=n, nz=1, logk=logk,
+                          poro=np.full(N, inputs.POROSITY), T0=np.full(N, inputs.T_INITIAL),
+                          p_left=0.0, p_right=inputs.DP_COUPLED)
+
+
+class _BothEnds:
+    """Both boundary temperatures move: T_left a slow ramp, T_right a sine."""
+
+    def __call__(self, t):
+        w = 2.0 * np.pi / 2.0e7
+        return (40.0 + 1e-6 * t, 50.0 + 25.0 * np.sin(w * t), 1e-6, 25.0 * w * np.cos(w * t))
+
+
+@pytest.mark.parametrize("case", ["reversed flow, both ends moving", "adiabatic x = 0, both ends moving"])
+def test_nonautonomous_right_boundary_and_adiabatic_left(torch_mod, case):
+    """The boundary-rate kernel's other branches: the rate of the right
+    (inflow) temperature, and x = 0 without the conduction half-cell."""
+    prob = _reversed_flow_problem(24, 15) if case.startswith("reversed") else inputs.linear_problem(24, seed=16)
+    if case.startswith("adiabatic"):
+        prob.dirichlet_left = False
+    sched = _BothEnds()
+    got, stats, _ = _run_gpu(torch_mod, prob, sched, 3, 2.0e6)
+    ref, _ = oerem.run_nonautonomous(prob, sched, nsteps=3, t0=2.0e6, tier="dense")
+    err = rel_inf(got - prob.T0, ref - prob.T0)
+    _say(f"{case}: {stats[-1]}, rel err {err:.2e}")
+    assert err <= TOL
