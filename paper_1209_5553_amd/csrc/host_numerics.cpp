@@ -71,14 +71,17 @@ void extend_leja(int n) {
 }
 
 // Lower-triangular (row-major, n x n) product C = A * B.
+// Row i of C is the combination of rows k <= i of B with weights A[i][k], so
+// the inner loop runs along contiguous rows (it vectorises).
 void tri_mul(int n, const double* A, const double* B, double* C) {
   for (int i = 0; i < n; ++i) {
-    for (int j = 0; j <= i; ++j) {
-      double s = 0.0;
-      for (int k = j; k <= i; ++k) s += A[i * n + k] * B[k * n + j];
-      C[i * n + j] = s;
+    double* c = C + static_cast<size_t>(i) * n;
+    for (int j = 0; j < n; ++j) c[j] = 0.0;
+    for (int k = 0; k <= i; ++k) {
+      const double a = A[static_cast<size_t>(i) * n + k];
+      const double* b = B + static_cast<size_t>(k) * n;
+      for (int j = 0; j <= k; ++j) c[j] += a * b[j];
     }
-    for (int j = i + 1; j < n; ++j) C[i * n + j] = 0.0;
   }
 }
 
@@ -125,11 +128,17 @@ void phi_divided_differences(int ell, double hc, double hg, const double* xi, in
   for (int k = degree; k >= 1; --k) {
     const double inv = 1.0 / k;
     for (int i = 0; i < M; ++i) {
-      for (int j = 0; j <= i; ++j) {
-        double v = dg[i] * E[i * M + j];
-        if (i > 0) v += sd[i] * E[(i - 1) * M + j];
-        T[i * M + j] = v * inv + (i == j ? 1.0 : 0.0);
+      double* t = T.data() + static_cast<size_t>(i) * M;
+      const double* e = E.data() + static_cast<size_t>(i) * M;
+      const double di = dg[i];
+      if (i == 0) {
+        t[0] = di * e[0] * inv;
+      } else {
+        const double* ep = e - M;  // row i - 1 (zero at column i)
+        const double si = sd[i];
+        for (int j = 0; j <= i; ++j) t[j] = (di * e[j] + si * ep[j]) * inv;
       }
+      t[i] += 1.0;
     }
     std::swap(E, T);
   }
