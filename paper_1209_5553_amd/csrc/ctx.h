@@ -79,6 +79,7 @@ struct erem_ctx {
   int pcg_last = 0;  // iterations of the last converged CG solve (poll placement)
   int prof = 0;  // per-launch event timing: 0 off, n > 0 one launch in n
   std::vector<hipEvent_t> ev;
+  hipEvent_t ev_setup = nullptr;  // the first residual readback of a pressure solve
   double t_leja = 0.0, t_pcg_a = 0.0, t_pcg_b = 0.0, t_mg = 0.0;
   long long n_leja = 0, n_pcg_a = 0, n_pcg_b = 0, n_mg = 0;
   double t_adj = 0.0;

@@ -901,6 +901,8 @@ int erem_destroy(erem_ctx* c) {
   (void)hipStreamSynchronize(c->stream);
   for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
   c->ev.clear();
+  if (c->ev_setup) (void)hipEventDestroy(c->ev_setup);
+  c->ev_setup = nullptr;
   free_mg(c);
   free_all(c);
   delete c;
@@ -974,12 +976,25 @@ int erem_solve_pressure(erem_ctx* c, double rtol, int32_t max_iter, int32_t warm
   int total = 0;
   bool ok = false;
   double relres = NAN;
-  if (c->use_mg) HIP_TRY(c, mg_setup(c->mg, c->stream));
+  // The multigrid setup (coarse operators, bottom inverse) follows the first
+  // residual readback on the stream, and the host waits for the readback
+  // only: the device builds the hierarchy while the host reads the residual
+  // and enqueues the iterations, which queue behind it.  The residual does
+  // not read the hierarchy.
+  bool setup_pending = c->use_mg;
+  if (setup_pending && !c->ev_setup) HIP_TRY(c, hipEventCreateWithFlags(&c->ev_setup, hipEventDisableTiming));
   for (int outer = 0; outer < 8; ++outer) {
     HIP_TRY(c, launch_pcg_reset(c->pcg, 0.0, c->stream));
     HIP_TRY(c, launch_dd_residual(d, c->ph, c->tx, c->ty, c->tz, c->pres, c->pres_lo, c->prhs, c->pcg, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->h_pcg, c->pcg, sizeof(PcgState), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (setup_pending) {
+      HIP_TRY(c, hipEventRecord(c->ev_setup, c->stream));
+      HIP_TRY(c, mg_setup(c->mg, c->stream));
+      setup_pending = false;
+      HIP_TRY(c, hipEventSynchronize(c->ev_setup));
+    } else {
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
     double rr = 0.0, bb = 0.0;
     for (int q = 0; q < kSlots; ++q) { rr += c->h_pcg->rr[q]; bb += c->h_pcg->bb_sl[q]; }
     if (!std::isfinite(rr)) return fail(c, EREM_ENONFINITE, "non-finite pressure residual");
