@@ -737,14 +737,24 @@ int spd_solve(erem_ctx* c, const double* b, double* x, double rtol, int max_iter
   const Dims& d = c->d;
   if (d.dim != 2) return fail(c, EREM_EINVAL, "the general right-hand-side solve supports 2D grids");
   HIP_TRY(c, hipMemsetAsync(x, 0, sizeof(double) * d.N, c->stream));
-  if (c->use_mg) HIP_TRY(c, mg_setup(c->mg, c->stream));
   int total = 0;
   bool ok = false;
+  // multigrid setup behind the first residual readback, as in the pressure
+  // solve (the residual does not read the hierarchy)
+  bool setup_pending = c->use_mg;
+  if (setup_pending && !c->ev_setup) HIP_TRY(c, hipEventCreateWithFlags(&c->ev_setup, hipEventDisableTiming));
   for (int outer = 0; outer < 12; ++outer) {
     HIP_TRY(c, launch_pcg_reset(c->pcg, 0.0, c->stream));
     HIP_TRY(c, launch_spd_residual(d, c->tx, c->ty, x, b, c->prhs, c->pcg, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->h_pcg, c->pcg, sizeof(PcgState), hipMemcpyDeviceToHost, c->stream));
-    HIP_TRY(c, hipStreamSynchronize(c->stream));
+    if (setup_pending) {
+      HIP_TRY(c, hipEventRecord(c->ev_setup, c->stream));
+      HIP_TRY(c, mg_setup(c->mg, c->stream));
+      setup_pending = false;
+      HIP_TRY(c, hipEventSynchronize(c->ev_setup));
+    } else {
+      HIP_TRY(c, hipStreamSynchronize(c->stream));
+    }
     double rr = 0.0, bb = 0.0;
     for (int q = 0; q < kSlots; ++q) { rr += c->h_pcg->rr[q]; bb += c->h_pcg->bb_sl[q]; }
     if (!std::isfinite(rr)) return fail(c, EREM_ENONFINITE, "non-finite residual in the adjoint pressure solve");
