@@ -426,7 +426,9 @@ TRAFFIC = {
     ("injector512", "fp64", "leja_term"): 6.15e6,    # the same kernel on the same grid: 24.60 MB
     ("layered128", "fp64", "leja_term"): 186.49e6,
     ("compressible50", "fp64", "leja_term"): 11.34e6,   # the 3D one-term kernel on 125 000 cells
+    ("layered128", "mixed", "leja_term"): 93.30e6,      # FP32 one-term kernel, 44 B per cell algorithmic
     ("batch256", "fp64", "k_batch_fused"): 486.8e9,
+    ("batch256", "mixed", "k_batch_blocks"): 574.1e9,   # 1024 x 2 shape, one 50-step launch
     # one BiCGSTAB iteration (three kernels) of the comparison schemes
     ("coupled512", "fp64", "bicg_iteration"): 65.23e6,
 }
