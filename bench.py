@@ -385,6 +385,7 @@ def bench_adjoint(args):
     desc = (f"adjoint: coupled 2D 256x256 water laws, {nst} EREM-Leja steps with tapes + {nst} adjoint steps "
             f"(reverse Leja, transposed stencil, stored iterates), gradient of the producer-block mean T "
             f"wrt T0 and log K ({args.adjoint_start} start)")
+    dom = max(kern, key=lambda k: kern[k][0])
     line = {
         "metric": METRIC, "value": round(nst * args.steps / elapsed, 3), "unit": "steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * elapsed / (nst * args.steps), 4),
@@ -392,8 +393,8 @@ def bench_adjoint(args):
         "data": "synthetic (seeded generators)",
         "config": {"workload": desc, "grid": [prob.nx, prob.ny, 1], "cells": N, "h_s": prob.h,
                    "step_unit": "one coupled step forward plus its adjoint", "tol_r": 1e-12},
-        "roofline": _roof(kern, max(kern, key=lambda k: kern[k][0])),
-        "adjoint_rev_term": _roof(kern, "adj_rev_term"),
+        "roofline": _roof(kern, dom, _traffic("adjoint256", "fp64", dom)),
+        "adjoint_rev_term": _roof(kern, "adj_rev_term", _traffic("adjoint256", "fp64", "adj_rev_term")),
         "leja": _roof(kern, "leja_term"),
         "forward_only_steps_per_s": round(nst * args.steps / fwd, 3),
         "gradient_cost_in_forward_runs": round(elapsed / fwd, 3),
@@ -431,6 +432,9 @@ TRAFFIC = {
     ("batch256", "mixed", "k_batch_blocks"): 574.1e9,   # 1024 x 2 shape, one 50-step launch
     # one BiCGSTAB iteration (three kernels) of the comparison schemes
     ("coupled512", "fp64", "bicg_iteration"): 65.23e6,
+    # adjoint workload (256 x 256): V-cycle + CG iteration, reverse Newton term
+    ("adjoint256", "fp64", "mg_vcycle"): 15.55e6,
+    ("adjoint256", "fp64", "adj_rev_term"): 11.10e6,
 }
 
 
