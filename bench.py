@@ -475,8 +475,8 @@ def main():
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py: this EREM build runs on exactly one GPU; multi-GPU runs "
-              "(--gpus > 1) are not part of it.", file=sys.stderr, flush=True)
+        print("bench.py: the EREM library runs on one GPU; multi-GPU runs "
+              "(--gpus > 1) are not supported.", file=sys.stderr, flush=True)
         sys.exit(2)
     # the first min(3, cpu-steps) GPU steps are kept for the oracle comparison
     args.cpu_steps = max(1, min(args.cpu_steps, 3))
