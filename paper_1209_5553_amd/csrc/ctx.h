@@ -26,6 +26,9 @@ struct erem_ctx {
   erem::Phys ph{};
   bool rock_set = false, fluid_set = false, bc_set = false;
   bool trans_set = false, flux_set = false, jac_set = false;
+  // coef and F hold the pressure operator J_p and G4 of erem_step_pressure
+  // (false: the heat Jacobian J and G2 = dT/dt)
+  bool op_pressure = false;
 
   // fields (device)
   double *logk = nullptr, *poro = nullptr;
@@ -111,6 +114,11 @@ struct erem_ctx {
 namespace erem_internal {
 
 int fail(erem_ctx* c, int code, const std::string& msg);
+
+// Message of the calls that need the heat Jacobian and G2 while the context
+// holds the pressure operator of erem_step_pressure.
+constexpr const char* kHoldsPressure =
+    "the context holds the pressure operator of erem_step_pressure: call erem_form_jacobian first";
 
 #define HIP_TRY(ctx, expr)                                                        \
   do {                                                                            \

@@ -601,7 +601,8 @@ int hphi1_eval(erem_ctx* c, double h, const double* v, const double* g, double s
   // the non-autonomous evaluation keeps one stop-state slot for its phi2 pass
   const int smax = std::min(o->max_substeps, g ? c->nstates - 1 : c->nstates);
   int s = 1;
-  if (o->rho_max > 0.0) s = std::max(1, static_cast<int>(std::ceil(h * width / o->rho_max)));
+  const double rho = o->precision == EREM_PREC_MIXED ? std::min(o->rho_max, kMixedRhoMax) : o->rho_max;
+  if (rho > 0.0) s = std::max(1, static_cast<int>(std::ceil(h * width / rho)));
   if (s > smax) s = smax;
   // term budget: the previous evaluation's largest substep degree plus one
   // stop-test group (the launches past the stop return at entry); a degree
@@ -1063,6 +1064,7 @@ int erem_form_jacobian(erem_ctx* c, const double* d_T) {
   HIP_TRY(c, launch_reset_reduce(c->red, c->stream));
   HIP_TRY(c, launch_assemble(c->d, c->ph, c->poro, c->fx, c->fy, c->fz, d_T, c->coef, c->F, c->red, c->stream));
   c->jac_set = true;
+  c->op_pressure = false;
   c->coef32_valid = false;
   return EREM_OK;
 }
@@ -1070,6 +1072,7 @@ int erem_form_jacobian(erem_ctx* c, const double* d_T) {
 int erem_get_jacobian(erem_ctx* c, double* d_coef, double* d_F) {
   if (!c) return EREM_EINVAL;
   if (!c->jac_set) return fail(c, EREM_EINVAL, "erem_form_jacobian must come first");
+  if (c->op_pressure) return fail(c, EREM_EINVAL, kHoldsPressure);
   const size_t n = c->d.N;
   if (d_coef) HIP_TRY(c, hipMemcpyAsync(d_coef, c->coef, n * ndir(c) * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   if (d_F) HIP_TRY(c, hipMemcpyAsync(d_F, c->F, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
@@ -1082,6 +1085,7 @@ int erem_phi1_apply(erem_ctx* c, double h, const double* d_v, double* d_out, con
   if (rc) return rc;
   if (!d_v || !d_out || d_v == d_out) return fail(c, EREM_EINVAL, "v and out must be distinct non-NULL");
   if (!c->jac_set) return fail(c, EREM_EINVAL, "erem_form_jacobian must come first");
+  if (c->op_pressure) return fail(c, EREM_EINVAL, kHoldsPressure);
   if (!(h > 0) || !std::isfinite(h)) return fail(c, EREM_EINVAL, "h must be > 0");
   if (o->method == EREM_METHOD_KRYLOV && o->precision != EREM_PREC_FP64)
     return fail(c, EREM_EINVAL, "the Krylov method runs in FP64 only");
@@ -1112,6 +1116,7 @@ int erem_set_jacobian(erem_ctx* c, const double* d_coef, const double* d_F) {
   HIP_TRY(c, hipMemcpyAsync(c->F, d_F, n * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   HIP_TRY(c, launch_gershgorin(c->d, c->coef, c->red, c->stream));
   c->jac_set = true;
+  c->op_pressure = false;
   c->coef32_valid = false;
   return EREM_OK;
 }
@@ -1197,11 +1202,15 @@ int erem_step_pressure(erem_ctx* c, double h, double* d_p, const double* d_T, do
     return fail(c, EREM_EINVAL, "alpha_b and beta_f must be >= 0, finite and not both 0");
   if (!c->trans_set) return fail(c, EREM_EINVAL, "erem_assemble_transmissibilities must come first");
   if (!c->jac_set) return fail(c, EREM_EINVAL, "G2 = dT/dt must be in the context (erem_form_jacobian or erem_step)");
+  if (c->op_pressure)
+    return fail(c, EREM_EINVAL, "G2 = dT/dt must be formed again (erem_form_jacobian or erem_step): the context holds "
+                                "the pressure operator of the previous erem_step_pressure");
   if (o->method == EREM_METHOD_KRYLOV && o->precision != EREM_PREC_FP64)
     return fail(c, EREM_EINVAL, "the Krylov method runs in FP64 only");
   HIP_TRY(c, launch_pressure_ode(c->d, c->ph, c->poro, d_T, d_p, c->tx, c->ty, c->tz, alpha_b, beta_f, c->coef,
                                  c->F, c->red, c->stream));
   c->coef32_valid = false;
+  c->op_pressure = true;
   rc = read_reduce(c);
   if (rc) return rc;
   // the pressure keeps its own Newton-degree memory (the temperature
@@ -1217,6 +1226,7 @@ int erem_step_frozen(erem_ctx* c, double h, double* d_T, const erem_opts* o, ere
   int rc = step_checks(c, h, d_T, o);
   if (rc) return rc;
   if (!c->jac_set) return fail(c, EREM_EINVAL, "no Jacobian in the context");
+  if (c->op_pressure) return fail(c, EREM_EINVAL, kHoldsPressure);
   HIP_TRY(c, launch_absmax(c->d, d_T, c->red, c->stream));
   rc = read_reduce(c);
   if (rc) return rc;

@@ -232,6 +232,7 @@ int erem_shifted_solve(erem_ctx* c, double sigma, const double* d_b, double* d_x
                        erem_stats* stats) {
   if (!c) return EREM_EINVAL;
   if (!c->jac_set) return fail(c, EREM_EINVAL, "erem_form_jacobian (or erem_set_jacobian) must come first");
+  if (c->op_pressure) return fail(c, EREM_EINVAL, kHoldsPressure);
   if (!d_b || !d_x || d_b == d_x) return fail(c, EREM_EINVAL, "b and x must be distinct non-NULL");
   if (!(sigma > 0) || !std::isfinite(sigma)) return fail(c, EREM_EINVAL, "sigma must be > 0");
   if (!(rtol > 0) || !(rtol < 1)) return fail(c, EREM_EINVAL, "rtol must be in (0, 1)");
