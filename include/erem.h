@@ -69,7 +69,11 @@ typedef struct {
  * max_substeps: maximum number of substeps the step may be split into.
  * krylov_m: Arnoldi dimension of the Krylov method.
  * rho_max: a-priori substep rule, substeps s = ceil(h (beta - alpha) / rho_max)
- *   where [alpha, beta] is the Gershgorin interval of J (<= 0 disables).
+ *   where [alpha, beta] is the Gershgorin interval of J (<= 0 disables).  With
+ *   precision MIXED a rho_max above 32 is taken as 32: on an interval of width
+ *   rho the Newton terms grow to about e^(rho/10) times the result before they
+ *   cancel, and in FP32 that growth is lost accuracy (at 64, about 3e-5 of
+ *   the step on the 128^3 layered workload; at 32, below 1e-5).
  * chunk: Leja terms enqueued before the host polls the device stop flag
  *   (0 = automatic). */
 typedef struct {
@@ -238,7 +242,10 @@ int erem_face_fluxes_from_pressure(erem_ctx* ctx, const double* d_p);
  * compressibility) in 1/Pa, >= 0, not both 0.  phi1 by opts->method (the
  * paper pairs Krylov for the pressure with Leja for the temperature); the
  * error scale is tol_a + tol_r max|p|.  Afterwards the context's J and F are
- * J_p and G4. */
+ * J_p and G4: until the next erem_form_jacobian, erem_step or
+ * erem_set_jacobian, this call (which needs G2) and erem_get_jacobian,
+ * erem_phi1_apply, erem_step_frozen and erem_shifted_solve (which need the
+ * heat Jacobian) return EREM_EINVAL and leave their outputs unchanged. */
 int erem_step_pressure(erem_ctx* ctx, double h, double* d_p, const double* d_T, double alpha_b, double beta_f,
                        const erem_opts* opts, erem_stats* stats);
 
@@ -338,32 +345,44 @@ int erem_coupled_step_adjoint(erem_ctx* ctx, double h, const double* d_T, double
                               const erem_opts* opts, const erem_tape* tape, int32_t ckpt_stride,
                               double* d_Tbar, double* d_logk_bar, erem_stats* stats);
 
-/* ---- batched form: many independent linear problems, one persistent launch ----
+/* ---- batched form: many independent linear problems in one graph launch ----
  *
  * Each problem is a 2D grid with fixed face fluxes and constant heat capacity
  * (constant fluid law), so G_p(T) = J_p T + g_p with constant J_p and the EREM
  * step (Eq. EERM) uses a fixed Gershgorin interval, substep count and set of
  * divided differences per problem (Sec. 4.2).  erem_batch_run advances all
- * problems by nsteps steps in ONE kernel launch: one workgroup owns one problem
- * for all its steps, substeps and Newton terms and applies its own stop test,
- * largest problems first; the launch can be captured once in a hipGraph and
- * replayed.  Temperatures are packed: problem i owns cells
- * [off_i, off_i + nx_i ny_i) of the caller's array (erem_batch_offsets). */
+ * problems by nsteps steps.  The problems are cut into 64 x rows tiles that
+ * form one list; a run is a sequence of phases, and each phase is one work
+ * launch over the whole list - every problem that is not done takes one step
+ * of its own schedule: a substep's start pass (q_0, p = d_0 q_0), four Newton
+ * terms (Eq. newt) staged in LDS, or the last step's T update - followed by a
+ * control launch that reduces each problem's tile partials in a fixed order
+ * (so runs are bit-for-bit reproducible), applies the stop test of Sec. 4.2
+ * and picks the problem's next phase.  With use_graph the whole sequence is
+ * one hipGraph, captured on first use with the number of phases a
+ * calibration run on a copy of T needed plus a margin; a run that needs more
+ * continues with launches from the host.  Temperatures are packed: problem i
+ * owns cells [off_i, off_i + nx_i ny_i) of the caller's array
+ * (erem_batch_offsets). */
 typedef struct erem_batch erem_batch;
 
 typedef struct {
     int64_t terms_total;   /* Newton-Leja terms summed over problems and steps */
     int32_t terms_min, terms_max;  /* per problem, over the run */
-    int32_t failed;        /* problems that stopped on an error (see flags) */
-    int32_t tile_shape;    /* workgroup per problem: 0: 256 threads x 4 cells loaded ahead,
-                              1: 256 x 8, 2: 512 x 4, 3: 1024 x 2, 4: 1024 threads taking
-                              the Newton terms four per pass over 64 x 16 tiles staged in
-                              LDS (runs the largest multiple of 4 not above m_max terms) */
-    int32_t graph;         /* 1 if the launch was replayed from a hipGraph */
-    int32_t grid;          /* workgroups of the launch (one per problem) */
-    double ms;             /* device time of the launch (HIP events) */
+    int32_t failed;        /* problems that stopped on an error (see the return code) */
+    int32_t tile_shape;    /* 0: 64 x 8 tiles (512 threads), 1: 64 x 16 (1024 threads),
+                              2: 64 x 8 with each XCD taking a contiguous range of tiles;
+                              the Newton terms go four per pass (the applied degree is the
+                              first multiple of 4 at which the stop test holds) */
+    int32_t graph;         /* 1 if the run was replayed from a hipGraph */
+    int32_t grid;          /* workgroups of a work launch (tiles) */
+    double ms;             /* device time of the run (HIP events) */
     double leja_bytes;     /* algorithmic bytes of the Newton terms: sum over
                               problems of terms x cells x (72 B FP64, 36 B FP32) */
+    int32_t phases;        /* work passes the longest problem needed */
+    int32_t work_timed;    /* work launches timed (erem_batch_profile) */
+    int64_t passes;        /* work launches of the run (graph budget included) */
+    double work_ms;        /* summed device time of the timed work launches */
 } erem_batch_stats;
 
 /* nprob 2D grids (dim 2, nz 1).  Errors: EINVAL, ENOMEM, EDEVICE. */
@@ -383,16 +402,21 @@ int erem_batch_set_problem(erem_batch* b, int32_t i, const double* d_logk, const
  * substeps s = ceil(h (beta - alpha) / rho_max), divided differences up to
  * m_max; opts->precision selects FP64 or FP32 Newton passes. */
 int erem_batch_prepare(erem_batch* b, double h, const erem_opts* opts);
-/* Time every workgroup size on a copy of d_T (nsteps steps) and keep the fastest;
+/* Time every tile shape on a copy of d_T (nsteps steps) and keep the fastest;
  * *chosen receives its index.  d_T is not modified. */
 int erem_batch_autotune(erem_batch* b, const double* d_T, int32_t nsteps, int32_t* chosen);
-/* Select a workgroup shape by index (0 .. 4, see erem_batch_stats.tile_shape)
+/* Select a tile shape by index (0 .. 2, see erem_batch_stats.tile_shape)
  * instead of timing them.  EINVAL for another index. */
 int erem_batch_set_tile_shape(erem_batch* b, int32_t shape);
-/* Advance the packed temperatures d_T by nsteps EREM steps in one launch;
- * use_graph != 0 captures the launch in a hipGraph on first use (per nsteps)
- * and replays it.  ENOCONV / ENONFINITE if a problem failed (the others are
- * still advanced). */
+/* Time every stride-th work launch of the following runs with a HIP event
+ * pair (recorded into the graph when one is used); 0 turns it off.  The sums
+ * go to erem_batch_stats.work_ms / work_timed.  EINVAL for stride < 0. */
+int erem_batch_profile(erem_batch* b, int32_t stride);
+/* Advance the packed temperatures d_T by nsteps EREM steps; use_graph != 0
+ * replays one hipGraph (captured on first use per nsteps, tile shape and T
+ * array).  Synchronises the batch's stream.  ENOCONV / ENONFINITE (EINVAL for
+ * a zero error scale) if a problem failed: the others are still advanced and
+ * a failed problem's cells hold the T of its last completed step. */
 int erem_batch_run(erem_batch* b, double* d_T, int32_t nsteps, int32_t use_graph, erem_batch_stats* st);
 
 /* ---- measurement support ---- */

@@ -58,7 +58,8 @@ class KernelTimes(ctypes.Structure):
 class BatchStats(ctypes.Structure):
     _fields_ = [("terms_total", c_int64), ("terms_min", c_int32), ("terms_max", c_int32),
                 ("failed", c_int32), ("tile_shape", c_int32), ("graph", c_int32),
-                ("grid", c_int32), ("ms", c_double), ("leja_bytes", c_double)]
+                ("grid", c_int32), ("ms", c_double), ("leja_bytes", c_double), ("phases", c_int32),
+                ("work_timed", c_int32), ("passes", c_int64), ("work_ms", c_double)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -122,6 +123,7 @@ SIGNATURES = {
     "erem_batch_autotune": (c_int32, [_P, _P, c_int32, POINTER(c_int32)]),
     "erem_batch_run": (c_int32, [_P, _P, c_int32, c_int32, POINTER(BatchStats)]),
     "erem_batch_set_tile_shape": (c_int32, [_P, c_int32]),
+    "erem_batch_profile": (c_int32, [_P, c_int32]),
     "erem_profile": (c_int32, [_P, c_int32]),
     "erem_profile_read": (c_int32, [_P, POINTER(KernelTimes)]),
     "erem_leja_points": (c_int32, [c_int32, _PD]),

@@ -421,6 +421,10 @@ class EremBatch:
     def set_tile_shape(self, shape: int):
         self._check(self.lib.erem_batch_set_tile_shape(self.handle, int(shape)), "erem_batch_set_tile_shape")
 
+    def profile(self, stride: int):
+        """Time every stride-th work launch of later runs (0: off)."""
+        self._check(self.lib.erem_batch_profile(self.handle, int(stride)), "erem_batch_profile")
+
     def run(self, T, nsteps: int, use_graph: bool = True):
         st = nat.BatchStats()
         self.stream.wait_stream(torch.cuda.current_stream(self.device))

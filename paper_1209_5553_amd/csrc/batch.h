@@ -1,4 +1,5 @@
-// Batched EREM kernel (batch.hip): shared structures.
+// Batched EREM over many independent linear problems (batch.hip): shared
+// structures and launchers.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -7,8 +8,11 @@
 
 namespace erem {
 
-constexpr int kNumTileShapes = 5;
-extern const int kTileShapes[kNumTileShapes][2];  // {threads per problem, cells loaded ahead per thread (0: fused terms)}
+// Tile shapes of the work kernel: 64 x kBatchTileRows[shape] cells, one
+// thread per cell; shape 2 is shape 0 with the XCD-contiguous placement.
+constexpr int kNumTileShapes = 3;
+constexpr int kBatchTileRows[kNumTileShapes] = {8, 16, 8};
+constexpr int kBatchTileX = 64;
 
 // Static description of one problem of the batch.
 struct BProb {
@@ -18,36 +22,80 @@ struct BProb {
   long long off;  // first cell in the packed vectors
   double inv_g;   // 1 / gamma
   double delta;   // substep length h / s
+  double rootN;   // sqrt(nx ny)
+  int tile0;      // first tile of the problem in the tile list
+  int ntiles;     // its tiles (tiles_x rows of 64 x rows cells)
+  int tiles_x;
+  int pad;
 };
 
-// Outcome of one problem, written once by its workgroup.
-struct BDyn {
+// Tile list entry: the problem and the tile's first cell.
+struct BTile {
+  int pid, x0, y0, pad;
+};
+
+// Phases of a problem; every work launch advances each problem that is not
+// done by one phase, and the control kernel that follows picks the next.
+enum BPhase : int {
+  kPhInit = 0,    // start of a substep: q_0, p = d_0 q_0 (and the end of the previous substep or step)
+  kPhTerms = 1,   // four Newton terms k .. k + 3
+  kPhFinish = 2,  // the last step's T update
+  kPhDone = 3,
+};
+
+// Kinds of start pass.
+enum BInit : int {
+  kInitFirst = 0,  // first step: T^0 as given
+  kInitSub = 1,    // substep j >= 1: u += delta p of substep j - 1
+  kInitStep = 2,   // next step: T += u + delta p of the last substep
+};
+
+// Dynamic state of one problem, written only by the control kernel.
+struct BState {
+  int phase, kind;
   int step;   // steps completed
-  int terms;  // Leja terms applied
+  int sub;    // current substep
+  int k;      // first term of the next group of four
+  int terms;  // Newton terms applied
   int flags;  // 1: no convergence within m_max, 2: non-finite norm
+  int tpar;   // buffer holding T^n: 0 the caller's array, 1 the internal copy
+  int upar;   // buffer holding u (sum of the finished substeps' increments)
+  int ppar;   // buffer holding p (the current substep's Newton sum)
+  int phases; // work passes taken
   int pad;
+  double scal;     // error scale tol_a + tol_r max|T^n|
+  double ring[5];  // the last five scaled error estimates
 };
 
 struct BatchArgs {
   const BProb* prob;
-  BDyn* dyn;
-  const int* order;     // problems in the order the workgroups take them
-  const double* coef64; // 5-point stencil, SoA with stride ntot (FP64)
-  const void* coef;     // stencil used by the Newton terms (FP64 or FP32)
-  const double* g;      // G(T) = J T + g
-  double* T;
-  double* v;            // G(T^n) of the current step
-  double* u;            // sum of the finished substeps' increments
-  void *q0, *q1, *p;    // Newton vectors (FP64 or FP32)
-  const double* dk;     // divided differences, (m_max + 1) per problem
-  const double* shift;  // c/gamma + xi_{k-1}, (m_max + 1) per problem
+  const BTile* tile;
+  BState* state;
+  int* ndone;            // problems done (control kernel counts them)
+  const double* coef64;  // 5-point stencil, SoA with stride ntot (FP64)
+  const void* coef;      // stencil of the Newton terms (FP64 or FP32)
+  const double* g;       // G(T) = J T + g
+  double* T0;            // the caller's temperatures
+  double* T1;            // internal temperature buffer
+  double *u0, *u1;       // substep increment sums (ping-pong)
+  double* v;             // G(T^n) of the current step
+  void *q0, *q1;         // Newton vectors (FP64 or FP32)
+  void *p0, *p1;         // Newton sums (ping-pong over substeps)
+  const double* dk;      // divided differences, (m_max + 1) per problem
+  const double* shift;   // c/gamma + xi_{k-1}, (m_max + 1) per problem
+  double* part;          // four partials per tile
   long long ntot;
-  int nprob, nsteps, m_max;
+  int nprob, ntiles, nsteps, m_max;
   double tol_a, tol_r, thresh;
 };
 
 hipError_t batch_pack(int nx, int ny, const double* coef, const double* F, const double* T0,
                       double* bcoef, double* g, long long ntot, long long off, hipStream_t s);
-hipError_t batch_launch(const BatchArgs& a, int shape, int fp32, int grid, hipStream_t s);
+hipError_t batch_reset(const BatchArgs& a, hipStream_t s);
+// One phase of every problem: the work pass over all tiles, then the control
+// kernel.  e0 / e1 (optional) time the work pass alone.
+hipError_t batch_phase(const BatchArgs& a, int shape, int fp32, hipStream_t s, hipEvent_t e0 = nullptr,
+                       hipEvent_t e1 = nullptr);
+size_t batch_lds_bytes(int shape, int fp32);
 
 }  // namespace erem

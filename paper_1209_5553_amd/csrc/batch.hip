@@ -1,20 +1,37 @@
-// Batched EREM for many independent linear problems in one persistent launch.
+// Batched EREM for many independent linear problems.
 //
 // Every problem p (its own n_x x n_y grid, packed one after the other) has a
 // constant Jacobian J_p and G_p(T) = J_p T + g_p (fixed fluxes, constant
 // capacity), so one EREM step is T <- T + h phi1(h J_p)(J_p T + g_p)
 // (Eq. EERM) with a Gershgorin interval, substep count and divided
-// differences fixed for the whole run.
+// differences fixed for the whole run (Sec. 4.2).
 //
-// MI355X mapping: one workgroup owns one whole problem at a time (the batch
-// is a queue of problems, largest first, taken round-robin by the resident
-// workgroups; with 256 realisations each of the 256 CUs gets one).  All
-// steps, substeps and Newton-Leja terms (Eq. newt) of that problem run inside
-// the workgroup, separated only by workgroup barriers, and the scaled-norm
-// stop test of Sec. 4.2 is a workgroup reduction, so every problem converges
-// on its own with no grid-wide synchronisation and no atomics.  The launch
-// can be captured in a hipGraph.  The tunable "tile" is the workgroup size
-// and the number of cells a thread loads ahead in each Newton pass.
+// MI355X mapping.  The problems are cut into 64 x rows tiles and all tiles
+// of all problems form one list.  A run is a sequence of phases; in each
+// phase ONE work launch covers the whole tile list and advances every
+// problem that is not done by one step of its own schedule:
+//
+//   start pass  q_0 = v + J u, p = d_0 q_0 (with the end of the previous
+//               substep, u += delta p, or of the previous step,
+//               T += u + delta p, folded in: a cell's neighbours' values are
+//               formed from their own u, p, T, so no extra pass is needed);
+//   term pass   four Newton terms q_k = ((J - cI)/gamma - xi_{k-1}) q_{k-1},
+//               p += d_k q_k (Eq. newt) on the tile, staged in LDS with the
+//               halo that four stencil applications need; the intermediate
+//               terms never leave the CU;
+//   finish pass T += u + delta p of the last step.
+//
+// Each tile stores its block partial sums (sum q_k^2 per term, in FP64); a
+// control kernel then reduces each problem's partials in a fixed order (one
+// wavefront per problem), applies the scaled-norm stop test of Sec. 4.2 to
+// the group's four estimates in order, and sets the problem's next phase.
+// Problems of every size and substep count thus share every launch, the
+// work spreads over all CUs whatever the mix, and the whole run is a fixed
+// sequence of launches with no grid-wide synchronisation and no waiting
+// inside a kernel, which a hipGraph captures.  Tiles of problems that are
+// done return at entry.  Buffers the start pass reads with a halo and
+// rewrites (T, u, p) are ping-ponged so that no tile reads a neighbour's
+// updated value.
 #include "batch.h"
 
 #include <cmath>
@@ -26,471 +43,353 @@ namespace {
 template <class V>
 __device__ inline V cv(double x) { return static_cast<V>(x); }
 
-// Sum (and max) over the workgroup; every thread gets the result.
-template <int NT>
-__device__ inline double wg_sum(double v, double* sh) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double s = 0.0;
-#pragma unroll
-  for (int w = 0; w < NT / 64; ++w) s += sh[w];
-  __syncthreads();
-  return s;
+template <int TY, class V>
+constexpr size_t work_lds_bytes() {
+  return sizeof(V) * (static_cast<size_t>(TY + 8) * (kBatchTileX + 8) +
+                      7 * static_cast<size_t>(TY + 6) * (kBatchTileX + 6));
 }
 
-template <int NT>
-__device__ inline double wg_max(double v, double* sh) {
-  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_down(v, off, 64));
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
-  __syncthreads();
-  double s = 0.0;
-#pragma unroll
-  for (int w = 0; w < NT / 64; ++w) s = fmax(s, sh[w]);
-  __syncthreads();
-  return s;
-}
-
-template <int NT, int U, class V>
-__global__ __launch_bounds__(NT) void k_batch_blocks(BatchArgs a) {
-  __shared__ double sh[NT / 64];
-  const long long Ntot = a.ntot;
-  const double* c64 = a.coef64;
-  const V* cV = reinterpret_cast<const V*>(a.coef);
-  V* q0 = reinterpret_cast<V*>(a.q0);
-  V* q1 = reinterpret_cast<V*>(a.q1);
-  V* pv = reinterpret_cast<V*>(a.p);
-  for (int slot = blockIdx.x; slot < a.nprob; slot += gridDim.x) {
-    const int pid = a.order[slot];
-    const BProb P = a.prob[pid];
-    const int nx = P.nx, ny = P.ny, N = nx * ny;
-    const long long o = P.off;
-    const double* dk = a.dk + P.coef_off;
-    const double* sf = a.shift + P.coef_off;
-    const double rootN = sqrt(static_cast<double>(N));
-    // (x, y) of a thread's cells advance by (sx, sy) per NT cells and (ux, uy) per U NT
-    const int sx = NT % nx, sy = NT / nx, ux = (U * NT) % nx, uy = (U * NT) / nx;
-    const int x0 = threadIdx.x % nx, y0 = threadIdx.x / nx;
-    int terms = 0, flags = 0, steps = 0;
-    for (int step = 0; step < a.nsteps && !flags; ++step) {
-      // v = J T + g (FP64), max |T| for the error scale
-      double mx = 0.0;
-      for (int c = threadIdx.x; c < N; c += NT) {
-        const long long i = o + c;
-        const int x = c % nx, y = c / nx;
-        const double* T = a.T;
-        double jt = c64[i] * T[i];
-        if (x > 0) jt += c64[Ntot + i] * T[i - 1];
-        if (x + 1 < nx) jt += c64[2 * Ntot + i] * T[i + 1];
-        if (y > 0) jt += c64[3 * Ntot + i] * T[i - nx];
-        if (y + 1 < ny) jt += c64[4 * Ntot + i] * T[i + nx];
-        a.v[i] = jt + a.g[i];
-        mx = fmax(mx, fabs(T[i]));
-      }
-      const double scal = a.tol_a + a.tol_r * wg_max<NT>(mx, sh);
-      for (int j = 0; j < P.s && !flags; ++j) {
-        // q_0 = v + J u (u = 0 on the first substep), p = d_0 q_0
-        double s0 = 0.0;
-        for (int c = threadIdx.x; c < N; c += NT) {
-          const long long i = o + c;
-          double w = a.v[i];
-          if (j > 0) {
-            const int x = c % nx, y = c / nx;
-            const double* u = a.u;
-            double ju = c64[i] * u[i];
-            if (x > 0) ju += c64[Ntot + i] * u[i - 1];
-            if (x + 1 < nx) ju += c64[2 * Ntot + i] * u[i + 1];
-            if (y > 0) ju += c64[3 * Ntot + i] * u[i - nx];
-            if (y + 1 < ny) ju += c64[4 * Ntot + i] * u[i + nx];
-            w += ju;
-          }
-          const V q = cv<V>(w);
-          q0[i] = q;
-          pv[i] = cv<V>(dk[0]) * q;
-          s0 += static_cast<double>(q) * static_cast<double>(q);
-        }
-        double ring[5];
-        ring[0] = fabs(P.delta * dk[0]) * sqrt(wg_sum<NT>(s0, sh)) / (rootN * scal);
-        bool done = false;
-        for (int k = 1; k <= a.m_max; ++k) {
-          const V* __restrict__ qin = (k & 1) ? q0 : q1;
-          V* __restrict__ qout = (k & 1) ? q1 : q0;
-          const V ig = cv<V>(P.inv_g), sk = cv<V>(sf[k]), dkk = cv<V>(dk[k]);
-          double sk2 = 0.0;
-          int x = x0, y = y0;
-          for (int c = threadIdx.x; c < N; c += U * NT) {
-            // U cells per thread with every load issued before any use
-            long long ii[U];
-            bool in[U], hw[U], he[U], hs[U], hn[U];
-            int xu = x, yu = y;
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-              in[u] = c + u * NT < N;
-              ii[u] = o + (in[u] ? c + u * NT : N - 1);
-              hw[u] = in[u] && xu > 0;
-              he[u] = in[u] && xu + 1 < nx;
-              hs[u] = in[u] && yu > 0;
-              hn[u] = in[u] && yu + 1 < ny;
-              xu += sx;
-              yu += sy;
-              if (xu >= nx) {
-                xu -= nx;
-                ++yu;
-              }
-            }
-            V qc[U], a0[U], aw[U], ae[U], as[U], an[U], qw[U], qe[U], qs[U], qn[U], pp[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-              const long long i = ii[u];
-              qc[u] = qin[i];
-              a0[u] = cV[i];
-              aw[u] = cV[Ntot + i];
-              ae[u] = cV[2 * Ntot + i];
-              as[u] = cV[3 * Ntot + i];
-              an[u] = cV[4 * Ntot + i];
-              qw[u] = qin[hw[u] ? i - 1 : i];
-              qe[u] = qin[he[u] ? i + 1 : i];
-              qs[u] = qin[hs[u] ? i - nx : i];
-              qn[u] = qin[hn[u] ? i + nx : i];
-              pp[u] = pv[i];
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-              V jq = a0[u] * qc[u];
-              if (hw[u]) jq += aw[u] * qw[u];
-              if (he[u]) jq += ae[u] * qe[u];
-              if (hs[u]) jq += as[u] * qs[u];
-              if (hn[u]) jq += an[u] * qn[u];
-              const V r = jq * ig - sk * qc[u];
-              if (in[u]) {
-                pv[ii[u]] = pp[u] + dkk * r;
-                qout[ii[u]] = r;
-                sk2 += static_cast<double>(r) * static_cast<double>(r);
-              }
-            }
-            x += ux;
-            y += uy;
-            if (x >= nx) {
-              x -= nx;
-              ++y;
-            }
-          }
-          const double S = wg_sum<NT>(sk2, sh);  // also orders qout before the next term
-          ++terms;
-          if (!isfinite(S)) {
-            flags |= 2;
-            break;
-          }
-          ring[k % 5] = fabs(P.delta * dk[k]) * sqrt(S) / (rootN * scal);
-          if (k >= 4) {
-            const double mean = 0.2 * (ring[0] + ring[1] + ring[2] + ring[3] + ring[4]);
-            if (mean < a.thresh) {
-              done = true;
-              break;
-            }
-          }
-        }
-        if (!done) {
-          if (!flags) flags |= 1;
-          break;
-        }
-        // substep end: u += delta p (earlier substeps) or T += u + delta p (last)
-        const bool last = j + 1 == P.s;
-        for (int c = threadIdx.x; c < N; c += NT) {
-          const long long i = o + c;
-          const double pi = static_cast<double>(pv[i]);
-          if (!last) a.u[i] = (j == 0 ? 0.0 : a.u[i]) + P.delta * pi;
-          else a.T[i] += (P.s > 1 ? a.u[i] : 0.0) + P.delta * pi;
-        }
-        __syncthreads();
-      }
-      if (!flags) ++steps;
-    }
-    if (threadIdx.x == 0) {
-      BDyn& D = a.dyn[pid];
-      D.terms = terms;
-      D.flags = flags;
-      D.step = steps;
-    }
-    __syncthreads();
+// Sum (or max) over the workgroup of one double per thread; fixed order
+// (each wavefront by a shuffle tree, then the wavefronts in order); the
+// result is valid in thread 0.
+template <int NW, bool MAX>
+__device__ inline double block_reduce(double v, double* sh, int tid) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const double o = __shfl_down(v, off, 64);
+    v = MAX ? fmax(v, o) : v + o;
   }
+  if ((tid & 63) == 0) sh[tid >> 6] = v;
+  __syncthreads();
+  double r = 0.0;
+  if (tid == 0) {
+    r = sh[0];
+    for (int w = 1; w < NW; ++w) r = MAX ? fmax(r, sh[w]) : r + sh[w];
+  }
+  __syncthreads();
+  return r;
 }
 
-// ---------------------------------------------------------------------------
-// Fused variant: the same per-problem workgroup (1024 threads), but the Newton
-// terms go four at a time.  For each group of four terms the workgroup walks
-// its problem in 64 x 16 tiles; a tile stages q_{k-1} with a halo of four
-// cells and the stencil with a halo of three in LDS, computes the four terms
-// on shrinking regions (the last on the tile), and writes only p and the
-// group's last q.  The stop test of Sec. 4.2 runs on the group's four
-// estimates in order, as the single-problem path does after every four terms.
-// ---------------------------------------------------------------------------
-constexpr int kFX = 64, kFY = 16, kFThreads = kFX * kFY;
-constexpr int kFWQ = kFX + 8, kFHQ = kFY + 8;   // q_{k-1}: halo 4
-constexpr int kFWI = kFX + 6, kFHI = kFY + 6;   // stencil, intermediates: halo 3
-static_assert(kFHQ * kFWQ <= 2 * kFThreads && kFHI * kFWI <= 2 * kFThreads, "two staged values per thread");
-#ifndef EREM_BATCH_LOAD_GROUPS
-#define EREM_BATCH_LOAD_GROUPS 2
-#endif
-constexpr int kFLoadGroups = EREM_BATCH_LOAD_GROUPS;  // 1 or 2
-static_assert(kFLoadGroups == 1 || kFLoadGroups == 2, "one or two load groups");
+template <int TY, bool XCD, class V>
+__global__ __launch_bounds__(kBatchTileX* TY) void k_bt_work(BatchArgs a) {
+  constexpr int NTH = kBatchTileX * TY;
+  constexpr int NW = NTH / 64;
+  constexpr int NT = 4, H = NT - 1;
+  constexpr int WQ = kBatchTileX + 2 * NT, HQ = TY + 2 * NT;  // q_{k-1}: halo 4
+  constexpr int WI = kBatchTileX + 2 * H, HI = TY + 2 * H;    // stencil, intermediates: halo 3
+  extern __shared__ __align__(16) unsigned char smem[];
+  V(*sq)[WQ] = reinterpret_cast<V(*)[WQ]>(smem);
+  V(*sc)[HI][WI] = reinterpret_cast<V(*)[HI][WI]>(smem + sizeof(V) * HQ * WQ);
+  V(*sb)[HI][WI] = sc + 5;
+  __shared__ double red[NT][NW];
 
-template <class V>
-constexpr size_t fused_lds_bytes() {
-  return sizeof(V) * (static_cast<size_t>(kFHQ) * kFWQ + 7 * static_cast<size_t>(kFHI) * kFWI);
-}
+  const int t = XCD ? xcd_tile_id() : static_cast<int>(blockIdx.x);
+  const BTile tl = a.tile[t];
+  const BState S = a.state[tl.pid];
+  if (S.phase == kPhDone) return;
+  const BProb P = a.prob[tl.pid];
+  const int nx = P.nx, ny = P.ny;
+  const long long o = P.off, Nt = a.ntot;
+  const int lx = threadIdx.x, ly = threadIdx.y;
+  const int tid = lx + kBatchTileX * ly;
+  const int x = tl.x0 + lx, y = tl.y0 + ly;
+  const bool own = x < nx && y < ny;
+  const long long i = o + (own ? x + static_cast<long long>(nx) * y : 0);
+  double* part = a.part + 4LL * t;
 
-template <class V>
-__global__ __launch_bounds__(kFThreads) void k_batch_fused(BatchArgs a) {
-  extern __shared__ unsigned char fsm[];
-  V(*sq)[kFWQ] = reinterpret_cast<V(*)[kFWQ]>(fsm);
-  V(*sc)[kFHI][kFWI] = reinterpret_cast<V(*)[kFHI][kFWI]>(fsm + sizeof(V) * kFHQ * kFWQ);
-  V(*sb)[kFHI][kFWI] = sc + 5;
-  __shared__ double sh[kFThreads / 64];
-  __shared__ double red[4][kFThreads / 64];
-  const int tid = threadIdx.x;
-  const int lx = tid % kFX, ly = tid / kFX;
-  const long long Ntot = a.ntot;
-  const double* c64 = a.coef64;
-  const V* cV = reinterpret_cast<const V*>(a.coef);
-  V* q0 = reinterpret_cast<V*>(a.q0);
-  V* q1 = reinterpret_cast<V*>(a.q1);
-  V* pv = reinterpret_cast<V*>(a.p);
-  for (int slot = blockIdx.x; slot < a.nprob; slot += gridDim.x) {
-    const int pid = a.order[slot];
-    const BProb P = a.prob[pid];
-    const int nx = P.nx, ny = P.ny, N = nx * ny;
-    const long long o = P.off;
-    const double* dk = a.dk + P.coef_off;
-    const double* sf = a.shift + P.coef_off;
-    const double rootN = sqrt(static_cast<double>(N));
-    int terms = 0, flags = 0, steps = 0;
-    for (int step = 0; step < a.nsteps && !flags; ++step) {
-      double mx = 0.0;
-      for (int c = tid; c < N; c += kFThreads) {
-        const long long i = o + c;
-        const int x = c % nx, y = c / nx;
-        const double* T = a.T;
-        double jt = c64[i] * T[i];
-        if (x > 0) jt += c64[Ntot + i] * T[i - 1];
-        if (x + 1 < nx) jt += c64[2 * Ntot + i] * T[i + 1];
-        if (y > 0) jt += c64[3 * Ntot + i] * T[i - nx];
-        if (y + 1 < ny) jt += c64[4 * Ntot + i] * T[i + nx];
-        a.v[i] = jt + a.g[i];
-        mx = fmax(mx, fabs(T[i]));
+  if (S.phase == kPhFinish) {
+    // T^N = T^{N-1} + u + delta p (a failed problem keeps its last step's T)
+    if (own) {
+      const double* Tc = S.tpar ? a.T1 : a.T0;
+      double Tn = Tc[i];
+      if (S.flags == 0) {
+        const V* pc = reinterpret_cast<const V*>(S.ppar ? a.p1 : a.p0);
+        const double* uc = S.upar ? a.u1 : a.u0;
+        Tn += (P.s > 1 ? uc[i] : 0.0) + P.delta * static_cast<double>(pc[i]);
       }
-      const double scal = a.tol_a + a.tol_r * wg_max<kFThreads>(mx, sh);
-      for (int j = 0; j < P.s && !flags; ++j) {
-        double s0 = 0.0;
-        for (int c = tid; c < N; c += kFThreads) {
-          const long long i = o + c;
-          double w = a.v[i];
-          if (j > 0) {
-            const int x = c % nx, y = c / nx;
-            const double* u = a.u;
-            double ju = c64[i] * u[i];
-            if (x > 0) ju += c64[Ntot + i] * u[i - 1];
-            if (x + 1 < nx) ju += c64[2 * Ntot + i] * u[i + 1];
-            if (y > 0) ju += c64[3 * Ntot + i] * u[i - nx];
-            if (y + 1 < ny) ju += c64[4 * Ntot + i] * u[i + nx];
-            w += ju;
-          }
-          const V q = cv<V>(w);
-          q0[i] = q;
-          pv[i] = cv<V>(dk[0]) * q;
-          s0 += static_cast<double>(q) * static_cast<double>(q);
-        }
-        double ring[5];
-        ring[0] = fabs(P.delta * dk[0]) * sqrt(wg_sum<kFThreads>(s0, sh)) / (rootN * scal);
-        bool done = false;
-        const V ig = cv<V>(P.inv_g);
-        for (int k = 1; k + 3 <= a.m_max; k += 4) {
-          const int g = (k - 1) / 4;
-          const V* __restrict__ qin = (g & 1) ? q1 : q0;
-          V* __restrict__ qout = (g & 1) ? q0 : q1;
-          double part[4] = {0.0, 0.0, 0.0, 0.0};
-          for (int y0 = 0; y0 < ny; y0 += kFY)
-            for (int x0 = 0; x0 < nx; x0 += kFX) {
-              // the tile's loads are issued in groups before their LDS
-              // stores (q with the first half of the stencil, then the
-              // second half), so the tile waits for a few memory latencies
-              // instead of one per loop trip
-              const int gx = x0 + lx, gy = y0 + ly;
-              const bool own = gx < nx && gy < ny;
-              const long long i = o + gx + nx * gy;
-              V acc;
-#pragma unroll
-              for (int grp = 0; grp < kFLoadGroups; ++grp) {
-                constexpr int UG = 2 / kFLoadGroups;  // stencil values per thread and group
-                V rq[2], rc[5][UG];
-                if (grp == 0) {
-#pragma unroll
-                  for (int u = 0; u < 2; ++u) {
-                    const int e = tid + u * kFThreads;
-                    const int ry = e / kFWQ, rx = e - ry * kFWQ;
-                    const int qx = x0 - 4 + rx, qy = y0 - 4 + ry;
-                    rq[u] = (e < kFHQ * kFWQ && qx >= 0 && qx < nx && qy >= 0 && qy < ny) ? qin[o + qx + nx * qy]
-                                                                                        : V(0);
-                  }
-                  acc = own ? pv[i] : V(0);
-                }
-#pragma unroll
-                for (int uu = 0; uu < UG; ++uu) {
-                  const int e = tid + (grp * UG + uu) * kFThreads;
-                  const int ry = e / kFWI, rx = e - ry * kFWI;
-                  const int cx = x0 - 3 + rx, cy = y0 - 3 + ry;
-                  const bool in = e < kFHI * kFWI && cx >= 0 && cx < nx && cy >= 0 && cy < ny;
-                  const long long ci = o + cx + nx * cy;
-#pragma unroll
-                  for (int d = 0; d < 5; ++d) rc[d][uu] = in ? cV[d * Ntot + ci] : V(0);
-                }
-                if (grp == 0) {
-#pragma unroll
-                  for (int u = 0; u < 2; ++u) {
-                    const int e = tid + u * kFThreads;
-                    if (e < kFHQ * kFWQ) sq[e / kFWQ][e % kFWQ] = rq[u];
-                  }
-                }
-#pragma unroll
-                for (int uu = 0; uu < UG; ++uu) {
-                  const int e = tid + (grp * UG + uu) * kFThreads;
-                  if (e < kFHI * kFWI) {
-#pragma unroll
-                    for (int d = 0; d < 5; ++d) sc[d][e / kFWI][e % kFWI] = rc[d][uu];
-                  }
-                }
-              }
-              __syncthreads();
-              V last = V(0);
-#pragma unroll
-              for (int t = 0; t < 4; ++t) {
-                const int h = 3 - t;
-                const V shk = cv<V>(sf[k + t]);
-                const int w = kFX + 2 * h, hh = kFY + 2 * h;
-                V(*outb)[kFWI] = sb[t & 1];
-                for (int e = tid; e < w * hh; e += kFThreads) {
-                  const int ry = e / w, rx = e - ry * w;
-                  const int iy = ry + t, ix = rx + t;
-                  V qc, qw, qe, qs, qn;
-                  if (t == 0) {
-                    qc = sq[iy + 1][ix + 1];
-                    qw = sq[iy + 1][ix];
-                    qe = sq[iy + 1][ix + 2];
-                    qs = sq[iy][ix + 1];
-                    qn = sq[iy + 2][ix + 1];
-                  } else {
-                    const V(*prev)[kFWI] = sb[(t - 1) & 1];
-                    qc = prev[iy][ix];
-                    qw = prev[iy][ix - 1];
-                    qe = prev[iy][ix + 1];
-                    qs = prev[iy - 1][ix];
-                    qn = prev[iy + 1][ix];
-                  }
-                  V jq = sc[0][iy][ix] * qc;
-                  jq += sc[1][iy][ix] * qw;
-                  jq += sc[2][iy][ix] * qe;
-                  jq += sc[3][iy][ix] * qs;
-                  jq += sc[4][iy][ix] * qn;
-                  outb[iy][ix] = jq * ig - shk * qc;
-                }
-                __syncthreads();
-                const V qo = outb[ly + 3][lx + 3];
-                acc += cv<V>(dk[k + t]) * qo;
-                if (own) part[t] += static_cast<double>(qo) * static_cast<double>(qo);
-                last = qo;
-              }
-              if (own) {
-                pv[i] = acc;
-                qout[i] = last;
-              }
-              __syncthreads();  // the next tile reuses LDS
-            }
-          // the four sums, in the same order in every thread
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            double v = part[t];
-            for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-            if ((tid & 63) == 0) red[t][tid >> 6] = v;
-          }
-          __syncthreads();
-          double S[4];
-#pragma unroll
-          for (int t = 0; t < 4; ++t) {
-            double v = 0.0;
-            for (int w = 0; w < kFThreads / 64; ++w) v += red[t][w];
-            S[t] = v;
-          }
-          __syncthreads();
-          terms += 4;
-          for (int t = 0; t < 4 && !done; ++t) {
-            const int kk = k + t;
-            if (!isfinite(S[t])) {
-              flags |= 2;
-              break;
-            }
-            ring[kk % 5] = fabs(P.delta * dk[kk]) * sqrt(S[t]) / (rootN * scal);
-            if (kk >= 4) {
-              const double mean = 0.2 * (ring[0] + ring[1] + ring[2] + ring[3] + ring[4]);
-              if (mean < a.thresh) done = true;
-            }
-          }
-          if (flags || done) break;  // the substep end needs p only
-        }
-        if (!done) {
-          if (!flags) flags |= 1;
-          break;
-        }
-        const bool lastsub = j + 1 == P.s;
-        for (int c = tid; c < N; c += kFThreads) {
-          const long long i = o + c;
-          const double pi = static_cast<double>(pv[i]);
-          if (!lastsub) a.u[i] = (j == 0 ? 0.0 : a.u[i]) + P.delta * pi;
-          else a.T[i] += (P.s > 1 ? a.u[i] : 0.0) + P.delta * pi;
-        }
-        __syncthreads();
-      }
-      if (!flags) ++steps;
+      a.T0[i] = Tn;
     }
+    return;
+  }
+
+  if (S.phase == kPhInit) {
+    // start of substep S.sub of step S.step
+    double s0 = 0.0, mx = 0.0;
+    if (own) {
+      const long long jw = x > 0 ? i - 1 : i, je = x + 1 < nx ? i + 1 : i;
+      const long long js = y > 0 ? i - nx : i, jn = y + 1 < ny ? i + nx : i;
+      const long long jj[5] = {i, jw, je, js, jn};
+      double c[5], w[5];
+#pragma unroll
+      for (int d = 0; d < 5; ++d) c[d] = a.coef64[d * Nt + i];  // 0 toward missing neighbours
+      const double* Tc = S.tpar ? a.T1 : a.T0;
+      const double* uc = S.upar ? a.u1 : a.u0;
+      const V* pc = reinterpret_cast<const V*>(S.ppar ? a.p1 : a.p0);
+      if (S.kind == kInitFirst) {
+#pragma unroll
+        for (int d = 0; d < 5; ++d) w[d] = Tc[jj[d]];
+      } else if (S.kind == kInitStep) {
+        // T^{n} = T^{n-1} + u + delta p at the cell and its neighbours
+        const bool use_u = P.s > 1;
+#pragma unroll
+        for (int d = 0; d < 5; ++d)
+          w[d] = Tc[jj[d]] + (use_u ? uc[jj[d]] : 0.0) + P.delta * static_cast<double>(pc[jj[d]]);
+      } else {
+        // u after substep S.sub - 1: u + delta p (u = 0 after the first)
+        const bool use_u = S.sub > 1;
+#pragma unroll
+        for (int d = 0; d < 5; ++d) w[d] = (use_u ? uc[jj[d]] : 0.0) + P.delta * static_cast<double>(pc[jj[d]]);
+      }
+      double jw_ = c[0] * w[0];
+#pragma unroll
+      for (int d = 1; d < 5; ++d) jw_ += c[d] * w[d];
+      double q;
+      if (S.kind == kInitSub) {
+        (S.upar ? a.u0 : a.u1)[i] = w[0];
+        q = a.v[i] + jw_;
+      } else {
+        if (S.kind == kInitStep) (S.tpar ? a.T0 : a.T1)[i] = w[0];
+        q = jw_ + a.g[i];
+        a.v[i] = q;
+        mx = fabs(w[0]);
+      }
+      const V qv = cv<V>(q);
+      reinterpret_cast<V*>(a.q0)[i] = qv;
+      reinterpret_cast<V*>(S.ppar ? a.p0 : a.p1)[i] = cv<V>(a.dk[P.coef_off]) * qv;
+      s0 = static_cast<double>(qv) * static_cast<double>(qv);
+    }
+    const double S0 = block_reduce<NW, false>(s0, &red[0][0], tid);
+    const double M0 = block_reduce<NW, true>(mx, &red[1][0], tid);
     if (tid == 0) {
-      BDyn& D = a.dyn[pid];
-      D.terms = terms;
-      D.flags = flags;
-      D.step = steps;
+      part[0] = S0;
+      part[1] = M0;
+    }
+    return;
+  }
+
+  // four Newton terms S.k .. S.k + 3 on the tile
+  const int grp = (S.k - 1) >> 2;
+  const V* __restrict__ qin = reinterpret_cast<const V*>((grp & 1) ? a.q1 : a.q0);
+  V* __restrict__ qout = reinterpret_cast<V*>((grp & 1) ? a.q0 : a.q1);
+  V* __restrict__ p = reinterpret_cast<V*>(S.ppar ? a.p1 : a.p0);
+  const V* __restrict__ coef = reinterpret_cast<const V*>(a.coef);
+  const int x0 = tl.x0, y0 = tl.y0;
+  // every load of the tile is issued (into registers) before the first LDS
+  // store, so the tile waits for one memory latency instead of one per trip
+  constexpr int UQ = (HQ * WQ + NTH - 1) / NTH, UI = (HI * WI + NTH - 1) / NTH;
+  V rq[UQ], rc[5][UI];
+#pragma unroll
+  for (int u = 0; u < UQ; ++u) {
+    const int e = tid + u * NTH;
+    const int ry = e / WQ, rx = e - ry * WQ;
+    const int gx = x0 - NT + rx, gy = y0 - NT + ry;
+    rq[u] = (e < HQ * WQ && gx >= 0 && gx < nx && gy >= 0 && gy < ny) ? qin[o + gx + nx * gy] : V(0);
+  }
+#pragma unroll
+  for (int u = 0; u < UI; ++u) {
+    const int e = tid + u * NTH;
+    const int ry = e / WI, rx = e - ry * WI;
+    const int gx = x0 - H + rx, gy = y0 - H + ry;
+    const bool in = e < HI * WI && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+    const long long j = o + gx + nx * gy;
+#pragma unroll
+    for (int d = 0; d < 5; ++d) rc[d][u] = in ? coef[d * Nt + j] : V(0);
+  }
+  V acc = own ? p[i] : V(0);
+#pragma unroll
+  for (int u = 0; u < UQ; ++u) {
+    const int e = tid + u * NTH;
+    if (e < HQ * WQ) sq[e / WQ][e % WQ] = rq[u];
+  }
+#pragma unroll
+  for (int u = 0; u < UI; ++u) {
+    const int e = tid + u * NTH;
+    if (e < HI * WI) {
+#pragma unroll
+      for (int d = 0; d < 5; ++d) sc[d][e / WI][e % WI] = rc[d][u];
+    }
+  }
+  __syncthreads();
+  const V ig = cv<V>(P.inv_g);
+  const double* shf = a.shift + P.coef_off + S.k;
+  const double* dkp = a.dk + P.coef_off + S.k;
+  double sums[NT];
+  V last = V(0);
+#pragma unroll
+  for (int tt = 0; tt < NT; ++tt) {
+    const int h = H - tt;  // halo of the region computed in this term
+    const V sh = cv<V>(shf[tt]);
+    const int w = kBatchTileX + 2 * h, hh = TY + 2 * h;
+    V(*out)[WI] = sb[tt & 1];
+    for (int e = tid; e < w * hh; e += NTH) {
+      const int ry = e / w, rx = e - ry * w;
+      const int iy = ry + tt, ix = rx + tt;  // position in the halo-H buffers
+      V qc, qw, qe, qs, qn;
+      if (tt == 0) {
+        qc = sq[iy + 1][ix + 1];
+        qw = sq[iy + 1][ix];
+        qe = sq[iy + 1][ix + 2];
+        qs = sq[iy][ix + 1];
+        qn = sq[iy + 2][ix + 1];
+      } else {
+        const V(*prev)[WI] = sb[(tt - 1) & 1];
+        qc = prev[iy][ix];
+        qw = prev[iy][ix - 1];
+        qe = prev[iy][ix + 1];
+        qs = prev[iy - 1][ix];
+        qn = prev[iy + 1][ix];
+      }
+      V jq = sc[0][iy][ix] * qc;
+      jq += sc[1][iy][ix] * qw;
+      jq += sc[2][iy][ix] * qe;
+      jq += sc[3][iy][ix] * qs;
+      jq += sc[4][iy][ix] * qn;
+      out[iy][ix] = jq * ig - sh * qc;  // zero outside the grid (stencil and q are)
     }
     __syncthreads();
+    const V qo = out[ly + H][lx + H];
+    acc += cv<V>(dkp[tt]) * qo;
+    sums[tt] = own ? static_cast<double>(qo) * static_cast<double>(qo) : 0.0;
+    last = qo;
+  }
+  if (own) {
+    p[i] = acc;
+    qout[i] = last;
+  }
+#pragma unroll
+  for (int tt = 0; tt < NT; ++tt) {
+    double v = sums[tt];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((tid & 63) == 0) red[tt][tid >> 6] = v;
+  }
+  __syncthreads();
+  if (tid < NT) {
+    double v = red[tid][0];
+    for (int w = 1; w < NW; ++w) v += red[tid][w];
+    part[tid] = v;
   }
 }
 
-hipError_t launch_fused(const BatchArgs& a, int fp32, int grid, hipStream_t s) {
-  static bool granted[2] = {false, false};
-  const size_t bytes = fp32 ? fused_lds_bytes<float>() : fused_lds_bytes<double>();
-  if (!granted[fp32]) {
-    const hipError_t e = fp32 ? hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch_fused<float>),
-                                                    hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes))
-                              : hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch_fused<double>),
-                                                    hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
-    if (e != hipSuccess) return e;
-    granted[fp32] = true;
+// One wavefront per problem: reduce the problem's tile partials of the last
+// work pass in a fixed order, apply the stop test and pick the next phase.
+constexpr int kCtrlThreads = 256;
+
+__global__ __launch_bounds__(kCtrlThreads) void k_bt_ctrl(BatchArgs a) {
+  const int lane = threadIdx.x & 63;
+  const int pid = blockIdx.x * (kCtrlThreads / 64) + (threadIdx.x >> 6);
+  if (pid >= a.nprob) return;
+  BState S = a.state[pid];
+  if (S.phase == kPhDone) return;
+  if (S.phase == kPhFinish) {
+    if (lane == 0) {
+      S.phase = kPhDone;
+      ++S.phases;
+      a.state[pid] = S;
+      atomicAdd(a.ndone, 1);
+    }
+    return;
   }
-  if (fp32)
-    hipLaunchKernelGGL(k_batch_fused<float>, dim3(grid), dim3(kFThreads), bytes, s, a);
-  else
-    hipLaunchKernelGGL(k_batch_fused<double>, dim3(grid), dim3(kFThreads), bytes, s, a);
-  return hipGetLastError();
+  const BProb P = a.prob[pid];
+  const bool init = S.phase == kPhInit;
+  const double* pp = a.part + 4LL * P.tile0;
+  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  double mx = 0.0;
+  for (int tt = lane; tt < P.ntiles; tt += 64) {
+    if (init) {
+      s[0] += pp[4 * tt];
+      mx = fmax(mx, pp[4 * tt + 1]);
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) s[j] += pp[4 * tt + j];
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) s[j] += __shfl_down(s[j], off, 64);
+    mx = fmax(mx, __shfl_down(mx, off, 64));
+  }
+  if (lane != 0) return;
+  ++S.phases;
+  const double* dk = a.dk + P.coef_off;
+  bool stop = false;  // no further Newton work for this problem
+  if (init) {
+    if (S.kind != kInitSub) S.scal = a.tol_a + a.tol_r * mx;
+    if (S.kind == kInitStep) S.tpar ^= 1;
+    if (S.kind == kInitSub) S.upar ^= 1;
+    S.ppar ^= 1;
+    if (!isfinite(s[0]) || !isfinite(mx)) {
+      S.flags |= 2;
+      stop = true;
+    } else if (!(S.scal > 0.0)) {
+      S.flags |= 4;
+      stop = true;
+    } else {
+      S.ring[0] = fabs(P.delta * dk[0]) * sqrt(s[0]) / (P.rootN * S.scal);
+      S.k = 1;
+      S.phase = kPhTerms;
+    }
+  } else {
+    bool done = false, bad = false;
+    for (int j = 0; j < 4 && !done; ++j) {
+      const int kk = S.k + j;
+      if (!isfinite(s[j])) {
+        bad = true;
+        break;
+      }
+      S.ring[kk % 5] = fabs(P.delta * dk[kk]) * sqrt(s[j]) / (P.rootN * S.scal);
+      if (kk >= 4) {
+        const double mean = 0.2 * (S.ring[0] + S.ring[1] + S.ring[2] + S.ring[3] + S.ring[4]);
+        done = mean < a.thresh;
+      }
+    }
+    S.terms += 4;  // all four terms of the group are kept
+    if (bad) {
+      S.flags |= 2;
+      stop = true;
+    } else if (done) {
+      if (S.sub + 1 < P.s) {
+        ++S.sub;
+        S.kind = kInitSub;
+        S.phase = kPhInit;
+      } else {
+        ++S.step;
+        S.sub = 0;
+        if (S.step == a.nsteps) {
+          S.phase = kPhFinish;
+        } else {
+          S.kind = kInitStep;
+          S.phase = kPhInit;
+        }
+      }
+    } else if (S.k + 4 + 3 > a.m_max) {
+      S.flags |= 1;
+      stop = true;
+    } else {
+      S.k += 4;
+    }
+  }
+  // a failed problem still takes the finish pass, which copies the T of its
+  // last completed step into the caller's array
+  if (stop) S.phase = kPhFinish;
+  a.state[pid] = S;
 }
 
-template <int NT, int U, class V>
-hipError_t launch_variant(const BatchArgs& a, int grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_batch_blocks<NT, U, V>), dim3(grid), dim3(NT), 0, s, a);
-  return hipGetLastError();
+__global__ void k_bt_reset(BatchArgs a) {
+  const int pid = blockIdx.x * blockDim.x + threadIdx.x;
+  if (pid == 0) *a.ndone = 0;
+  if (pid >= a.nprob) return;
+  BState S{};
+  S.phase = kPhInit;
+  S.kind = kInitFirst;
+  S.k = 1;
+  a.state[pid] = S;
 }
 
 // Pack one problem's stencil (SoA, stride N) into the batch layout (SoA,
 // stride ntot, offset off) and form g = F - J T0 (so that G(T) = J T + g).
 __global__ __launch_bounds__(256) void k_batch_pack(int nx, int ny, const double* __restrict__ coef,
-                                          const double* __restrict__ F, const double* __restrict__ T0,
-                                          double* __restrict__ bcoef, double* __restrict__ g, long long ntot,
-                                          long long off) {
+                                                    const double* __restrict__ F, const double* __restrict__ T0,
+                                                    double* __restrict__ bcoef, double* __restrict__ g,
+                                                    long long ntot, long long off) {
   const int N = nx * ny;
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < N; i += gridDim.x * blockDim.x) {
     const int x = i % nx, y = i / nx;
@@ -504,11 +403,30 @@ __global__ __launch_bounds__(256) void k_batch_pack(int nx, int ny, const double
   }
 }
 
+template <int TY, bool XCD, class V>
+hipError_t launch_work(const BatchArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  const size_t bytes = work_lds_bytes<TY, V>();
+  if (bytes > 65536) {
+    static bool granted = false;
+    if (!granted) {
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bt_work<TY, XCD, V>),
+                                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
+      if (e != hipSuccess) return e;
+      granted = true;
+    }
+  }
+  launch_timed(k_bt_work<TY, XCD, V>, dim3(a.ntiles), dim3(kBatchTileX, TY), static_cast<unsigned>(bytes), s, e0, e1,
+               a);
+  return hipGetLastError();
+}
+
 }  // namespace
 
-// {threads, cells loaded ahead per thread}; the last shape is the fused
-// variant (1024 threads, four Newton terms per pass over 64 x 16 tiles).
-const int kTileShapes[kNumTileShapes][2] = {{256, 4}, {256, 8}, {512, 4}, {1024, 2}, {1024, 0}};
+size_t batch_lds_bytes(int shape, int fp32) {
+  const int rows = kBatchTileRows[shape];
+  if (rows == 16) return fp32 ? work_lds_bytes<16, float>() : work_lds_bytes<16, double>();
+  return fp32 ? work_lds_bytes<8, float>() : work_lds_bytes<8, double>();
+}
 
 hipError_t batch_pack(int nx, int ny, const double* coef, const double* F, const double* T0, double* bcoef,
                       double* g, long long ntot, long long off, hipStream_t s) {
@@ -519,20 +437,26 @@ hipError_t batch_pack(int nx, int ny, const double* coef, const double* F, const
   return hipGetLastError();
 }
 
-hipError_t batch_launch(const BatchArgs& a, int shape, int fp32, int grid, hipStream_t s) {
+hipError_t batch_reset(const BatchArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_bt_reset, dim3((a.nprob + 255) / 256), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t batch_phase(const BatchArgs& a, int shape, int fp32, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  hipError_t e;
   switch (shape * 2 + fp32) {
-    case 0: return launch_variant<256, 4, double>(a, grid, s);
-    case 1: return launch_variant<256, 4, float>(a, grid, s);
-    case 2: return launch_variant<256, 8, double>(a, grid, s);
-    case 3: return launch_variant<256, 8, float>(a, grid, s);
-    case 4: return launch_variant<512, 4, double>(a, grid, s);
-    case 5: return launch_variant<512, 4, float>(a, grid, s);
-    case 6: return launch_variant<1024, 2, double>(a, grid, s);
-    case 7: return launch_variant<1024, 2, float>(a, grid, s);
-    case 8: return launch_fused(a, 0, grid, s);
-    case 9: return launch_fused(a, 1, grid, s);
+    case 0: e = launch_work<8, false, double>(a, s, e0, e1); break;
+    case 1: e = launch_work<8, false, float>(a, s, e0, e1); break;
+    case 2: e = launch_work<16, false, double>(a, s, e0, e1); break;
+    case 3: e = launch_work<16, false, float>(a, s, e0, e1); break;
+    case 4: e = launch_work<8, true, double>(a, s, e0, e1); break;
+    case 5: e = launch_work<8, true, float>(a, s, e0, e1); break;
     default: return hipErrorInvalidValue;
   }
+  if (e != hipSuccess) return e;
+  const int per = kCtrlThreads / 64;
+  hipLaunchKernelGGL(k_bt_ctrl, dim3((a.nprob + per - 1) / per), dim3(kCtrlThreads), 0, s, a);
+  return hipGetLastError();
 }
 
 }  // namespace erem

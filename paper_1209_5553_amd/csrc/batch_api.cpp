@@ -1,7 +1,7 @@
 // C ABI of the batched form (erem_batch_*): per-problem setup through the
-// single-problem path, packing, per-problem Leja data, and the one launch of
-// batch.hip that runs every problem for all steps (optionally captured in a
-// hipGraph).
+// single-problem path, packing, per-problem Leja data, the tile list, and the
+// sequence of phase launches of batch.hip that runs every problem for all
+// steps (captured in one hipGraph, or enqueued from the host in chunks).
 #include "erem.h"
 
 #include <hip/hip_runtime.h>
@@ -32,19 +32,31 @@ struct erem_batch {
   std::vector<double> alpha, beta;
   std::vector<char> set;
   // device arrays
-  double *coef = nullptr, *g = nullptr, *v = nullptr, *u = nullptr, *q0 = nullptr, *q1 = nullptr, *p = nullptr;
+  double *coef = nullptr, *g = nullptr, *v = nullptr, *u0 = nullptr, *u1 = nullptr, *T1 = nullptr;
+  double *q0 = nullptr, *q1 = nullptr, *p0 = nullptr, *p1 = nullptr;  // FP64 or FP32 (sized for FP64)
   float* coef32 = nullptr;
-  double *dk = nullptr, *shift = nullptr, *tscratch = nullptr;
+  double *dk = nullptr, *shift = nullptr, *tscratch = nullptr, *part = nullptr;
   BProb* prob = nullptr;
-  int* order = nullptr;  // largest problem first
-  BDyn* dyn = nullptr;
+  BTile* tile = nullptr;
+  BState* state = nullptr;
+  int* ndone = nullptr;
+  int* h_ndone = nullptr;  // pinned
+  int ntiles = 0, tile_cap = 0;
+  std::vector<BProb> hprob;
   // prepared state
   bool prepared = false;
   int fp32 = 0, m_max = 0;
   double tol_a = 0.0, tol_r = 1e-12, thresh = 1e-2;
-  int shape = 3;  // 1024 threads x 2 cells: fastest on the 256-realisation workload
-  std::map<std::pair<int, int>, hipGraphExec_t> graphs;  // (nsteps, shape) -> graph
-  const double* graph_T = nullptr;                       // T array the graphs were captured with
+  int shape = 0;
+  int prof_stride = 0;  // work passes between timed ones (0: no timing)
+  struct Graph {
+    hipGraphExec_t exec = nullptr;
+    int phases = 0;                   // work passes captured
+    std::vector<hipEvent_t> ev;       // start / stop pairs of the timed passes
+  };
+  std::map<std::pair<int, int>, Graph> graphs;  // (nsteps, shape) -> graph
+  const double* graph_T = nullptr;              // T array the graphs were captured with
+  std::map<std::pair<int, int>, int> calib;     // (nsteps, shape) -> work passes of a calibration run
   // per-size single-problem contexts used for setup
   std::map<std::pair<long long, long long>, erem_ctx*> ctxs;
   double *tmp_coef = nullptr, *tmp_F = nullptr;
@@ -75,46 +87,94 @@ int balloc(erem_batch* b, T** p, size_t n) {
   return EREM_OK;
 }
 
+void drop_graphs(erem_batch* b) {
+  for (auto& kv : b->graphs) {
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    for (hipEvent_t e : kv.second.ev) (void)hipEventDestroy(e);
+  }
+  b->graphs.clear();
+}
+
 void free_batch(erem_batch* b) {
-  double** d[] = {&b->coef, &b->g, &b->v, &b->u, &b->q0, &b->q1, &b->p, &b->dk, &b->shift,
-                  &b->tscratch, &b->tmp_coef, &b->tmp_F};
+  double** d[] = {&b->coef, &b->g, &b->v, &b->u0, &b->u1, &b->T1, &b->q0, &b->q1, &b->p0, &b->p1,
+                  &b->dk, &b->shift, &b->tscratch, &b->part, &b->tmp_coef, &b->tmp_F};
   for (double** x : d)
     if (*x) { (void)hipFree(*x); *x = nullptr; }
   if (b->coef32) (void)hipFree(b->coef32);
   if (b->prob) (void)hipFree(b->prob);
-  if (b->order) (void)hipFree(b->order);
-  if (b->dyn) (void)hipFree(b->dyn);
+  if (b->tile) (void)hipFree(b->tile);
+  if (b->state) (void)hipFree(b->state);
+  if (b->ndone) (void)hipFree(b->ndone);
+  if (b->h_ndone) (void)hipHostFree(b->h_ndone);
   if (b->red) (void)hipFree(b->red);
   if (b->h_red) (void)hipHostFree(b->h_red);
-  for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
-  b->graphs.clear();
+  drop_graphs(b);
   for (auto& kv : b->ctxs) erem_destroy(kv.second);
   b->ctxs.clear();
 }
 
-void drop_graphs(erem_batch* b) {
-  for (auto& kv : b->graphs) (void)hipGraphExecDestroy(kv.second);
-  b->graphs.clear();
+// Tile list and per-problem tile ranges for the current shape (64 x rows
+// tiles, problems in order, each problem's tiles row by row).
+int build_tiles(erem_batch* b) {
+  const int rows = kBatchTileRows[b->shape];
+  std::vector<BTile> tiles;
+  for (int i = 0; i < b->nprob; ++i) {
+    BProb& P = b->hprob[i];
+    const int tx = static_cast<int>((b->grids[i].nx + kBatchTileX - 1) / kBatchTileX);
+    const int ty = static_cast<int>((b->grids[i].ny + rows - 1) / rows);
+    P.tile0 = static_cast<int>(tiles.size());
+    P.ntiles = tx * ty;
+    P.tiles_x = tx;
+    for (int y = 0; y < ty; ++y)
+      for (int x = 0; x < tx; ++x) tiles.push_back(BTile{i, x * kBatchTileX, y * rows, 0});
+  }
+  if (tiles.size() > static_cast<size_t>(1 << 30)) return bfail(b, EREM_EINVAL, "too many tiles");
+  b->ntiles = static_cast<int>(tiles.size());
+  if (b->ntiles > b->tile_cap) {
+    // sized once for the largest tile count of any shape (the fewest rows),
+    // so that the arrays the graphs hold are never reallocated
+    long long cap = 0;
+    int rmin = kBatchTileRows[0];
+    for (int k = 1; k < kNumTileShapes; ++k) rmin = std::min(rmin, kBatchTileRows[k]);
+    for (int i = 0; i < b->nprob; ++i)
+      cap += ((b->grids[i].nx + kBatchTileX - 1) / kBatchTileX) * ((b->grids[i].ny + rmin - 1) / rmin);
+    cap = std::max<long long>(cap, b->ntiles);
+    if (b->tile) (void)hipFree(b->tile);
+    if (b->part) (void)hipFree(b->part);
+    b->tile = nullptr;
+    b->part = nullptr;
+    if (balloc(b, &b->tile, cap) || balloc(b, &b->part, 4 * static_cast<size_t>(cap))) return EREM_ENOMEM;
+    b->tile_cap = static_cast<int>(cap);
+  }
+  BHIP(b, hipMemcpy(b->tile, tiles.data(), sizeof(BTile) * tiles.size(), hipMemcpyHostToDevice));
+  BHIP(b, hipMemcpy(b->prob, b->hprob.data(), sizeof(BProb) * b->nprob, hipMemcpyHostToDevice));
+  return EREM_OK;
 }
 
 BatchArgs make_args(erem_batch* b, double* T, int nsteps) {
   BatchArgs a{};
   a.prob = b->prob;
-  a.dyn = b->dyn;
-  a.order = b->order;
+  a.tile = b->tile;
+  a.state = b->state;
+  a.ndone = b->ndone;
   a.coef64 = b->coef;
   a.coef = b->fp32 ? static_cast<const void*>(b->coef32) : static_cast<const void*>(b->coef);
   a.g = b->g;
-  a.T = T;
+  a.T0 = T;
+  a.T1 = b->T1;
+  a.u0 = b->u0;
+  a.u1 = b->u1;
   a.v = b->v;
-  a.u = b->u;
   a.q0 = b->q0;
   a.q1 = b->q1;
-  a.p = b->p;
+  a.p0 = b->p0;
+  a.p1 = b->p1;
   a.dk = b->dk;
   a.shift = b->shift;
+  a.part = b->part;
   a.ntot = b->ntot;
   a.nprob = b->nprob;
+  a.ntiles = b->ntiles;
   a.nsteps = nsteps;
   a.m_max = b->m_max;
   a.tol_a = b->tol_a;
@@ -123,63 +183,187 @@ BatchArgs make_args(erem_batch* b, double* T, int nsteps) {
   return a;
 }
 
-// One workgroup per problem; the hardware hands the next (smaller) problem to
-// a CU as soon as one finishes, so the largest-first order balances the load.
-int grid_size(erem_batch* b) { return std::min(b->nprob, 1 << 20); }
+// Upper bound of the work passes a run can take: every problem needs, per
+// step and substep, one start pass and at most m_max / 4 term passes, and
+// one finish pass.
+long long max_phases(erem_batch* b, int nsteps) {
+  int smax = 1;
+  for (const BProb& P : b->hprob) smax = std::max(smax, P.s);
+  return static_cast<long long>(nsteps) * smax * (1 + b->m_max / 4) + 2;
+}
 
-// One launch (optionally through a cached graph).  Synchronises the stream.
+// Phases enqueued eagerly in chunks, the host reading the count of finished
+// problems after each chunk, until every problem is done.  Returns the work
+// passes enqueued.  With prof_stride > 0 every prof_stride-th pass is timed
+// into *work_ms / *timed.
+int run_eager(erem_batch* b, const BatchArgs& a, long long start, long long* passes, double* work_ms, int* timed) {
+  constexpr int kChunk = 64;
+  const long long limit = max_phases(b, a.nsteps);
+  long long n = start;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (b->prof_stride > 0) {
+    BHIP(b, hipEventCreate(&e0));
+    BHIP(b, hipEventCreate(&e1));
+  }
+  while (true) {
+    BHIP(b, hipMemcpyAsync(b->h_ndone, b->ndone, sizeof(int), hipMemcpyDeviceToHost, b->stream));
+    BHIP(b, hipStreamSynchronize(b->stream));
+    if (*b->h_ndone >= b->nprob) break;
+    if (n >= limit) {
+      if (e0) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); }
+      return bfail(b, EREM_EDEVICE, "batch run did not finish within its phase bound");
+    }
+    for (int c = 0; c < kChunk && n < limit; ++c, ++n) {
+      const bool time_it = e0 && n % b->prof_stride == 0;
+      BHIP(b, batch_phase(a, b->shape, b->fp32, b->stream, time_it ? e0 : nullptr, time_it ? e1 : nullptr));
+      if (time_it) {
+        BHIP(b, hipEventSynchronize(e1));
+        float ms = 0.0f;
+        BHIP(b, hipEventElapsedTime(&ms, e0, e1));
+        *work_ms += ms;
+        ++*timed;
+      }
+    }
+  }
+  if (e0) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); }
+  *passes = n;
+  return EREM_OK;
+}
+
+// Capture reset + `phases` work passes (every prof_stride-th between event
+// records) into a graph.
+int capture(erem_batch* b, const BatchArgs& a, int phases, erem_batch::Graph* g) {
+  g->phases = phases;
+  if (b->prof_stride > 0) {
+    for (int n = 0; n < phases; n += b->prof_stride) {
+      hipEvent_t e0, e1;
+      BHIP(b, hipEventCreate(&e0));
+      BHIP(b, hipEventCreate(&e1));
+      g->ev.push_back(e0);
+      g->ev.push_back(e1);
+    }
+  }
+  hipGraph_t graph;
+  BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+  hipError_t le = batch_reset(a, b->stream);
+  for (int n = 0; n < phases && le == hipSuccess; ++n) {
+    const bool time_it = b->prof_stride > 0 && n % b->prof_stride == 0;
+    if (time_it) le = hipEventRecord(g->ev[2 * (n / b->prof_stride)], b->stream);
+    if (le == hipSuccess) le = batch_phase(a, b->shape, b->fp32, b->stream);
+    if (time_it && le == hipSuccess) le = hipEventRecord(g->ev[2 * (n / b->prof_stride) + 1], b->stream);
+  }
+  const hipError_t ce = hipStreamEndCapture(b->stream, &graph);
+  if (le != hipSuccess || ce != hipSuccess) {
+    (void)hipGetLastError();
+    return bfail(b, EREM_EDEVICE, std::string("graph capture failed: ") + hipGetErrorString(le != hipSuccess ? le : ce));
+  }
+  const hipError_t ie = hipGraphInstantiate(&g->exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ie != hipSuccess) return bfail(b, EREM_EDEVICE, std::string("graph instantiation failed: ") + hipGetErrorString(ie));
+  return EREM_OK;
+}
+
+// One run of nsteps steps on T (synchronises the stream).
 int launch(erem_batch* b, double* T, int nsteps, bool use_graph, erem_batch_stats* st) {
   const BatchArgs a = make_args(b, T, nsteps);
-  const int grid = grid_size(b);
+  const auto key = std::make_pair(nsteps, b->shape);
+  erem_batch::Graph* g = nullptr;
+  if (use_graph) {
+    auto it = b->graphs.find(key);
+    if (it == b->graphs.end()) {
+      // the budget of captured passes comes from a calibration run on a copy
+      auto ci = b->calib.find(key);
+      if (ci == b->calib.end()) {
+        BHIP(b, hipMemcpyAsync(b->tscratch, T, sizeof(double) * b->ntot, hipMemcpyDeviceToDevice, b->stream));
+        const BatchArgs ac = make_args(b, b->tscratch, nsteps);
+        BHIP(b, batch_reset(ac, b->stream));
+        long long used = 0;
+        double wm = 0.0;
+        int tn = 0;
+        const int saved = b->prof_stride;
+        b->prof_stride = 0;
+        const int rc = run_eager(b, ac, 0, &used, &wm, &tn);
+        b->prof_stride = saved;
+        if (rc) return rc;
+        // passes up to the last problem's finish (the eager run overshoots by < one chunk)
+        std::vector<BState> S(b->nprob);
+        BHIP(b, hipMemcpy(S.data(), b->state, sizeof(BState) * b->nprob, hipMemcpyDeviceToHost));
+        int need = 0;
+        for (const BState& s : S) need = std::max(need, s.phases);
+        ci = b->calib.emplace(key, need).first;
+      }
+      const int budget = ci->second + std::max(8, ci->second / 32);
+      erem_batch::Graph ng;
+      int rc = capture(b, a, budget, &ng);
+      if (rc && b->prof_stride > 0) {
+        // event records that a capture does not take: capture without them
+        // (the runs then report no work-launch timing)
+        if (ng.exec) (void)hipGraphExecDestroy(ng.exec);
+        for (hipEvent_t e : ng.ev) (void)hipEventDestroy(e);
+        ng = erem_batch::Graph{};
+        const int saved = b->prof_stride;
+        b->prof_stride = 0;
+        rc = capture(b, a, budget, &ng);
+        b->prof_stride = saved;
+      }
+      if (rc) {
+        if (ng.exec) (void)hipGraphExecDestroy(ng.exec);
+        for (hipEvent_t e : ng.ev) (void)hipEventDestroy(e);
+        return rc;
+      }
+      it = b->graphs.emplace(key, std::move(ng)).first;
+    }
+    g = &it->second;
+  }
   hipEvent_t e0, e1;
   BHIP(b, hipEventCreate(&e0));
   BHIP(b, hipEventCreate(&e1));
-  bool graphed = false;
   BHIP(b, hipEventRecord(e0, b->stream));
-  if (use_graph) {
-    const auto key = std::make_pair(nsteps, b->shape);
-    auto it = b->graphs.find(key);
-    if (it == b->graphs.end()) {
-      hipGraph_t graph;
-      hipGraphExec_t exec;
-      bool ok = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
-      if (ok) {
-        const hipError_t le = batch_launch(a, b->shape, b->fp32, grid, b->stream);
-        const hipError_t ce = hipStreamEndCapture(b->stream, &graph);
-        ok = le == hipSuccess && ce == hipSuccess;
-        if (ok) {
-          ok = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) == hipSuccess;
-          (void)hipGraphDestroy(graph);
-        }
-      }
-      (void)hipGetLastError();
-      if (ok) it = b->graphs.emplace(key, exec).first;
-    }
-    if (it != b->graphs.end()) {
-      // the captured launch holds T's pointer: replay only for the same array
-      BHIP(b, hipGraphLaunch(it->second, b->stream));
-      graphed = true;
-    }
+  long long passes = 0;
+  double work_ms = 0.0;
+  int timed = 0;
+  int rc = EREM_OK;
+  if (g) {
+    BHIP(b, hipGraphLaunch(g->exec, b->stream));
+    // a run that needs more passes than the graph holds continues eagerly
+    rc = run_eager(b, a, g->phases, &passes, &work_ms, &timed);
+  } else {
+    BHIP(b, batch_reset(a, b->stream));
+    rc = run_eager(b, a, 0, &passes, &work_ms, &timed);
   }
-  if (!graphed) BHIP(b, batch_launch(a, b->shape, b->fp32, grid, b->stream));
   BHIP(b, hipEventRecord(e1, b->stream));
   BHIP(b, hipStreamSynchronize(b->stream));
+  if (rc) {
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
+  }
   float ms = 0.0f;
   (void)hipEventElapsedTime(&ms, e0, e1);
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  std::vector<BDyn> dyn(b->nprob);
-  BHIP(b, hipMemcpy(dyn.data(), b->dyn, sizeof(BDyn) * b->nprob, hipMemcpyDeviceToHost));
+  if (g) {
+    for (size_t j = 0; j + 1 < g->ev.size(); j += 2) {
+      float w = 0.0f;
+      if (hipEventElapsedTime(&w, g->ev[j], g->ev[j + 1]) == hipSuccess) {
+        work_ms += w;
+        ++timed;
+      }
+    }
+  }
+  std::vector<BState> S(b->nprob);
+  BHIP(b, hipMemcpy(S.data(), b->state, sizeof(BState) * b->nprob, hipMemcpyDeviceToHost));
   long long tot = 0;
-  int tmin = 1 << 30, tmax = 0, failed = 0, flags = 0;
+  int tmin = 1 << 30, tmax = 0, failed = 0, flags = 0, phases = 0;
   double bytes = 0.0;
   const double per_cell = b->fp32 ? 36.0 : 72.0;  // 5 coef + q_in + p rd/wr + q_out
   for (int i = 0; i < b->nprob; ++i) {
-    const BDyn& d = dyn[i];
+    const BState& d = S[i];
     bytes += per_cell * static_cast<double>(d.terms) * static_cast<double>(b->off[i + 1] - b->off[i]);
     tot += d.terms;
     tmin = std::min(tmin, d.terms);
     tmax = std::max(tmax, d.terms);
+    phases = std::max(phases, d.phases);
     if (d.flags || d.step < nsteps) ++failed;
     flags |= d.flags;
   }
@@ -189,14 +373,28 @@ int launch(erem_batch* b, double* T, int nsteps, bool use_graph, erem_batch_stat
     st->terms_max = tmax;
     st->failed = failed;
     st->tile_shape = b->shape;
-    st->graph = graphed ? 1 : 0;
-    st->grid = grid;
+    st->graph = g ? 1 : 0;
+    st->grid = b->ntiles;
     st->ms = ms;
     st->leja_bytes = bytes;
+    st->phases = phases;
+    st->passes = g ? std::max<long long>(g->phases, passes) : passes;
+    st->work_ms = work_ms;
+    st->work_timed = timed;
   }
   if (flags & 2) return bfail(b, EREM_ENONFINITE, "non-finite Leja norm in a batch problem");
+  if (flags & 4) return bfail(b, EREM_EINVAL, "error scale is zero in a batch problem (tol_a = 0 and T = 0)");
   if (failed) return bfail(b, EREM_ENOCONV, "a batch problem did not converge within m_max terms");
   return EREM_OK;
+}
+
+// Switch the tile shape: the tile list changes, so the captured graphs go.
+int set_shape(erem_batch* b, int shape) {
+  if (shape == b->shape) return EREM_OK;
+  BHIP(b, hipStreamSynchronize(b->stream));
+  drop_graphs(b);
+  b->shape = shape;
+  return build_tiles(b);
 }
 
 }  // namespace
@@ -233,23 +431,31 @@ int erem_batch_create(int32_t nprob, const erem_grid* grids, void* stream, erem_
   rc |= balloc(b, &b->coef, 5 * n);
   rc |= balloc(b, &b->g, n);
   rc |= balloc(b, &b->v, n);
-  rc |= balloc(b, &b->u, n);
+  rc |= balloc(b, &b->u0, n);
+  rc |= balloc(b, &b->u1, n);
+  rc |= balloc(b, &b->T1, n);
   rc |= balloc(b, &b->q0, n);
   rc |= balloc(b, &b->q1, n);
-  rc |= balloc(b, &b->p, n);
+  rc |= balloc(b, &b->p0, n);
+  rc |= balloc(b, &b->p1, n);
   rc |= balloc(b, &b->tscratch, n);
-  rc |= balloc(b, &b->dyn, nprob);
   rc |= balloc(b, &b->prob, nprob);
-  rc |= balloc(b, &b->order, nprob);
+  rc |= balloc(b, &b->state, nprob);
+  rc |= balloc(b, &b->ndone, 1);
   rc |= balloc(b, &b->red, 1);
   if (rc == EREM_OK && hipHostMalloc(reinterpret_cast<void**>(&b->h_red), sizeof(AsmReduce), hipHostMallocDefault) != hipSuccess)
     rc = EREM_ENOMEM;
+  if (rc == EREM_OK && hipHostMalloc(reinterpret_cast<void**>(&b->h_ndone), sizeof(int), hipHostMallocDefault) != hipSuccess)
+    rc = EREM_ENOMEM;
   if (rc == EREM_OK) {
-    std::vector<int> order(nprob);
-    for (int i = 0; i < nprob; ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int x, int y) { return b->off[x + 1] - b->off[x] > b->off[y + 1] - b->off[y]; });
-    if (hipMemcpy(b->order, order.data(), sizeof(int) * nprob, hipMemcpyHostToDevice) != hipSuccess) rc = EREM_EDEVICE;
+    b->hprob.assign(nprob, BProb{});
+    for (int i = 0; i < nprob; ++i) {
+      b->hprob[i].nx = static_cast<int>(grids[i].nx);
+      b->hprob[i].ny = static_cast<int>(grids[i].ny);
+      b->hprob[i].s = 1;
+      b->hprob[i].off = b->off[i];
+    }
+    rc = build_tiles(b);
   }
   if (rc != EREM_OK) {
     free_batch(b);
@@ -341,7 +547,7 @@ int erem_batch_prepare(erem_batch* b, double h, const erem_opts* o) {
   std::vector<double> xi;
   if (!leja_points(M + 1, xi)) return bfail(b, EREM_EINVAL, "Leja points");
   std::vector<double> dk(static_cast<size_t>(b->nprob) * (M + 1)), sh(dk.size());
-  std::vector<BProb> prob(b->nprob);
+  std::vector<BProb>& prob = b->hprob;
   std::vector<double> cc(b->nprob), gg(b->nprob);
   for (int i = 0; i < b->nprob; ++i) {
     const double a = b->alpha[i], be = b->beta[i];
@@ -349,7 +555,8 @@ int erem_batch_prepare(erem_batch* b, double h, const erem_opts* o) {
     if (!std::isfinite(width)) return bfail(b, EREM_ENONFINITE, "non-finite Gershgorin interval");
     if (!(width > 1e-14 * std::max(std::fabs(a), std::fabs(be)))) return bfail(b, EREM_EINVAL, "degenerate interval in a batch problem");
     int s = 1;
-    if (o->rho_max > 0) s = std::max(1, static_cast<int>(std::ceil(h * width / o->rho_max)));
+    const double rho = o->precision == EREM_PREC_MIXED ? std::min(o->rho_max, kMixedRhoMax) : o->rho_max;
+    if (rho > 0) s = std::max(1, static_cast<int>(std::ceil(h * width / rho)));
     s = std::min(s, std::max(1, o->max_substeps));
     cc[i] = 0.5 * (a + be);
     gg[i] = 0.25 * width;
@@ -360,6 +567,7 @@ int erem_batch_prepare(erem_batch* b, double h, const erem_opts* o) {
     P.off = b->off[i];
     P.inv_g = 1.0 / gg[i];
     P.delta = h / s;
+    P.rootN = std::sqrt(static_cast<double>(P.nx) * P.ny);
     P.coef_off = i * (M + 1);
     for (int k = 0; k <= M; ++k) sh[P.coef_off + k] = k > 0 ? cc[i] / gg[i] + xi[k - 1] : 0.0;
   }
@@ -381,7 +589,8 @@ int erem_batch_prepare(erem_batch* b, double h, const erem_opts* o) {
   if (balloc(b, &b->dk, dk.size()) || balloc(b, &b->shift, sh.size())) return EREM_ENOMEM;
   BHIP(b, hipMemcpy(b->dk, dk.data(), sizeof(double) * dk.size(), hipMemcpyHostToDevice));
   BHIP(b, hipMemcpy(b->shift, sh.data(), sizeof(double) * sh.size(), hipMemcpyHostToDevice));
-  BHIP(b, hipMemcpy(b->prob, prob.data(), sizeof(BProb) * b->nprob, hipMemcpyHostToDevice));
+  const int trc = build_tiles(b);  // uploads the problem records
+  if (trc) return trc;
   b->fp32 = o->precision == EREM_PREC_MIXED ? 1 : 0;
   if (b->fp32) {
     if (!b->coef32 && balloc(b, &b->coef32, 5 * static_cast<size_t>(b->ntot))) return EREM_ENOMEM;
@@ -393,6 +602,7 @@ int erem_batch_prepare(erem_batch* b, double h, const erem_opts* o) {
   b->tol_r = o->tol_r;
   b->thresh = std::pow(10.0, -o->p_order);
   drop_graphs(b);
+  b->calib.clear();
   b->prepared = true;
   return EREM_OK;
 }
@@ -403,18 +613,26 @@ int erem_batch_autotune(erem_batch* b, const double* d_T, int32_t nsteps, int32_
   if (!d_T || nsteps < 1) return bfail(b, EREM_EINVAL, "bad arguments");
   double best = 1e300;
   int best_s = 0;
+  const int saved = b->prof_stride;
+  b->prof_stride = 0;
   for (int s = 0; s < kNumTileShapes; ++s) {
-    b->shape = s;
+    const int rc0 = set_shape(b, s);
+    if (rc0) return rc0;
     BHIP(b, hipMemcpyAsync(b->tscratch, d_T, sizeof(double) * b->ntot, hipMemcpyDeviceToDevice, b->stream));
     erem_batch_stats st{};
     const int rc = launch(b, b->tscratch, nsteps, false, &st);
-    if (rc) return rc;
+    if (rc) {
+      b->prof_stride = saved;
+      return rc;
+    }
     if (st.ms < best) {
       best = st.ms;
       best_s = s;
     }
   }
-  b->shape = best_s;
+  b->prof_stride = saved;
+  const int rc = set_shape(b, best_s);
+  if (rc) return rc;
   if (chosen) *chosen = best_s;
   return EREM_OK;
 }
@@ -422,7 +640,17 @@ int erem_batch_autotune(erem_batch* b, const double* d_T, int32_t nsteps, int32_
 int erem_batch_set_tile_shape(erem_batch* b, int32_t shape) {
   if (!b) return EREM_EINVAL;
   if (shape < 0 || shape >= kNumTileShapes) return bfail(b, EREM_EINVAL, "tile shape index out of range");
-  b->shape = shape;
+  return set_shape(b, shape);
+}
+
+int erem_batch_profile(erem_batch* b, int32_t stride) {
+  if (!b) return EREM_EINVAL;
+  if (stride < 0) return bfail(b, EREM_EINVAL, "stride must be >= 0");
+  if (stride != b->prof_stride) {
+    BHIP(b, hipStreamSynchronize(b->stream));
+    drop_graphs(b);
+    b->prof_stride = stride;
+  }
   return EREM_OK;
 }
 

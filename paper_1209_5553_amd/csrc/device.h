@@ -12,6 +12,10 @@ constexpr int kBY = 4;         // rows per block -> 256 threads, 4 wavefronts
 constexpr int kThreads = kBX * kBY;
 constexpr int kSlots = 64;     // spread of the atomic partial sums (one wavefront sums them)
 constexpr int kMaxTerms = 1024;  // Leja degree cap per substep
+// Widest substep interval h (beta - alpha) / s of the FP32 Newton passes: the
+// terms grow to about e^(rho/10) times the result before they cancel, and in
+// FP32 that growth is lost accuracy.
+constexpr double kMixedRhoMax = 32.0;
 
 struct Dims {
   int nx, ny, nz;      // cells

@@ -98,7 +98,7 @@ def test_adjoint_matches_oracle_dense_adjoint(torch_mod, shape):
     eK = np.abs(gK - gK_ref).max() / np.abs(gK_ref).max()
     _say(f"adjoint {shape} vs oracle: dT0 {eT:.3e} (max {np.abs(gT_ref).max():.3e}), "
          f"dlogK {eK:.3e} (max {np.abs(gK_ref).max():.3e})")
-    assert eT <= 1e-8 and eK <= 1e-8
+    assert eT <= 1e-10 and eK <= 1e-10
 
 
 def test_checkpoint_stride_matches_full_store(torch_mod):

@@ -1,8 +1,9 @@
-"""GPU parity of the batched persistent form (many ragged problems, one launch).
+"""GPU parity of the batched form (many ragged problems, one graph launch).
 
-Each realisation of the batch must equal the single-problem HIP path (which
-the oracle pins) to 1e-12, the oracle itself to 1e-10 on small grids, and the
-FP32 variant the FP64 one to 1e-5.
+Each realisation of the batch must equal the oracle to 1e-10 (small grids,
+and sampled realisations of the full 256-problem workload), the
+single-problem HIP path to 1e-12, and in FP32 the oracle to 1e-5; graph and
+host-driven runs agree bit for bit.
 """
 import numpy as np
 import pytest
@@ -61,9 +62,9 @@ def test_batch_small_matches_oracle(torch_mod):
         assert rel_inf(Tg - p.T0, Tref - p.T0) <= 1e-10, p.name
 
 
-@pytest.mark.parametrize("shape", [0, 1, 2, 3, 4])
+@pytest.mark.parametrize("shape", [0, 1, 2])
 def test_batch_every_tile_shape_matches_oracle(torch_mod, shape):
-    """Every workgroup shape, on sides that span several 64 x 16 tiles with
+    """Every tile shape, on sides that span several 64 x 16 tiles with
     ragged tails (70 x 70) and on grids smaller than one tile."""
     torch = torch_mod
     from paper_1209_5553_amd.api import EremBatch, make_opts
@@ -113,9 +114,16 @@ def test_batch_graph_replay_and_fp32(torch_mod):
     Tc = T0.clone()
     sc = b.run(Tc, nsteps, use_graph=False)
     _say(f"graph runs: {sa} {sb} plain {sc}")
-    assert sa["graph"] == 1 and sb["graph"] == 1
+    assert sa["graph"] == 1 and sb["graph"] == 1 and sc["graph"] == 0
     assert torch.equal(Ta, Tb)
-    assert rel_inf(Ta.cpu().numpy(), Tc.cpu().numpy()) <= 1e-14
+    assert torch.equal(Ta, Tc)      # fixed-order reductions: the same bits either way
+    Td = T0.clone()
+    b.run(Td, nsteps, use_graph=True)
+    for _ in range(2):              # replays with eager work and syncs between them
+        Td.copy_(T0)
+        torch.cuda.synchronize()
+        sd = b.run(Td, nsteps, use_graph=True)
+        assert sd["graph"] == 1 and torch.equal(Td, Ta)
     # FP32 Newton passes
     b.prepare(probs[0].h, make_opts(m_max=128, precision=1, tol_r=1e-7))
     Tf = T0.clone()
@@ -133,7 +141,7 @@ def test_batch_autotune_picks_a_shape_and_results_agree(torch_mod):
     b.prepare(probs[0].h, make_opts(m_max=128))
     T0 = b.pack([p.T0 for p in probs])
     shape = b.autotune(T0, nsteps=1)
-    assert shape in (0, 1, 2, 3, 4)
+    assert shape in (0, 1, 2)
     assert torch.equal(T0, b.pack([p.T0 for p in probs]))   # autotune leaves T alone
     T = T0.clone()
     st = b.run(T, 2, use_graph=False)
@@ -144,14 +152,92 @@ def test_batch_autotune_picks_a_shape_and_results_agree(torch_mod):
         assert rel_inf(Tg - p.T0, Ts - p.T0) <= 1e-12
 
 
-def test_batch_256_realisations_full_size(torch_mod):
+def test_batch_graph_budget_exceeded_continues_from_host(torch_mod):
+    """A graph captured for a start that needs almost no Newton terms (each
+    realisation's steady state, where G(T) = 0 up to rounding), replayed on
+    the workload's start: the run goes on with launches from the host where
+    the graph's passes end, with the same result, bit for bit, as a run
+    without the graph, and the oracle's."""
+    import scipy.sparse.linalg as spla
+    torch = torch_mod
+    from paper_1209_5553_amd.api import EremBatch, make_opts
+    probs = [inputs.batch_problem(s) for s in range(30, 34)]
+    nsteps = 2
+    b = EremBatch(probs, device="cuda:0")
+    b.prepare(probs[0].h, make_opts(m_max=256))
+    steady = []
+    for p in probs:
+        m = oerem.Discretisation(p, p.T0).model
+        steady.append(spla.spsolve(m.A.tocsc(), -m.b))
+    T = b.pack(steady)
+    sg = b.run(T, nsteps, use_graph=True)           # calibrated and captured on the steady start
+    T.copy_(b.pack([p.T0 for p in probs]))
+    sr = b.run(T, nsteps, use_graph=True)           # same array: the same graph, too short
+    Te = b.pack([p.T0 for p in probs])
+    se = b.run(Te, nsteps, use_graph=False)
+    _say(f"steady start {sg}; workload start through the graph {sr}; without {se}")
+    assert sr["graph"] == 1 and sr["failed"] == 0
+    assert sr["passes"] > sg["passes"]               # launched past the end of the graph
+    assert torch.equal(T, Te)
+    for p, Tg in zip(probs, b.unpack(Te)):
+        Tref, _ = oerem.run_linear(p, nsteps=nsteps, tier="taylor")
+        assert rel_inf(Tg - p.T0, Tref - p.T0) <= 1e-10, p.name
+
+
+@pytest.fixture(scope="module")
+def full_batch(torch_mod):
+    """The full workload's 256 realisations (seeds 0..255) set up once."""
+    from paper_1209_5553_amd.api import EremBatch
+    probs = [inputs.batch_problem(s) for s in range(256)]
+    b = EremBatch(probs, device="cuda:0")
+    _say(f"256 problems set up ({b.ntot} cells)")
+    yield probs, b
+    b.close()
+
+
+def _sample_of(probs):
+    """The smallest and the largest realisation and two drawn at random."""
+    sides = np.array([p.nx for p in probs])
+    rnd = np.random.default_rng(7).choice(len(probs), 2, replace=False)
+    return [int(np.argmin(sides)), int(np.argmax(sides))] + [int(i) for i in rnd]
+
+
+def test_batch_256_first_steps_match_oracle(torch_mod, full_batch):
+    """The full 256-realisation launch, 3 steps, FP64 and FP32 Newton passes:
+    the smallest, the largest and two random realisations on every cell
+    against the oracle's sparse action (1e-10 FP64, 1e-5 FP32)."""
+    from paper_1209_5553_amd.api import make_opts
+    probs, b = full_batch
+    nsteps = 3
+    T0 = b.pack([p.T0 for p in probs])
+    b.prepare(probs[0].h, make_opts(m_max=128))
+    T64 = T0.clone()
+    st = b.run(T64, nsteps, use_graph=True)
+    _say(f"256 x {nsteps} FP64: {st}")
+    assert st["failed"] == 0
+    b.prepare(probs[0].h, make_opts(m_max=128, precision=1, tol_r=1e-7))
+    T32 = T0.clone()
+    st = b.run(T32, nsteps, use_graph=True)
+    _say(f"256 x {nsteps} FP32: {st}")
+    assert st["failed"] == 0
+    g64, g32 = b.unpack(T64), b.unpack(T32)
+    for i in _sample_of(probs):
+        p = probs[i]
+        Tref, _ = oerem.run_linear(p, nsteps=nsteps, tier="taylor")
+        e64 = rel_inf(g64[i] - p.T0, Tref - p.T0)
+        e32 = rel_inf(g32[i] - p.T0, Tref - p.T0)
+        _say(f"realisation {i} (side {p.nx}): FP64 increment err {e64:.3e}, FP32 {e32:.3e}, "
+             f"FP32 T err {rel_inf(g32[i], Tref):.3e}")
+        assert e64 <= 1e-10, i
+        assert e32 <= 1e-5 and rel_inf(g32[i], Tref) <= 1e-5, i
+
+
+def test_batch_256_realisations_full_size(torch_mod, full_batch):
     """The full workload: 256 realisations (seeds 0..255), 50 steps in one
     graph launch; sampled realisations against the single-problem path."""
     torch = torch_mod
-    from paper_1209_5553_amd.api import EremBatch, make_opts
-    probs = [inputs.batch_problem(s) for s in range(256)]
-    b = EremBatch(probs, device="cuda:0")
-    _say("256 problems set up")
+    from paper_1209_5553_amd.api import make_opts
+    probs, b = full_batch
     b.prepare(probs[0].h, make_opts(m_max=128))
     T = b.pack([p.T0 for p in probs])
     _say("prepared; running 256 x 50 in one graph launch")
@@ -160,8 +246,7 @@ def test_batch_256_realisations_full_size(torch_mod):
     assert st["failed"] == 0
     got = b.unpack(T)
     sides = np.array([p.nx for p in probs])
-    sample = [int(np.argmin(sides)), int(np.argmax(sides)), 17, 130]
-    for i in sample:
+    for i in _sample_of(probs):
         Ts = _single(torch, probs[i], 50, make_opts(m_max=128))
         err = rel_inf(got[i] - probs[i].T0, Ts - probs[i].T0)
         _say(f"realisation {i} (side {sides[i]}): rel err {err:.3e}")
