@@ -370,8 +370,9 @@ typedef struct {
     int64_t terms_total;   /* Newton-Leja terms summed over problems and steps */
     int32_t terms_min, terms_max;  /* per problem, over the run */
     int32_t failed;        /* problems that stopped on an error (see the return code) */
-    int32_t tile_shape;    /* 0: 64 x 8 tiles (512 threads), 1: 64 x 16 (1024 threads),
-                              2: 64 x 8 with each XCD taking a contiguous range of tiles;
+    int32_t tile_shape;    /* 0: 64 x 8 tiles on 512 threads, 1: 64 x 16 on 1024 threads,
+                              2: 64 x 8 on 512 threads, 3: 64 x 16 on 512, 4: 64 x 32 on
+                              512, with each XCD taking a contiguous range of tiles in 2-4;
                               the Newton terms go four per pass (the applied degree is the
                               first multiple of 4 at which the stop test holds) */
     int32_t graph;         /* 1 if the run was replayed from a hipGraph */
@@ -405,12 +406,14 @@ int erem_batch_prepare(erem_batch* b, double h, const erem_opts* opts);
 /* Time every tile shape on a copy of d_T (nsteps steps) and keep the fastest;
  * *chosen receives its index.  d_T is not modified. */
 int erem_batch_autotune(erem_batch* b, const double* d_T, int32_t nsteps, int32_t* chosen);
-/* Select a tile shape by index (0 .. 2, see erem_batch_stats.tile_shape)
+/* Select a tile shape by index (0 .. 4, see erem_batch_stats.tile_shape)
  * instead of timing them.  EINVAL for another index. */
 int erem_batch_set_tile_shape(erem_batch* b, int32_t shape);
-/* Time every stride-th work launch of the following runs with a HIP event
- * pair (recorded into the graph when one is used); 0 turns it off.  The sums
- * go to erem_batch_stats.work_ms / work_timed.  EINVAL for stride < 0. */
+/* Time every stride-th work launch of the following runs by the start and
+ * stop events of its own dispatch; 0 turns it off.  While it is on, runs are
+ * enqueued from the host (use_graph is ignored: a graph cannot carry the
+ * dispatch events).  The sums go to erem_batch_stats.work_ms / work_timed.
+ * EINVAL for stride < 0. */
 int erem_batch_profile(erem_batch* b, int32_t stride);
 /* Advance the packed temperatures d_T by nsteps EREM steps; use_graph != 0
  * replays one hipGraph (captured on first use per nsteps, tile shape and T

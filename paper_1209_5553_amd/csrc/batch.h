@@ -8,10 +8,12 @@
 
 namespace erem {
 
-// Tile shapes of the work kernel: 64 x kBatchTileRows[shape] cells, one
-// thread per cell; shape 2 is shape 0 with the XCD-contiguous placement.
-constexpr int kNumTileShapes = 3;
-constexpr int kBatchTileRows[kNumTileShapes] = {8, 16, 8};
+// Tile shapes of the work kernel: 64 x kBatchTileRows[shape] cells on 64 x
+// kBatchThreadRows[shape] threads; shapes 2-4 place the tiles so that each
+// XCD takes a contiguous range of them.
+constexpr int kNumTileShapes = 5;
+constexpr int kBatchTileRows[kNumTileShapes] = {8, 16, 8, 16, 32};
+constexpr int kBatchThreadRows[kNumTileShapes] = {8, 16, 8, 8, 8};
 constexpr int kBatchTileX = 64;
 
 // Static description of one problem of the batch.

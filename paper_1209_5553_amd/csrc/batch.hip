@@ -46,7 +46,7 @@ __device__ inline V cv(double x) { return static_cast<V>(x); }
 template <int TY, class V>
 constexpr size_t work_lds_bytes() {
   return sizeof(V) * (static_cast<size_t>(TY + 8) * (kBatchTileX + 8) +
-                      7 * static_cast<size_t>(TY + 6) * (kBatchTileX + 6));
+                      2 * static_cast<size_t>(TY + 6) * (kBatchTileX + 6));
 }
 
 // Sum (or max) over the workgroup of one double per thread; fixed order
@@ -69,17 +69,18 @@ __device__ inline double block_reduce(double v, double* sh, int tid) {
   return r;
 }
 
-template <int TY, bool XCD, class V>
-__global__ __launch_bounds__(kBatchTileX* TY) void k_bt_work(BatchArgs a) {
-  constexpr int NTH = kBatchTileX * TY;
+template <int TY, int BY, bool XCD, class V>
+__global__ __launch_bounds__(kBatchTileX* BY) void k_bt_work(BatchArgs a) {
+  static_assert(TY % BY == 0, "whole thread rows per tile");
+  constexpr int NTH = kBatchTileX * BY;  // threads
   constexpr int NW = NTH / 64;
+  constexpr int R = TY / BY;             // tile rows per thread in the start and finish passes
   constexpr int NT = 4, H = NT - 1;
   constexpr int WQ = kBatchTileX + 2 * NT, HQ = TY + 2 * NT;  // q_{k-1}: halo 4
   constexpr int WI = kBatchTileX + 2 * H, HI = TY + 2 * H;    // stencil, intermediates: halo 3
   extern __shared__ __align__(16) unsigned char smem[];
-  V(*sq)[WQ] = reinterpret_cast<V(*)[WQ]>(smem);
-  V(*sc)[HI][WI] = reinterpret_cast<V(*)[HI][WI]>(smem + sizeof(V) * HQ * WQ);
-  V(*sb)[HI][WI] = sc + 5;
+  V(*sq)[WQ] = reinterpret_cast<V(*)[WQ]>(smem);                           // q_{k-1}
+  V(*sb)[HI][WI] = reinterpret_cast<V(*)[HI][WI]>(smem + sizeof(V) * HQ * WQ);  // intermediate terms
   __shared__ double red[NT][NW];
 
   const int t = XCD ? xcd_tile_id() : static_cast<int>(blockIdx.x);
@@ -91,22 +92,25 @@ __global__ __launch_bounds__(kBatchTileX* TY) void k_bt_work(BatchArgs a) {
   const long long o = P.off, Nt = a.ntot;
   const int lx = threadIdx.x, ly = threadIdx.y;
   const int tid = lx + kBatchTileX * ly;
-  const int x = tl.x0 + lx, y = tl.y0 + ly;
-  const bool own = x < nx && y < ny;
-  const long long i = o + (own ? x + static_cast<long long>(nx) * y : 0);
+  const int x = tl.x0 + lx;
   double* part = a.part + 4LL * t;
 
   if (S.phase == kPhFinish) {
     // T^N = T^{N-1} + u + delta p (a failed problem keeps its last step's T)
-    if (own) {
-      const double* Tc = S.tpar ? a.T1 : a.T0;
-      double Tn = Tc[i];
-      if (S.flags == 0) {
-        const V* pc = reinterpret_cast<const V*>(S.ppar ? a.p1 : a.p0);
-        const double* uc = S.upar ? a.u1 : a.u0;
-        Tn += (P.s > 1 ? uc[i] : 0.0) + P.delta * static_cast<double>(pc[i]);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int y = tl.y0 + ly + r * BY;
+      if (x < nx && y < ny) {
+        const long long i = o + x + static_cast<long long>(nx) * y;
+        const double* Tc = S.tpar ? a.T1 : a.T0;
+        double Tn = Tc[i];
+        if (S.flags == 0) {
+          const V* pc = reinterpret_cast<const V*>(S.ppar ? a.p1 : a.p0);
+          const double* uc = S.upar ? a.u1 : a.u0;
+          Tn += (P.s > 1 ? uc[i] : 0.0) + P.delta * static_cast<double>(pc[i]);
+        }
+        a.T0[i] = Tn;
       }
-      a.T0[i] = Tn;
     }
     return;
   }
@@ -114,7 +118,11 @@ __global__ __launch_bounds__(kBatchTileX* TY) void k_bt_work(BatchArgs a) {
   if (S.phase == kPhInit) {
     // start of substep S.sub of step S.step
     double s0 = 0.0, mx = 0.0;
-    if (own) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int y = tl.y0 + ly + r * BY;
+      if (!(x < nx && y < ny)) continue;
+      const long long i = o + x + static_cast<long long>(nx) * y;
       const long long jw = x > 0 ? i - 1 : i, je = x + 1 < nx ? i + 1 : i;
       const long long js = y > 0 ? i - nx : i, jn = y + 1 < ny ? i + nx : i;
       const long long jj[5] = {i, jw, je, js, jn};
@@ -150,12 +158,12 @@ __global__ __launch_bounds__(kBatchTileX* TY) void k_bt_work(BatchArgs a) {
         if (S.kind == kInitStep) (S.tpar ? a.T0 : a.T1)[i] = w[0];
         q = jw_ + a.g[i];
         a.v[i] = q;
-        mx = fabs(w[0]);
+        mx = fmax(mx, fabs(w[0]));
       }
       const V qv = cv<V>(q);
       reinterpret_cast<V*>(a.q0)[i] = qv;
       reinterpret_cast<V*>(S.ppar ? a.p0 : a.p1)[i] = cv<V>(a.dk[P.coef_off]) * qv;
-      s0 = static_cast<double>(qv) * static_cast<double>(qv);
+      s0 += static_cast<double>(qv) * static_cast<double>(qv);
     }
     const double S0 = block_reduce<NW, false>(s0, &red[0][0], tid);
     const double M0 = block_reduce<NW, true>(mx, &red[1][0], tid);
@@ -166,17 +174,24 @@ __global__ __launch_bounds__(kBatchTileX* TY) void k_bt_work(BatchArgs a) {
     return;
   }
 
-  // four Newton terms S.k .. S.k + 3 on the tile
+  // four Newton terms S.k .. S.k + 3 on the tile.  Each thread owns up to
+  // UC cells of the tile plus its halo of three (the "box") for all four
+  // terms: it keeps their stencil in registers, computes them in every term
+  // whose region (the box shrinking by one cell per term) holds them, and
+  // accumulates p and the partial sums for those of its cells in the tile.
+  // Only q goes through LDS: q_{k-1} with a halo of four, then the
+  // intermediate terms.
   const int grp = (S.k - 1) >> 2;
   const V* __restrict__ qin = reinterpret_cast<const V*>((grp & 1) ? a.q1 : a.q0);
   V* __restrict__ qout = reinterpret_cast<V*>((grp & 1) ? a.q0 : a.q1);
   V* __restrict__ p = reinterpret_cast<V*>(S.ppar ? a.p1 : a.p0);
   const V* __restrict__ coef = reinterpret_cast<const V*>(a.coef);
   const int x0 = tl.x0, y0 = tl.y0;
+  constexpr int UQ = (HQ * WQ + NTH - 1) / NTH;  // q values staged per thread
+  constexpr int UC = (HI * WI + NTH - 1) / NTH;  // box cells per thread
   // every load of the tile is issued (into registers) before the first LDS
-  // store, so the tile waits for one memory latency instead of one per trip
-  constexpr int UQ = (HQ * WQ + NTH - 1) / NTH, UI = (HI * WI + NTH - 1) / NTH;
-  V rq[UQ], rc[5][UI];
+  // store, so the tile waits for one memory latency
+  V rq[UQ];
 #pragma unroll
   for (int u = 0; u < UQ; ++u) {
     const int e = tid + u * NTH;
@@ -184,76 +199,81 @@ __global__ __launch_bounds__(kBatchTileX* TY) void k_bt_work(BatchArgs a) {
     const int gx = x0 - NT + rx, gy = y0 - NT + ry;
     rq[u] = (e < HQ * WQ && gx >= 0 && gx < nx && gy >= 0 && gy < ny) ? qin[o + gx + nx * gy] : V(0);
   }
+  V rc[5][UC], acc[UC];
+  int by[UC], bx[UC];
+  bool tile_cell[UC];
 #pragma unroll
-  for (int u = 0; u < UI; ++u) {
+  for (int u = 0; u < UC; ++u) {
     const int e = tid + u * NTH;
-    const int ry = e / WI, rx = e - ry * WI;
-    const int gx = x0 - H + rx, gy = y0 - H + ry;
+    by[u] = e / WI;
+    bx[u] = e - by[u] * WI;
+    const int gx = x0 - H + bx[u], gy = y0 - H + by[u];
     const bool in = e < HI * WI && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-    const long long j = o + gx + nx * gy;
+    tile_cell[u] = in && bx[u] >= H && bx[u] < H + kBatchTileX && by[u] >= H && by[u] < H + TY;
+    const long long j = o + (in ? gx + nx * gy : 0);
 #pragma unroll
     for (int d = 0; d < 5; ++d) rc[d][u] = in ? coef[d * Nt + j] : V(0);
+    acc[u] = tile_cell[u] ? p[j] : V(0);
   }
-  V acc = own ? p[i] : V(0);
 #pragma unroll
   for (int u = 0; u < UQ; ++u) {
     const int e = tid + u * NTH;
     if (e < HQ * WQ) sq[e / WQ][e % WQ] = rq[u];
   }
-#pragma unroll
-  for (int u = 0; u < UI; ++u) {
-    const int e = tid + u * NTH;
-    if (e < HI * WI) {
-#pragma unroll
-      for (int d = 0; d < 5; ++d) sc[d][e / WI][e % WI] = rc[d][u];
-    }
-  }
   __syncthreads();
   const V ig = cv<V>(P.inv_g);
   const double* shf = a.shift + P.coef_off + S.k;
   const double* dkp = a.dk + P.coef_off + S.k;
-  double sums[NT];
-  V last = V(0);
+  double sums[NT] = {0.0, 0.0, 0.0, 0.0};
+  V last[UC];
 #pragma unroll
   for (int tt = 0; tt < NT; ++tt) {
-    const int h = H - tt;  // halo of the region computed in this term
     const V sh = cv<V>(shf[tt]);
-    const int w = kBatchTileX + 2 * h, hh = TY + 2 * h;
+    const V dkt = cv<V>(dkp[tt]);
     V(*out)[WI] = sb[tt & 1];
-    for (int e = tid; e < w * hh; e += NTH) {
-      const int ry = e / w, rx = e - ry * w;
-      const int iy = ry + tt, ix = rx + tt;  // position in the halo-H buffers
-      V qc, qw, qe, qs, qn;
-      if (tt == 0) {
-        qc = sq[iy + 1][ix + 1];
-        qw = sq[iy + 1][ix];
-        qe = sq[iy + 1][ix + 2];
-        qs = sq[iy][ix + 1];
-        qn = sq[iy + 2][ix + 1];
-      } else {
-        const V(*prev)[WI] = sb[(tt - 1) & 1];
-        qc = prev[iy][ix];
-        qw = prev[iy][ix - 1];
-        qe = prev[iy][ix + 1];
-        qs = prev[iy - 1][ix];
-        qn = prev[iy + 1][ix];
+    const V(*prev)[WI] = sb[(tt - 1) & 1];
+#pragma unroll
+    for (int u = 0; u < UC; ++u) {
+      const int iy = by[u], ix = bx[u];
+      // the region of term tt: the box less tt cells on every side
+      if (tid + u * NTH < HI * WI && iy >= tt && iy < HI - tt && ix >= tt && ix < WI - tt) {
+        V qc, qw, qe, qs, qn;
+        if (tt == 0) {
+          qc = sq[iy + 1][ix + 1];
+          qw = sq[iy + 1][ix];
+          qe = sq[iy + 1][ix + 2];
+          qs = sq[iy][ix + 1];
+          qn = sq[iy + 2][ix + 1];
+        } else {
+          qc = prev[iy][ix];
+          qw = prev[iy][ix - 1];
+          qe = prev[iy][ix + 1];
+          qs = prev[iy - 1][ix];
+          qn = prev[iy + 1][ix];
+        }
+        V jq = rc[0][u] * qc;
+        jq += rc[1][u] * qw;
+        jq += rc[2][u] * qe;
+        jq += rc[3][u] * qs;
+        jq += rc[4][u] * qn;
+        const V qo = jq * ig - sh * qc;  // zero outside the grid (stencil and q are)
+        if (tt + 1 < NT) out[iy][ix] = qo;
+        if (tile_cell[u]) {
+          acc[u] += dkt * qo;
+          sums[tt] += static_cast<double>(qo) * static_cast<double>(qo);
+          last[u] = qo;
+        }
       }
-      V jq = sc[0][iy][ix] * qc;
-      jq += sc[1][iy][ix] * qw;
-      jq += sc[2][iy][ix] * qe;
-      jq += sc[3][iy][ix] * qs;
-      jq += sc[4][iy][ix] * qn;
-      out[iy][ix] = jq * ig - sh * qc;  // zero outside the grid (stencil and q are)
     }
-    __syncthreads();
-    const V qo = out[ly + H][lx + H];
-    acc += cv<V>(dkp[tt]) * qo;
-    sums[tt] = own ? static_cast<double>(qo) * static_cast<double>(qo) : 0.0;
-    last = qo;
+    if (tt + 1 < NT) __syncthreads();
   }
-  if (own) {
-    p[i] = acc;
-    qout[i] = last;
+#pragma unroll
+  for (int u = 0; u < UC; ++u) {
+    if (tile_cell[u]) {
+      const long long j = o + (x0 - H + bx[u]) + static_cast<long long>(nx) * (y0 - H + by[u]);
+      p[j] = acc[u];
+      qout[j] = last[u];
+    }
   }
 #pragma unroll
   for (int tt = 0; tt < NT; ++tt) {
@@ -277,7 +297,10 @@ __global__ __launch_bounds__(kCtrlThreads) void k_bt_ctrl(BatchArgs a) {
   const int lane = threadIdx.x & 63;
   const int pid = blockIdx.x * (kCtrlThreads / 64) + (threadIdx.x >> 6);
   if (pid >= a.nprob) return;
+  // the state and the problem record are loaded together, then the partials
+  // with the stop test's coefficients: two memory round trips
   BState S = a.state[pid];
+  const BProb P = a.prob[pid];
   if (S.phase == kPhDone) return;
   if (S.phase == kPhFinish) {
     if (lane == 0) {
@@ -288,8 +311,11 @@ __global__ __launch_bounds__(kCtrlThreads) void k_bt_ctrl(BatchArgs a) {
     }
     return;
   }
-  const BProb P = a.prob[pid];
   const bool init = S.phase == kPhInit;
+  const double* dk = a.dk + P.coef_off;
+  double dkv[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) dkv[j] = init ? dk[0] : dk[S.k + j];
   const double* pp = a.part + 4LL * P.tile0;
   double s[4] = {0.0, 0.0, 0.0, 0.0};
   double mx = 0.0;
@@ -309,7 +335,6 @@ __global__ __launch_bounds__(kCtrlThreads) void k_bt_ctrl(BatchArgs a) {
   }
   if (lane != 0) return;
   ++S.phases;
-  const double* dk = a.dk + P.coef_off;
   bool stop = false;  // no further Newton work for this problem
   if (init) {
     if (S.kind != kInitSub) S.scal = a.tol_a + a.tol_r * mx;
@@ -323,7 +348,7 @@ __global__ __launch_bounds__(kCtrlThreads) void k_bt_ctrl(BatchArgs a) {
       S.flags |= 4;
       stop = true;
     } else {
-      S.ring[0] = fabs(P.delta * dk[0]) * sqrt(s[0]) / (P.rootN * S.scal);
+      S.ring[0] = fabs(P.delta * dkv[0]) * sqrt(s[0]) / (P.rootN * S.scal);
       S.k = 1;
       S.phase = kPhTerms;
     }
@@ -335,7 +360,7 @@ __global__ __launch_bounds__(kCtrlThreads) void k_bt_ctrl(BatchArgs a) {
         bad = true;
         break;
       }
-      S.ring[kk % 5] = fabs(P.delta * dk[kk]) * sqrt(s[j]) / (P.rootN * S.scal);
+      S.ring[kk % 5] = fabs(P.delta * dkv[j]) * sqrt(s[j]) / (P.rootN * S.scal);
       if (kk >= 4) {
         const double mean = 0.2 * (S.ring[0] + S.ring[1] + S.ring[2] + S.ring[3] + S.ring[4]);
         done = mean < a.thresh;
@@ -403,27 +428,40 @@ __global__ __launch_bounds__(256) void k_batch_pack(int nx, int ny, const double
   }
 }
 
-template <int TY, bool XCD, class V>
+template <int TY, int BY, bool XCD, class V>
 hipError_t launch_work(const BatchArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   const size_t bytes = work_lds_bytes<TY, V>();
   if (bytes > 65536) {
     static bool granted = false;
     if (!granted) {
-      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bt_work<TY, XCD, V>),
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bt_work<TY, BY, XCD, V>),
                                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
       if (e != hipSuccess) return e;
       granted = true;
     }
   }
-  launch_timed(k_bt_work<TY, XCD, V>, dim3(a.ntiles), dim3(kBatchTileX, TY), static_cast<unsigned>(bytes), s, e0, e1,
-               a);
+  launch_timed(k_bt_work<TY, BY, XCD, V>, dim3(a.ntiles), dim3(kBatchTileX, BY), static_cast<unsigned>(bytes), s, e0,
+               e1, a);
   return hipGetLastError();
+}
+
+template <class V>
+hipError_t launch_work_shape(const BatchArgs& a, int shape, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  switch (shape) {
+    case 0: return launch_work<8, 8, false, V>(a, s, e0, e1);
+    case 1: return launch_work<16, 16, false, V>(a, s, e0, e1);
+    case 2: return launch_work<8, 8, true, V>(a, s, e0, e1);
+    case 3: return launch_work<16, 8, true, V>(a, s, e0, e1);
+    case 4: return launch_work<32, 8, true, V>(a, s, e0, e1);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace
 
 size_t batch_lds_bytes(int shape, int fp32) {
   const int rows = kBatchTileRows[shape];
+  if (rows == 32) return fp32 ? work_lds_bytes<32, float>() : work_lds_bytes<32, double>();
   if (rows == 16) return fp32 ? work_lds_bytes<16, float>() : work_lds_bytes<16, double>();
   return fp32 ? work_lds_bytes<8, float>() : work_lds_bytes<8, double>();
 }
@@ -443,16 +481,7 @@ hipError_t batch_reset(const BatchArgs& a, hipStream_t s) {
 }
 
 hipError_t batch_phase(const BatchArgs& a, int shape, int fp32, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  hipError_t e;
-  switch (shape * 2 + fp32) {
-    case 0: e = launch_work<8, false, double>(a, s, e0, e1); break;
-    case 1: e = launch_work<8, false, float>(a, s, e0, e1); break;
-    case 2: e = launch_work<16, false, double>(a, s, e0, e1); break;
-    case 3: e = launch_work<16, false, float>(a, s, e0, e1); break;
-    case 4: e = launch_work<8, true, double>(a, s, e0, e1); break;
-    case 5: e = launch_work<8, true, float>(a, s, e0, e1); break;
-    default: return hipErrorInvalidValue;
-  }
+  const hipError_t e = fp32 ? launch_work_shape<float>(a, shape, s, e0, e1) : launch_work_shape<double>(a, shape, s, e0, e1);
   if (e != hipSuccess) return e;
   const int per = kCtrlThreads / 64;
   hipLaunchKernelGGL(k_bt_ctrl, dim3((a.nprob + per - 1) / per), dim3(kCtrlThreads), 0, s, a);

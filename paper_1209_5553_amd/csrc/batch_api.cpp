@@ -52,7 +52,6 @@ struct erem_batch {
   struct Graph {
     hipGraphExec_t exec = nullptr;
     int phases = 0;                   // work passes captured
-    std::vector<hipEvent_t> ev;       // start / stop pairs of the timed passes
   };
   std::map<std::pair<int, int>, Graph> graphs;  // (nsteps, shape) -> graph
   const double* graph_T = nullptr;              // T array the graphs were captured with
@@ -88,10 +87,8 @@ int balloc(erem_batch* b, T** p, size_t n) {
 }
 
 void drop_graphs(erem_batch* b) {
-  for (auto& kv : b->graphs) {
+  for (auto& kv : b->graphs)
     if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
-    for (hipEvent_t e : kv.second.ev) (void)hipEventDestroy(e);
-  }
   b->graphs.clear();
 }
 
@@ -194,64 +191,74 @@ long long max_phases(erem_batch* b, int nsteps) {
 
 // Phases enqueued eagerly in chunks, the host reading the count of finished
 // problems after each chunk, until every problem is done.  Returns the work
-// passes enqueued.  With prof_stride > 0 every prof_stride-th pass is timed
-// into *work_ms / *timed.
+// passes enqueued.  With prof_stride > 0 every prof_stride-th work launch
+// records its own start and stop (events of the dispatch itself), read when
+// its chunk has finished, into *work_ms / *timed.
 int run_eager(erem_batch* b, const BatchArgs& a, long long start, long long* passes, double* work_ms, int* timed) {
   constexpr int kChunk = 64;
   const long long limit = max_phases(b, a.nsteps);
   long long n = start;
-  hipEvent_t e0 = nullptr, e1 = nullptr;
+  std::vector<hipEvent_t> ev;
+  auto drop = [&]() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    ev.clear();
+  };
   if (b->prof_stride > 0) {
-    BHIP(b, hipEventCreate(&e0));
-    BHIP(b, hipEventCreate(&e1));
+    ev.resize(2 * kChunk, nullptr);
+    for (hipEvent_t& e : ev)
+      if (hipEventCreate(&e) != hipSuccess) {
+        e = nullptr;
+        drop();
+        return bfail(b, EREM_EDEVICE, "hipEventCreate failed");
+      }
   }
+  std::vector<char> was_timed(kChunk, 0);
   while (true) {
     BHIP(b, hipMemcpyAsync(b->h_ndone, b->ndone, sizeof(int), hipMemcpyDeviceToHost, b->stream));
-    BHIP(b, hipStreamSynchronize(b->stream));
+    const hipError_t se = hipStreamSynchronize(b->stream);
+    if (se != hipSuccess) {
+      drop();
+      return bfail(b, EREM_EDEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(se));
+    }
+    for (int c = 0; c < kChunk; ++c) {
+      if (!was_timed[c]) continue;
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, ev[2 * c], ev[2 * c + 1]) == hipSuccess) {
+        *work_ms += ms;
+        ++*timed;
+      } else {
+        (void)hipGetLastError();  // leave no error behind for the caller's next check
+      }
+      was_timed[c] = 0;
+    }
     if (*b->h_ndone >= b->nprob) break;
     if (n >= limit) {
-      if (e0) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); }
+      drop();
       return bfail(b, EREM_EDEVICE, "batch run did not finish within its phase bound");
     }
     for (int c = 0; c < kChunk && n < limit; ++c, ++n) {
-      const bool time_it = e0 && n % b->prof_stride == 0;
-      BHIP(b, batch_phase(a, b->shape, b->fp32, b->stream, time_it ? e0 : nullptr, time_it ? e1 : nullptr));
-      if (time_it) {
-        BHIP(b, hipEventSynchronize(e1));
-        float ms = 0.0f;
-        BHIP(b, hipEventElapsedTime(&ms, e0, e1));
-        *work_ms += ms;
-        ++*timed;
+      const bool time_it = !ev.empty() && n % b->prof_stride == 0;
+      const hipError_t le = batch_phase(a, b->shape, b->fp32, b->stream, time_it ? ev[2 * c] : nullptr,
+                                        time_it ? ev[2 * c + 1] : nullptr);
+      if (le != hipSuccess) {
+        drop();
+        return bfail(b, EREM_EDEVICE, std::string("batch phase launch: ") + hipGetErrorString(le));
       }
+      was_timed[c] = time_it ? 1 : 0;
     }
   }
-  if (e0) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); }
+  drop();
   *passes = n;
   return EREM_OK;
 }
 
-// Capture reset + `phases` work passes (every prof_stride-th between event
-// records) into a graph.
+// Capture reset + `phases` work passes into a graph.
 int capture(erem_batch* b, const BatchArgs& a, int phases, erem_batch::Graph* g) {
   g->phases = phases;
-  if (b->prof_stride > 0) {
-    for (int n = 0; n < phases; n += b->prof_stride) {
-      hipEvent_t e0, e1;
-      BHIP(b, hipEventCreate(&e0));
-      BHIP(b, hipEventCreate(&e1));
-      g->ev.push_back(e0);
-      g->ev.push_back(e1);
-    }
-  }
   hipGraph_t graph;
   BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
   hipError_t le = batch_reset(a, b->stream);
-  for (int n = 0; n < phases && le == hipSuccess; ++n) {
-    const bool time_it = b->prof_stride > 0 && n % b->prof_stride == 0;
-    if (time_it) le = hipEventRecord(g->ev[2 * (n / b->prof_stride)], b->stream);
-    if (le == hipSuccess) le = batch_phase(a, b->shape, b->fp32, b->stream);
-    if (time_it && le == hipSuccess) le = hipEventRecord(g->ev[2 * (n / b->prof_stride) + 1], b->stream);
-  }
+  for (int n = 0; n < phases && le == hipSuccess; ++n) le = batch_phase(a, b->shape, b->fp32, b->stream);
   const hipError_t ce = hipStreamEndCapture(b->stream, &graph);
   if (le != hipSuccess || ce != hipSuccess) {
     (void)hipGetLastError();
@@ -268,6 +275,8 @@ int launch(erem_batch* b, double* T, int nsteps, bool use_graph, erem_batch_stat
   const BatchArgs a = make_args(b, T, nsteps);
   const auto key = std::make_pair(nsteps, b->shape);
   erem_batch::Graph* g = nullptr;
+  // timed work launches need their own dispatch events: such runs go eagerly
+  if (b->prof_stride > 0) use_graph = false;
   if (use_graph) {
     auto it = b->graphs.find(key);
     if (it == b->graphs.end()) {
@@ -294,21 +303,9 @@ int launch(erem_batch* b, double* T, int nsteps, bool use_graph, erem_batch_stat
       }
       const int budget = ci->second + std::max(8, ci->second / 32);
       erem_batch::Graph ng;
-      int rc = capture(b, a, budget, &ng);
-      if (rc && b->prof_stride > 0) {
-        // event records that a capture does not take: capture without them
-        // (the runs then report no work-launch timing)
-        if (ng.exec) (void)hipGraphExecDestroy(ng.exec);
-        for (hipEvent_t e : ng.ev) (void)hipEventDestroy(e);
-        ng = erem_batch::Graph{};
-        const int saved = b->prof_stride;
-        b->prof_stride = 0;
-        rc = capture(b, a, budget, &ng);
-        b->prof_stride = saved;
-      }
+      const int rc = capture(b, a, budget, &ng);
       if (rc) {
         if (ng.exec) (void)hipGraphExecDestroy(ng.exec);
-        for (hipEvent_t e : ng.ev) (void)hipEventDestroy(e);
         return rc;
       }
       it = b->graphs.emplace(key, std::move(ng)).first;
@@ -339,18 +336,9 @@ int launch(erem_batch* b, double* T, int nsteps, bool use_graph, erem_batch_stat
     return rc;
   }
   float ms = 0.0f;
-  (void)hipEventElapsedTime(&ms, e0, e1);
+  BHIP(b, hipEventElapsedTime(&ms, e0, e1));
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
-  if (g) {
-    for (size_t j = 0; j + 1 < g->ev.size(); j += 2) {
-      float w = 0.0f;
-      if (hipEventElapsedTime(&w, g->ev[j], g->ev[j + 1]) == hipSuccess) {
-        work_ms += w;
-        ++timed;
-      }
-    }
-  }
   std::vector<BState> S(b->nprob);
   BHIP(b, hipMemcpy(S.data(), b->state, sizeof(BState) * b->nprob, hipMemcpyDeviceToHost));
   long long tot = 0;

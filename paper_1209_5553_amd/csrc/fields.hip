@@ -6,7 +6,7 @@
 // 64-lane wavefront per grid row segment, so loads along x are fully
 // coalesced; +-y / +-z neighbours come from the same block's other rows or
 // from L2.  Reductions: wavefront shuffles, then the four wavefront partials
-// through LDS, then one device-scope atomic add per block into one of eight
+// through LDS, then one device-scope atomic add per block into one of kSlots
 // slots (spreading contention); the consumer of a sum is always a later
 // kernel, so kernel boundaries order every producer/consumer pair.
 #include "device.h"

@@ -5,14 +5,18 @@
 // again a two-point-flux matrix whose face transmissibility is the sum of the
 // fine transmissibilities crossing the coarse face (Dirichlet faces included),
 // so every level keeps the same face-array layout as the fine grid.
-// Smoother: damped Jacobi (omega 0.8), the same sweeps before and after the
-// coarse correction; the coarse correction is over-relaxed by omega_c; the
-// bottom level (at most kMgBottomCells cells) is solved exactly with a dense
-// inverse formed once per setup.  The cycle is symmetric, so it is a valid
-// conjugate-gradient preconditioner.  Each fine level runs two kernels: the
-// down leg (two sweeps from zero + restricted residual) and the up leg
-// (coarse correction + two sweeps), each recomputing its neighbours'
-// intermediate sweep instead of waiting for a grid-wide pass; the levels with
+// Smoother: on the 2D grid levels three Jacobi-type sweeps weighted by the
+// reciprocals of the Chebyshev points of [2/3, 2] (the degree-3 Chebyshev
+// polynomial in D^-1 A, whose spectrum these diagonally dominant M-matrices
+// keep inside (0, 2]); on the 3D grid levels and the LDS-resident levels two
+// damped-Jacobi sweeps (omega 0.8); the same sweeps before and after the
+// coarse correction, which is over-relaxed by omega_c.  The bottom level (at
+// most kMgBottomCells cells) is solved exactly with a dense inverse formed
+// once per setup.  The cycle is symmetric, so it is a valid
+// conjugate-gradient preconditioner.  Each grid level runs two kernels: the
+// down leg (sweeps from zero + restricted residual) and the up leg (coarse
+// correction + sweeps), each recomputing its neighbours' intermediate sweeps
+// on shrinking halos instead of waiting for a grid-wide pass; the levels with
 // at most kMgLdsCells cells run inside one workgroup with everything in LDS.
 #include "device.h"
 #include "mg.h"
@@ -23,17 +27,13 @@ namespace {
 
 constexpr double kOmega = 0.8;
 
-// Weights of the sweeps on the 2D grid levels: with EREM_MG_CHEB the
-// reciprocals of the Chebyshev points of [lmax / 3, lmax] for lmax = 2 (the
-// Gershgorin bound of D^-1 A for these operators), i.e. the smoother is the
-// degree-kMgSweeps Chebyshev polynomial in D^-1 A; otherwise damped Jacobi.
-// Any order gives the same polynomial, so the cycle stays symmetric.
-#ifndef EREM_MG_CHEB
-#define EREM_MG_CHEB 1
-#endif
+// Weights of the sweeps on the 2D grid levels: the reciprocals of the
+// Chebyshev points of [lmax / 3, lmax] for lmax = 2 (the Gershgorin bound of
+// D^-1 A for these operators), so the smoother is the degree-NU Chebyshev
+// polynomial in D^-1 A.  Any order gives the same polynomial, so the cycle
+// stays symmetric.
 template <int NU>
 __device__ inline double sweep_weight(int k) {
-  if (!EREM_MG_CHEB) return kOmega;
   const double lmax = 2.0, lmin = lmax / 3.0;
   const double z = 0.5 * (lmax + lmin) + 0.5 * (lmax - lmin) * cos(M_PI * (2 * k + 1) / (2.0 * NU));
   return 1.0 / z;
@@ -45,19 +45,6 @@ __device__ inline int fzi(int nx, int ny, int x, int y, int z) { return (z * ny 
 
 __device__ inline bool pcg_done(const PcgState* st) { return st && *(volatile const int*)&st->done; }
 
-// sum over interior faces of t * v_nb  (so that (A v)_i = diag_i v_i - offdiag_sum)
-__device__ inline double offdiag_sum(int nx, int ny, int nz, const double* __restrict__ tx,
-                                     const double* __restrict__ ty, const double* __restrict__ tz,
-                                     const double* __restrict__ v, int x, int y, int z, int i) {
-  double s = 0.0;
-  if (x > 0) s += tx[fxi(nx, ny, x, y, z)] * v[i - 1];
-  if (x + 1 < nx) s += tx[fxi(nx, ny, x + 1, y, z)] * v[i + 1];
-  if (y > 0) s += ty[fyi(nx, ny, x, y, z)] * v[i - nx];
-  if (y + 1 < ny) s += ty[fyi(nx, ny, x, y + 1, z)] * v[i + nx];
-  if (z > 0) s += tz[fzi(nx, ny, x, y, z)] * v[i - nx * ny];
-  if (z + 1 < nz) s += tz[fzi(nx, ny, x, y, z + 1)] * v[i + nx * ny];
-  return s;
-}
 
 // ---------------------------------------------------------------------------
 // Setup: coarse faces and diagonal from the fine faces.

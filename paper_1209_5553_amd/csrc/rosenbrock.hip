@@ -112,10 +112,12 @@ __global__ __launch_bounds__(kThreads) void k_bicg_pv(Dims d, double sigma, cons
   const int i = in ? x + d.nx * (y + d.ny * z) : 0;
   const Nbrs<NB> nb(d, x, y, z, i);
   // operands first, so that their loads overlap the scalar decision below
-  double rc = 0.0, pc = 0.0, vc = 0.0, c0 = 0.0, rh = 0.0;
+  // (the diagonal of J is needed only at the neighbours: the preconditioned
+  // operator's own-cell term is p itself)
+  double rc = 0.0, pc = 0.0, vc = 0.0, rh = 0.0;
   double rn[NB], pn[NB], vn[NB], cn0[NB], ck[NB];
   if (in) {
-    rc = r[i]; pc = pold[i]; vc = vold[i]; c0 = coef[i]; rh = rhat[i];
+    rc = r[i]; pc = pold[i]; vc = vold[i]; rh = rhat[i];
 #pragma unroll
     for (int k = 0; k < NB; ++k) {
       const int j = nb.idx[k];
