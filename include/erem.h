@@ -422,6 +422,32 @@ int erem_batch_profile(erem_batch* b, int32_t stride);
  * a failed problem's cells hold the T of its last completed step. */
 int erem_batch_run(erem_batch* b, double* d_T, int32_t nsteps, int32_t use_graph, erem_batch_stats* st);
 
+/* ---- allocation-free evaluation ----
+ *
+ * For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): out = phi1(h J) v, the operation of
+ * erem_set_jacobian(J) followed by erem_phi1_apply, without a context.
+ * d_coef is J as a 5-point (2D) or 7-point (3D) stencil in the context's
+ * layout (ndir x N, SoA: centre, -x, +x, -y, +y, -z, +z; 0 toward missing
+ * neighbours), d_v and d_out N values; all device pointers owned by the
+ * caller, d_out distinct from d_v.  FP64, Leja method only; opts as for
+ * erem_phi1_apply (the term budget starts at opts->chunk if > 0, else m_max).
+ * Every device buffer of the evaluation lives in one statically sized array
+ * of the library (13.1 MB per GPU, held until the process ends); the first
+ * call on a device looks up that device's copy and, once per process,
+ * computes the Leja points; after that set-up a call allocates nothing,
+ * host or device.
+ * Limits: N <= 262144 cells, at most 16384 blocks of 64 x 4 cells
+ * (ceil(nx/64) ceil(ny/4) nz), m_max <= 256, at most 64 substeps; beyond
+ * them EREM_EINVAL.  The call enqueues on `stream` and synchronises it.
+ * Every call on a GPU shares that GPU's array: calls that overlap on one GPU
+ * (from several threads or streams) race and must be serialised by the
+ * caller.  Returns EREM_OK, EREM_EINVAL (bad arguments or limits),
+ * EREM_ENOCONV, EREM_ENONFINITE (non-finite J or v), EREM_EDEVICE; d_out is
+ * written only on EREM_OK.  stats (may be NULL) as for erem_phi1_apply. */
+int erem_phi1_apply_noalloc(const erem_grid* grid, const double* d_coef, double h, const double* d_v,
+                            double* d_out, const erem_opts* opts, void* stream, erem_stats* stats);
+
 /* ---- measurement support ---- */
 
 /* Accumulated device time of the hot kernels while profiling is on,

@@ -124,6 +124,7 @@ SIGNATURES = {
     "erem_batch_run": (c_int32, [_P, _P, c_int32, c_int32, POINTER(BatchStats)]),
     "erem_batch_set_tile_shape": (c_int32, [_P, c_int32]),
     "erem_batch_profile": (c_int32, [_P, c_int32]),
+    "erem_phi1_apply_noalloc": (c_int32, [POINTER(Grid), _P, c_double, _P, _P, POINTER(Opts), _P, POINTER(Stats)]),
     "erem_profile": (c_int32, [_P, c_int32]),
     "erem_profile_read": (c_int32, [_P, POINTER(KernelTimes)]),
     "erem_leja_points": (c_int32, [c_int32, _PD]),

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liberem.so")
 
-SOURCES = ["fields.hip", "leja.hip", "krylov.hip", "mg.hip", "batch.hip", "adjoint.hip", "rosenbrock.hip",
+SOURCES = ["fields.hip", "leja.hip", "krylov.hip", "mg.hip", "batch.hip", "adjoint.hip", "rosenbrock.hip", "noalloc.hip",
            "erem_api.cpp", "batch_api.cpp", "adjoint_api.cpp", "ros_api.cpp", "host_numerics.cpp"]
 
 HIPCC_FLAGS = [

@@ -95,7 +95,12 @@ bool leja_points(int n, std::vector<double>& out) {
   return true;
 }
 
-void phi_divided_differences(int ell, double hc, double hg, const double* xi, int n, double* out) {
+size_t divided_differences_work(int ell, int n) {
+  const size_t M = static_cast<size_t>(n) + ell;
+  return 2 * M + 2 * M * M;
+}
+
+void phi_divided_differences_ws(int ell, double hc, double hg, const double* xi, int n, double* out, double* work) {
   // Augmented lower-bidiagonal matrix of order M = n + ell:
   //   diag = (0 (ell times), hc + hg xi_0, ..., hc + hg xi_{n-1}),
   //   subdiag = (1 (ell times), hg, ..., hg).
@@ -106,7 +111,9 @@ void phi_divided_differences(int ell, double hc, double hg, const double* xi, in
   // definition of phi_ell.  phi_ell(L) e_1 holds the divided differences of
   // phi_ell(hc + hg xi).
   const int M = n + ell;
-  std::vector<double> dg(M, 0.0), sd(M, 0.0);
+  double* dg = work;
+  double* sd = work + M;
+  for (int k = 0; k < M; ++k) dg[k] = sd[k] = 0.0;
   for (int k = 0; k < n; ++k) dg[k + ell] = hc + hg * xi[k];
   for (int k = 1; k <= ell && k < M; ++k) sd[k] = 1.0;  // A[k][k-1]
   for (int k = ell + 1; k < M; ++k) sd[k] = hg;
@@ -123,13 +130,16 @@ void phi_divided_differences(int ell, double hc, double hg, const double* xi, in
   // Taylor series of degree 20 by Horner's rule, E <- I + X E / k, where X is
   // bidiagonal so X E costs O(M^2).
   const int degree = 20;
-  std::vector<double> E(static_cast<size_t>(M) * M, 0.0), T(E.size(), 0.0);
+  const size_t MM = static_cast<size_t>(M) * M;
+  double* E = work + 2 * M;
+  double* T = E + MM;
+  for (size_t i = 0; i < MM; ++i) E[i] = T[i] = 0.0;
   for (int i = 0; i < M; ++i) E[i * M + i] = 1.0;
   for (int k = degree; k >= 1; --k) {
     const double inv = 1.0 / k;
     for (int i = 0; i < M; ++i) {
-      double* t = T.data() + static_cast<size_t>(i) * M;
-      const double* e = E.data() + static_cast<size_t>(i) * M;
+      double* t = T + static_cast<size_t>(i) * M;
+      const double* e = E + static_cast<size_t>(i) * M;
       const double di = dg[i];
       if (i == 0) {
         t[0] = di * e[0] * inv;
@@ -152,11 +162,16 @@ void phi_divided_differences(int ell, double hc, double hg, const double* xi, in
       }
       for (int i = 0; i < M; ++i) E[i * M + 0] = T[i * M + 0];
     } else {
-      tri_mul(M, E.data(), E.data(), T.data());
+      tri_mul(M, E, E, T);
       std::swap(E, T);
     }
   }
   for (int k = 0; k < n; ++k) out[k] = E[(k + ell) * M + 0];
+}
+
+void phi_divided_differences(int ell, double hc, double hg, const double* xi, int n, double* out) {
+  std::vector<double> work(divided_differences_work(ell, n));
+  phi_divided_differences_ws(ell, hc, hg, xi, n, out, work.data());
 }
 
 void phi1_divided_differences(double hc, double hg, const double* xi, int n, double* out) {

@@ -1,6 +1,7 @@
 // Host-side small dense numerics of the EREM library (no device code).
 #pragma once
 
+#include <cstddef>
 #include <cstdint>
 #include <vector>
 
@@ -20,6 +21,10 @@ void phi1_divided_differences(double hc, double hg, const double* xi, int n, dou
 // non-autonomous step, Sec. 3.2.3): first column of phi_ell(hc I + hg L),
 // read off the exponential of the bidiagonal matrix augmented by ell rows.
 void phi_divided_differences(int ell, double hc, double hg, const double* xi, int n, double* out);
+// The same on a caller's workspace of divided_differences_work(ell, n)
+// doubles (no allocation).
+size_t divided_differences_work(int ell, int n);
+void phi_divided_differences_ws(int ell, double hc, double hg, const double* xi, int n, double* out, double* work);
 
 // phi2(z) = (e^z - 1 - z) / z^2 (Sec. 3.2.3), by its series for |z| < 1.
 double phi2_scalar(double z);
