@@ -9,12 +9,15 @@
 namespace erem {
 
 // Tile shapes of the work kernel: 64 x kBatchTileRows[shape] cells on 64 x
-// kBatchThreadRows[shape] threads; shapes 2-4 place the tiles so that each
-// XCD takes a contiguous range of them.
-constexpr int kNumTileShapes = 5;
-constexpr int kBatchTileRows[kNumTileShapes] = {8, 16, 8, 16, 32};
-constexpr int kBatchThreadRows[kNumTileShapes] = {8, 16, 8, 8, 8};
+// kBatchThreadRows[shape] threads, kBatchPassTerms[shape] Newton terms per
+// pass; shapes 2-6 place the tiles so that each XCD takes a contiguous range
+// of them.
+constexpr int kNumTileShapes = 7;
+constexpr int kBatchTileRows[kNumTileShapes] = {8, 16, 8, 16, 32, 16, 8};
+constexpr int kBatchThreadRows[kNumTileShapes] = {8, 16, 8, 8, 8, 8, 8};
+constexpr int kBatchPassTerms[kNumTileShapes] = {4, 4, 4, 4, 4, 8, 8};
 constexpr int kBatchTileX = 64;
+constexpr int kBatchPartStride = 8;  // partials per tile (one per term of a pass)
 
 // Static description of one problem of the batch.
 struct BProb {
@@ -40,7 +43,7 @@ struct BTile {
 // done by one phase, and the control kernel that follows picks the next.
 enum BPhase : int {
   kPhInit = 0,    // start of a substep: q_0, p = d_0 q_0 (and the end of the previous substep or step)
-  kPhTerms = 1,   // four Newton terms k .. k + 3
+  kPhTerms = 1,   // Newton terms k .. k + nt - 1
   kPhFinish = 2,  // the last step's T update
   kPhDone = 3,
 };
@@ -57,7 +60,7 @@ struct BState {
   int phase, kind;
   int step;   // steps completed
   int sub;    // current substep
-  int k;      // first term of the next group of four
+  int k;      // first term of the next pass
   int terms;  // Newton terms applied
   int flags;  // 1: no convergence within m_max, 2: non-finite norm
   int tpar;   // buffer holding T^n: 0 the caller's array, 1 the internal copy
@@ -85,9 +88,10 @@ struct BatchArgs {
   void *p0, *p1;         // Newton sums (ping-pong over substeps)
   const double* dk;      // divided differences, (m_max + 1) per problem
   const double* shift;   // c/gamma + xi_{k-1}, (m_max + 1) per problem
-  double* part;          // four partials per tile
+  double* part;          // kBatchPartStride partials per tile
   long long ntot;
   int nprob, ntiles, nsteps, m_max;
+  int nt;                // Newton terms per pass of the tile shape
   double tol_a, tol_r, thresh;
 };
 

@@ -43,10 +43,10 @@ namespace {
 template <class V>
 __device__ inline V cv(double x) { return static_cast<V>(x); }
 
-template <int TY, class V>
+template <int TY, int NT, class V>
 constexpr size_t work_lds_bytes() {
-  return sizeof(V) * (static_cast<size_t>(TY + 8) * (kBatchTileX + 8) +
-                      2 * static_cast<size_t>(TY + 6) * (kBatchTileX + 6));
+  return sizeof(V) * (static_cast<size_t>(TY + 2 * NT) * (kBatchTileX + 2 * NT) +
+                      2 * static_cast<size_t>(TY + 2 * NT - 2) * (kBatchTileX + 2 * NT - 2));
 }
 
 // Sum (or max) over the workgroup of one double per thread; fixed order
@@ -69,15 +69,16 @@ __device__ inline double block_reduce(double v, double* sh, int tid) {
   return r;
 }
 
-template <int TY, int BY, bool XCD, class V>
+template <int TY, int BY, int NT, bool XCD, class V>
 __global__ __launch_bounds__(kBatchTileX* BY) void k_bt_work(BatchArgs a) {
   static_assert(TY % BY == 0, "whole thread rows per tile");
+  static_assert(NT >= 2 && NT <= kBatchPartStride, "terms per pass");
   constexpr int NTH = kBatchTileX * BY;  // threads
   constexpr int NW = NTH / 64;
   constexpr int R = TY / BY;             // tile rows per thread in the start and finish passes
-  constexpr int NT = 4, H = NT - 1;
-  constexpr int WQ = kBatchTileX + 2 * NT, HQ = TY + 2 * NT;  // q_{k-1}: halo 4
-  constexpr int WI = kBatchTileX + 2 * H, HI = TY + 2 * H;    // stencil, intermediates: halo 3
+  constexpr int H = NT - 1;
+  constexpr int WQ = kBatchTileX + 2 * NT, HQ = TY + 2 * NT;  // q_{k-1}: halo NT
+  constexpr int WI = kBatchTileX + 2 * H, HI = TY + 2 * H;    // stencil, intermediates: halo NT - 1
   extern __shared__ __align__(16) unsigned char smem[];
   V(*sq)[WQ] = reinterpret_cast<V(*)[WQ]>(smem);                           // q_{k-1}
   V(*sb)[HI][WI] = reinterpret_cast<V(*)[HI][WI]>(smem + sizeof(V) * HQ * WQ);  // intermediate terms
@@ -93,7 +94,7 @@ __global__ __launch_bounds__(kBatchTileX* BY) void k_bt_work(BatchArgs a) {
   const int lx = threadIdx.x, ly = threadIdx.y;
   const int tid = lx + kBatchTileX * ly;
   const int x = tl.x0 + lx;
-  double* part = a.part + 4LL * t;
+  double* part = a.part + static_cast<long long>(kBatchPartStride) * t;
 
   if (S.phase == kPhFinish) {
     // T^N = T^{N-1} + u + delta p (a failed problem keeps its last step's T)
@@ -174,14 +175,14 @@ __global__ __launch_bounds__(kBatchTileX* BY) void k_bt_work(BatchArgs a) {
     return;
   }
 
-  // four Newton terms S.k .. S.k + 3 on the tile.  Each thread owns up to
-  // UC cells of the tile plus its halo of three (the "box") for all four
+  // NT Newton terms S.k .. S.k + NT - 1 on the tile.  Each thread owns up to
+  // UC cells of the tile plus its halo of NT - 1 (the "box") for all the
   // terms: it keeps their stencil in registers, computes them in every term
   // whose region (the box shrinking by one cell per term) holds them, and
   // accumulates p and the partial sums for those of its cells in the tile.
-  // Only q goes through LDS: q_{k-1} with a halo of four, then the
+  // Only q goes through LDS: q_{k-1} with a halo of NT, then the
   // intermediate terms.
-  const int grp = (S.k - 1) >> 2;
+  const int grp = (S.k - 1) / NT;
   const V* __restrict__ qin = reinterpret_cast<const V*>((grp & 1) ? a.q1 : a.q0);
   V* __restrict__ qout = reinterpret_cast<V*>((grp & 1) ? a.q0 : a.q1);
   V* __restrict__ p = reinterpret_cast<V*>(S.ppar ? a.p1 : a.p0);
@@ -224,7 +225,9 @@ __global__ __launch_bounds__(kBatchTileX* BY) void k_bt_work(BatchArgs a) {
   const V ig = cv<V>(P.inv_g);
   const double* shf = a.shift + P.coef_off + S.k;
   const double* dkp = a.dk + P.coef_off + S.k;
-  double sums[NT] = {0.0, 0.0, 0.0, 0.0};
+  double sums[NT];
+#pragma unroll
+  for (int tt = 0; tt < NT; ++tt) sums[tt] = 0.0;
   V last[UC];
 #pragma unroll
   for (int tt = 0; tt < NT; ++tt) {
@@ -312,25 +315,30 @@ __global__ __launch_bounds__(kCtrlThreads) void k_bt_ctrl(BatchArgs a) {
     return;
   }
   const bool init = S.phase == kPhInit;
+  const int nt = a.nt;
   const double* dk = a.dk + P.coef_off;
-  double dkv[4];
+  double dkv[kBatchPartStride];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) dkv[j] = init ? dk[0] : dk[S.k + j];
-  const double* pp = a.part + 4LL * P.tile0;
-  double s[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int j = 0; j < kBatchPartStride; ++j) dkv[j] = init ? dk[0] : (j < nt ? dk[S.k + j] : 0.0);
+  const double* pp = a.part + static_cast<long long>(kBatchPartStride) * P.tile0;
+  double s[kBatchPartStride];
+#pragma unroll
+  for (int j = 0; j < kBatchPartStride; ++j) s[j] = 0.0;
   double mx = 0.0;
   for (int tt = lane; tt < P.ntiles; tt += 64) {
+    const double* pt = pp + kBatchPartStride * tt;
     if (init) {
-      s[0] += pp[4 * tt];
-      mx = fmax(mx, pp[4 * tt + 1]);
+      s[0] += pt[0];
+      mx = fmax(mx, pt[1]);
     } else {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) s[j] += pp[4 * tt + j];
+      for (int j = 0; j < kBatchPartStride; ++j)
+        if (j < nt) s[j] += pt[j];
     }
   }
   for (int off = 32; off > 0; off >>= 1) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) s[j] += __shfl_down(s[j], off, 64);
+    for (int j = 0; j < kBatchPartStride; ++j) s[j] += __shfl_down(s[j], off, 64);
     mx = fmax(mx, __shfl_down(mx, off, 64));
   }
   if (lane != 0) return;
@@ -347,6 +355,9 @@ __global__ __launch_bounds__(kCtrlThreads) void k_bt_ctrl(BatchArgs a) {
     } else if (!(S.scal > 0.0)) {
       S.flags |= 4;
       stop = true;
+    } else if (nt > a.m_max) {
+      S.flags |= 1;  // not even one pass fits the term budget
+      stop = true;
     } else {
       S.ring[0] = fabs(P.delta * dkv[0]) * sqrt(s[0]) / (P.rootN * S.scal);
       S.k = 1;
@@ -354,7 +365,7 @@ __global__ __launch_bounds__(kCtrlThreads) void k_bt_ctrl(BatchArgs a) {
     }
   } else {
     bool done = false, bad = false;
-    for (int j = 0; j < 4 && !done; ++j) {
+    for (int j = 0; j < nt && !done; ++j) {
       const int kk = S.k + j;
       if (!isfinite(s[j])) {
         bad = true;
@@ -366,7 +377,7 @@ __global__ __launch_bounds__(kCtrlThreads) void k_bt_ctrl(BatchArgs a) {
         done = mean < a.thresh;
       }
     }
-    S.terms += 4;  // all four terms of the group are kept
+    S.terms += nt;  // all terms of the pass are kept
     if (bad) {
       S.flags |= 2;
       stop = true;
@@ -385,11 +396,11 @@ __global__ __launch_bounds__(kCtrlThreads) void k_bt_ctrl(BatchArgs a) {
           S.phase = kPhInit;
         }
       }
-    } else if (S.k + 4 + 3 > a.m_max) {
+    } else if (S.k + 2 * nt - 1 > a.m_max) {
       S.flags |= 1;
       stop = true;
     } else {
-      S.k += 4;
+      S.k += nt;
     }
   }
   // a failed problem still takes the finish pass, which copies the T of its
@@ -428,31 +439,33 @@ __global__ __launch_bounds__(256) void k_batch_pack(int nx, int ny, const double
   }
 }
 
-template <int TY, int BY, bool XCD, class V>
+template <int TY, int BY, int NT, bool XCD, class V>
 hipError_t launch_work(const BatchArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
-  const size_t bytes = work_lds_bytes<TY, V>();
+  const size_t bytes = work_lds_bytes<TY, NT, V>();
   if (bytes > 65536) {
     static bool granted = false;
     if (!granted) {
-      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bt_work<TY, BY, XCD, V>),
+      const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_bt_work<TY, BY, NT, XCD, V>),
                                                hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(bytes));
       if (e != hipSuccess) return e;
       granted = true;
     }
   }
-  launch_timed(k_bt_work<TY, BY, XCD, V>, dim3(a.ntiles), dim3(kBatchTileX, BY), static_cast<unsigned>(bytes), s, e0,
-               e1, a);
+  launch_timed(k_bt_work<TY, BY, NT, XCD, V>, dim3(a.ntiles), dim3(kBatchTileX, BY), static_cast<unsigned>(bytes), s,
+               e0, e1, a);
   return hipGetLastError();
 }
 
 template <class V>
 hipError_t launch_work_shape(const BatchArgs& a, int shape, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   switch (shape) {
-    case 0: return launch_work<8, 8, false, V>(a, s, e0, e1);
-    case 1: return launch_work<16, 16, false, V>(a, s, e0, e1);
-    case 2: return launch_work<8, 8, true, V>(a, s, e0, e1);
-    case 3: return launch_work<16, 8, true, V>(a, s, e0, e1);
-    case 4: return launch_work<32, 8, true, V>(a, s, e0, e1);
+    case 0: return launch_work<8, 8, 4, false, V>(a, s, e0, e1);
+    case 1: return launch_work<16, 16, 4, false, V>(a, s, e0, e1);
+    case 2: return launch_work<8, 8, 4, true, V>(a, s, e0, e1);
+    case 3: return launch_work<16, 8, 4, true, V>(a, s, e0, e1);
+    case 4: return launch_work<32, 8, 4, true, V>(a, s, e0, e1);
+    case 5: return launch_work<16, 8, 8, true, V>(a, s, e0, e1);
+    case 6: return launch_work<8, 8, 8, true, V>(a, s, e0, e1);
     default: return hipErrorInvalidValue;
   }
 }
@@ -460,10 +473,9 @@ hipError_t launch_work_shape(const BatchArgs& a, int shape, hipStream_t s, hipEv
 }  // namespace
 
 size_t batch_lds_bytes(int shape, int fp32) {
-  const int rows = kBatchTileRows[shape];
-  if (rows == 32) return fp32 ? work_lds_bytes<32, float>() : work_lds_bytes<32, double>();
-  if (rows == 16) return fp32 ? work_lds_bytes<16, float>() : work_lds_bytes<16, double>();
-  return fp32 ? work_lds_bytes<8, float>() : work_lds_bytes<8, double>();
+  const size_t vb = fp32 ? sizeof(float) : sizeof(double);
+  const size_t rows = kBatchTileRows[shape], nt = kBatchPassTerms[shape];
+  return vb * ((rows + 2 * nt) * (kBatchTileX + 2 * nt) + 2 * (rows + 2 * nt - 2) * (kBatchTileX + 2 * nt - 2));
 }
 
 hipError_t batch_pack(int nx, int ny, const double* coef, const double* F, const double* T0, double* bcoef,

@@ -140,7 +140,8 @@ int build_tiles(erem_batch* b) {
     if (b->part) (void)hipFree(b->part);
     b->tile = nullptr;
     b->part = nullptr;
-    if (balloc(b, &b->tile, cap) || balloc(b, &b->part, 4 * static_cast<size_t>(cap))) return EREM_ENOMEM;
+    if (balloc(b, &b->tile, cap) || balloc(b, &b->part, kBatchPartStride * static_cast<size_t>(cap)))
+      return EREM_ENOMEM;
     b->tile_cap = static_cast<int>(cap);
   }
   BHIP(b, hipMemcpy(b->tile, tiles.data(), sizeof(BTile) * tiles.size(), hipMemcpyHostToDevice));
@@ -177,6 +178,7 @@ BatchArgs make_args(erem_batch* b, double* T, int nsteps) {
   a.tol_a = b->tol_a;
   a.tol_r = b->tol_r;
   a.thresh = b->thresh;
+  a.nt = kBatchPassTerms[b->shape];
   return a;
 }
 
