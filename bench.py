@@ -161,8 +161,10 @@ def gpu_run(prob, coupled, steps, warmup, rtol_p, mixed=False, sched=None, schem
             return
         if coupled:
             # the pressure stays resident in the context: after the first
-            # step each solve starts from the previous double-double pressure
-            sp = ctx.pressure_and_fluxes(T, rtol=rtol_p, p=p if state["n"] == 0 else None, warm=state["n"] > 0)
+            # step each solve starts from the linear extrapolation of the
+            # last two pressures
+            sp = ctx.pressure_and_fluxes(T, rtol=rtol_p, p=p if state["n"] == 0 else None,
+                                         warm=2 if state["n"] > 0 else 0)
             state["pcg"] += sp["iterations"]
         if sched is not None:
             # boundary temperatures and their rates at t_n = n h
@@ -302,7 +304,7 @@ def bench_batch(args, mixed):
     opts = make_opts(m_max=128, precision=1, tol_r=1e-7) if mixed else make_opts(m_max=128)
     b.prepare(probs[0].h, opts)
     T0 = b.pack([p.T0 for p in probs])
-    shape = b.autotune(T0, nsteps=2)
+    shape = b.autotune(T0, nsteps=5)
     log(f"batch: {nprob} problems, {b.ntot} cells, autotuned tile shape {shape}")
     T = T0.clone()
     for _ in range(max(1, args.warmup)):

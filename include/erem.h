@@ -139,9 +139,11 @@ int erem_assemble_transmissibilities(erem_ctx* ctx, const double* d_T);
  * (Darcy's law, Eq. darcy, g = 0).  d_p (N, may be NULL) is read as the
  * initial guess when warm != 0 and receives the pressure; with warm != 0 and
  * d_p NULL the context's own (double-double) pressure of the last solve is
- * the initial guess, and no copy is made.  stats (may be NULL) gets
- * iterations and the final relative residual.  ENOCONV if rtol is not
- * reached. */
+ * the initial guess, and no copy is made; with warm == 2 and d_p NULL the
+ * guess is the linear extrapolation 2 p^n - p^(n-1) of the context's last two
+ * solutions when the previous call also kept the context's pressure (else
+ * p^n, as with warm == 1).  stats (may be NULL) gets iterations and the
+ * final relative residual.  ENOCONV if rtol is not reached. */
 int erem_solve_pressure(erem_ctx* ctx, double rtol, int32_t max_iter, int32_t warm,
                         double* d_p, erem_stats* stats);
 
@@ -372,9 +374,12 @@ typedef struct {
     int32_t failed;        /* problems that stopped on an error (see the return code) */
     int32_t tile_shape;    /* 0: 64 x 8 tiles on 512 threads, 1: 64 x 16 on 1024 threads,
                               2: 64 x 8 on 512 threads, 3: 64 x 16 on 512, 4: 64 x 32 on
-                              512, with each XCD taking a contiguous range of tiles in 2-4;
-                              the Newton terms go four per pass (the applied degree is the
-                              first multiple of 4 at which the stop test holds) */
+                              512, all with four Newton terms per pass; 5: 64 x 16 and
+                              6: 64 x 8 on 512 threads with eight terms per pass; each XCD
+                              takes a contiguous range of tiles in 2-6.  The stop test is
+                              evaluated term by term after each pass and all terms of the
+                              pass are kept (the applied degree is the first multiple of
+                              the pass width at which the test holds) */
     int32_t graph;         /* 1 if the run was replayed from a hipGraph */
     int32_t grid;          /* workgroups of a work launch (tiles) */
     double ms;             /* device time of the run (HIP events) */
@@ -406,7 +411,7 @@ int erem_batch_prepare(erem_batch* b, double h, const erem_opts* opts);
 /* Time every tile shape on a copy of d_T (nsteps steps) and keep the fastest;
  * *chosen receives its index.  d_T is not modified. */
 int erem_batch_autotune(erem_batch* b, const double* d_T, int32_t nsteps, int32_t* chosen);
-/* Select a tile shape by index (0 .. 4, see erem_batch_stats.tile_shape)
+/* Select a tile shape by index (0 .. 6, see erem_batch_stats.tile_shape)
  * instead of timing them.  EINVAL for another index. */
 int erem_batch_set_tile_shape(erem_batch* b, int32_t shape);
 /* Time every stride-th work launch of the following runs by the start and

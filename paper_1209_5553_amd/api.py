@@ -138,7 +138,7 @@ class EremContext:
 
     def solve_pressure(self, rtol=1e-16, max_iter=50000, p=None, warm=False):
         st = nat.Stats()
-        self._check(self.lib.erem_solve_pressure(self.handle, rtol, max_iter, 1 if warm else 0,
+        self._check(self.lib.erem_solve_pressure(self.handle, rtol, max_iter, int(warm),
                                                  self._ptr(p, self.n, "p"), ctypes.byref(st)),
                     "erem_solve_pressure")
         return st.as_dict()

@@ -282,7 +282,7 @@ __global__ __launch_bounds__(kThreads) void k_adj_flux_p(Dims d, const double* _
   pbar[i] = pb;
 }
 
-__device__ inline void slot_add(PcgState* st, double rr, double bb) {
+__device__ inline void band_store(PcgState* st, double rr, double bb) {
   __shared__ double sh[kThreads / 64][2];
   for (int off = 32; off > 0; off >>= 1) {
     rr += __shfl_down(rr, off, 64);
@@ -295,9 +295,9 @@ __device__ inline void slot_add(PcgState* st, double rr, double bb) {
   }
   __syncthreads();
   if (t == 0) {
-    const int sl = (blockIdx.x + gridDim.x * blockIdx.y) & (kSlots - 1);
-    atomicAdd(&st->rr[sl], sh[0][0] + sh[1][0] + sh[2][0] + sh[3][0]);
-    atomicAdd(&st->bb_sl[sl], sh[0][1] + sh[1][1] + sh[2][1] + sh[3][1]);
+    const int b = blockIdx.x + gridDim.x * blockIdx.y;  // the block's band
+    st->rr[b] = sh[0][0] + sh[1][0] + sh[2][0] + sh[3][0];
+    st->bb_sl[b] = sh[0][1] + sh[1][1] + sh[2][1] + sh[3][1];
   }
 }
 
@@ -322,7 +322,7 @@ __global__ __launch_bounds__(kThreads) void k_spd_residual(Dims d, const double*
     rr = ri * ri;
     bb = bi * bi;
   }
-  slot_add(st, rr, bb);
+  band_store(st, rr, bb);
 }
 
 __global__ __launch_bounds__(kThreads) void k_adj_trans(Dims d, Phys ph, const double* __restrict__ logk,

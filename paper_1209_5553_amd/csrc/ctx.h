@@ -46,11 +46,14 @@ struct erem_ctx {
          *rs_rhs = nullptr, *rs_coef = nullptr;
   erem::BicgState* bicg = nullptr;
   erem::BicgState* h_bicg = nullptr;
+  double* bicg_parts = nullptr;  // the BiCGSTAB partial slots (erem::bicg_parts_words(cell bands))
   int bicg_last = 0;  // iterations of the last converged solve (poll placement)
   double *qa = nullptr, *qb = nullptr, *pacc = nullptr, *u = nullptr, *w = nullptr;
   double *pres = nullptr, *pr = nullptr, *pr2 = nullptr, *pz = nullptr, *pp0 = nullptr, *pp1 = nullptr;
   double *pw = nullptr, *ps0 = nullptr, *ps1 = nullptr;  // Chronopoulos-Gear w = A z and s
   double *pq = nullptr, *pdiag = nullptr, *pres_lo = nullptr, *pdelta = nullptr, *prhs = nullptr;
+  double* pres_prev = nullptr;  // previous pressure for the extrapolated warm start (on first use)
+  bool pres_prev_set = false;   // pres_prev holds the solution before the context's current one
   double* part = nullptr;  // Leja block partial sums (ring of kLejaRing terms)
   // FP32 copies for the mixed-precision Leja passes (allocated on first use)
   float *coef32 = nullptr, *qa32 = nullptr, *qb32 = nullptr, *p32 = nullptr;
@@ -73,6 +76,9 @@ struct erem_ctx {
   erem::LejaState* h_states = nullptr;
   erem::AsmReduce* h_red = nullptr;
   erem::PcgState* h_pcg = nullptr;
+  double* pcg_parts = nullptr;    // the PCG partial slots (erem::pcg_parts_words(pcg_nb))
+  double* h_pcg_parts = nullptr;  // pinned: ||b||^2 and r.r partials of a residual
+  int pcg_nb = 0;
 
   std::vector<double> xi;  // Leja points
   DivDiffCache dd, dd2;  // phi1 and phi2 divided differences

@@ -10,7 +10,7 @@ namespace erem {
 constexpr int kBX = 64;        // threads along x per block (one wavefront)
 constexpr int kBY = 4;         // rows per block -> 256 threads, 4 wavefronts
 constexpr int kThreads = kBX * kBY;
-constexpr int kSlots = 64;     // spread of the atomic partial sums (one wavefront sums them)
+constexpr int kSlots = 64;     // spread of the atomic min / max targets (AsmReduce)
 constexpr int kMaxTerms = 1024;  // Leja degree cap per substep
 // Widest substep interval h (beta - alpha) / s of the FP32 Newton passes: the
 // terms grow to about e^(rho/10) times the result before they cancel, and in
@@ -59,24 +59,46 @@ struct AsmReduce {
   unsigned long long vmax[kSlots];  // max_i |v_i| (phi1_apply)
 };
 
-// Conjugate-gradient scalars: ring of 4 iterations x kSlots partial sums.
+// Conjugate-gradient scalars.  The inner products are kept as partial sums,
+// one per 64 x 4 cell band of the grid (the blocks of cell_grid), in a ring
+// of four iterations: each band's slot is written by the block or tile that
+// covers it (a tile of several bands writes its sum into its first band and
+// zeros into the others), and every consumer sums the slots in band order
+// (wave_part_sum), so the result does not depend on the order in which the
+// blocks ran.  The arrays live in one device allocation of
+// pcg_parts_words(nb) doubles.
 struct PcgState {
   int done;        // 1 once converged
   int it_done;     // iteration count at convergence
   int nonfinite;
-  int pad;
+  int nb;          // partial slots per inner product (bands of the grid)
   double bb;       // ||b||^2 (reduced by the start kernel)
   double tol2;     // rtol^2
-  double bb_sl[kSlots];
-  double rz[4 * kSlots];
-  double rr[4 * kSlots];
-  double pq[4 * kSlots];
-  double wz[4 * kSlots];  // w.z (Chronopoulos-Gear form)
   double alpha[4];        // step lengths (Chronopoulos-Gear form)
+  double* bb_sl;          // [nb]
+  double* rz;             // [4][nb]
+  double* rr;             // [4][nb]
+  double* pq;             // [4][nb]
+  double* wz;             // [4][nb] w.z (Chronopoulos-Gear form)
 };
+inline size_t pcg_parts_words(int nb) { return static_cast<size_t>(17) * nb; }
+// The state's array pointers into a parts allocation of pcg_parts_words(nb).
+inline void pcg_bind_parts(PcgState* st, double* parts, int nb) {
+  st->nb = nb;
+  st->bb_sl = parts;
+  st->rz = parts + nb;
+  st->rr = parts + 5 * static_cast<size_t>(nb);
+  st->pq = parts + 9 * static_cast<size_t>(nb);
+  st->wz = parts + 13 * static_cast<size_t>(nb);
+}
 
 inline dim3 cell_grid(const Dims& d) {
   return dim3((d.nx + kBX - 1) / kBX, (d.ny + kBY - 1) / kBY, d.nz);
+}
+// Number of 64 x 4 cell bands (the blocks of cell_grid).
+inline int cell_bands(const Dims& d) {
+  const dim3 g = cell_grid(d);
+  return static_cast<int>(g.x * g.y * g.z);
 }
 inline dim3 cell_block() { return dim3(kBX, kBY, 1); }
 
@@ -119,6 +141,9 @@ hipError_t launch_dd_residual(const Dims& d, const Phys& ph, const double* tx, c
                               PcgState* st, hipStream_t s);
 hipError_t launch_dd_update(const Dims& d, double* phi, double* plo, const double* delta,
                             hipStream_t s);
+// Extrapolated warm start: prev <- p; with extrapolate, p <- 2 p - prev_old.
+hipError_t launch_pressure_extrapolate(const Dims& d, double* phi, double* plo, double* prev, int extrapolate,
+                                      hipStream_t s);
 hipError_t launch_face_fluxes_dd(const Dims& d, const Phys& ph, const double* phi,
                                  const double* plo, const double* tx, const double* ty,
                                  const double* tz, double* fx, double* fy, double* fz,
@@ -161,14 +186,24 @@ inline void launch_timed(K kernel, dim3 grid, dim3 block, unsigned shmem, hipStr
     hipLaunchKernelGGL(kernel, grid, block, shmem, s, args...);
 }
 
-// Sum of the kSlots partial sums at base, by one wavefront (kSlots == 64):
-// every lane loads one slot; a butterfly sums them and lane 0's result is
-// broadcast so that every lane takes the same decisions.
-static_assert(kSlots == 64, "one slot per lane");
-__device__ inline double wave_slot_sum(const double* base) {
-  double s = base[threadIdx.x & 63];
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
-  return __shfl(s, 0, 64);  // lane 0's rounding for every lane
+// Sum of n partials at base in a fixed order, by one wavefront: lane l adds
+// base[l], base[l + 64], ... in turn, a shuffle tree adds the lanes, and lane
+// 0's result is broadcast so that every lane takes the same decisions.  The
+// loads go sixteen at a time (a lane's share of 1024 partials is one memory
+// latency), and are added in order after they arrive.
+__device__ inline double wave_part_sum(const double* __restrict__ base, int n) {
+  constexpr int kBatch = 16;
+  const int lane = __lane_id();
+  double s = 0.0;
+  for (int k = lane; k < n; k += kBatch * 64) {
+    double v[kBatch];
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) v[j] = k + j * 64 < n ? base[k + j * 64] : 0.0;
+#pragma unroll
+    for (int j = 0; j < kBatch; ++j) s += v[j];
+  }
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  return __shfl(s, 0, 64);
 }
 
 // Ordered encoding of doubles for atomic min/max on 64-bit unsigned integers.

@@ -82,12 +82,21 @@ void free_all(erem_ctx* c) {
   if (c->pcg) (void)hipFree(c->pcg);
   if (c->bicg) (void)hipFree(c->bicg);
   if (c->h_bicg) (void)hipHostFree(c->h_bicg);
+  if (c->bicg_parts) (void)hipFree(c->bicg_parts);
   c->bicg = nullptr;
   c->h_bicg = nullptr;
+  c->bicg_parts = nullptr;
   if (c->h_cf) (void)hipHostFree(c->h_cf);
   if (c->h_states) (void)hipHostFree(c->h_states);
   if (c->h_red) (void)hipHostFree(c->h_red);
   if (c->h_pcg) (void)hipHostFree(c->h_pcg);
+  if (c->pcg_parts) (void)hipFree(c->pcg_parts);
+  if (c->pres_prev) (void)hipFree(c->pres_prev);
+  c->pres_prev = nullptr;
+  c->pres_prev_set = false;
+  if (c->h_pcg_parts) (void)hipHostFree(c->h_pcg_parts);
+  c->pcg_parts = nullptr;
+  c->h_pcg_parts = nullptr;
   float** fbufs[] = {&c->coef32, &c->qa32, &c->qb32, &c->p32};
   for (float** b : fbufs)
     if (*b) { (void)hipFree(*b); *b = nullptr; }
@@ -253,6 +262,29 @@ const std::vector<double>& divided_differences(erem_ctx* c, double hc, double hg
     dd.n = n;
   }
   return dd.d;
+}
+
+// Enqueue the readback of a residual kernel's results: the PCG state and
+// the ||b||^2 and r.r partials (ring slot 0).  Sum them after the stream
+// has been synchronised (residual_sums).
+int enqueue_residual_readback(erem_ctx* c) {
+  const size_t nb = static_cast<size_t>(c->pcg_nb);
+  HIP_TRY(c, hipMemcpyAsync(c->h_pcg, c->pcg, sizeof(PcgState), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->h_pcg_parts, c->pcg_parts, sizeof(double) * nb, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(c, hipMemcpyAsync(c->h_pcg_parts + nb, c->pcg_parts + 5 * nb, sizeof(double) * nb, hipMemcpyDeviceToHost,
+                            c->stream));
+  return EREM_OK;
+}
+
+// r.r and ||b||^2 of the last residual, the partials added in band order.
+void residual_sums(const erem_ctx* c, double* rr, double* bb) {
+  double a = 0.0, b = 0.0;
+  for (int q = 0; q < c->pcg_nb; ++q) {
+    b += c->h_pcg_parts[q];
+    a += c->h_pcg_parts[c->pcg_nb + q];
+  }
+  *rr = a;
+  *bb = b;
 }
 
 // Read the assembly reductions (Gershgorin interval, max |T|, max |v|).
@@ -747,7 +779,10 @@ int spd_solve(erem_ctx* c, const double* b, double* x, double rtol, int max_iter
   for (int outer = 0; outer < 12; ++outer) {
     HIP_TRY(c, launch_pcg_reset(c->pcg, 0.0, c->stream));
     HIP_TRY(c, launch_spd_residual(d, c->tx, c->ty, x, b, c->prhs, c->pcg, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(c->h_pcg, c->pcg, sizeof(PcgState), hipMemcpyDeviceToHost, c->stream));
+    {
+      const int rc = enqueue_residual_readback(c);
+      if (rc) return rc;
+    }
     if (setup_pending) {
       HIP_TRY(c, hipEventRecord(c->ev_setup, c->stream));
       HIP_TRY(c, mg_setup(c->mg, c->stream));
@@ -757,7 +792,7 @@ int spd_solve(erem_ctx* c, const double* b, double* x, double rtol, int max_iter
       HIP_TRY(c, hipStreamSynchronize(c->stream));
     }
     double rr = 0.0, bb = 0.0;
-    for (int q = 0; q < kSlots; ++q) { rr += c->h_pcg->rr[q]; bb += c->h_pcg->bb_sl[q]; }
+    residual_sums(c, &rr, &bb);
     if (!std::isfinite(rr)) return fail(c, EREM_ENONFINITE, "non-finite residual in the adjoint pressure solve");
     if (bb == 0.0 || rr <= rtol * rtol * bb) { ok = true; break; }
     if (total >= max_iter) break;
@@ -859,12 +894,22 @@ int erem_create(const erem_grid* g, void* stream, erem_ctx** out) {
   rc |= dev_alloc(c, &c->states, c->nstates);
   rc |= dev_alloc(c, &c->red, 1);
   rc |= dev_alloc(c, &c->pcg, 1);
+  c->pcg_nb = cell_bands(c->d);
+  rc |= dev_alloc(c, &c->pcg_parts, pcg_parts_words(c->pcg_nb));
   if (rc == EREM_OK) {
     if (hipHostMalloc(reinterpret_cast<void**>(&c->h_cf), 2 * sizeof(LejaCoef), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&c->h_states), sizeof(LejaState) * c->nstates, hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&c->h_red), sizeof(AsmReduce), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&c->h_pcg), sizeof(PcgState), hipHostMallocDefault) != hipSuccess)
+        hipHostMalloc(reinterpret_cast<void**>(&c->h_pcg), sizeof(PcgState), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&c->h_pcg_parts), 2 * sizeof(double) * c->pcg_nb,
+                      hipHostMallocDefault) != hipSuccess)
       rc = EREM_ENOMEM;
+  }
+  if (rc == EREM_OK) {
+    // the state's pointers into the partial slots, set once
+    PcgState init{};
+    pcg_bind_parts(&init, c->pcg_parts, c->pcg_nb);
+    if (hipMemcpy(c->pcg, &init, sizeof(PcgState), hipMemcpyHostToDevice) != hipSuccess) rc = EREM_EDEVICE;
   }
   if (rc != EREM_OK) {
     free_all(c);
@@ -981,6 +1026,15 @@ int erem_solve_pressure(erem_ctx* c, double rtol, int32_t max_iter, int32_t warm
   if (warm && d_p) HIP_TRY(c, hipMemcpyAsync(c->pres, d_p, bytes, hipMemcpyDeviceToDevice, c->stream));
   if (!warm) HIP_TRY(c, hipMemsetAsync(c->pres, 0, bytes, c->stream));
   if (!warm || d_p) HIP_TRY(c, hipMemsetAsync(c->pres_lo, 0, bytes, c->stream));
+  if (warm == 2 && !d_p) {
+    // linear extrapolation from the last two solutions (first call: keep p^n)
+    if (!c->pres_prev && dev_alloc(c, &c->pres_prev, d.N)) return EREM_ENOMEM;
+    HIP_TRY(c, launch_pressure_extrapolate(d, c->pres, c->pres_lo, c->pres_prev, c->pres_prev_set ? 1 : 0,
+                                           c->stream));
+    c->pres_prev_set = true;
+  } else {
+    c->pres_prev_set = false;
+  }
   // Iterative refinement: residual of the double-double pressure, PCG on the
   // correction to the reduction the tolerance still needs (at most 1e-12 per
   // correction), double-double update.
@@ -997,7 +1051,10 @@ int erem_solve_pressure(erem_ctx* c, double rtol, int32_t max_iter, int32_t warm
   for (int outer = 0; outer < 8; ++outer) {
     HIP_TRY(c, launch_pcg_reset(c->pcg, 0.0, c->stream));
     HIP_TRY(c, launch_dd_residual(d, c->ph, c->tx, c->ty, c->tz, c->pres, c->pres_lo, c->prhs, c->pcg, c->stream));
-    HIP_TRY(c, hipMemcpyAsync(c->h_pcg, c->pcg, sizeof(PcgState), hipMemcpyDeviceToHost, c->stream));
+    {
+      const int rc = enqueue_residual_readback(c);
+      if (rc) return rc;
+    }
     if (setup_pending) {
       HIP_TRY(c, hipEventRecord(c->ev_setup, c->stream));
       HIP_TRY(c, mg_setup(c->mg, c->stream));
@@ -1007,7 +1064,7 @@ int erem_solve_pressure(erem_ctx* c, double rtol, int32_t max_iter, int32_t warm
       HIP_TRY(c, hipStreamSynchronize(c->stream));
     }
     double rr = 0.0, bb = 0.0;
-    for (int q = 0; q < kSlots; ++q) { rr += c->h_pcg->rr[q]; bb += c->h_pcg->bb_sl[q]; }
+    residual_sums(c, &rr, &bb);
     if (!std::isfinite(rr)) return fail(c, EREM_ENONFINITE, "non-finite pressure residual");
     relres = bb > 0 ? std::sqrt(rr / bb) : std::sqrt(rr);
     if (relres <= rtol || rr == 0.0) { ok = true; break; }

@@ -6,9 +6,11 @@
 // 64-lane wavefront per grid row segment, so loads along x are fully
 // coalesced; +-y / +-z neighbours come from the same block's other rows or
 // from L2.  Reductions: wavefront shuffles, then the four wavefront partials
-// through LDS, then one device-scope atomic add per block into one of kSlots
-// slots (spreading contention); the consumer of a sum is always a later
-// kernel, so kernel boundaries order every producer/consumer pair.
+// through LDS; the conjugate-gradient inner products then go to the block's
+// own partial slot, which consumers add up in a fixed order (PcgState), and
+// the assembly's min / max targets take an atomic min / max over kSlots
+// slots (order-free); the consumer of a sum is always a later kernel, so
+// kernel boundaries order every producer/consumer pair.
 #include "device.h"
 
 #include <cmath>
@@ -431,16 +433,16 @@ __device__ inline FaceT load_faces(const Dims& d, const double* tx, const double
   return f;
 }
 
+// Scalars of a new solve; the partial slots need no clearing, every
+// producer overwrites the slots of all bands.
 __global__ void k_pcg_reset(PcgState* st, double tol2) {
-  double* words = (double*)st;
-  const int n = sizeof(PcgState) / sizeof(double);
-  for (int j = threadIdx.x; j < n; j += blockDim.x) words[j] = 0.0;
-  __syncthreads();
   if (threadIdx.x == 0) {
     st->done = 0;
     st->it_done = -1;
     st->nonfinite = 0;
+    st->bb = 0.0;
     st->tol2 = tol2;
+    for (int k = 0; k < 4; ++k) st->alpha[k] = 0.0;
   }
 }
 
@@ -480,10 +482,10 @@ __global__ __launch_bounds__(kThreads) void k_pcg_start(Dims d, Phys ph, const d
   }
   block_sum<3>(s);
   if (tid_lin() == 0) {
-    const int sl = bid_lin() & (kSlots - 1);
-    atomicAdd(&st->rz[sl], s[0]);
-    atomicAdd(&st->rr[sl], s[1]);
-    atomicAdd(&st->bb_sl[sl], s[2]);
+    const int b = bid_lin();  // the block's band
+    st->rz[b] = s[0];
+    st->rr[b] = s[1];
+    st->bb_sl[b] = s[2];
   }
 }
 
@@ -514,10 +516,10 @@ __global__ __launch_bounds__(kThreads) void k_pcg_start_rhs(Dims d, const double
   }
   block_sum<2>(s);
   if (tid_lin() == 0) {
-    const int sl = bid_lin() & (kSlots - 1);
-    if (jacobi) atomicAdd(&st->rz[sl], s[0]);  // otherwise the preconditioner adds r.z
-    atomicAdd(&st->rr[sl], s[1]);
-    atomicAdd(&st->bb_sl[sl], s[1]);
+    const int b = bid_lin();
+    if (jacobi) st->rz[b] = s[0];  // otherwise the preconditioner writes r.z
+    st->rr[b] = s[1];
+    st->bb_sl[b] = s[1];
   }
 }
 
@@ -589,10 +591,29 @@ __global__ __launch_bounds__(kThreads) void k_dd_residual(Dims d, Phys ph, const
   }
   block_sum<2>(s);
   if (tid_lin() == 0) {
-    const int sl = bid_lin() & (kSlots - 1);
-    atomicAdd(&st->rr[sl], s[0]);
-    atomicAdd(&st->bb_sl[sl], s[1]);
+    const int b = bid_lin();
+    st->rr[b] = s[0];
+    st->bb_sl[b] = s[1];
   }
+}
+
+// Warm start of the next pressure solve from the last two solutions: the
+// previous one (prev) and the current double-double one (hi + lo).  With
+// extrapolate, hi = 2 p - prev and lo = 0; prev takes the current p.
+__global__ __launch_bounds__(kThreads) void k_pressure_extrapolate(Dims d, double* __restrict__ phi,
+                                                         double* __restrict__ plo, double* __restrict__ prev,
+                                                         int extrapolate) {
+  const int x = blockIdx.x * kBX + threadIdx.x;
+  const int y = blockIdx.y * kBY + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= d.nx || y >= d.ny) return;
+  const int i = x + d.nx * (y + d.ny * z);
+  const double cur = phi[i] + plo[i];
+  if (extrapolate) {
+    phi[i] = 2.0 * cur - prev[i];
+    plo[i] = 0.0;
+  }
+  prev[i] = cur;
 }
 
 // p_hi + p_lo += delta (double-double)
@@ -682,10 +703,11 @@ __global__ __launch_bounds__(kThreads) void k_pcg_a(Dims d, const double* __rest
     int stop = *(volatile int*)&st->done;
     double beta = 0.0;
     if (!stop) {
-      const double rr = wave_slot_sum(st->rr + (it & 3) * kSlots);
-      const double bb = wave_slot_sum(st->bb_sl);
-      const double rz1 = wave_slot_sum(st->rz + (it & 3) * kSlots);
-      const double rz0 = wave_slot_sum(st->rz + ((it - 1) & 3) * kSlots);
+      const int nb = st->nb;
+      const double rr = wave_part_sum(st->rr + (it & 3) * nb, nb);
+      const double bb = wave_part_sum(st->bb_sl, nb);
+      const double rz1 = wave_part_sum(st->rz + (it & 3) * nb, nb);
+      const double rz0 = it > 0 ? wave_part_sum(st->rz + ((it - 1) & 3) * nb, nb) : 1.0;
       if (!isfinite(rr)) {
         stop = 1;
         if (bid_lin() == 0 && t == 0) { st->nonfinite = 1; st->done = 1; st->it_done = it; }
@@ -699,10 +721,6 @@ __global__ __launch_bounds__(kThreads) void k_pcg_a(Dims d, const double* __rest
     if (t == 0) {
       stop_sh = stop;
       beta_sh = beta;
-    }
-    if (!stop && bid_lin() == 0) {
-      st->rz[((it + 1) & 3) * kSlots + t] = 0.0;
-      st->rr[((it + 1) & 3) * kSlots + t] = 0.0;
     }
   }
   __syncthreads();
@@ -722,7 +740,7 @@ __global__ __launch_bounds__(kThreads) void k_pcg_a(Dims d, const double* __rest
     s[0] = pi * Ap;
   }
   block_sum<1>(s);
-  if (t == 0) atomicAdd(&st->pq[(it & 3) * kSlots + (bid_lin() & (kSlots - 1))], s[0]);
+  if (t == 0) st->pq[(it & 3) * st->nb + bid_lin()] = s[0];
 }
 
 // Iteration `it`, second half: alpha = rz/pq, x += alpha p, r -= alpha q,
@@ -752,9 +770,9 @@ __global__ __launch_bounds__(kThreads) void k_pcg_b(Dims d, double* __restrict__
     const int stop = *(volatile int*)&st->done;
     if (t == 0) stop_sh = stop;
     if (!stop) {
-      const double alpha = wave_slot_sum(st->rz + (it & 3) * kSlots) / wave_slot_sum(st->pq + (it & 3) * kSlots);
+      const int nb = st->nb;
+      const double alpha = wave_part_sum(st->rz + (it & 3) * nb, nb) / wave_part_sum(st->pq + (it & 3) * nb, nb);
       if (t == 0) alpha_sh = alpha;
-      if (bid_lin() == 0) st->pq[((it + 1) & 3) * kSlots + t] = 0.0;
     }
   }
   __syncthreads();
@@ -774,9 +792,9 @@ __global__ __launch_bounds__(kThreads) void k_pcg_b(Dims d, double* __restrict__
   }
   block_sum<2>(s);
   if (t == 0) {
-    const int sl = ((it + 1) & 3) * kSlots + (bid_lin() & (kSlots - 1));
-    if (jacobi) atomicAdd(&st->rz[sl], s[0]);  // otherwise the preconditioner adds r.z
-    atomicAdd(&st->rr[sl], s[1]);
+    const int sl = ((it + 1) & 3) * st->nb + bid_lin();
+    if (jacobi) st->rz[sl] = s[0];  // otherwise the preconditioner writes r.z
+    st->rr[sl] = s[1];
   }
 }
 
@@ -956,6 +974,12 @@ hipError_t launch_dd_residual(const Dims& d, const Phys& ph, const double* tx, c
                               const double* tz, const double* phi, const double* plo, double* r, PcgState* st,
                               hipStream_t s) {
   hipLaunchKernelGGL(k_dd_residual, cell_grid(d), cell_block(), 0, s, d, ph, tx, ty, tz, phi, plo, r, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_pressure_extrapolate(const Dims& d, double* phi, double* plo, double* prev, int extrapolate,
+                                      hipStream_t s) {
+  hipLaunchKernelGGL(k_pressure_extrapolate, cell_grid(d), cell_block(), 0, s, d, phi, plo, prev, extrapolate);
   return hipGetLastError();
 }
 

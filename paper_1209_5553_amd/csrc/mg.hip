@@ -267,8 +267,8 @@ __global__ __launch_bounds__(kThreads) void k_mg_up_smooth(MgLevelDev F, MgLevel
   if ((t & 63) == 0) sh[t >> 6] = part;
   __syncthreads();
   if (t == 0) {
-    const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-    atomicAdd(&st->rz[rz_slot * kSlots + (bid & (kSlots - 1))], sh[0] + sh[1] + sh[2] + sh[3]);
+    const int bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);  // the block's band
+    st->rz[rz_slot * st->nb + bid] = sh[0] + sh[1] + sh[2] + sh[3];
   }
 }
 
@@ -281,6 +281,15 @@ __global__ __launch_bounds__(kThreads) void k_mg_up_smooth(MgLevelDev F, MgLevel
 // from LDS.  Same arithmetic, in the same order, as the generic forms above.
 // ---------------------------------------------------------------------------
 constexpr int kTY = 8;           // tile rows (two per thread)
+
+// A 64 x kTY tile covers the 64 x 4 bands (bx, 2 by) and (bx, 2 by + 1) of
+// the finest grid: its partial goes to the first, zero to the second.
+__device__ inline void tile_band_store(double* slots, int nx, int ny, double v) {
+  const int gx = (nx + kBX - 1) / kBX, gyb = (ny + kBY - 1) / kBY;
+  const int b0 = blockIdx.x + gx * (2 * blockIdx.y);
+  slots[b0] = v;
+  if (2 * static_cast<int>(blockIdx.y) + 1 < gyb) slots[b0 + gx] = 0.0;
+}
 
 // Faces of the halo-H region: x faces of its rows (face gx of cell gx is its
 // -x face) and y faces of its columns.
@@ -460,11 +469,12 @@ __global__ __launch_bounds__(kThreads) void k_mg_down_restrict_2d(MgLevelDev F, 
   if (CG && tid < 64) {  // the first wavefront decides for the block
     int halt = stop ? 1 : 0;
     double alpha = 0.0, beta = 0.0;
-    const double rr = wave_slot_sum(st->rr + (it & 3) * kSlots);
-    const double bb = wave_slot_sum(st->bb_sl);
-    const double g1 = wave_slot_sum(st->rz + (it & 3) * kSlots);
-    const double d1 = wave_slot_sum(st->wz + (it & 3) * kSlots);
-    const double g0 = wave_slot_sum(st->rz + ((it - 1) & 3) * kSlots);
+    const int nb = st->nb;
+    const double rr = wave_part_sum(st->rr + (it & 3) * nb, nb);
+    const double bb = wave_part_sum(st->bb_sl, nb);
+    const double g1 = wave_part_sum(st->rz + (it & 3) * nb, nb);
+    const double d1 = wave_part_sum(st->wz + (it & 3) * nb, nb);
+    const double g0 = it > 0 ? wave_part_sum(st->rz + ((it - 1) & 3) * nb, nb) : 1.0;
     const bool lead = tile == 0;
     if (halt) {
       // an earlier iteration converged
@@ -485,13 +495,7 @@ __global__ __launch_bounds__(kThreads) void k_mg_down_restrict_2d(MgLevelDev F, 
       alpha_sh = alpha;
       beta_sh = beta;
     }
-    if (!halt && lead) {
-      if (tid == 0) st->alpha[it & 3] = alpha;
-      // clear the slots two iterations ahead (nobody reads them now)
-      st->rz[((it + 2) & 3) * kSlots + tid] = 0.0;
-      st->rr[((it + 2) & 3) * kSlots + tid] = 0.0;
-      st->wz[((it + 2) & 3) * kSlots + tid] = 0.0;
-    }
+    if (!halt && lead && tid == 0) st->alpha[it & 3] = alpha;
   }
   if (CG) {
     // block (0, 0) may set the stop flag while this kernel runs, so every
@@ -527,10 +531,7 @@ __global__ __launch_bounds__(kThreads) void k_mg_down_restrict_2d(MgLevelDev F, 
     __shared__ double sh[kThreads / 64];
     if ((tid & 63) == 0) sh[tid >> 6] = rr;
     __syncthreads();
-    if (tid == 0) {
-      const int bid = blockIdx.x + gridDim.x * blockIdx.y;
-      atomicAdd(&st->rr[((it + 1) & 3) * kSlots + (bid & (kSlots - 1))], sh[0] + sh[1] + sh[2] + sh[3]);
-    }
+    if (tid == 0) tile_band_store(st->rr + ((it + 1) & 3) * st->nb, nx, ny, sh[0] + sh[1] + sh[2] + sh[3]);
   } else {
     if (stop) return;
     __syncthreads();
@@ -648,9 +649,8 @@ __global__ __launch_bounds__(kThreads) void k_mg_up_smooth_2d(MgLevelDev F, MgLe
   }
   __syncthreads();
   if (tid == 0) {
-    const int sl = rz_slot * kSlots + ((blockIdx.x + gridDim.x * blockIdx.y) & (kSlots - 1));
-    atomicAdd(&st->rz[sl], sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3]);
-    if (CG) atomicAdd(&st->wz[sl], sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3]);
+    tile_band_store(st->rz + rz_slot * st->nb, nx, ny, sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3]);
+    if (CG) tile_band_store(st->wz + rz_slot * st->nb, nx, ny, sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3]);
   }
 }
 
@@ -977,10 +977,14 @@ __global__ __launch_bounds__(1024) void k_mg_coarse_lds(MgCoarseArgs a, const do
   __shared__ double sh[16];
   if ((t & 63) == 0) sh[t >> 6] = part;
   __syncthreads();
+  // the whole grid is this workgroup's: its sum in the first band's slot,
+  // zeros in the others
+  double* slots = st->rz + rz_slot * st->nb;
+  for (int k = t + 1; k < st->nb; k += bd) slots[k] = 0.0;
   if (t == 0) {
     double s = 0.0;
     for (int w = 0; w < (bd + 63) / 64; ++w) s += sh[w];
-    atomicAdd(&st->rz[rz_slot * kSlots], s);
+    slots[0] = s;
   }
 }
 

@@ -73,10 +73,16 @@ int ensure_bicg(erem_ctx* c) {
                   &c->rs_k0, &c->rs_k1, &c->rs_k2, &c->rs_y, &c->rs_g, &c->rs_rhs};
   for (double** b : v) rc |= dev_alloc(c, b, n);
   rc |= dev_alloc(c, &c->rs_coef, n * ndir(c));
+  const int nb = cell_bands(c->d);
+  rc |= dev_alloc(c, &c->bicg_parts, bicg_parts_words(nb));
   rc |= dev_alloc(c, &c->bicg, 1);
   if (rc) return EREM_ENOMEM;
   if (hipHostMalloc(reinterpret_cast<void**>(&c->h_bicg), sizeof(BicgState), hipHostMallocDefault) != hipSuccess)
     return fail(c, EREM_ENOMEM, "hipHostMalloc failed");
+  // the state's pointers into the partial slots, set once
+  BicgState init{};
+  bicg_bind_parts(&init, c->bicg_parts, nb);
+  HIP_TRY(c, hipMemcpy(c->bicg, &init, sizeof(BicgState), hipMemcpyHostToDevice));
   return EREM_OK;
 }
 

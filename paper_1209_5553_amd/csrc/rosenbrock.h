@@ -9,22 +9,34 @@
 
 namespace erem {
 
-// Reduction ring of the BiCGSTAB iteration: four iterations of kSlots
-// partial sums per inner product (a slot is cleared two kernels before it
-// is accumulated again).
+// Scalars of the BiCGSTAB iteration.  Its inner products are kept as
+// partial sums, one per 64 x 4 cell band (the blocks of cell_grid), in a ring
+// of four iterations; every consumer adds a product's partials in band order
+// (wave_part_sum), so results do not depend on the order in which blocks
+// ran.  The arrays live in one allocation of bicg_parts_words(nb) doubles.
 struct BicgState {
   int done;       // 1 once converged (or broken down)
   int it_done;    // iteration at which the test passed
   int breakdown;  // rho = 0, omega = 0 or a non-finite scalar
-  int pad;
+  int nb;         // partial slots per inner product
   double tol2;    // rtol^2
-  double bb_sl[kSlots];      // ||b||^2
-  double rho[4 * kSlots];    // (rhat, r_it)
-  double rr[4 * kSlots];     // (r_it, r_it)
-  double rv[4 * kSlots];     // (rhat, v_it)
-  double ts[4 * kSlots];     // (t_it, s_it)
-  double tt[4 * kSlots];     // (t_it, t_it)
+  double* bb_sl;  // [nb] ||b||^2
+  double* rho;    // [4][nb] (rhat, r_it)
+  double* rr;     // [4][nb] (r_it, r_it)
+  double* rv;     // [4][nb] (rhat, v_it)
+  double* ts;     // [4][nb] (t_it, s_it)
+  double* tt;     // [4][nb] (t_it, t_it)
 };
+inline size_t bicg_parts_words(int nb) { return static_cast<size_t>(21) * nb; }
+inline void bicg_bind_parts(BicgState* st, double* parts, int nb) {
+  st->nb = nb;
+  st->bb_sl = parts;
+  st->rho = parts + nb;
+  st->rr = parts + 5 * static_cast<size_t>(nb);
+  st->rv = parts + 9 * static_cast<size_t>(nb);
+  st->ts = parts + 13 * static_cast<size_t>(nb);
+  st->tt = parts + 17 * static_cast<size_t>(nb);
+}
 
 // Vectors of one solve (N values each, device).
 struct BicgBufs {

@@ -42,7 +42,8 @@ __device__ inline void rb_block_sum(double (&v)[NV]) {
   }
 }
 
-__device__ inline int slot_of(int it) { return (it & 3) * kSlots; }
+// First slot of iteration it's partials in a ring of four.
+__device__ inline int slot_of(const BicgState* st, int it) { return (it & 3) * st->nb; }
 
 // Neighbour k of cell (x, y, z) in the stencil's order (-x, +x, -y, +y, -z,
 // +z); a missing neighbour maps to the cell itself (its coefficient is 0).
@@ -62,12 +63,15 @@ struct Nbrs {
   }
 };
 
+// Scalars of a new solve (every producer overwrites the partial slots of
+// all bands, so they need no clearing).
 __global__ void k_bicg_reset(BicgState* st, double tol2) {
-  double* w = reinterpret_cast<double*>(st);
-  const int n = static_cast<int>(sizeof(BicgState) / sizeof(double));
-  for (int k = threadIdx.x; k < n; k += blockDim.x) w[k] = 0.0;
-  __syncthreads();
-  if (threadIdx.x == 0) st->tol2 = tol2;
+  if (threadIdx.x == 0) {
+    st->done = 0;
+    st->it_done = 0;
+    st->breakdown = 0;
+    st->tol2 = tol2;
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void k_bicg_start(Dims d, const double* __restrict__ b,
@@ -87,10 +91,10 @@ __global__ __launch_bounds__(kThreads) void k_bicg_start(Dims d, const double* _
   }
   rb_block_sum<1>(s);
   if (rb_tid() == 0) {
-    const int sl = rb_bid() & (kSlots - 1);
-    atomicAdd(&st->bb_sl[sl], s[0]);
-    atomicAdd(&st->rho[slot_of(0) + sl], s[0]);
-    atomicAdd(&st->rr[slot_of(0) + sl], s[0]);
+    const int b = rb_bid();  // the block's band
+    st->bb_sl[b] = s[0];
+    st->rho[slot_of(st, 0) + b] = s[0];
+    st->rr[slot_of(st, 0) + b] = s[0];
   }
 }
 
@@ -129,18 +133,18 @@ __global__ __launch_bounds__(kThreads) void k_bicg_pv(Dims d, double sigma, cons
     int stop = *(volatile int*)&st->done;
     double beta = 0.0, om = 0.0;
     if (!stop) {
-      const double rr = wave_slot_sum(st->rr + slot_of(it));
-      const double bb = wave_slot_sum(st->bb_sl);
+      const double rr = wave_part_sum(st->rr + slot_of(st, it), st->nb);
+      const double bb = wave_part_sum(st->bb_sl, st->nb);
       bool bad = !isfinite(rr);
       if (!bad && rr <= st->tol2 * bb) {
         stop = 1;
         if (rb_bid() == 0 && t == 0) { st->it_done = it; st->done = 1; }
       } else if (!bad && it > 0) {
-        const double rho = wave_slot_sum(st->rho + slot_of(it));
-        const double rho_p = wave_slot_sum(st->rho + slot_of(it - 1));
-        const double rv_p = wave_slot_sum(st->rv + slot_of(it - 1));
-        const double ts_p = wave_slot_sum(st->ts + slot_of(it - 1));
-        const double tt_p = wave_slot_sum(st->tt + slot_of(it - 1));
+        const double rho = wave_part_sum(st->rho + slot_of(st, it), st->nb);
+        const double rho_p = wave_part_sum(st->rho + slot_of(st, it - 1), st->nb);
+        const double rv_p = wave_part_sum(st->rv + slot_of(st, it - 1), st->nb);
+        const double ts_p = wave_part_sum(st->ts + slot_of(st, it - 1), st->nb);
+        const double tt_p = wave_part_sum(st->tt + slot_of(st, it - 1), st->nb);
         const double alpha_p = rho_p / rv_p;
         om = tt_p > 0.0 ? ts_p / tt_p : 0.0;
         beta = (rho / rho_p) * (alpha_p / om);
@@ -152,10 +156,7 @@ __global__ __launch_bounds__(kThreads) void k_bicg_pv(Dims d, double sigma, cons
       }
     }
     if (t == 0) { stop_sh = stop; beta_sh = beta; om_sh = om; }
-    if (!stop && rb_bid() == 0) {
-      st->rho[slot_of(it + 1) + t] = 0.0;
-      st->rr[slot_of(it + 1) + t] = 0.0;
-    }
+
   }
   __syncthreads();
   if (stop_sh) return;
@@ -174,7 +175,7 @@ __global__ __launch_bounds__(kThreads) void k_bicg_pv(Dims d, double sigma, cons
     s[0] = rh * v;
   }
   rb_block_sum<1>(s);
-  if (t == 0) atomicAdd(&st->rv[slot_of(it) + (rb_bid() & (kSlots - 1))], s[0]);
+  if (t == 0) st->rv[slot_of(st, it) + rb_bid()] = s[0];
 }
 
 // K2: alpha, s = r - alpha v, t = A z, (t, s), (t, t).
@@ -208,14 +209,14 @@ __global__ __launch_bounds__(kThreads) void k_bicg_st(Dims d, double sigma, cons
     int stop = *(volatile int*)&st->done;
     double alpha = 0.0;
     if (!stop) {
-      alpha = wave_slot_sum(st->rho + slot_of(it)) / wave_slot_sum(st->rv + slot_of(it));
+      alpha = wave_part_sum(st->rho + slot_of(st, it), st->nb) / wave_part_sum(st->rv + slot_of(st, it), st->nb);
       if (!isfinite(alpha)) {
         stop = 1;
         if (rb_bid() == 0 && t == 0) { st->breakdown = 1; st->it_done = it; st->done = 1; }
       }
     }
     if (t == 0) { stop_sh = stop; alpha_sh = alpha; }
-    if (!stop && rb_bid() == 0) st->rv[slot_of(it + 1) + t] = 0.0;
+
   }
   __syncthreads();
   if (stop_sh) return;
@@ -233,9 +234,9 @@ __global__ __launch_bounds__(kThreads) void k_bicg_st(Dims d, double sigma, cons
   }
   rb_block_sum<2>(s);
   if (t == 0) {
-    const int sl = rb_bid() & (kSlots - 1);
-    atomicAdd(&st->ts[slot_of(it) + sl], s[0]);
-    atomicAdd(&st->tt[slot_of(it) + sl], s[1]);
+    const int b = rb_bid();
+    st->ts[slot_of(st, it) + b] = s[0];
+    st->tt[slot_of(st, it) + b] = s[1];
   }
 }
 
@@ -261,13 +262,10 @@ __global__ __launch_bounds__(kThreads) void k_bicg_xr(Dims d, double sigma, cons
     const int stop = *(volatile int*)&st->done;
     double alpha = 0.0, om = 0.0;
     if (!stop) {
-      alpha = wave_slot_sum(st->rho + slot_of(it)) / wave_slot_sum(st->rv + slot_of(it));
-      const double tt = wave_slot_sum(st->tt + slot_of(it));
-      om = tt > 0.0 ? wave_slot_sum(st->ts + slot_of(it)) / tt : 0.0;
-      if (rb_bid() == 0) {
-        st->ts[slot_of(it + 1) + t] = 0.0;
-        st->tt[slot_of(it + 1) + t] = 0.0;
-      }
+      alpha = wave_part_sum(st->rho + slot_of(st, it), st->nb) / wave_part_sum(st->rv + slot_of(st, it), st->nb);
+      const double tt = wave_part_sum(st->tt + slot_of(st, it), st->nb);
+      om = tt > 0.0 ? wave_part_sum(st->ts + slot_of(st, it), st->nb) / tt : 0.0;
+
     }
     if (t == 0) { stop_sh = stop; alpha_sh = alpha; om_sh = om; }
   }
@@ -284,9 +282,9 @@ __global__ __launch_bounds__(kThreads) void k_bicg_xr(Dims d, double sigma, cons
   }
   rb_block_sum<2>(s);
   if (t == 0) {
-    const int sl = rb_bid() & (kSlots - 1);
-    atomicAdd(&st->rho[slot_of(it + 1) + sl], s[0]);
-    atomicAdd(&st->rr[slot_of(it + 1) + sl], s[1]);
+    const int b = rb_bid();
+    st->rho[slot_of(st, it + 1) + b] = s[0];
+    st->rr[slot_of(st, it + 1) + b] = s[1];
   }
 }
 

@@ -145,6 +145,27 @@ def test_adjoint_rejects_bad_arguments(torch_mod):
         ctx.coupled_step(p.h, T.clone(), opts=make_opts(method=1))
 
 
+def test_adjoint_gradient_is_bitwise_reproducible(torch_mod):
+    """A 128 x 96 coupled run (many blocks per inner product in the forward
+    and adjoint pressure solves) and its gradient, twice in fresh contexts:
+    the same bits."""
+    torch = torch_mod
+    from paper_1209_5553_amd.adjoint import coupled_run
+    p = _small(128, 96, seed=11)
+    dev = "cuda:0"
+    c = torch.as_tensor(np.cos(np.arange(p.nx * p.ny) * 0.37), dtype=torch.float64, device=dev)
+    grads = []
+    for _ in range(2):
+        ctx = _ctx(torch, p)
+        T0 = torch.as_tensor(np.linspace(20.0, 70.0, p.nx * p.ny), dtype=torch.float64, device=dev)
+        T0.requires_grad_(True)
+        lk = torch.as_tensor(p.logk, dtype=torch.float64, device=dev).requires_grad_(True)
+        (coupled_run(ctx, T0, lk, p.h, 2) * c).sum().backward()
+        torch.cuda.synchronize()
+        grads.append((T0.grad.clone(), lk.grad.clone()))
+    assert torch.equal(grads[0][0], grads[1][0]) and torch.equal(grads[0][1], grads[1][1])
+
+
 def _workload_fd_check(torch, p, label):
     from paper_1209_5553_amd.adjoint import coupled_run, run_with_tapes
     N = p.nx * p.ny

@@ -357,6 +357,26 @@ def test_coupled_steps_match_oracle(torch_mod):
     assert err <= TOL
 
 
+def test_coupled_steps_with_extrapolated_pressure_start_match_oracle(torch_mod):
+    """The same sequential steps with each pressure solve started from the
+    linear extrapolation of the last two pressures (warm = 2): the solve
+    reaches the same tolerance, so the steps match the oracle as before."""
+    torch = torch_mod
+    prob = inputs.coupled_problem(48, seed=2, nsteps=4)
+    ctx = _ctx(prob)
+    T = _dev(torch, prob.T0)
+    p = torch.zeros(prob.n, dtype=torch.float64, device="cuda:0")
+    its = []
+    for n in range(prob.nsteps):
+        st = ctx.pressure_and_fluxes(T, rtol=1e-16, p=p if n == 0 else None, warm=2 if n > 0 else 0)
+        its.append(st["iterations"])
+        ctx.step(prob.h, T)
+    T_ref = oerem.run_coupled(prob)
+    err = rel_inf(T.cpu().numpy() - prob.T0, T_ref - prob.T0)
+    _say(f"coupled 48x48 x 4, extrapolated pressure starts: CG iterations {its}, increment err {err:.2e}")
+    assert err <= TOL
+
+
 def test_coupled_512_one_step_full_size(torch_mod):
     """The 512x512 coupled workload at full size: one step against the
     sparse (tier B) oracle."""
@@ -552,3 +572,28 @@ def test_step_is_deterministic(torch_mod):
     a, _ = _run_gpu_linear(torch, prob, 2)
     b, _ = _run_gpu_linear(torch, prob, 2)
     assert np.array_equal(a, b)
+
+
+def test_coupled_512_steps_are_bitwise_reproducible(torch_mod):
+    """Three steps of the 512x512 coupled workload (multigrid-preconditioned
+    CG pressure with warm starts, assembly, Leja step), run twice in fresh
+    contexts: every inner product is summed from per-band partials in a
+    fixed order, so the two runs agree bit for bit (with 1024 blocks,
+    atomically accumulated sums would not)."""
+    torch = torch_mod
+    prob = inputs.coupled_problem(512)
+    runs = []
+    for r in range(2):
+        ctx = _ctx(prob)
+        T = _dev(torch, prob.T0)
+        p = torch.zeros(prob.n, dtype=torch.float64, device="cuda:0")
+        iters = []
+        for n in range(3):
+            st = ctx.pressure_and_fluxes(T, rtol=1e-16, p=p if n == 0 else None, warm=n > 0)
+            iters.append(st["iterations"])
+            ctx.step(prob.h, T)
+        torch.cuda.synchronize()
+        runs.append((T.clone(), ctx.get_faces()["fx"].clone()))
+        _say(f"coupled 512 run {r}: CG iterations {iters}")
+    assert torch.equal(runs[0][0], runs[1][0])
+    assert torch.equal(runs[0][1], runs[1][1])

@@ -144,6 +144,22 @@ def test_full_size_coupled_512_ros2_and_theta(torch_mod):
         assert err <= TOL
 
 
+def test_ros2_512_step_is_bitwise_reproducible(torch_mod):
+    """The BiCGSTAB inner products are summed from per-band partials in a
+    fixed order: a ROS2(1) step of the 512 x 512 coupled problem (fluxes of
+    the pressure at T0), run twice in fresh contexts, gives the same bits."""
+    torch = torch_mod
+    prob = inputs.coupled_problem(512)
+    out = []
+    for _ in range(2):
+        ctx, T = _ctx(torch, prob)
+        st = ctx.step_rosenbrock(prob.h, T, "ros2")
+        torch.cuda.synchronize()
+        out.append(T.clone())
+    _say(f"ROS2 512^2 twice: {st}")
+    assert torch.equal(out[0], out[1])
+
+
 def test_bad_arguments_are_rejected(torch_mod):
     torch = torch_mod
     from paper_1209_5553_amd.api import EremError
