@@ -59,7 +59,8 @@ struct erem_ctx {
   float *coef32 = nullptr, *qa32 = nullptr, *qb32 = nullptr, *p32 = nullptr;
   bool coef32_valid = false;
   // Krylov basis (m+1 vectors), work vector, Hessenberg matrix, norm, coefficients
-  double *kV = nullptr, *kw = nullptr, *kH = nullptr, *kbeta = nullptr, *kc = nullptr;
+  double *kV = nullptr, *kw = nullptr, *kH = nullptr, *kbeta = nullptr, *kc = nullptr, *kg = nullptr,
+         *kpart = nullptr;
   int kry_m = 0;
   std::vector<double> hH;
   size_t nfx = 0, nfy = 0, nfz = 0;

@@ -100,7 +100,7 @@ void free_all(erem_ctx* c) {
   float** fbufs[] = {&c->coef32, &c->qa32, &c->qb32, &c->p32};
   for (float** b : fbufs)
     if (*b) { (void)hipFree(*b); *b = nullptr; }
-  double** kbufs[] = {&c->kV, &c->kw, &c->kH, &c->kbeta, &c->kc};
+  double** kbufs[] = {&c->kV, &c->kw, &c->kH, &c->kbeta, &c->kc, &c->kg, &c->kpart};
   for (double** b : kbufs)
     if (*b) { (void)hipFree(*b); *b = nullptr; }
   double** abufs[] = {&c->adj_q, &c->adj_u, &c->adj_seg, &c->adj_block};
@@ -492,7 +492,8 @@ int leja_hphi1(erem_ctx* c, double h, const double* v, const double* g, double s
 
 // u <- h phi1(h J) v by the Krylov projection of Sec. 4.1 (Eq. approphi):
 // on each substep the Arnoldi basis V_{m+1}, H of w = v + J u is built on the
-// device (Alg. alg:al2), and on the host y = phi1(delta Hbar) e_1 with
+// device (Alg. alg:al2, with classical Gram-Schmidt applied twice), and on
+// the host y = phi1(delta Hbar) e_1 with
 // Hbar = [[H_m, 0], [h_{m+1,m} e_m^T, 0]] is read off
 // exp([[delta Hbar, e_1], [0, 0]]).  The a-posteriori estimate is the size of
 // the last basis vector's contribution, delta beta |y_{m+1}| (scaled norm of
@@ -503,15 +504,17 @@ int krylov_hphi1(erem_ctx* c, double h, const double* v, double scal, const erem
   if (m < 1 || m > kMaxKrylov) return fail(c, EREM_EINVAL, "krylov_m must be in [1, 64]");
   const size_t N = c->d.N;
   if (c->kry_m < m) {
-    double** kbufs[] = {&c->kV, &c->kw, &c->kH, &c->kbeta, &c->kc};
+    double** kbufs[] = {&c->kV, &c->kw, &c->kH, &c->kbeta, &c->kc, &c->kg, &c->kpart};
     for (double** b : kbufs)
       if (*b) { (void)hipFree(*b); *b = nullptr; }
     int rc = EREM_OK;
     rc |= dev_alloc(c, &c->kV, N * (m + 1));
-    rc |= dev_alloc(c, &c->kw, N);
+    rc |= dev_alloc(c, &c->kw, 2 * N);
     rc |= dev_alloc(c, &c->kH, static_cast<size_t>(m + 1) * m);
     rc |= dev_alloc(c, &c->kbeta, 1);
     rc |= dev_alloc(c, &c->kc, m + 1);
+    rc |= dev_alloc(c, &c->kg, m + 1);
+    rc |= dev_alloc(c, &c->kpart, static_cast<size_t>(m + 1) * kry_num_blocks(c->d));
     if (rc) return EREM_ENOMEM;
     c->kry_m = m;
   }
@@ -527,10 +530,10 @@ int krylov_hphi1(erem_ctx* c, double h, const double* v, double scal, const erem
   while (t < h) {
     if (nsub >= o->max_substeps)
       return fail(c, EREM_ENOCONV, "Krylov phi1 needs more than max_substeps substeps");
-    // w = v + J u (u = 0 on the first substep) into V[0]
-    if (first) HIP_TRY(c, hipMemcpyAsync(c->kV, v, N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
-    else HIP_TRY(c, launch_stencil_axpy(d, c->coef, v, c->u, c->kV, c->stream));
-    HIP_TRY(c, arnoldi_mgs(d, c->coef, c->kV, c->kw, c->kH, c->kbeta, c->part, m, c->stream));
+    // start vector v + J u (u = 0 on the first substep) into the first half of kw
+    if (first) HIP_TRY(c, hipMemcpyAsync(c->kw, v, N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    else HIP_TRY(c, launch_stencil_axpy(d, c->coef, v, c->u, c->kw, c->stream));
+    HIP_TRY(c, arnoldi_cgs2(d, c->coef, c->kV, c->kw, c->kH, c->kbeta, c->kg, c->kpart, m, c->stream));
     HIP_TRY(c, hipMemcpyAsync(c->hH.data(), c->kH, sizeof(double) * (m + 1) * m, hipMemcpyDeviceToHost, c->stream));
     double beta = 0.0;
     HIP_TRY(c, hipMemcpyAsync(&beta, c->kbeta, sizeof(double), hipMemcpyDeviceToHost, c->stream));

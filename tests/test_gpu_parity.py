@@ -460,6 +460,49 @@ def test_krylov_and_leja_agree_on_coupled_step(torch_mod):
     assert rel_inf(res[1] - prob.T0, res[0] - prob.T0) <= TOL
 
 
+def test_krylov_ragged_grid_matches_taylor_oracle_and_repeats_bitwise(torch_mod):
+    """Arnoldi across many 64 x 4 cell bands with ragged edges (200 x 70,
+    m = 30): phi1(hJ) v against the oracle's sparse Taylor action (tier B),
+    and a second evaluation is bit-for-bit the first (every inner product is
+    reduced in a fixed order)."""
+    torch = torch_mod
+    nx, ny = 200, 70
+    rng = np.random.default_rng(77)
+    logk = np.log(1e-12) + 0.8 * rng.standard_normal(nx * ny)
+    prob = inputs.Problem(name="krylov200x70", nx=nx, ny=ny, nz=1, logk=logk,
+                          poro=np.full(nx * ny, 0.2), T0=np.full(nx * ny, 20.0), nsteps=1)
+    disc = oerem.Discretisation(prob, prob.T0)
+    ctx = _ctx(prob)
+    ctx.set_face_fluxes(*_oracle_fluxes_to_dev(torch, disc))
+    ctx.form_jacobian(_dev(torch, prob.T0))
+    v = rng.standard_normal(prob.n)
+    outs = []
+    for _ in range(2):
+        out, st = ctx.phi1_apply(prob.h, _dev(torch, v), opts=_krylov_opts(30))
+        outs.append(out.cpu().numpy())
+    ref = ophi.hphi1_action_taylor(disc.model.J_sparse(prob.T0), v, prob.h) / prob.h
+    err = rel_inf(outs[0], ref)
+    _say(f"krylov 200x70 m=30: arnoldi steps={st['m_total']} substeps={st['substeps']} err={err:.2e}")
+    assert err <= TOL
+    assert np.array_equal(outs[0], outs[1])
+
+
+def test_krylov_3d_matches_dense_oracle(torch_mod):
+    """The 7-point Arnoldi pass on a 10^3 layered grid against the dense
+    phi1 (tier A)."""
+    torch = torch_mod
+    prob = inputs.layered3d_problem(10, seed=5)
+    disc = oerem.Discretisation(prob, prob.T0)
+    ctx = _ctx(prob)
+    ctx.set_face_fluxes(*_oracle_fluxes_to_dev(torch, disc))
+    ctx.form_jacobian(_dev(torch, prob.T0))
+    v = np.random.default_rng(12).standard_normal(prob.n)
+    out, st = ctx.phi1_apply(prob.h, _dev(torch, v), opts=_krylov_opts(20))
+    err = rel_inf(out.cpu().numpy(), ophi.phi1_action_dense(disc.model.J(prob.T0), v, prob.h))
+    _say(f"krylov 10^3 m=20: arnoldi steps={st['m_total']} substeps={st['substeps']} err={err:.2e}")
+    assert err <= TOL
+
+
 # ------------------------------------------------------- mixed precision
 
 MIXED_TOL = 1e-5
