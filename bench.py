@@ -304,8 +304,13 @@ def bench_batch(args, mixed):
     opts = make_opts(m_max=128, precision=1, tol_r=1e-7) if mixed else make_opts(m_max=128)
     b.prepare(probs[0].h, opts)
     T0 = b.pack([p.T0 for p in probs])
-    shape = b.autotune(T0, nsteps=5)
-    log(f"batch: {nprob} problems, {b.ntot} cells, autotuned tile shape {shape}")
+    if args.tile_shape is None:
+        shape = b.autotune(T0, nsteps=5)
+    else:
+        shape = args.tile_shape
+        b.set_tile_shape(shape)
+    log(f"batch: {nprob} problems, {b.ntot} cells, "
+        f"{'autotuned' if args.tile_shape is None else 'requested'} tile shape {shape}")
     T = T0.clone()
     for _ in range(max(1, args.warmup)):
         T.copy_(T0)
@@ -329,7 +334,7 @@ def bench_batch(args, mixed):
     avg_work_s = prof["work_ms"] * 1e-3 / max(prof["work_timed"], 1)
     byts = prof["leja_bytes"]
     kname = "k_bt_work"
-    tr = _traffic("batch256", args.precision, kname)
+    tr = _traffic("batch256", args.precision, f"{kname}/shape{shape}")   # counters are per tile shape
     roof = roofline_entry(kname, byts / passes, avg_work_s, int(passes),
                           traffic=None if tr is None else tr / passes,
                           working_set=(36 if mixed else 72) * b.ntot)
@@ -348,7 +353,8 @@ def bench_batch(args, mixed):
         "config": {"workload": desc, "cells": int(b.ntot), "problems": nprob, "steps_per_run": nst,
                    "step_unit": f"one EREM step of all realisations (timed: {len(runs)} graph runs + 1 "
                                 f"profiled run, x {nst} steps)",
-                   "tile_shape": shape, "tol_r": 1e-7 if mixed else 1e-12, "precision": args.precision,
+                   "tile_shape": shape, "tile_shape_from": "autotune" if args.tile_shape is None else "--tile-shape",
+                   "tol_r": 1e-7 if mixed else 1e-12, "precision": args.precision,
                    "m_max": 128},
         "roofline": roof,
         "leja_terms_per_run": prof["terms_total"],
@@ -363,14 +369,21 @@ def bench_batch(args, mixed):
     return line
 
 
+CPU_SAMPLE_CELLS = 2_400_000   # about 10-15 s of one host core for the oracle's sparse action
+
+
 def batch_cpu_baseline(probs, b, T0):
-    """Oracle (tier-B action), one step of the first four realisations, scaled
-    to one step of the whole batch by cell count; agreement of the GPU's
-    one-step batch on those realisations."""
+    """Oracle (tier-B action), one step of the leading realisations up to
+    CPU_SAMPLE_CELLS cells, scaled to one step of the whole batch by cell
+    count; agreement of the GPU's one-step batch on those realisations."""
     from threadpoolctl import threadpool_limits
 
     from oracle import erem as oerem
-    sample = probs[:4]
+    k, cells = 0, 0
+    while k < len(probs) and cells < CPU_SAMPLE_CELLS:
+        cells += probs[k].n
+        k += 1
+    sample = probs[:k]
     T1 = T0.clone()
     b.run(T1, 1, use_graph=False)
     got = b.unpack(T1)
@@ -387,7 +400,7 @@ def batch_cpu_baseline(probs, b, T0):
     cells_all = sum(p.n for p in probs)
     per_batch_step = (t1 - t0) * cells_all / cells_sample
     return {"value": 1.0 / per_batch_step, "unit": "steps/s", "cores": 1, "kind": "oracle",
-            "sample": f"1 EREM step of realisations 0-3 ({cells_sample} cells, substepped Taylor action, "
+            "sample": f"1 EREM step of realisations 0-{k - 1} ({cells_sample} cells, substepped Taylor action, "
                       f"FP64, 1 thread), scaled by cell count to the {cells_all}-cell batch",
             "seconds": t1 - t0, "gpu_rel_err": max(terr), "gpu_increment_rel_err": max(errs), **cpu_info()}
 
@@ -489,6 +502,9 @@ TRAFFIC = {
     ("compressible50", "fp64", "leja_term"): 11.34e6,   # the 3D one-term kernel on 125 000 cells
     ("layered128", "mixed", "leja_term"): 93.30e6,      # FP32 one-term kernel, 44 B per cell algorithmic
     # batch256: whole-run totals of the work kernel (divided by its launches)
+    ("batch256", "fp64", "k_bt_work/shape5"): 257.33e9,   # one 50-step run
+    # layered256: a working launch (the z-neighbour planes are fetched again: 1.16x algorithmic)
+    ("layered256", "fp64", "leja_term"): 1714.26e6,
     # one BiCGSTAB iteration (three kernels) of the comparison schemes
     ("coupled512", "fp64", "bicg_iteration"): 65.23e6,
     # adjoint workload (256 x 256): V-cycle + CG iteration, reverse Newton term
@@ -587,6 +603,8 @@ def main():
                     choices=["batch256", "coupled512", "linear32", "layered128", "layered256", "injector512",
                              "compressible50", "adjoint256"])
     ap.add_argument("--no-ceiling", action="store_true", help="skip the copy / triad bandwidth measurement")
+    ap.add_argument("--tile-shape", type=int, default=None,
+                    help="batch256: use this tile shape (0-7) instead of autotuning (profiler runs)")
     ap.add_argument("--adjoint-start", default="uniform", choices=["uniform", "structured"])
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")

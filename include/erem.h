@@ -375,8 +375,8 @@ typedef struct {
     int32_t tile_shape;    /* 0: 64 x 8 tiles on 512 threads, 1: 64 x 16 on 1024 threads,
                               2: 64 x 8 on 512 threads, 3: 64 x 16 on 512, 4: 64 x 32 on
                               512, all with four Newton terms per pass; 5: 64 x 16 and
-                              6: 64 x 8 on 512 threads with eight terms per pass; each XCD
-                              takes a contiguous range of tiles in 2-6.  The stop test is
+                              6: 64 x 8 and 7: 64 x 32 on 512 threads with eight terms per
+                              pass; each XCD takes a contiguous range of tiles in 2-7.  The stop test is
                               evaluated term by term after each pass and all terms of the
                               pass are kept (the applied degree is the first multiple of
                               the pass width at which the test holds) */
@@ -411,7 +411,7 @@ int erem_batch_prepare(erem_batch* b, double h, const erem_opts* opts);
 /* Time every tile shape on a copy of d_T (nsteps steps) and keep the fastest;
  * *chosen receives its index.  d_T is not modified. */
 int erem_batch_autotune(erem_batch* b, const double* d_T, int32_t nsteps, int32_t* chosen);
-/* Select a tile shape by index (0 .. 6, see erem_batch_stats.tile_shape)
+/* Select a tile shape by index (0 .. 7, see erem_batch_stats.tile_shape)
  * instead of timing them.  EINVAL for another index. */
 int erem_batch_set_tile_shape(erem_batch* b, int32_t shape);
 /* Time every stride-th work launch of the following runs by the start and

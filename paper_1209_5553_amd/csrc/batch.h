@@ -10,12 +10,12 @@ namespace erem {
 
 // Tile shapes of the work kernel: 64 x kBatchTileRows[shape] cells on 64 x
 // kBatchThreadRows[shape] threads, kBatchPassTerms[shape] Newton terms per
-// pass; shapes 2-6 place the tiles so that each XCD takes a contiguous range
+// pass; shapes 2-7 place the tiles so that each XCD takes a contiguous range
 // of them.
-constexpr int kNumTileShapes = 7;
-constexpr int kBatchTileRows[kNumTileShapes] = {8, 16, 8, 16, 32, 16, 8};
-constexpr int kBatchThreadRows[kNumTileShapes] = {8, 16, 8, 8, 8, 8, 8};
-constexpr int kBatchPassTerms[kNumTileShapes] = {4, 4, 4, 4, 4, 8, 8};
+constexpr int kNumTileShapes = 8;
+constexpr int kBatchTileRows[kNumTileShapes] = {8, 16, 8, 16, 32, 16, 8, 32};
+constexpr int kBatchThreadRows[kNumTileShapes] = {8, 16, 8, 8, 8, 8, 8, 8};
+constexpr int kBatchPassTerms[kNumTileShapes] = {4, 4, 4, 4, 4, 8, 8, 8};
 constexpr int kBatchTileX = 64;
 constexpr int kBatchPartStride = 8;  // partials per tile (one per term of a pass)
 

@@ -466,6 +466,7 @@ hipError_t launch_work_shape(const BatchArgs& a, int shape, hipStream_t s, hipEv
     case 4: return launch_work<32, 8, 4, true, V>(a, s, e0, e1);
     case 5: return launch_work<16, 8, 8, true, V>(a, s, e0, e1);
     case 6: return launch_work<8, 8, 8, true, V>(a, s, e0, e1);
+    case 7: return launch_work<32, 8, 8, true, V>(a, s, e0, e1);
     default: return hipErrorInvalidValue;
   }
 }
