@@ -15,16 +15,17 @@
 //               substep, u += delta p, or of the previous step,
 //               T += u + delta p, folded in: a cell's neighbours' values are
 //               formed from their own u, p, T, so no extra pass is needed);
-//   term pass   four Newton terms q_k = ((J - cI)/gamma - xi_{k-1}) q_{k-1},
-//               p += d_k q_k (Eq. newt) on the tile, staged in LDS with the
-//               halo that four stencil applications need; the intermediate
-//               terms never leave the CU;
+//   term pass   NT = 4 or 8 Newton terms
+//               q_k = ((J - cI)/gamma - xi_{k-1}) q_{k-1}, p += d_k q_k
+//               (Eq. newt) on the tile, computed over the tile plus the halo
+//               that NT stencil applications need; the intermediate terms
+//               never leave the CU;
 //   finish pass T += u + delta p of the last step.
 //
 // Each tile stores its block partial sums (sum q_k^2 per term, in FP64); a
 // control kernel then reduces each problem's partials in a fixed order (one
 // wavefront per problem), applies the scaled-norm stop test of Sec. 4.2 to
-// the group's four estimates in order, and sets the problem's next phase.
+// the pass's NT estimates in order, and sets the problem's next phase.
 // Problems of every size and substep count thus share every launch, the
 // work spreads over all CUs whatever the mix, and the whole run is a fixed
 // sequence of launches with no grid-wide synchronisation and no waiting
@@ -43,10 +44,13 @@ namespace {
 template <class V>
 __device__ inline V cv(double x) { return static_cast<V>(x); }
 
+// q_{k-1} with a halo of NT, and one intermediate-term buffer (halo NT - 1);
+// the other intermediate buffer reuses the space of q_{k-1} once the first
+// term has read it.
 template <int TY, int NT, class V>
 constexpr size_t work_lds_bytes() {
   return sizeof(V) * (static_cast<size_t>(TY + 2 * NT) * (kBatchTileX + 2 * NT) +
-                      2 * static_cast<size_t>(TY + 2 * NT - 2) * (kBatchTileX + 2 * NT - 2));
+                      static_cast<size_t>(TY + 2 * NT - 2) * (kBatchTileX + 2 * NT - 2));
 }
 
 // Sum (or max) over the workgroup of one double per thread; fixed order
@@ -80,8 +84,10 @@ __global__ __launch_bounds__(kBatchTileX* BY) void k_bt_work(BatchArgs a) {
   constexpr int WQ = kBatchTileX + 2 * NT, HQ = TY + 2 * NT;  // q_{k-1}: halo NT
   constexpr int WI = kBatchTileX + 2 * H, HI = TY + 2 * H;    // stencil, intermediates: halo NT - 1
   extern __shared__ __align__(16) unsigned char smem[];
-  V(*sq)[WQ] = reinterpret_cast<V(*)[WQ]>(smem);                           // q_{k-1}
-  V(*sb)[HI][WI] = reinterpret_cast<V(*)[HI][WI]>(smem + sizeof(V) * HQ * WQ);  // intermediate terms
+  V(*sq)[WQ] = reinterpret_cast<V(*)[WQ]>(smem);  // q_{k-1}
+  // intermediate terms: even terms write sb_even, odd terms write over q_{k-1}
+  V(*sb_even)[WI] = reinterpret_cast<V(*)[WI]>(smem + sizeof(V) * HQ * WQ);
+  V(*sb_odd)[WI] = reinterpret_cast<V(*)[WI]>(smem);
   __shared__ double red[NT][NW];
 
   const int t = XCD ? xcd_tile_id() : static_cast<int>(blockIdx.x);
@@ -225,16 +231,13 @@ __global__ __launch_bounds__(kBatchTileX* BY) void k_bt_work(BatchArgs a) {
   const V ig = cv<V>(P.inv_g);
   const double* shf = a.shift + P.coef_off + S.k;
   const double* dkp = a.dk + P.coef_off + S.k;
-  double sums[NT];
-#pragma unroll
-  for (int tt = 0; tt < NT; ++tt) sums[tt] = 0.0;
-  V last[UC];
 #pragma unroll
   for (int tt = 0; tt < NT; ++tt) {
     const V sh = cv<V>(shf[tt]);
     const V dkt = cv<V>(dkp[tt]);
-    V(*out)[WI] = sb[tt & 1];
-    const V(*prev)[WI] = sb[(tt - 1) & 1];
+    V(*out)[WI] = (tt & 1) ? sb_odd : sb_even;
+    const V(*prev)[WI] = (tt & 1) ? sb_even : sb_odd;
+    double sum = 0.0;  // this thread's share of sum q_k^2 over the tile
 #pragma unroll
     for (int u = 0; u < UC; ++u) {
       const int iy = by[u], ix = bx[u];
@@ -263,26 +266,20 @@ __global__ __launch_bounds__(kBatchTileX* BY) void k_bt_work(BatchArgs a) {
         if (tt + 1 < NT) out[iy][ix] = qo;
         if (tile_cell[u]) {
           acc[u] += dkt * qo;
-          sums[tt] += static_cast<double>(qo) * static_cast<double>(qo);
-          last[u] = qo;
+          sum += static_cast<double>(qo) * static_cast<double>(qo);
+          if (tt + 1 == NT) {
+            // the last term: p and q_k of the tile go straight out
+            const long long j = o + (x0 - H + ix) + static_cast<long long>(nx) * (y0 - H + iy);
+            p[j] = acc[u];
+            qout[j] = qo;
+          }
         }
       }
     }
+    // the wavefront's share of the term's norm, to LDS in wavefront order
+    for (int off = 32; off > 0; off >>= 1) sum += __shfl_down(sum, off, 64);
+    if ((tid & 63) == 0) red[tt][tid >> 6] = sum;
     if (tt + 1 < NT) __syncthreads();
-  }
-#pragma unroll
-  for (int u = 0; u < UC; ++u) {
-    if (tile_cell[u]) {
-      const long long j = o + (x0 - H + bx[u]) + static_cast<long long>(nx) * (y0 - H + by[u]);
-      p[j] = acc[u];
-      qout[j] = last[u];
-    }
-  }
-#pragma unroll
-  for (int tt = 0; tt < NT; ++tt) {
-    double v = sums[tt];
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
-    if ((tid & 63) == 0) red[tt][tid >> 6] = v;
   }
   __syncthreads();
   if (tid < NT) {
@@ -476,7 +473,7 @@ hipError_t launch_work_shape(const BatchArgs& a, int shape, hipStream_t s, hipEv
 size_t batch_lds_bytes(int shape, int fp32) {
   const size_t vb = fp32 ? sizeof(float) : sizeof(double);
   const size_t rows = kBatchTileRows[shape], nt = kBatchPassTerms[shape];
-  return vb * ((rows + 2 * nt) * (kBatchTileX + 2 * nt) + 2 * (rows + 2 * nt - 2) * (kBatchTileX + 2 * nt - 2));
+  return vb * ((rows + 2 * nt) * (kBatchTileX + 2 * nt) + (rows + 2 * nt - 2) * (kBatchTileX + 2 * nt - 2));
 }
 
 hipError_t batch_pack(int nx, int ny, const double* coef, const double* F, const double* T0, double* bcoef,
