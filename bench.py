@@ -495,7 +495,7 @@ def bench_adjoint(args):
 # describe the kernels as measured: reset an entry to None when its kernel
 # changes.
 TRAFFIC = {
-    ("coupled512", "fp64", "mg_vcycle"): 53.22e6,
+    ("coupled512", "fp64", "mg_vcycle"): 57.55e6,
     ("coupled512", "fp64", "leja_term"): 6.15e6,     # a working 4-term launch moves 24.60 MB
     ("injector512", "fp64", "leja_term"): 6.15e6,    # the same kernel on the same grid: 24.60 MB
     ("layered128", "fp64", "leja_term"): 186.49e6,
@@ -508,9 +508,9 @@ TRAFFIC = {
     ("layered256", "fp64", "leja_term"): 1714.26e6,
     ("layered256", "mixed", "leja_term"): 742.57e6,    # FP32: exactly its algorithmic bytes
     # one BiCGSTAB iteration (three kernels) of the comparison schemes
-    ("coupled512", "fp64", "bicg_iteration"): 65.23e6,
+    ("coupled512", "fp64", "bicg_iteration"): 66.55e6,
     # adjoint workload (256 x 256): V-cycle + CG iteration, reverse Newton term
-    ("adjoint256", "fp64", "mg_vcycle"): 15.55e6,
+    ("adjoint256", "fp64", "mg_vcycle"): 15.69e6,
     ("adjoint256", "fp64", "adj_rev_term"): 11.10e6,
 }
 
