@@ -86,7 +86,11 @@ struct erem_ctx {
   int last_m = 0;          // largest substep degree of the previous evaluation
   int last_m_p = 0;        // the same for the transient pressure (its own degree)
   // profiling (HIP events around each Leja term and PCG half-iteration)
-  int pcg_last = 0;  // iterations of the last converged CG solve (poll placement)
+  // iterations of the last converged CG solve (poll placement), per kind of
+  // solve (0: pressure, 1: other SPD right-hand sides) and refinement
+  // correction (the first correction of a solve takes many more iterations
+  // than the later ones)
+  int pcg_last[2][4] = {};
   int prof = 0;  // per-launch event timing: 0 off, n > 0 one launch in n
   std::vector<hipEvent_t> ev;
   hipEvent_t ev_setup = nullptr;  // the first residual readback of a pressure solve

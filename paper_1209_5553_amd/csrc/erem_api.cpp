@@ -686,7 +686,7 @@ double inner_tolerance(double relres, double rtol) {
   return std::min(1e-2, std::max(1e-12, want));
 }
 
-int pcg_inner(erem_ctx* c, double inner_tol, int budget, int* iters, bool* done) {
+int pcg_inner(erem_ctx* c, double inner_tol, int budget, int* iters, bool* done, int* last) {
   const Dims& d = c->d;
   HIP_TRY(c, launch_pcg_reset(c->pcg, inner_tol * inner_tol, c->stream));
   const int jac = c->use_mg ? 0 : 1;
@@ -703,9 +703,10 @@ int pcg_inner(erem_ctx* c, double inner_tol, int budget, int* iters, bool* done)
   }
   // Iterations after convergence still launch (their kernels return at
   // entry), so the host polls where the solve is expected to end: with
-  // multigrid the first poll follows the previous solve's count plus the
-  // test iteration (at most 24), then every two iterations.
-  const int first_chunk = c->use_mg ? (c->pcg_last > 0 ? std::min(c->pcg_last + 1, 24) : 8) : 64;
+  // multigrid the first poll follows the count of the previous solve of the
+  // same kind and correction (*last) plus the test iteration (at most 24),
+  // then every two iterations.
+  const int first_chunk = c->use_mg ? (*last > 0 ? std::min(*last + 1, 24) : 8) : 64;
   const int chunk = c->use_mg ? 2 : 64;
   int it = 0;
   *done = false;
@@ -765,7 +766,7 @@ int pcg_inner(erem_ctx* c, double inner_tol, int budget, int* iters, bool* done)
     if (fin) { *done = true; it = c->h_pcg->it_done; break; }
   }
   *iters = it;
-  if (*done) c->pcg_last = it;
+  if (*done) *last = it;
   return EREM_OK;
 }
 
@@ -802,7 +803,8 @@ int spd_solve(erem_ctx* c, const double* b, double* x, double rtol, int max_iter
     int it = 0;
     bool done = false;
     const double relres = std::sqrt(rr / bb);
-    const int rc = pcg_inner(c, inner_tolerance(relres, rtol), max_iter - total, &it, &done);
+    const int rc = pcg_inner(c, inner_tolerance(relres, rtol), max_iter - total, &it, &done,
+                             &c->pcg_last[1][std::min(outer, 3)]);
     if (rc) return rc;
     total += it;
     HIP_TRY(c, launch_axpby(d, x, 1.0, c->pdelta, 1.0, c->stream));
@@ -1075,7 +1077,8 @@ int erem_solve_pressure(erem_ctx* c, double rtol, int32_t max_iter, int32_t warm
     int it = 0;
     bool done = false;
     {
-      const int rc = pcg_inner(c, inner_tolerance(relres, rtol), max_iter - total, &it, &done);
+      const int rc = pcg_inner(c, inner_tolerance(relres, rtol), max_iter - total, &it, &done,
+                               &c->pcg_last[0][std::min(outer, 3)]);
       if (rc) return rc;
     }
     total += it;
