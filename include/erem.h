@@ -405,8 +405,11 @@ int erem_batch_set_problem(erem_batch* b, int32_t i, const double* d_logk, const
                            double p_left, double p_right, double T_left, double T_right,
                            const double* d_T0);
 /* Fix the step h and the options for every problem: Gershgorin interval,
- * substeps s = ceil(h (beta - alpha) / rho_max), divided differences up to
- * m_max; opts->precision selects FP64 or FP32 Newton passes. */
+ * substeps s = ceil(h (beta - alpha) / rho_max) (at most max_substeps),
+ * divided differences up to m_max; opts->precision selects FP64 or FP32
+ * Newton passes.  EINVAL for a problem whose interval is degenerate
+ * (beta - alpha <= 1e-14 max(|alpha|, |beta|), e.g. one cell: J = c I), for
+ * the Krylov method, m_max outside [5, 1024] or bad tolerances. */
 int erem_batch_prepare(erem_batch* b, double h, const erem_opts* opts);
 /* Time every tile shape on a copy of d_T (nsteps steps) and keep the fastest;
  * *chosen receives its index.  d_T is not modified. */

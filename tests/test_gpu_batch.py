@@ -251,3 +251,75 @@ def test_batch_256_realisations_full_size(torch_mod, full_batch):
         err = rel_inf(got[i] - probs[i].T0, Ts - probs[i].T0)
         _say(f"realisation {i} (side {sides[i]}): rel err {err:.3e}")
         assert err <= 1e-12, i
+
+
+def _rect_problem(nx, ny, seed):
+    rng = np.random.default_rng(seed)
+    logk = np.log(1e-12) + 0.7 * rng.standard_normal(nx * ny)
+    return inputs.Problem(name=f"rect{nx}x{ny}", nx=nx, ny=ny, nz=1, logk=logk,
+                          poro=np.full(nx * ny, 0.2), T0=np.full(nx * ny, 20.0), nsteps=2)
+
+
+@pytest.mark.parametrize("shape", [0, 5, 7])
+def test_batch_degenerate_and_rectangular_problems_match_oracle(torch_mod, shape):
+    """Two cells, a single row and a single column, and rectangles ragged in
+    both directions (65 x 17, 130 x 3, 3 x 130, one exact 64 x 16 tile) in
+    one batch, for a four-term and both eight-term tile shapes: every
+    realisation against the oracle.  The stiff thin grids (h (beta - alpha)
+    up to 5500) run at the 64-substep cap."""
+    from paper_1209_5553_amd.api import EremBatch, make_opts
+    sides = [(2, 1), (1, 40), (40, 1), (65, 17), (130, 3), (3, 130), (64, 16)]
+    probs = [_rect_problem(nx, ny, seed=40 + i) for i, (nx, ny) in enumerate(sides)]
+    nsteps = 2
+    b = EremBatch(probs, device="cuda:0")
+    b.prepare(probs[0].h, make_opts(m_max=256))
+    b.set_tile_shape(shape)
+    T = b.pack([p.T0 for p in probs])
+    st = b.run(T, nsteps, use_graph=True)
+    _say(f"degenerate batch, shape {shape}: {st}")
+    assert st["failed"] == 0
+    for p, Tg in zip(probs, b.unpack(T)):
+        Tref, _ = oerem.run_linear(p, nsteps=nsteps)
+        assert rel_inf(Tg - p.T0, Tref - p.T0) <= 1e-10, (shape, p.name)
+
+
+def test_batch_problem_over_the_term_budget_fails_alone(torch_mod):
+    """Substeps capped at two: a stiff two-cell problem (h (beta - alpha)
+    about 1200) cannot meet the tolerance within m_max terms of a substep of
+    600, while a workload realisation (one substep) converges.  The run
+    reports the failure, the failed problem keeps its initial temperatures,
+    and the other one is bit for bit what it is in a batch of its own."""
+    torch = torch_mod
+    from paper_1209_5553_amd.api import EremBatch, EremError, make_opts
+    p_hard = _rect_problem(2, 1, seed=47)
+    p_easy = inputs.batch_problem(41)
+    opts = make_opts(m_max=128, max_substeps=2)
+    solo = EremBatch([p_easy], device="cuda:0")
+    solo.prepare(p_easy.h, opts)
+    solo.set_tile_shape(5)
+    Ts = solo.pack([p_easy.T0])
+    st = solo.run(Ts, 1, use_graph=False)
+    assert st["failed"] == 0
+    b = EremBatch([p_hard, p_easy], device="cuda:0")
+    b.prepare(p_easy.h, opts)
+    b.set_tile_shape(5)
+    T = b.pack([p_hard.T0, p_easy.T0])
+    with pytest.raises(EremError) as ei:
+        b.run(T, 1, use_graph=False)
+    _say(f"over budget: {ei.value}")
+    assert "ENOCONV" in str(ei.value) or "ENONFINITE" in str(ei.value)
+    hard, easy = b.unpack(T)
+    assert np.array_equal(hard, p_hard.T0)
+    assert np.array_equal(easy, solo.unpack(Ts)[0])
+
+
+def test_batch_rejects_a_degenerate_interval(torch_mod):
+    """A one-cell problem has J = c I (alpha = beta): the batched form, which
+    fixes one Leja interval per problem, refuses it at prepare with
+    EREM_EINVAL (the single-problem path takes the closed form instead)."""
+    from paper_1209_5553_amd.api import EremBatch, EremError, make_opts
+    probs = [_rect_problem(1, 1, seed=3), _rect_problem(16, 16, seed=4)]
+    b = EremBatch(probs, device="cuda:0")
+    with pytest.raises(EremError) as ei:
+        b.prepare(probs[0].h, make_opts(m_max=128))
+    assert "EINVAL" in str(ei.value)
