@@ -49,8 +49,7 @@ hipError_t launch_spd_residual(const Dims& d, const double* tx, const double* ty
 // pressure adjoint lambda and the (double-double) pressure; then
 // logkbar += mbar m and Tbar += mbar m (rho'/rho - mu'/mu).
 hipError_t launch_adj_trans(const Dims& d, const Phys& ph, const double* logk, const double* T,
-                            const double* tx, const double* ty, const double* phi, const double* plo,
-                            const double* fxbar, const double* fybar, const double* lam, double* Tbar,
-                            double* logkbar, hipStream_t s);
+                            const double* phi, const double* plo, const double* fxbar, const double* fybar,
+                            const double* lam, double* Tbar, double* logkbar, hipStream_t s);
 
 }  // namespace erem

@@ -326,8 +326,7 @@ __global__ __launch_bounds__(kThreads) void k_spd_residual(Dims d, const double*
 }
 
 __global__ __launch_bounds__(kThreads) void k_adj_trans(Dims d, Phys ph, const double* __restrict__ logk,
-                                              const double* __restrict__ T, const double* __restrict__ tx,
-                                              const double* __restrict__ ty, const double* __restrict__ phi,
+                                              const double* __restrict__ T, const double* __restrict__ phi,
                                               const double* __restrict__ plo, const double* __restrict__ fxbar,
                                               const double* __restrict__ fybar, const double* __restrict__ lam,
                                               double* __restrict__ Tbar, double* __restrict__ logkbar) {
@@ -431,10 +430,10 @@ hipError_t launch_spd_residual(const Dims& d, const double* tx, const double* ty
   return hipGetLastError();
 }
 
-hipError_t launch_adj_trans(const Dims& d, const Phys& ph, const double* logk, const double* T, const double* tx,
-                            const double* ty, const double* phi, const double* plo, const double* fxbar,
-                            const double* fybar, const double* lam, double* Tbar, double* logkbar, hipStream_t s) {
-  hipLaunchKernelGGL(k_adj_trans, grid2(d), block2(), 0, s, d, ph, logk, T, tx, ty, phi, plo, fxbar, fybar, lam,
+hipError_t launch_adj_trans(const Dims& d, const Phys& ph, const double* logk, const double* T, const double* phi,
+                            const double* plo, const double* fxbar, const double* fybar, const double* lam,
+                            double* Tbar, double* logkbar, hipStream_t s) {
+  hipLaunchKernelGGL(k_adj_trans, grid2(d), block2(), 0, s, d, ph, logk, T, phi, plo, fxbar, fybar, lam,
                      Tbar, logkbar);
   return hipGetLastError();
 }

@@ -309,8 +309,8 @@ int erem_coupled_step_adjoint(erem_ctx* c, double h, const double* d_T, double p
   // the FP64 residual of the adjoint system cannot certify much below 1e-13;
   // 1e-12 leaves the gradient accurate far beyond what it is used for
   if ((rc = spd_solve(c, c->adj_pbar, c->adj_lam, std::max(p_rtol, 1e-12), kPressureMaxIter, &aiters))) return rc;
-  HIP_TRY(c, launch_adj_trans(d, c->ph, c->logk, d_T, c->tx, c->ty, c->pres, c->pres_lo, c->adj_fxbar, c->adj_fybar,
-                              c->adj_lam, d_Tbar, d_logk_bar, c->stream));
+  HIP_TRY(c, launch_adj_trans(d, c->ph, c->logk, d_T, c->pres, c->pres_lo, c->adj_fxbar, c->adj_fybar, c->adj_lam,
+                              d_Tbar, d_logk_bar, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
   if (stats) {
     std::memset(stats, 0, sizeof(*stats));

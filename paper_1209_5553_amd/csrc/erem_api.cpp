@@ -435,7 +435,7 @@ int leja_hphi1(erem_ctx* c, double h, const double* v, const double* g, double s
   const LejaPass p2{c->cf + 1, c->states + s, c->zt, nullptr, nullptr, ev ? ev + static_cast<size_t>(nprof) * 2 * K : nullptr,
                     c->prof ? 1 : 0};
   const LejaPass p1{c->cf, c->states, c->u, g, na ? c->zt : nullptr, ev, nprof};
-  int rc;
+  int rc = EREM_OK;
   if (o->precision == EREM_PREC_MIXED) {
     rc = ensure_mixed(c);
     if (rc) return rc;

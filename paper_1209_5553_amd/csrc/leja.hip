@@ -53,7 +53,7 @@ __global__ void k_leja_reset(LejaState* st, int nslots, int nterms) {
 template <class V>
 __global__ __launch_bounds__(kThreads) void k_leja_init(Dims d, const LejaCoef* __restrict__ cf,
                                               const double* __restrict__ v, V* __restrict__ q0,
-                                              V* __restrict__ p, double* __restrict__ part, int nb) {
+                                              V* __restrict__ p, double* __restrict__ part) {
   const int x = blockIdx.x * kBX + threadIdx.x;
   const int y = blockIdx.y * kBY + threadIdx.y;
   const int z = blockIdx.z;
@@ -341,8 +341,7 @@ hipError_t launch_leja_reset(LejaState* st, int nslots, int nterms, hipStream_t 
 template <class V>
 hipError_t launch_leja_init(const Dims& d, const LejaCoef* cf, const double* v, V* q0, V* p, double* part,
                             hipStream_t s) {
-  hipLaunchKernelGGL(k_leja_init<V>, cell_grid(d), cell_block(), 0, s, d, cf, v, q0, p, part,
-                     leja_num_blocks(d));
+  hipLaunchKernelGGL(k_leja_init<V>, cell_grid(d), cell_block(), 0, s, d, cf, v, q0, p, part);
   return hipGetLastError();
 }
 
