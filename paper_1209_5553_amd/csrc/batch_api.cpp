@@ -379,6 +379,17 @@ int launch(erem_batch* b, double* T, int nsteps, bool use_graph, erem_batch_stat
 }
 
 // Switch the tile shape: the tile list changes, so the captured graphs go.
+// Whether a tile shape's dynamic LDS (at the batch's precision) fits the
+// device's limit per workgroup.
+bool shape_fits(const erem_batch* b, int shape) {
+  int max_lds = 0;
+  if (hipDeviceGetAttribute(&max_lds, hipDeviceAttributeMaxSharedMemoryPerBlock, b->device) != hipSuccess) {
+    (void)hipGetLastError();
+    return false;
+  }
+  return batch_lds_bytes(shape, b->fp32) + 1024 <= static_cast<size_t>(max_lds);  // + the static reduction arrays
+}
+
 int set_shape(erem_batch* b, int shape) {
   if (shape == b->shape) return EREM_OK;
   BHIP(b, hipStreamSynchronize(b->stream));
@@ -606,6 +617,7 @@ int erem_batch_autotune(erem_batch* b, const double* d_T, int32_t nsteps, int32_
   const int saved = b->prof_stride;
   b->prof_stride = 0;
   for (int s = 0; s < kNumTileShapes; ++s) {
+    if (!shape_fits(b, s)) continue;
     const int rc0 = set_shape(b, s);
     if (rc0) return rc0;
     BHIP(b, hipMemcpyAsync(b->tscratch, d_T, sizeof(double) * b->ntot, hipMemcpyDeviceToDevice, b->stream));
@@ -630,6 +642,7 @@ int erem_batch_autotune(erem_batch* b, const double* d_T, int32_t nsteps, int32_
 int erem_batch_set_tile_shape(erem_batch* b, int32_t shape) {
   if (!b) return EREM_EINVAL;
   if (shape < 0 || shape >= kNumTileShapes) return bfail(b, EREM_EINVAL, "tile shape index out of range");
+  if (!shape_fits(b, shape)) return bfail(b, EREM_EINVAL, "tile shape needs more LDS than the device has");
   return set_shape(b, shape);
 }
 
