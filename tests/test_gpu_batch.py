@@ -323,3 +323,26 @@ def test_batch_rejects_a_degenerate_interval(torch_mod):
     with pytest.raises(EremError) as ei:
         b.prepare(probs[0].h, make_opts(m_max=128))
     assert "EINVAL" in str(ei.value)
+
+
+def test_batch_wide_substeps_match_oracle(torch_mod):
+    """The benchmark's FP64 setting, substep intervals up to 96 wide
+    (rho_max = 96, m_max = 128): the realisations of the workload with the
+    widest substeps at that setting (h (beta - alpha) of 96.0, 95.9, 186.0,
+    183.8 and 208.1, seeds 205, 118, 207, 94 and 74) after three steps
+    against the oracle on every cell."""
+    from paper_1209_5553_amd.api import EremBatch, make_opts
+    seeds = (205, 118, 207, 94, 74)
+    probs = [inputs.batch_problem(s) for s in seeds]
+    nsteps = 3
+    b = EremBatch(probs, device="cuda:0")
+    b.prepare(probs[0].h, make_opts(m_max=128, rho_max=96.0))
+    T = b.pack([p.T0 for p in probs])
+    st = b.run(T, nsteps, use_graph=True)
+    _say(f"rho_max 96: {st}")
+    assert st["failed"] == 0
+    for s, p, Tg in zip(seeds, probs, b.unpack(T)):
+        Tref, _ = oerem.run_linear(p, nsteps=nsteps, tier="taylor")
+        err = rel_inf(Tg - p.T0, Tref - p.T0)
+        _say(f"seed {s} (side {p.nx}): increment err {err:.2e}")
+        assert err <= 1e-10, s
