@@ -128,7 +128,8 @@ def schedule_of(name):
     return inputs.InjectorSchedule() if name == "injector512" else None
 
 
-def gpu_run(prob, coupled, steps, warmup, rtol_p, mixed=False, sched=None, scheme="erem", pmethod="leja"):
+def gpu_run(prob, coupled, steps, warmup, rtol_p, mixed=False, sched=None, scheme="erem", pmethod="leja",
+            rho_max=None):
     import torch
     from paper_1209_5553_amd.api import EremContext, make_opts
 
@@ -136,7 +137,8 @@ def gpu_run(prob, coupled, steps, warmup, rtol_p, mixed=False, sched=None, schem
     dev = ctx.device
     T = torch.as_tensor(prob.T0, dtype=torch.float64, device=dev).clone()
     p = torch.zeros(prob.n, dtype=torch.float64, device=dev)
-    opts = make_opts(precision=1, tol_r=1e-7) if mixed else make_opts()
+    extra = {} if rho_max is None else {"rho_max": rho_max}
+    opts = make_opts(precision=1, tol_r=1e-7, **extra) if mixed else make_opts(**extra)
     state = {"n": 0, "last": None, "pcg": 0}
 
     comp = prob.name.startswith("compressible")
@@ -618,6 +620,9 @@ def main():
                     choices=["batch256", "coupled512", "linear32", "layered128", "layered256", "injector512",
                              "compressible50", "adjoint256"])
     ap.add_argument("--no-ceiling", action="store_true", help="skip the copy / triad bandwidth measurement")
+    ap.add_argument("--rho-max", type=float, default=None,
+                    help="single-problem workloads: widest substep interval h (beta - alpha) / s "
+                         "(default: the library's)")
     ap.add_argument("--tile-shape", type=int, default=None,
                     help="batch256: use this tile shape (0-7) instead of autotuning (profiler runs)")
     ap.add_argument("--adjoint-start", default="uniform", choices=["uniform", "structured"])
@@ -657,7 +662,7 @@ def main():
     if args.workload == "compressible50":
         args.cpu_steps = min(args.cpu_steps, 2)
     res = gpu_run(prob, coupled, args.steps, args.warmup, args.pressure_rtol, mixed=mixed, sched=sched,
-                  scheme=args.scheme, pmethod=args.pressure_method)
+                  scheme=args.scheme, pmethod=args.pressure_method, rho_max=args.rho_max)
     dim = prob.dim
     N = prob.n
     t = res["times"]
@@ -686,7 +691,7 @@ def main():
         "data": "synthetic (seeded generators)",
         "config": {"workload": desc, "grid": [prob.nx, prob.ny, prob.nz], "cells": N, "h_s": prob.h,
                    "tol_r": 1e-7 if mixed else 1e-12, "precision": args.precision, "pressure_rtol": args.pressure_rtol if coupled else None,
-                   "scheme": args.scheme},
+                   "scheme": args.scheme, "rho_max": args.rho_max},
         "roofline": roof(dominant),
         "leja": roof("leja_term") if erem else None,
         "bicg": None if erem else roof("bicg_iteration"),
