@@ -49,6 +49,25 @@ def test_create_rejects_bad_grids_without_device_work(lib):
     assert lib.erem_create(None, None, ctypes.byref(h)) == -1
 
 
+def test_batch_create_rejects_bad_grids_without_device_work(lib):
+    """The batched form takes 2D grids only, at least one of them, each with
+    positive sides and spacings: anything else is EREM_EINVAL before any
+    device call, and no handle is returned."""
+    h = ctypes.c_void_p(1)
+    good = nat.Grid(2, 8, 8, 1, 1, 1, 1)
+    bad = [nat.Grid(3, 8, 8, 8, 1, 1, 1), nat.Grid(2, 8, 8, 2, 1, 1, 1), nat.Grid(2, 0, 8, 1, 1, 1, 1),
+           nat.Grid(2, 8, 0, 1, 1, 1, 1), nat.Grid(2, 8, 8, 1, 0, 1, 1), nat.Grid(2, 70000, 8, 1, 1, 1, 1)]
+    for g in bad:
+        grids = (nat.Grid * 2)(good, g)
+        assert lib.erem_batch_create(2, grids, None, ctypes.byref(h)) == -1
+        assert not h.value
+        h = ctypes.c_void_p(1)
+    grids = (nat.Grid * 1)(good)
+    assert lib.erem_batch_create(0, grids, None, ctypes.byref(h)) == -1
+    assert lib.erem_batch_create(1, None, None, ctypes.byref(h)) == -1
+    assert lib.erem_batch_create(1, grids, None, None) == -1
+
+
 def _leja(n):
     out = np.zeros(n)
     assert nat.load().erem_leja_points(n, out.ctypes.data_as(nat._PD)) == 0
