@@ -44,13 +44,12 @@ namespace {
 template <class V>
 __device__ inline V cv(double x) { return static_cast<V>(x); }
 
-// q_{k-1} with a halo of NT, and one intermediate-term buffer (halo NT - 1);
-// the other intermediate buffer reuses the space of q_{k-1} once the first
-// term has read it.
+// Two buffers in the frame of q_{k-1} (the tile plus a halo of NT): the
+// first holds q_{k-1}, then the odd intermediate terms; the second the even
+// ones.
 template <int TY, int NT, class V>
 constexpr size_t work_lds_bytes() {
-  return sizeof(V) * (static_cast<size_t>(TY + 2 * NT) * (kBatchTileX + 2 * NT) +
-                      static_cast<size_t>(TY + 2 * NT - 2) * (kBatchTileX + 2 * NT - 2));
+  return 2 * sizeof(V) * static_cast<size_t>(TY + 2 * NT) * (kBatchTileX + 2 * NT);
 }
 
 // Sum (or max) over the workgroup of one double per thread; fixed order
@@ -84,10 +83,8 @@ __global__ __launch_bounds__(kBatchTileX* BY) void k_bt_work(BatchArgs a) {
   constexpr int WQ = kBatchTileX + 2 * NT, HQ = TY + 2 * NT;  // q_{k-1}: halo NT
   constexpr int WI = kBatchTileX + 2 * H, HI = TY + 2 * H;    // stencil, intermediates: halo NT - 1
   extern __shared__ __align__(16) unsigned char smem[];
-  V(*sq)[WQ] = reinterpret_cast<V(*)[WQ]>(smem);  // q_{k-1}
-  // intermediate terms: even terms write sb_even, odd terms write over q_{k-1}
-  V(*sb_even)[WI] = reinterpret_cast<V(*)[WI]>(smem + sizeof(V) * HQ * WQ);
-  V(*sb_odd)[WI] = reinterpret_cast<V(*)[WI]>(smem);
+  V(*sq)[WQ] = reinterpret_cast<V(*)[WQ]>(smem);  // q_{k-1}, then the odd terms
+  V(*sb)[WQ] = reinterpret_cast<V(*)[WQ]>(smem + sizeof(V) * HQ * WQ);  // the even terms
   __shared__ double red[NT][NW];
 
   const int t = XCD ? xcd_tile_id() : static_cast<int>(blockIdx.x);
@@ -181,13 +178,16 @@ __global__ __launch_bounds__(kBatchTileX* BY) void k_bt_work(BatchArgs a) {
     return;
   }
 
-  // NT Newton terms S.k .. S.k + NT - 1 on the tile.  Each thread owns up to
-  // UC cells of the tile plus its halo of NT - 1 (the "box") for all the
-  // terms: it keeps their stencil in registers, computes them in every term
-  // whose region (the box shrinking by one cell per term) holds them, and
-  // accumulates p and the partial sums for those of its cells in the tile.
-  // Only q goes through LDS: q_{k-1} with a halo of NT, then the
-  // intermediate terms.
+  // NT Newton terms S.k .. S.k + NT - 1 on the tile.  The tile plus its
+  // halo of NT - 1 (the "box", HI x WI cells) is cut into vertical strips of
+  // SH cells, one per thread, consecutive threads taking consecutive
+  // columns.  A thread keeps the stencil and the current term of its strip
+  // in registers and computes its cells in every term whose region (the box
+  // shrinking by one cell per term) holds them: the north and south
+  // neighbours come from its own registers (from LDS at the strip's ends),
+  // the west and east ones from LDS, where every term is written for the
+  // neighbouring strips.  p and the partial sums accumulate for the strip's
+  // cells in the tile.
   const int grp = (S.k - 1) / NT;
   const V* __restrict__ qin = reinterpret_cast<const V*>((grp & 1) ? a.q1 : a.q0);
   V* __restrict__ qout = reinterpret_cast<V*>((grp & 1) ? a.q0 : a.q1);
@@ -195,7 +195,13 @@ __global__ __launch_bounds__(kBatchTileX* BY) void k_bt_work(BatchArgs a) {
   const V* __restrict__ coef = reinterpret_cast<const V*>(a.coef);
   const int x0 = tl.x0, y0 = tl.y0;
   constexpr int UQ = (HQ * WQ + NTH - 1) / NTH;  // q values staged per thread
-  constexpr int UC = (HI * WI + NTH - 1) / NTH;  // box cells per thread
+  constexpr int SROWS = NTH / WI;                // strip rows the threads can cover
+  static_assert(SROWS >= 1, "a thread per box column");
+  constexpr int SH = (HI + SROWS - 1) / SROWS;   // cells per strip
+  constexpr int NSR = (HI + SH - 1) / SH;        // strip rows used
+  const bool has_strip = tid < NSR * WI;
+  const int bx = has_strip ? tid % WI : 0;
+  const int by0 = has_strip ? (tid / WI) * SH : HI;  // first cell of the strip (box rows)
   // every load of the tile is issued (into registers) before the first LDS
   // store, so the tile waits for one memory latency
   V rq[UQ];
@@ -206,21 +212,19 @@ __global__ __launch_bounds__(kBatchTileX* BY) void k_bt_work(BatchArgs a) {
     const int gx = x0 - NT + rx, gy = y0 - NT + ry;
     rq[u] = (e < HQ * WQ && gx >= 0 && gx < nx && gy >= 0 && gy < ny) ? qin[o + gx + nx * gy] : V(0);
   }
-  V rc[5][UC], acc[UC];
-  int by[UC], bx[UC];
-  bool tile_cell[UC];
+  const int gx = x0 - H + bx;
+  const bool col_in = has_strip && gx >= 0 && gx < nx;
+  const bool col_tile = has_strip && bx >= H && bx < H + kBatchTileX;
+  V rc[5][SH], acc[SH];
 #pragma unroll
-  for (int u = 0; u < UC; ++u) {
-    const int e = tid + u * NTH;
-    by[u] = e / WI;
-    bx[u] = e - by[u] * WI;
-    const int gx = x0 - H + bx[u], gy = y0 - H + by[u];
-    const bool in = e < HI * WI && gx >= 0 && gx < nx && gy >= 0 && gy < ny;
-    tile_cell[u] = in && bx[u] >= H && bx[u] < H + kBatchTileX && by[u] >= H && by[u] < H + TY;
-    const long long j = o + (in ? gx + nx * gy : 0);
+  for (int r = 0; r < SH; ++r) {
+    const int by = by0 + r, gy = y0 - H + by;
+    const bool in = col_in && by < HI && gy >= 0 && gy < ny;
+    const long long j = o + (in ? gx + static_cast<long long>(nx) * gy : 0);
 #pragma unroll
-    for (int d = 0; d < 5; ++d) rc[d][u] = in ? coef[d * Nt + j] : V(0);
-    acc[u] = tile_cell[u] ? p[j] : V(0);
+    for (int d = 0; d < 5; ++d) rc[d][r] = in ? coef[d * Nt + j] : V(0);
+    const bool tile_cell = in && col_tile && by >= H && by < H + TY;
+    acc[r] = tile_cell ? p[j] : V(0);
   }
 #pragma unroll
   for (int u = 0; u < UQ; ++u) {
@@ -228,6 +232,10 @@ __global__ __launch_bounds__(kBatchTileX* BY) void k_bt_work(BatchArgs a) {
     if (e < HQ * WQ) sq[e / WQ][e % WQ] = rq[u];
   }
   __syncthreads();
+  // the strip's q_{k-1} (rows up to HI: the halo of q_{k-1} above the box)
+  V cur[SH];
+#pragma unroll
+  for (int r = 0; r < SH; ++r) cur[r] = has_strip && by0 + r <= HI ? sq[by0 + r + 1][bx + 1] : V(0);
   const V ig = cv<V>(P.inv_g);
   const double* shf = a.shift + P.coef_off + S.k;
   const double* dkp = a.dk + P.coef_off + S.k;
@@ -235,47 +243,49 @@ __global__ __launch_bounds__(kBatchTileX* BY) void k_bt_work(BatchArgs a) {
   for (int tt = 0; tt < NT; ++tt) {
     const V sh = cv<V>(shf[tt]);
     const V dkt = cv<V>(dkp[tt]);
-    V(*out)[WI] = (tt & 1) ? sb_odd : sb_even;
-    const V(*prev)[WI] = (tt & 1) ? sb_even : sb_odd;
+    const V(*src)[WQ] = (tt & 1) ? sb : sq;
+    V(*dst)[WQ] = (tt & 1) ? sq : sb;
     double sum = 0.0;  // this thread's share of sum q_k^2 over the tile
+    // the cell below the strip, from LDS (the strip above computed it)
+    const V below = has_strip ? src[by0][bx + 1] : V(0);
+    const V above = has_strip && by0 + SH + 1 < HQ ? src[by0 + SH + 1][bx + 1] : V(0);
+    V nxt[SH];
 #pragma unroll
-    for (int u = 0; u < UC; ++u) {
-      const int iy = by[u], ix = bx[u];
+    for (int r = 0; r < SH; ++r) {
+      const int by = by0 + r;
+      nxt[r] = cur[r];
       // the region of term tt: the box less tt cells on every side
-      if (tid + u * NTH < HI * WI && iy >= tt && iy < HI - tt && ix >= tt && ix < WI - tt) {
-        V qc, qw, qe, qs, qn;
-        if (tt == 0) {
-          qc = sq[iy + 1][ix + 1];
-          qw = sq[iy + 1][ix];
-          qe = sq[iy + 1][ix + 2];
-          qs = sq[iy][ix + 1];
-          qn = sq[iy + 2][ix + 1];
-        } else {
-          qc = prev[iy][ix];
-          qw = prev[iy][ix - 1];
-          qe = prev[iy][ix + 1];
-          qs = prev[iy - 1][ix];
-          qn = prev[iy + 1][ix];
-        }
-        V jq = rc[0][u] * qc;
-        jq += rc[1][u] * qw;
-        jq += rc[2][u] * qe;
-        jq += rc[3][u] * qs;
-        jq += rc[4][u] * qn;
+      if (has_strip && by >= tt && by < HI - tt && bx >= tt && bx < WI - tt) {
+        const V qc = cur[r];
+        const V qw = src[by + 1][bx];
+        const V qe = src[by + 1][bx + 2];
+        const V qs = r > 0 ? cur[r - 1] : below;
+        const V qn = r + 1 < SH ? cur[r + 1] : above;
+        V jq = rc[0][r] * qc;
+        jq += rc[1][r] * qw;
+        jq += rc[2][r] * qe;
+        jq += rc[3][r] * qs;
+        jq += rc[4][r] * qn;
         const V qo = jq * ig - sh * qc;  // zero outside the grid (stencil and q are)
-        if (tt + 1 < NT) out[iy][ix] = qo;
-        if (tile_cell[u]) {
-          acc[u] += dkt * qo;
+        nxt[r] = qo;
+        if (tt + 1 < NT) dst[by + 1][bx + 1] = qo;
+        if (col_tile && by >= H && by < H + TY) {
+          acc[r] += dkt * qo;
           sum += static_cast<double>(qo) * static_cast<double>(qo);
           if (tt + 1 == NT) {
             // the last term: p and q_k of the tile go straight out
-            const long long j = o + (x0 - H + ix) + static_cast<long long>(nx) * (y0 - H + iy);
-            p[j] = acc[u];
-            qout[j] = qo;
+            const int gy = y0 - H + by;
+            if (col_in && gy < ny) {
+              const long long j = o + gx + static_cast<long long>(nx) * gy;
+              p[j] = acc[r];
+              qout[j] = qo;
+            }
           }
         }
       }
     }
+#pragma unroll
+    for (int r = 0; r < SH; ++r) cur[r] = nxt[r];
     // the wavefront's share of the term's norm, to LDS in wavefront order
     for (int off = 32; off > 0; off >>= 1) sum += __shfl_down(sum, off, 64);
     if ((tid & 63) == 0) red[tt][tid >> 6] = sum;
@@ -473,7 +483,7 @@ hipError_t launch_work_shape(const BatchArgs& a, int shape, hipStream_t s, hipEv
 size_t batch_lds_bytes(int shape, int fp32) {
   const size_t vb = fp32 ? sizeof(float) : sizeof(double);
   const size_t rows = kBatchTileRows[shape], nt = kBatchPassTerms[shape];
-  return vb * ((rows + 2 * nt) * (kBatchTileX + 2 * nt) + (rows + 2 * nt - 2) * (kBatchTileX + 2 * nt - 2));
+  return 2 * vb * (rows + 2 * nt) * (kBatchTileX + 2 * nt);
 }
 
 hipError_t batch_pack(int nx, int ny, const double* coef, const double* F, const double* T0, double* bcoef,
