@@ -194,7 +194,12 @@ int erem_phi1_apply(erem_ctx* ctx, double h, const double* d_v, double* d_out,
  * sets d_T <- d_T + h phi1(h J) G(d_T) (Eq. EERM).  Substeps (Sec. 4.2,
  * splitting when the degree is too large) integrate the linearised problem
  * u' = J u + G(T^n) exactly up to the tolerance: u <- u + delta phi1(delta J)
- * (G + J u). */
+ * (G + J u).  After a first Leja step on the context (and for budgets of at
+ * most 31 terms) the Newton passes are enqueued behind the assembly without
+ * a host synchronisation: the substep count is predicted from the previous
+ * step's interval width and confirmed afterwards (a failed prediction runs
+ * the step again on the interval read back); the result is the same bit for
+ * bit.  The call returns after the step has completed on the stream. */
 int erem_step(erem_ctx* ctx, double h, double* d_T, const erem_opts* opts, erem_stats* stats);
 
 /* As erem_step but with the J and F already held by the context (from

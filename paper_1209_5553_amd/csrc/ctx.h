@@ -85,6 +85,13 @@ struct erem_ctx {
   DivDiffCache dd, dd2;  // phi1 and phi2 divided differences
   int last_m = 0;          // largest substep degree of the previous evaluation
   int last_m_p = 0;        // the same for the transient pressure (its own degree)
+  // interval width beta - alpha of the previous Leja evaluation (0: none), which
+  // predicts the next one's substep count; the same for the transient pressure
+  double last_w = 0.0, last_w_p = 0.0;
+  // coefficients formed on the device: the Leja points and the
+  // divided-difference cache
+  double* xi_dev = nullptr;
+  erem::DdCache* ddc = nullptr;
   // profiling (HIP events around each Leja term and PCG half-iteration)
   // iterations of the last converged CG solve (poll placement), per kind of
   // solve (0: pressure, 1: other SPD right-hand sides) and refinement

@@ -49,6 +49,15 @@ struct LejaState {
   double sums[kMaxTerms + 1];  // sum q_k^2 (FP64)
 };
 
+// Divided differences of phi1 last formed on the device, with their key
+// (the scaled interval centre hc, half-width hg and how many were formed):
+// an evaluation with the same key reuses them.
+struct DdCache {
+  double hc, hg;
+  int n, pad;
+  double d[kMaxTerms + 1];
+};
+
 // Reduction targets of the assembly pass (ordered-integer encodings), one
 // partial per slot: the blocks spread their atomics over kSlots addresses
 // and the host folds the slots (slot_min / slot_max).

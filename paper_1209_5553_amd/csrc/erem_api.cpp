@@ -73,9 +73,12 @@ void free_all(erem_ctx* c) {
                      &c->pr, &c->pr2, &c->pw, &c->ps0, &c->ps1, &c->pz, &c->pp0, &c->pp1, &c->pq, &c->pdiag,
                      &c->pres_lo, &c->pdelta, &c->prhs, &c->part, &c->gt, &c->zt,
                      &c->bc_r, &c->bc_rhat, &c->bc_p0, &c->bc_p1, &c->bc_v0, &c->bc_v1, &c->bc_s, &c->bc_t,
-                     &c->rs_k0, &c->rs_k1, &c->rs_k2, &c->rs_y, &c->rs_g, &c->rs_rhs, &c->rs_coef};
+                     &c->rs_k0, &c->rs_k1, &c->rs_k2, &c->rs_y, &c->rs_g, &c->rs_rhs, &c->rs_coef,
+                     &c->xi_dev};
   for (double** b : bufs)
     if (*b) { (void)hipFree(*b); *b = nullptr; }
+  if (c->ddc) (void)hipFree(c->ddc);
+  c->ddc = nullptr;
   if (c->cf) (void)hipFree(c->cf);
   if (c->states) (void)hipFree(c->states);
   if (c->red) (void)hipFree(c->red);
@@ -405,25 +408,79 @@ void fill_coef(LejaCoef* hc, const std::vector<double>& dv, int n, double cc, do
 //   u_{j+1} = u_j + delta phi1(delta J) (v + J u_j)   (Sec. 4.2 splitting).
 // Returns EREM_OK, EREM_ENOCONV (some substep did not stop within K terms)
 // or an error.  `m_used` receives the summed degree actually applied.
+// Internal result of an evaluation enqueued on a predicted substep count
+// whose prediction did not hold: evaluate again on the interval read back.
+constexpr int kFallback = -100;  // not an EREM_ code
+
+// Widest substep interval h (beta - alpha) / s of the evaluation's precision.
+double substep_rho(const erem_opts* o) {
+  return o->precision == EREM_PREC_MIXED ? std::min(o->rho_max, kMixedRhoMax) : o->rho_max;
+}
+
+// Substep count of an interval of the given width: h width / rho rounded
+// up, at least 1, at most smax (one substep when rho <= 0).
+int substeps_for(double h, double width, double rho, int smax) {
+  int s = 1;
+  if (rho > 0.0) {
+    const double q = std::ceil(h * width / rho);
+    s = q >= smax ? smax : (q > 1.0 ? static_cast<int>(q) : 1);
+  }
+  return std::min(s, smax);
+}
+
+// Term budget of an evaluation's first attempt: the previous evaluation's
+// largest substep degree plus one stop-test group (the launches past the
+// stop return at entry), else m_max; a degree that outgrows it restarts the
+// evaluation with the full budget.
+int first_budget(const erem_ctx* c, const erem_opts* o) {
+  if (o->chunk > 0) return std::min(o->chunk, o->m_max);
+  return c->last_m > 0 ? std::min(o->m_max, c->last_m + kCheckEvery) : o->m_max;
+}
+
+// The host's reading of the reduction slots after an evaluation whose
+// coefficients the device formed (launch_leja_coef): the same checks and
+// substep count as the synchronous path.  EREM_OK when the device's
+// coefficients are the ones the synchronous path would have formed.
+int confirm_device_coef(erem_ctx* c, double h, int s, const erem_opts* o, const LejaCoefArgs& a) {
+  c->alpha = slot_min(c->h_red->lo);
+  c->beta = slot_max(c->h_red->hi);
+  c->tmax = slot_max(a.scale_v ? c->h_red->vmax : c->h_red->tmax);
+  if (!std::isfinite(c->tmax)) return fail(c, EREM_ENONFINITE, "non-finite temperature");
+  const double scal = o->tol_a + o->tol_r * c->tmax;
+  if (!(scal > 0)) return fail(c, EREM_EINVAL, "error scale is zero (tol_a = 0 and T = 0)");
+  const double width = c->beta - c->alpha;
+  const double mag = std::max(std::fabs(c->alpha), std::fabs(c->beta));
+  if (!std::isfinite(width)) return fail(c, EREM_ENONFINITE, "non-finite Gershgorin interval");
+  if (width <= 1e-14 * mag || width == 0.0) return kFallback;
+  if (substeps_for(h, width, a.rho, a.smax) != s) return kFallback;
+  // the kernel marks refused states with checked = -2
+  for (int j = 0; j < s; ++j)
+    if (c->h_states[j].checked == -2) return kFallback;
+  return EREM_OK;
+}
+
 int leja_hphi1(erem_ctx* c, double h, const double* v, const double* g, double scal, int s, int K,
-               const erem_opts* o, int* m_used, double* est_last) {
-  const double a = c->alpha, b = c->beta;
-  const double cc = 0.5 * (a + b);
-  const double gg = 0.25 * (b - a);
-  const double delta = h / s;
+               const erem_opts* o, int* m_used, double* est_last, const LejaCoefArgs* dev = nullptr) {
   const int n = K + 1;
   const bool na = g != nullptr;  // non-autonomous: one phi2 pass first, in slot s
   const int npass = s + (na ? 1 : 0);
-  const double rootN = std::sqrt(static_cast<double>(c->d.N));
-  fill_coef(c->h_cf, divided_differences(c, delta * cc, delta * gg, n, 1), n, cc, gg, delta, c->xi, rootN,
-            scal, o->p_order);
-  if (na)
-    fill_coef(c->h_cf + 1, divided_differences(c, delta * cc, delta * gg, n, 2), n, cc, gg, delta * delta,
-              c->xi, rootN, scal, o->p_order);
-  const size_t cf_bytes = offsetof(LejaCoef, shift) + 3 * sizeof(double) * (kMaxTerms + 1);
-  HIP_TRY(c, hipMemcpyAsync(c->cf, c->h_cf, na ? 2 * sizeof(LejaCoef) : cf_bytes, hipMemcpyHostToDevice,
-                            c->stream));
+  const double delta = h / s;
+  if (!dev) {
+    const double a = c->alpha, b = c->beta;
+    const double cc = 0.5 * (a + b);
+    const double gg = 0.25 * (b - a);
+    const double rootN = std::sqrt(static_cast<double>(c->d.N));
+    fill_coef(c->h_cf, divided_differences(c, delta * cc, delta * gg, n, 1), n, cc, gg, delta, c->xi, rootN,
+              scal, o->p_order);
+    if (na)
+      fill_coef(c->h_cf + 1, divided_differences(c, delta * cc, delta * gg, n, 2), n, cc, gg, delta * delta,
+                c->xi, rootN, scal, o->p_order);
+    const size_t cf_bytes = offsetof(LejaCoef, shift) + 3 * sizeof(double) * (kMaxTerms + 1);
+    HIP_TRY(c, hipMemcpyAsync(c->cf, c->h_cf, na ? 2 * sizeof(LejaCoef) : cf_bytes, hipMemcpyHostToDevice,
+                              c->stream));
+  }
   HIP_TRY(c, launch_leja_reset(c->states, npass, K, c->stream));
+  if (dev) HIP_TRY(c, launch_leja_coef(*dev, c->stream));
   const int nprof = c->prof ? std::min(s, kProfSubsteps) : 0;
   if (c->prof) {
     const int rc = ensure_events(c, static_cast<size_t>(nprof + 1) * 2 * K);
@@ -448,13 +505,21 @@ int leja_hphi1(erem_ctx* c, double h, const double* v, const double* g, double s
     if (!rc) rc = leja_run<double>(c, B, p1, v, delta, s, K);
   }
   if (rc) return rc;
-  // Read the stop state of every pass.
+  // Read the stop state of every pass (and the stop-test factors the device
+  // formed).
   const size_t hdr = offsetof(LejaState, sums);
   for (int j = 0; j < npass; ++j)
     HIP_TRY(c, hipMemcpyAsync(reinterpret_cast<char*>(c->h_states + j),
                               reinterpret_cast<const char*>(c->states + j),
                               hdr + sizeof(double) * (K + 1), hipMemcpyDeviceToHost, c->stream));
+  if (dev)
+    HIP_TRY(c, hipMemcpyAsync(c->h_cf->estf, reinterpret_cast<const char*>(c->cf) + offsetof(LejaCoef, estf),
+                              sizeof(double) * n, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(c, hipStreamSynchronize(c->stream));
+  if (dev) {
+    const int crc = confirm_device_coef(c, h, s, o, *dev);
+    if (crc) return crc;
+  }
   int total = 0;
   double last = 0.0;
   c->applied.assign(s, 0);
@@ -611,11 +676,27 @@ int krylov_hphi1(erem_ctx* c, double h, const double* v, double scal, const erem
   return EREM_OK;
 }
 
+// Bookkeeping of a converged Leja evaluation: the degree memory of the next
+// term budget and the statistics.
+void eval_done(erem_ctx* c, int s, int m_used, double est, int restarts, erem_stats* stats) {
+  int m1 = 0;  // the largest phi1 degree of a substep
+  for (int a : c->applied) m1 = std::max(m1, a);
+  c->last_m = m1;
+  if (stats) {
+    stats->m_total = m_used;
+    stats->substeps = s;
+    stats->est_err = est;
+    stats->restarts = restarts;
+  }
+}
+
 // Full evaluation with the substep / restart policy.  On success c->u holds
 // h phi1(h J) v, plus h^2 phi2(h J) g when g is not null (the increment of
 // the non-autonomous step, Sec. 3.2.3, Eq. nEERMg; Leja method only).
+// s_failed > 0: an attempt with s_failed substeps and budget K_failed has
+// already run and not converged; the policy continues from it.
 int hphi1_eval(erem_ctx* c, double h, const double* v, const double* g, double scal, const erem_opts* o,
-               erem_stats* stats) {
+               erem_stats* stats, int s_failed = 0, int K_failed = 0) {
   const double width = c->beta - c->alpha;
   const double mag = std::max(std::fabs(c->alpha), std::fabs(c->beta));
   if (!std::isfinite(width)) return fail(c, EREM_ENONFINITE, "non-finite Gershgorin interval");
@@ -629,48 +710,96 @@ int hphi1_eval(erem_ctx* c, double h, const double* v, const double* g, double s
     HIP_TRY(c, launch_axpby(c->d, c->u, 0.0, v, f, c->stream));
     if (g) HIP_TRY(c, launch_axpby(c->d, c->u, 1.0, g, h * h * phi2_scalar(z), c->stream));
     c->applied.clear();
+    c->last_w = 0.0;
     if (stats) { stats->m_total = 0; stats->substeps = 1; stats->est_err = 0.0; }
     return EREM_OK;
   }
   if (o->method == EREM_METHOD_KRYLOV) return krylov_hphi1(c, h, v, scal, o, stats);
   // the non-autonomous evaluation keeps one stop-state slot for its phi2 pass
   const int smax = std::min(o->max_substeps, g ? c->nstates - 1 : c->nstates);
-  int s = 1;
-  const double rho = o->precision == EREM_PREC_MIXED ? std::min(o->rho_max, kMixedRhoMax) : o->rho_max;
-  if (rho > 0.0) s = std::max(1, static_cast<int>(std::ceil(h * width / rho)));
-  if (s > smax) s = smax;
-  // term budget: the previous evaluation's largest substep degree plus one
-  // stop-test group (the launches past the stop return at entry); a degree
-  // that outgrows it restarts the evaluation with the full budget m_max
-  int K = o->chunk > 0 ? std::min(o->chunk, o->m_max)
-                       : (c->last_m > 0 ? std::min(o->m_max, c->last_m + kCheckEvery) : o->m_max);
+  int s = substeps_for(h, width, substep_rho(o), smax);
+  int K = first_budget(c, o);
   int restarts = 0;
+  bool retry = s_failed > 0;
+  if (retry) {
+    s = s_failed;
+    K = K_failed;
+  }
   for (;;) {
+    if (retry) {
+      ++restarts;
+      if (K < o->m_max) {
+        K = o->m_max;
+      } else if (2 * s <= smax) {
+        s *= 2;
+      } else {
+        return fail(c, EREM_ENOCONV, "phi1 did not converge within m_max terms and max_substeps substeps");
+      }
+    }
     int m_used = 0;
     double est = 0.0;
     const int rc = leja_hphi1(c, h, v, g, scal, s, K, o, &m_used, &est);
     if (rc == EREM_OK) {
-      int m1 = 0;  // the largest phi1 degree of a substep
-      for (int a : c->applied) m1 = std::max(m1, a);
-      c->last_m = m1;
-      if (stats) {
-        stats->m_total = m_used;
-        stats->substeps = s;
-        stats->est_err = est;
-        stats->restarts = restarts;
-      }
+      eval_done(c, s, m_used, est, restarts, stats);
+      c->last_w = width;
       return EREM_OK;
     }
     if (rc != EREM_ENOCONV) return rc;
-    ++restarts;
-    if (K < o->m_max) {
-      K = o->m_max;
-    } else if (2 * s <= smax) {
-      s *= 2;
-    } else {
-      return fail(c, EREM_ENOCONV, "phi1 did not converge within m_max terms and max_substeps substeps");
-    }
+    retry = true;
   }
+}
+
+// T += h phi1(h J) F (Leja method) enqueued right behind the assembly, with
+// no host synchronisation before the Newton passes: the substep count is
+// predicted from the previous evaluation's interval width, the coefficients
+// are formed on the device from the assembly's reduction slots
+// (launch_leja_coef), and the slots read back with the stop states confirm
+// the prediction.  kFallback when there is no prediction or it did not hold
+// (the step then runs on the interval read from the slots).
+int step_predicted(erem_ctx* c, double h, double* d_T, const erem_opts* o, erem_stats* stats) {
+  if (o->method != EREM_METHOD_LEJA || !(c->last_w > 0.0) || !std::isfinite(c->last_w)) return kFallback;
+  const int smax = std::min(o->max_substeps, c->nstates);
+  const double rho = substep_rho(o);
+  const int s = substeps_for(h, c->last_w, rho, smax);
+  const int K = first_budget(c, o);
+  const int n = K + 1;
+  // budgets past what the device forms in LDS take the synchronous path
+  if (n > kCoefMaxN) return kFallback;
+  HIP_TRY(c, hipMemcpyAsync(c->h_red, c->red, sizeof(AsmReduce), hipMemcpyDeviceToHost, c->stream));
+  LejaCoefArgs a{};
+  a.red = c->red;
+  a.scale_v = 0;
+  a.n = n;
+  a.s = s;
+  a.smax = smax;
+  a.h = h;
+  a.rho = rho;
+  a.tol_a = o->tol_a;
+  a.tol_r = o->tol_r;
+  a.thresh = std::pow(10.0, -o->p_order);
+  a.rootN = std::sqrt(static_cast<double>(c->d.N));
+  a.xi = c->xi_dev;
+  a.cache = c->ddc;
+  a.cf = c->cf;
+  a.st = c->states;
+  int m_used = 0;
+  double est = 0.0;
+  int rc = leja_hphi1(c, h, c->F, nullptr, 0.0, s, K, o, &m_used, &est, &a);
+  if (rc == kFallback) return kFallback;
+  if (stats && (rc == EREM_OK || rc == EREM_ENOCONV)) {
+    stats->alpha = c->alpha;
+    stats->beta = c->beta;
+    stats->restarts = 0;
+  }
+  if (rc == EREM_OK) {
+    eval_done(c, s, m_used, est, 0, stats);
+    c->last_w = c->beta - c->alpha;
+  } else if (rc == EREM_ENOCONV) {
+    rc = hphi1_eval(c, h, c->F, nullptr, o->tol_a + o->tol_r * c->tmax, o, stats, s, K);
+  }
+  if (rc) return rc;
+  HIP_TRY(c, launch_axpby(c->d, d_T, 1.0, c->u, 1.0, c->stream));
+  return EREM_OK;
 }
 
 // Conjugate gradients on A delta = prhs from delta = 0 (delta in c->pdelta)
@@ -899,6 +1028,8 @@ int erem_create(const erem_grid* g, void* stream, erem_ctx** out) {
   rc |= dev_alloc(c, &c->states, c->nstates);
   rc |= dev_alloc(c, &c->red, 1);
   rc |= dev_alloc(c, &c->pcg, 1);
+  rc |= dev_alloc(c, &c->xi_dev, kMaxTerms + 1);
+  rc |= dev_alloc(c, &c->ddc, 1);
   c->pcg_nb = cell_bands(c->d);
   rc |= dev_alloc(c, &c->pcg_parts, pcg_parts_words(c->pcg_nb));
   if (rc == EREM_OK) {
@@ -932,6 +1063,9 @@ int erem_create(const erem_grid* g, void* stream, erem_ctx** out) {
     delete c;
     return EREM_EINVAL;
   }
+  // the device's copy of the points; an empty divided-difference cache
+  (void)hipMemcpyAsync(c->xi_dev, c->xi.data(), sizeof(double) * (kMaxTerms + 1), hipMemcpyHostToDevice, c->stream);
+  (void)hipMemsetAsync(c->ddc, 0, sizeof(DdCache), c->stream);
   {
     const int mrc = build_mg(c);
     if (mrc != EREM_OK) {
@@ -1217,6 +1351,8 @@ int erem_step(erem_ctx* c, double h, double* d_T, const erem_opts* o, erem_stats
   if (rc) return rc;
   rc = erem_form_jacobian(c, d_T);
   if (rc) return rc;
+  rc = step_predicted(c, h, d_T, o, stats);
+  if (rc != kFallback) return rc;
   rc = read_reduce(c);
   if (rc) return rc;
   return step_core(c, h, d_T, o, stats, c->tmax);
@@ -1274,13 +1410,17 @@ int erem_step_pressure(erem_ctx* c, double h, double* d_p, const double* d_T, do
                                  c->F, c->red, c->stream));
   c->coef32_valid = false;
   c->op_pressure = true;
-  rc = read_reduce(c);
-  if (rc) return rc;
-  // the pressure keeps its own Newton-degree memory (the temperature
-  // evaluations of the same steps need far fewer terms)
+  // the pressure keeps its own Newton-degree and interval memory (the
+  // temperature evaluations of the same steps need far fewer terms)
   std::swap(c->last_m, c->last_m_p);
-  rc = step_core(c, h, d_p, o, stats, c->tmax);
+  std::swap(c->last_w, c->last_w_p);
+  rc = step_predicted(c, h, d_p, o, stats);
+  if (rc == kFallback) {
+    rc = read_reduce(c);
+    if (!rc) rc = step_core(c, h, d_p, o, stats, c->tmax);
+  }
   std::swap(c->last_m, c->last_m_p);
+  std::swap(c->last_w, c->last_w_p);
   return rc;
 }
 

@@ -123,7 +123,12 @@ void phi_divided_differences_ws(int ell, double hc, double hg, const double* xi,
     nrm = std::max(nrm, c);
   }
   int s = 0;
-  if (nrm > 0.5) s = static_cast<int>(std::ceil(std::log2(nrm / 0.5)));
+  if (nrm > 0.5) {
+    // s = ceil(log2(nrm / 0.5)) exactly: nrm / 0.5 = f 2^e with f in [1/2, 1)
+    int e = 0;
+    const double f = std::frexp(nrm / 0.5, &e);
+    s = f == 0.5 ? e - 1 : e;
+  }
   const double scale = std::ldexp(1.0, -s);
   for (int k = 0; k < M; ++k) { dg[k] *= scale; sd[k] *= scale; }
 

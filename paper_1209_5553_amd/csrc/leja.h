@@ -43,4 +43,38 @@ hipError_t launch_substep_update(const Dims& d, double* u, const V* p, double de
                                  hipStream_t s, const double* zt = nullptr);
 hipError_t launch_cast_f32(const double* a, float* b, long long n, hipStream_t s);
 
+// Coefficients of one Newton-Leja phi1 evaluation formed on the device from
+// the assembly's reduction slots, so that the evaluation can be enqueued
+// before the host has read the interval.  The kernel folds the slots into
+// the Gershgorin interval [alpha, beta] and the largest |T| (or |v|), forms
+// scal = tol_a + tol_r max|T|, and, when the interval is finite and not
+// degenerate and its substep count ceil(h (beta - alpha) / rho) (at least 1,
+// at most smax) equals the count s the evaluation was enqueued with, fills
+// cf for substeps of delta = h / s: the divided differences of
+// phi1(delta (c + gamma xi)) (Sec. 4.2; the augmented bidiagonal
+// exponential by Taylor scaling and squaring, as on the host), the shifts
+// c / gamma + xi_{k-1} and the stop-test factors |delta d_k| / (sqrt(N) scal).
+// Otherwise it marks the s stop states as stopped, so that the evaluation's
+// term launches return at entry, and the host, which reads the same slots
+// afterwards, evaluates again with the interval it has read.
+struct LejaCoefArgs {
+  const AsmReduce* red;
+  int scale_v;      // 0: scal from the max |T| slots, 1: from the max |v| slots
+  int n;            // coefficients d_0 .. d_{n-1}, 1 <= n <= kCoefMaxN
+  int s, smax;      // substeps enqueued; cap of the substep count
+  double h, rho;    // step; widest substep interval (rho <= 0: one substep)
+  double tol_a, tol_r, thresh, rootN;
+  const double* xi;  // device copy of the Leja points (n values)
+  DdCache* cache;
+  LejaCoef* cf;
+  LejaState* st;
+};
+constexpr int kCoefThreads = 256;
+// Most coefficients the kernel forms: the augmented matrix (order n + 1 <=
+// 32) and its square stay in LDS.  Past that its dependent phases (20 Taylor
+// steps and up to 8 squarings) take longer than the host round trip they
+// replace.
+constexpr int kCoefMaxN = 31;
+hipError_t launch_leja_coef(const LejaCoefArgs& a, hipStream_t s);
+
 }  // namespace erem

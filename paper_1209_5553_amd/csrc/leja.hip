@@ -326,6 +326,208 @@ __global__ void k_cast_f32(const double* __restrict__ a, float* __restrict__ b, 
     b[i] = static_cast<float>(a[i]);
 }
 
+constexpr int kCoefM = kCoefMaxN + 1;  // largest order of the augmented matrix
+constexpr int kCoefLd = kCoefM + 1;     // row stride of the LDS matrices (rows on distinct banks)
+constexpr int kTaylorDegree = 20;
+
+// Coefficients of one phi1 evaluation from the reduction slots (one
+// workgroup of 16 x 16 threads; launch_leja_coef).  Thread (ty, tx) owns the
+// entries (ty + 16 a, tx + 16 b), a, b < RB, of the lower triangle of the two
+// LDS matrices; RB = ceil((n + 1) / 16) blocks of 16 rows cover the matrix.
+template <int RB>
+__global__ __launch_bounds__(kCoefThreads) void k_leja_coef(LejaCoefArgs a) {
+  // every operation rounded on its own, in the host routine's order, so the
+  // coefficients equal the host's bit for bit
+#pragma clang fp contract(off)
+  __shared__ double sA[kCoefM * kCoefLd], sB[kCoefM * kCoefLd];
+  __shared__ double dg[kCoefM], sd[kCoefM], dd[kCoefM], inv[kTaylorDegree + 1];
+  __shared__ double bc[6];
+  __shared__ double wmax[kCoefThreads / 64];
+  __shared__ int okf, hit;
+  const int t = threadIdx.x;
+  const int tx = t & 15, ty = t >> 4;
+  if (t < 64) {
+    // fold the 64 slots of each target (the encodings order like the values)
+    unsigned long long lo = a.red->lo[t], hi = a.red->hi[t];
+    unsigned long long sm = a.scale_v ? a.red->vmax[t] : a.red->tmax[t];
+    for (int off = 32; off > 0; off >>= 1) {
+      const unsigned long long l2 = __shfl_xor(lo, off, 64);
+      const unsigned long long h2 = __shfl_xor(hi, off, 64);
+      const unsigned long long s2 = __shfl_xor(sm, off, 64);
+      lo = l2 < lo ? l2 : lo;
+      hi = h2 > hi ? h2 : hi;
+      sm = s2 > sm ? s2 : sm;
+    }
+    if (t == 0) {
+      const double alpha = ord_decode(lo), beta = ord_decode(hi), tm = ord_decode(sm);
+      const double width = beta - alpha;
+      const double mag = fmax(fabs(alpha), fabs(beta));
+      const double scal = a.tol_a + a.tol_r * tm;
+      bool ok = isfinite(tm) && scal > 0.0 && isfinite(width) && !(width <= 1e-14 * mag || width == 0.0);
+      if (ok) {
+        int s = 1;
+        if (a.rho > 0.0) {
+          const double q = ceil(a.h * width / a.rho);
+          s = q >= a.smax ? a.smax : (q > 1.0 ? static_cast<int>(q) : 1);
+        }
+        ok = s == a.s;
+      }
+      const double cc = 0.5 * (alpha + beta), gg = 0.25 * (beta - alpha);
+      const double delta = a.h / a.s;
+      bc[0] = cc;
+      bc[1] = gg;
+      bc[2] = delta;
+      bc[3] = delta * cc;
+      bc[4] = delta * gg;
+      bc[5] = scal;
+      okf = ok;
+      hit = ok && a.cache->n >= a.n && a.cache->hc == bc[3] && a.cache->hg == bc[4];
+    }
+  }
+  __syncthreads();
+  if (!okf) {
+    for (int j = t; j < a.s; j += kCoefThreads) {
+      a.st[j].stopped = 0;
+      a.st[j].checked = -2;  // refused: the host evaluates again
+    }
+    return;
+  }
+  const int n = a.n, M = n + 1;
+  if (hit) {
+    if (t < n) dd[t] = a.cache->d[t];
+  } else {
+    // Augmented lower-bidiagonal matrix: diagonal (0, hc + hg xi_0, ...,
+    // hc + hg xi_{n-1}), subdiagonal A[1][0] = 1, A[i][i-1] = hg (i >= 2).
+    // The first column of its exponential is (1, phi1(hc I + hg L) e_1), the
+    // divided differences of phi1(hc + hg xi).  Scaling by 2^-q brings its
+    // 1-norm (the largest column sum) to at most 1/2.
+    const double hc = bc[3], hg = bc[4];
+    double nrm = 0.0;
+    if (t < M) {
+      const double dj = t == 0 ? 0.0 : hc + hg * a.xi[t - 1];
+      const double below = t + 1 < M ? (t == 0 ? 1.0 : fabs(hg)) : 0.0;
+      nrm = fabs(dj) + below;
+    }
+    for (int off = 32; off > 0; off >>= 1) nrm = fmax(nrm, __shfl_xor(nrm, off, 64));
+    if ((t & 63) == 0) wmax[t >> 6] = nrm;
+    // E = I on the leading M x M block, zero elsewhere (rows and columns past
+    // M and the upper triangle stay zero throughout)
+    for (int e = t; e < kCoefM * kCoefLd; e += kCoefThreads) {
+      const int i = e / kCoefLd;
+      sA[e] = (e - i * kCoefLd == i && i < M) ? 1.0 : 0.0;
+      sB[e] = 0.0;
+    }
+    if (t >= 1 && t <= kTaylorDegree) inv[t] = 1.0 / t;
+    __syncthreads();
+    nrm = wmax[0];
+    for (int w = 1; w < kCoefThreads / 64; ++w) nrm = fmax(nrm, wmax[w]);
+    int nsq = 0;  // ceil(log2(nrm / 0.5)) exactly, as on the host
+    if (nrm > 0.5) {
+      int ex = 0;
+      const double f = frexp(nrm / 0.5, &ex);
+      nsq = f == 0.5 ? ex - 1 : ex;
+    }
+    const double scale = ldexp(1.0, -nsq);
+    if (t < M) {
+      dg[t] = (t == 0 ? 0.0 : hc + hg * a.xi[t - 1]) * scale;
+      sd[t] = (t == 0 ? 0.0 : (t == 1 ? 1.0 : hg)) * scale;
+    }
+    __syncthreads();
+    double* E = sA;
+    double* T = sB;
+    // Taylor polynomial by Horner's rule, E <- I + X E / k, on the lower
+    // triangle
+    for (int k = kTaylorDegree; k >= 1; --k) {
+      const double ik = inv[k];
+#pragma unroll
+      for (int ra = 0; ra < RB; ++ra) {
+        const int i = ty + 16 * ra;
+        if (i >= M) break;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+          const int j = tx + 16 * rb;
+          if (j > i) break;
+          double v = i == 0 ? dg[0] * E[0] * ik
+                            : (dg[i] * E[i * kCoefLd + j] + sd[i] * E[(i - 1) * kCoefLd + j]) * ik;
+          if (i == j) v += 1.0;
+          T[i * kCoefLd + j] = v;
+        }
+      }
+      __syncthreads();
+      double* x = E;
+      E = T;
+      T = x;
+    }
+    // Squaring; the last square forms the first column only.  A thread's
+    // sums run over every k < 16 RB in order: the products outside
+    // j <= k <= i hold a zero of the upper triangle or of the rows and
+    // columns past M and add nothing, so each sum equals the host's over
+    // k = j .. i.
+    for (int q = 0; q < nsq; ++q) {
+      if (q + 1 == nsq) {
+        if (t < M) {
+          double acc = 0.0;
+          for (int k = 0; k <= t; ++k) acc += E[t * kCoefLd + k] * E[k * kCoefLd];
+          T[t * kCoefLd] = acc;
+        }
+      } else {
+        double acc[RB][RB];
+#pragma unroll
+        for (int ra = 0; ra < RB; ++ra)
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) acc[ra][rb] = 0.0;
+#pragma unroll
+        for (int k = 0; k < 16 * RB; ++k) {
+          double ar[RB], br[RB];
+#pragma unroll
+          for (int ra = 0; ra < RB; ++ra) ar[ra] = E[(ty + 16 * ra) * kCoefLd + k];
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) br[rb] = E[k * kCoefLd + tx + 16 * rb];
+#pragma unroll
+          for (int ra = 0; ra < RB; ++ra)
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) acc[ra][rb] += ar[ra] * br[rb];
+        }
+#pragma unroll
+        for (int ra = 0; ra < RB; ++ra) {
+          const int i = ty + 16 * ra;
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb) {
+            const int j = tx + 16 * rb;
+            if (i < M && j <= i) T[i * kCoefLd + j] = acc[ra][rb];
+          }
+        }
+      }
+      __syncthreads();
+      double* x = E;
+      E = T;
+      T = x;
+    }
+    if (t < n) {
+      const double v = E[(t + 1) * kCoefLd];
+      dd[t] = v;
+      a.cache->d[t] = v;
+    }
+    if (t == 0) {
+      a.cache->hc = hc;
+      a.cache->hg = hg;
+      a.cache->n = n;
+    }
+  }
+  __syncthreads();
+  const double cc = bc[0], gg = bc[1], delta = bc[2], scal = bc[5];
+  if (t < n) {
+    const double d = dd[t];
+    a.cf->dk[t] = d;
+    a.cf->shift[t] = t > 0 ? cc / gg + a.xi[t - 1] : 0.0;
+    a.cf->estf[t] = fabs(delta * d) / (a.rootN * scal);
+  }
+  if (t == 0) {
+    a.cf->inv_g = 1.0 / gg;
+    a.cf->thresh = a.thresh;
+  }
+}
+
 }  // namespace
 
 int leja_num_blocks(const Dims& d) {
@@ -386,6 +588,15 @@ template <class V>
 hipError_t launch_substep_update(const Dims& d, double* u, const V* p, double delta, int first, hipStream_t s,
                                  const double* zt) {
   hipLaunchKernelGGL(k_substep_update<V>, cell_grid(d), cell_block(), 0, s, d, u, p, delta, first, zt);
+  return hipGetLastError();
+}
+
+hipError_t launch_leja_coef(const LejaCoefArgs& a, hipStream_t s) {
+  if (a.n < 1 || a.n > kCoefMaxN || a.s < 1 || a.s > a.smax) return hipErrorInvalidValue;
+  if (a.n + 1 <= 16)  // 16-row blocks of the order n + 1 matrix
+    hipLaunchKernelGGL(k_leja_coef<1>, dim3(1), dim3(kCoefThreads), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_leja_coef<2>, dim3(1), dim3(kCoefThreads), 0, s, a);
   return hipGetLastError();
 }
 

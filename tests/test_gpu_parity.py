@@ -286,17 +286,69 @@ def test_first_step_increment_32x32(torch_mod):
     assert rel_inf(T_gpu - prob.T0, T_ref - prob.T0) <= TOL
 
 
-def test_linear_exactness_on_gpu(torch_mod):
-    """Ten GPU steps of h equal one GPU step of 10 h (EREM is exact for
-    linear problems, R(z) = e^z), and both equal the oracle."""
+
+# Steps after the first are enqueued right behind the assembly: the substep
+# count is predicted from the previous step's interval width and the Leja
+# coefficients are formed on the device; the interval read back afterwards
+# confirms the prediction, else the step runs again on it.
+
+def _lam_steps(torch, prob, factors, h, opts=None):
+    """Steps with the conductivity scaled by each factor in turn (the
+    interval and the substep count change with it), each from a fresh seeded
+    temperature field (so that no step starts near the steady state) against
+    the oracle step from the same field with that conductivity."""
+    import dataclasses
+    ctx = _ctx(prob)
+    ctx.pressure_and_fluxes(rtol=1e-16)
+    rng = np.random.default_rng(17)
+    out = []
+    for f in factors:
+        lam = prob.lam * f
+        ctx.set_rock(ctx._logk, ctx._poro, lam, prob.rhoc_s)
+        start = rng.uniform(20.0, 80.0, prob.n)
+        T = _dev(torch, start)
+        st = ctx.step(h, T, opts)
+        model = oerem.Discretisation(dataclasses.replace(prob, lam=lam), start).model
+        a, b = oph.gershgorin_interval(model.J_sparse(start))
+        Tref = oerem.erem_step(model, start, h)
+        got = T.cpu().numpy()
+        err, inc = rel_inf(got, Tref), rel_inf(got - start, Tref - start)
+        _say(f"  lam x{f:g}: s={st['substeps']} m={st['m_total']} restarts={st['restarts']} "
+             f"err={err:.2e} inc={inc:.2e}")
+        assert err <= TOL and inc <= TOL
+        assert st["alpha"] == pytest.approx(a, rel=1e-13)
+        assert abs(st["beta"] - b) <= 1e-13 * abs(a)
+        out.append(st)
+    return out
+
+
+def test_predicted_substeps_follow_interval_changes(torch_mod):
+    """24x24: the substep count goes 3, 3, 4, 4, 5, 10, 3, 3 as the
+    conductivity changes; every change is a failed prediction that falls back
+    to the interval read back, every repeat a held one."""
     torch = torch_mod
     prob = inputs.linear_problem(24, seed=6)
-    T10, _ = _run_gpu_linear(torch, prob, 10)
-    T1, _ = _run_gpu_linear(torch, prob, 1, h=10 * prob.h)
-    assert rel_inf(T10 - prob.T0, T1 - prob.T0) <= TOL
-    disc = oerem.Discretisation(prob, prob.T0)
-    Tref = oerem.erem_step(disc.model, prob.T0, 10 * prob.h)
-    assert rel_inf(T1, Tref) <= TOL
+    _say("predicted substeps 24x24, conductivity x1 1 4 4 16 64 1 0.25")
+    sts = _lam_steps(torch, prob, (1, 1, 4, 4, 16, 64, 1, 0.25), prob.h)
+    assert [s["substeps"] for s in sts] == [3, 3, 4, 4, 5, 10, 3, 3]
+
+
+def test_predicted_step_budget_restart(torch_mod):
+    """One substep (rho_max = 0) at h / 64: the degree is about 20, so the
+    second and third steps' budgets (the previous degree plus one group) are
+    formed on the device; when the conductivity grows 256-fold the degree
+    grows to about 38, past the third step's budget of 28 terms, and the
+    predicted evaluation restarts with the full budget; the fourth step's
+    budget (44 terms) is more than the device forms and takes the
+    synchronous path."""
+    torch = torch_mod
+    from paper_1209_5553_amd.api import make_opts
+    prob = inputs.linear_problem(24, seed=6)
+    _say("predicted step 24x24, one substep, conductivity x1 1 256 256")
+    sts = _lam_steps(torch, prob, (1, 1, 256, 256), prob.h / 64, make_opts(rho_max=0.0))
+    assert all(s["substeps"] == 1 for s in sts)
+    assert sts[1]["restarts"] == 0 and sts[2]["restarts"] >= 1
+    assert sts[2]["m_total"] > 28
 
 
 def test_energy_conserved_with_closed_boundaries(torch_mod):
