@@ -286,6 +286,18 @@ def test_first_step_increment_32x32(torch_mod):
     assert rel_inf(T_gpu - prob.T0, T_ref - prob.T0) <= TOL
 
 
+def test_linear_exactness_on_gpu(torch_mod):
+    """Ten GPU steps of h equal one GPU step of 10 h (EREM is exact for
+    linear problems, R(z) = e^z), and both equal the oracle."""
+    torch = torch_mod
+    prob = inputs.linear_problem(24, seed=6)
+    T10, _ = _run_gpu_linear(torch, prob, 10)
+    T1, _ = _run_gpu_linear(torch, prob, 1, h=10 * prob.h)
+    assert rel_inf(T10 - prob.T0, T1 - prob.T0) <= TOL
+    disc = oerem.Discretisation(prob, prob.T0)
+    Tref = oerem.erem_step(disc.model, prob.T0, 10 * prob.h)
+    assert rel_inf(T1, Tref) <= TOL
+
 
 # Steps after the first are enqueued right behind the assembly: the substep
 # count is predicted from the previous step's interval width and the Leja
