@@ -300,11 +300,8 @@ int read_reduce(erem_ctx* c) {
   return EREM_OK;
 }
 
-// u <- h phi1(h J) v by s Leja substeps of delta = h/s, each an exact
-// integration of the linear ODE u' = J u + v over delta:
-//   u_{j+1} = u_j + delta phi1(delta J) (v + J u_j)   (Sec. 4.2 splitting).
-// Returns EREM_OK, EREM_ENOCONV (some substep did not stop within K terms)
-// or an error.  `m_used` receives the summed degree.
+// Device buffers of the Newton passes in one precision: the stencil of J,
+// the two q buffers and the accumulated polynomial p.
 template <class V>
 struct LejaBufs {
   const V* coef;
@@ -403,11 +400,6 @@ void fill_coef(LejaCoef* hc, const std::vector<double>& dv, int n, double cc, do
   }
 }
 
-// u <- h phi1(h J) v by s Leja substeps of delta = h/s, each an exact
-// integration of the linear ODE u' = J u + v over delta:
-//   u_{j+1} = u_j + delta phi1(delta J) (v + J u_j)   (Sec. 4.2 splitting).
-// Returns EREM_OK, EREM_ENOCONV (some substep did not stop within K terms)
-// or an error.  `m_used` receives the summed degree actually applied.
 // Internal result of an evaluation enqueued on a predicted substep count
 // whose prediction did not hold: evaluate again on the interval read back.
 constexpr int kFallback = -100;  // not an EREM_ code
@@ -459,6 +451,14 @@ int confirm_device_coef(erem_ctx* c, double h, int s, const erem_opts* o, const 
   return EREM_OK;
 }
 
+// u <- h phi1(h J) v by s Leja substeps of delta = h/s, each an exact
+// integration of the linear ODE u' = J u + v over delta:
+//   u_{j+1} = u_j + delta phi1(delta J) (v + J u_j)   (Sec. 4.2 splitting).
+// Returns EREM_OK, EREM_ENOCONV (some substep did not stop within K terms)
+// or an error.  `m_used` receives the summed degree actually applied.  With
+// `dev` the coefficients are formed on the device (launch_leja_coef) instead
+// of uploaded, and kFallback means the interval read back afterwards does not
+// give these coefficients (the caller evaluates again on it).
 int leja_hphi1(erem_ctx* c, double h, const double* v, const double* g, double scal, int s, int K,
                const erem_opts* o, int* m_used, double* est_last, const LejaCoefArgs* dev = nullptr) {
   const int n = K + 1;
