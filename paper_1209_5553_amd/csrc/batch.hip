@@ -348,11 +348,28 @@ __global__ __launch_bounds__(kCtrlThreads) void k_bt_ctrl(BatchArgs a) {
     for (int j = 0; j < kBatchPartStride; ++j) s[j] += __shfl_down(s[j], off, 64);
     mx = fmax(mx, __shfl_down(mx, off, 64));
   }
+  // the pass's scaled estimates |delta d_k| ||q_k|| / (sqrt(N) scal), lane j
+  // forming term S.k + j's (each the expression a sequential loop would
+  // evaluate, so the same bits), then gathered in lane 0
+  mx = __shfl(mx, 0, 64);
+  if (init && S.kind != kInitSub) S.scal = a.tol_a + a.tol_r * mx;
+  double sj = 0.0, dj = 0.0;
+#pragma unroll
+  for (int j = 0; j < kBatchPartStride; ++j) {
+    const double v = __shfl(s[j], 0, 64);
+    if (lane == j) {
+      sj = v;
+      dj = dkv[j];
+    }
+  }
+  const double est = fabs(P.delta * dj) * sqrt(sj) / (P.rootN * S.scal);
+  double estv[kBatchPartStride];
+#pragma unroll
+  for (int j = 0; j < kBatchPartStride; ++j) estv[j] = __shfl(est, j, 64);
   if (lane != 0) return;
   ++S.phases;
   bool stop = false;  // no further Newton work for this problem
   if (init) {
-    if (S.kind != kInitSub) S.scal = a.tol_a + a.tol_r * mx;
     if (S.kind == kInitStep) S.tpar ^= 1;
     if (S.kind == kInitSub) S.upar ^= 1;
     S.ppar ^= 1;
@@ -366,7 +383,7 @@ __global__ __launch_bounds__(kCtrlThreads) void k_bt_ctrl(BatchArgs a) {
       S.flags |= 1;  // not even one pass fits the term budget
       stop = true;
     } else {
-      S.ring[0] = fabs(P.delta * dkv[0]) * sqrt(s[0]) / (P.rootN * S.scal);
+      S.ring[0] = estv[0];
       S.k = 1;
       S.phase = kPhTerms;
     }
@@ -378,7 +395,7 @@ __global__ __launch_bounds__(kCtrlThreads) void k_bt_ctrl(BatchArgs a) {
         bad = true;
         break;
       }
-      S.ring[kk % 5] = fabs(P.delta * dkv[j]) * sqrt(s[j]) / (P.rootN * S.scal);
+      S.ring[kk % 5] = estv[j];
       if (kk >= 4) {
         const double mean = 0.2 * (S.ring[0] + S.ring[1] + S.ring[2] + S.ring[3] + S.ring[4]);
         done = mean < a.thresh;
