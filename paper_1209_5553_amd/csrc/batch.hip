@@ -388,19 +388,32 @@ __global__ __launch_bounds__(kCtrlThreads) void k_bt_ctrl(BatchArgs a) {
       S.phase = kPhTerms;
     }
   } else {
+    // the terms in order until the test passes; every index below is a
+    // compile-time constant (the unrolled loops select the ring slot), so
+    // the state stays in registers
     bool done = false, bad = false;
-    for (int j = 0; j < nt && !done; ++j) {
+    double ring[5];
+#pragma unroll
+    for (int q = 0; q < 5; ++q) ring[q] = S.ring[q];
+#pragma unroll
+    for (int j = 0; j < kBatchPartStride; ++j) {
+      if (j >= nt || done || bad) continue;
       const int kk = S.k + j;
       if (!isfinite(s[j])) {
         bad = true;
-        break;
+        continue;
       }
-      S.ring[kk % 5] = estv[j];
+      const int slot = kk % 5;
+#pragma unroll
+      for (int q = 0; q < 5; ++q)
+        if (q == slot) ring[q] = estv[j];
       if (kk >= 4) {
-        const double mean = 0.2 * (S.ring[0] + S.ring[1] + S.ring[2] + S.ring[3] + S.ring[4]);
+        const double mean = 0.2 * (ring[0] + ring[1] + ring[2] + ring[3] + ring[4]);
         done = mean < a.thresh;
       }
     }
+#pragma unroll
+    for (int q = 0; q < 5; ++q) S.ring[q] = ring[q];
     S.terms += nt;  // all terms of the pass are kept
     if (bad) {
       S.flags |= 2;
