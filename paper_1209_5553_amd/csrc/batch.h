@@ -36,7 +36,8 @@ struct BProb {
 
 // Tile list entry: the problem and the tile's first cell.
 struct BTile {
-  int pid, x0, y0, pad;
+  int pid, x0, y0;
+  int done;  // set by the control kernel once the problem is done: the tile returns at entry
 };
 
 // Phases of a problem; every work launch advances each problem that is not
@@ -74,7 +75,7 @@ struct BState {
 
 struct BatchArgs {
   const BProb* prob;
-  const BTile* tile;
+  BTile* tile;
   BState* state;
   int* ndone;            // problems done (control kernel counts them)
   const double* coef64;  // 5-point stencil, SoA with stride ntot (FP64)

@@ -89,6 +89,7 @@ __global__ __launch_bounds__(kBatchTileX* BY) void k_bt_work(BatchArgs a) {
 
   const int t = XCD ? xcd_tile_id() : static_cast<int>(blockIdx.x);
   const BTile tl = a.tile[t];
+  if (tl.done) return;  // the tiles of a finished problem stop here, before its state is read
   const BState S = a.state[tl.pid];
   if (S.phase == kPhDone) return;
   const BProb P = a.prob[tl.pid];
@@ -313,6 +314,9 @@ __global__ __launch_bounds__(kCtrlThreads) void k_bt_ctrl(BatchArgs a) {
   const BProb P = a.prob[pid];
   if (S.phase == kPhDone) return;
   if (S.phase == kPhFinish) {
+    // the finish pass is done: from the next launch on the problem's tiles
+    // return at entry
+    for (int tt = lane; tt < P.ntiles; tt += 64) a.tile[P.tile0 + tt].done = 1;
     if (lane == 0) {
       S.phase = kPhDone;
       ++S.phases;
@@ -449,6 +453,7 @@ __global__ __launch_bounds__(kCtrlThreads) void k_bt_ctrl(BatchArgs a) {
 __global__ void k_bt_reset(BatchArgs a) {
   const int pid = blockIdx.x * blockDim.x + threadIdx.x;
   if (pid == 0) *a.ndone = 0;
+  if (pid < a.ntiles) a.tile[pid].done = 0;
   if (pid >= a.nprob) return;
   BState S{};
   S.phase = kPhInit;
@@ -526,7 +531,8 @@ hipError_t batch_pack(int nx, int ny, const double* coef, const double* F, const
 }
 
 hipError_t batch_reset(const BatchArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_bt_reset, dim3((a.nprob + 255) / 256), dim3(256), 0, s, a);
+  const int n = a.nprob > a.ntiles ? a.nprob : a.ntiles;  // a thread per problem state and per tile
+  hipLaunchKernelGGL(k_bt_reset, dim3((n + 255) / 256), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 
