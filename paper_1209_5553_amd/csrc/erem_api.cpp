@@ -436,7 +436,7 @@ int first_budget(const erem_ctx* c, const erem_opts* o) {
 int confirm_device_coef(erem_ctx* c, double h, int s, const erem_opts* o, const LejaCoefArgs& a) {
   c->alpha = slot_min(c->h_red->lo);
   c->beta = slot_max(c->h_red->hi);
-  c->tmax = slot_max(a.scale_v ? c->h_red->vmax : c->h_red->tmax);
+  c->tmax = slot_max(c->h_red->tmax);
   if (!std::isfinite(c->tmax)) return fail(c, EREM_ENONFINITE, "non-finite temperature");
   const double scal = o->tol_a + o->tol_r * c->tmax;
   if (!(scal > 0)) return fail(c, EREM_EINVAL, "error scale is zero (tol_a = 0 and T = 0)");
@@ -768,7 +768,6 @@ int step_predicted(erem_ctx* c, double h, double* d_T, const erem_opts* o, erem_
   HIP_TRY(c, hipMemcpyAsync(c->h_red, c->red, sizeof(AsmReduce), hipMemcpyDeviceToHost, c->stream));
   LejaCoefArgs a{};
   a.red = c->red;
-  a.scale_v = 0;
   a.n = n;
   a.s = s;
   a.smax = smax;

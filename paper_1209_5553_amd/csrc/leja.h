@@ -46,7 +46,7 @@ hipError_t launch_cast_f32(const double* a, float* b, long long n, hipStream_t s
 // Coefficients of one Newton-Leja phi1 evaluation formed on the device from
 // the assembly's reduction slots, so that the evaluation can be enqueued
 // before the host has read the interval.  The kernel folds the slots into
-// the Gershgorin interval [alpha, beta] and the largest |T| (or |v|), forms
+// the Gershgorin interval [alpha, beta] and the largest |T|, forms
 // scal = tol_a + tol_r max|T|, and, when the interval is finite and not
 // degenerate and its substep count ceil(h (beta - alpha) / rho) (at least 1,
 // at most smax) equals the count s the evaluation was enqueued with, fills
@@ -59,7 +59,6 @@ hipError_t launch_cast_f32(const double* a, float* b, long long n, hipStream_t s
 // afterwards, evaluates again with the interval it has read.
 struct LejaCoefArgs {
   const AsmReduce* red;
-  int scale_v;      // 0: scal from the max |T| slots, 1: from the max |v| slots
   int n;            // coefficients d_0 .. d_{n-1}, 1 <= n <= kCoefMaxN
   int s, smax;      // substeps enqueued; cap of the substep count
   double h, rho;    // step; widest substep interval (rho <= 0: one substep)

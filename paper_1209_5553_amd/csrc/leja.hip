@@ -349,7 +349,7 @@ __global__ __launch_bounds__(kCoefThreads) void k_leja_coef(LejaCoefArgs a) {
   if (t < 64) {
     // fold the 64 slots of each target (the encodings order like the values)
     unsigned long long lo = a.red->lo[t], hi = a.red->hi[t];
-    unsigned long long sm = a.scale_v ? a.red->vmax[t] : a.red->tmax[t];
+    unsigned long long sm = a.red->tmax[t];
     for (int off = 32; off > 0; off >>= 1) {
       const unsigned long long l2 = __shfl_xor(lo, off, 64);
       const unsigned long long h2 = __shfl_xor(hi, off, 64);
