@@ -248,7 +248,10 @@ int erem_face_fluxes_from_pressure(erem_ctx* ctx, const double* d_p);
  * erem_form_jacobian / erem_step.  alpha_b (rock) and beta_f (fluid
  * compressibility) in 1/Pa, >= 0, not both 0.  phi1 by opts->method (the
  * paper pairs Krylov for the pressure with Leja for the temperature); the
- * error scale is tol_a + tol_r max|p|.  Afterwards the context's J and F are
+ * error scale is tol_a + tol_r max|p|.  With the Leja method, after a first
+ * pressure step and for budgets of at most 31 terms, the Newton passes are
+ * enqueued as in erem_step (substep count predicted from the previous
+ * pressure step's interval, confirmed afterwards).  Afterwards the context's J and F are
  * J_p and G4: until the next erem_form_jacobian, erem_step or
  * erem_set_jacobian, this call (which needs G2) and erem_get_jacobian,
  * erem_phi1_apply, erem_step_frozen and erem_shifted_solve (which need the
