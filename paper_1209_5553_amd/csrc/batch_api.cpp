@@ -111,11 +111,34 @@ void free_batch(erem_batch* b) {
 }
 
 // Tile list and per-problem tile ranges for the current shape (64 x rows
-// tiles, problems in order, each problem's tiles row by row).
+// tiles, each problem's tiles row by row).  The work pass deals the tile
+// list to the XCDs in eight contiguous chunks, so the order of the problems
+// decides which XCD works on which problem.  Once the intervals are known
+// the problems go in order of their schedule length h (beta - alpha) (the
+// Newton terms of a step grow with it), dealt to eight groups in serpentine
+// order (1..8, 8..1, ...), and the groups follow each other: each XCD gets a
+// like mix of long and short schedules, and the last phases, where only the
+// longest problems are left, run on all XCDs.  Each problem's own results do
+// not depend on the order.
 int build_tiles(erem_batch* b) {
   const int rows = kBatchTileRows[b->shape];
   std::vector<BTile> tiles;
+  std::vector<int> ord(b->nprob);
+  std::vector<double> len(b->nprob, 0.0);
   for (int i = 0; i < b->nprob; ++i) {
+    const BProb& P = b->hprob[i];
+    ord[i] = i;
+    len[i] = P.inv_g > 0.0 ? P.delta * P.s * 4.0 / P.inv_g : 0.0;  // h (beta - alpha); 0 before prepare
+  }
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return len[x] > len[y]; });
+  std::vector<std::vector<int>> groups(kXcds);
+  for (size_t r = 0; r < ord.size(); ++r) {
+    const size_t q = r % (2 * kXcds);
+    groups[q < kXcds ? q : 2 * kXcds - 1 - q].push_back(ord[r]);
+  }
+  ord.clear();
+  for (const auto& g : groups) ord.insert(ord.end(), g.begin(), g.end());
+  for (const int i : ord) {
     BProb& P = b->hprob[i];
     const int tx = static_cast<int>((b->grids[i].nx + kBatchTileX - 1) / kBatchTileX);
     const int ty = static_cast<int>((b->grids[i].ny + rows - 1) / rows);
