@@ -518,7 +518,7 @@ TRAFFIC = {
     ("layered128", "mixed", "leja_term"): 93.30e6,      # FP32 one-term kernel, 44 B per cell algorithmic
     # batch256: whole-run totals of the work kernel (divided by its launches)
     ("batch256", "fp64", "k_bt_work/shape5"): 213.05e9,   # one 50-step run, substep intervals up to 96
-    ("batch256", "mixed", "k_bt_work/shape7"): 174.74e9,  # one 50-step run, FP32 passes
+    ("batch256", "mixed", "k_bt_work/shape7"): 174.68e9,  # one 50-step run, FP32 passes
     # layered256: a working launch (the z-neighbour planes are fetched again: 1.16x algorithmic)
     ("layered256", "fp64", "leja_term"): 1714.26e6,
     ("layered256", "mixed", "leja_term"): 742.57e6,    # FP32: exactly its algorithmic bytes
