@@ -302,7 +302,7 @@ __global__ __launch_bounds__(kBatchTileX* BY) void k_bt_work(BatchArgs a) {
 
 // One wavefront per problem: reduce the problem's tile partials of the last
 // work pass in a fixed order, apply the stop test and pick the next phase.
-constexpr int kCtrlThreads = 256;
+constexpr int kCtrlThreads = 64;  // one wavefront (one problem) per workgroup
 
 __global__ __launch_bounds__(kCtrlThreads) void k_bt_ctrl(BatchArgs a) {
   const int lane = threadIdx.x & 63;
